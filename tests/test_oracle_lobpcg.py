@@ -1,0 +1,131 @@
+"""Pins of the oracle LOBPCG (Sec. II.B) against brute force, closed forms and
+an independent Krylov library."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as ssl
+
+import synth
+from oracle import dense, lobpcg as lob, teter
+from oracle.hamiltonian import Operator
+from oracle.solve import solve_element
+from tests._pins import fourier_d2, free_electron_levels
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "one_element_dense.json")
+
+
+def _run(el, tol, max_iter=400, X0=None):
+    op = Operator(el.grid, el.box, el.V, el.kb)
+    pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
+    return op, lob.lobpcg(op.apply, pre, el.X0 if X0 is None else X0, tol, max_iter)
+
+
+def test_small_grid_vs_dense_eigh():
+    el = synth.single_element(seed=2, grid=(12, 12, 12), n_states=10, n_atoms=3)
+    op, res = _run(el, 1e-9)
+    assert res.converged
+    H = op.dense()
+    w, U = dense.lowest(H, 14)
+    J = 10
+    assert np.abs(res.theta - w[:J]).max() < 1e-10
+    # orthonormality and residual reported honestly
+    assert np.abs(res.X.T @ res.X - np.eye(J)).max() < 1e-12
+    r = np.linalg.norm(H @ res.X - res.X * res.theta, axis=0)
+    assert np.allclose(r, res.resid, atol=1e-12)
+    # variational bound (Cauchy interlacing) and residual bound
+    assert np.all(res.theta >= w[:J] - 1e-12)
+    assert np.all(np.abs(res.theta - w[:J]) <= res.resid + 1e-13)
+    # subspace: largest principal angle, where the cut has a gap
+    if w[J] - w[J - 1] > 1e-4:
+        s = np.linalg.svd(U[:, :J].T @ res.X, compute_uv=False)
+        assert np.sqrt(max(0.0, 1 - s.min() ** 2)) < 1e-7
+
+
+def test_free_electron_closed_form():
+    el = synth.single_element(seed=0, grid=(16, 16, 16), n_states=19, wells=False, kb=False)
+    _, res = _run(el, 1e-9)
+    ref = free_electron_levels(el.grid, el.box, 19)
+    assert res.converged
+    assert np.abs(res.theta - ref).max() < 1e-12
+
+
+def test_separable_spectrum_36x36x60():
+    """Exact reference from three 1D closed-form operators; dense 3D is infeasible."""
+    grid = (36, 36, 60)
+    box = tuple(n * synth.H_SPACING for n in grid)
+    xs = [np.arange(n) * (L / n) for n, L in zip(grid, box)]
+    vs = [-1.5 * np.exp(-((x - L / 3) ** 2) / (2 * 0.8 ** 2)) for x, L in zip(xs, box)]
+    V = (vs[2][:, None, None] + vs[1][None, :, None] + vs[0][None, None, :]).reshape(-1)
+    ev = [np.linalg.eigvalsh(-0.5 * fourier_d2(n, L) + np.diag(v))
+          for n, L, v in zip(grid, box, vs)]
+    sums = np.sort((ev[2][:, None, None] + ev[1][None, :, None] + ev[0][None, None, :]).ravel())
+    J = 12
+    el = synth.Element(grid=grid, box=box, V=V,
+                       kb=synth.KB(np.zeros(0), np.zeros(1, np.int64), np.zeros(0, np.int32),
+                                   np.zeros(0)),
+                       X0=synth.initial_guess(int(np.prod(grid)), J, 9, 0, 0), n_states=J,
+                       elem_lo=(0, 0, 0), elem_hi=grid, n_alb=J, atoms=np.zeros((0, 5)))
+    _, res = _run(el, 1e-8)
+    assert res.converged
+    # compare values below the largest cut with a gap
+    assert np.abs(res.theta - sums[:J]).max() < 1e-11
+
+
+def test_one_element_workload_vs_stored_dense():
+    """Full one-element workload (24^3, 32 states) against the dense LAPACK
+    eigenvalues written by tests/golden/make_golden.py."""
+    gold = json.load(open(GOLDEN))
+    el = synth.single_element(seed=0)
+    _, res = _run(el, 1e-8)
+    w = np.asarray(gold["seeds"]["0"])
+    assert res.converged
+    assert np.abs(res.theta - w[:32]).max() < 1e-10
+    assert np.all(res.theta >= w[:32] - 1e-12)
+
+
+def test_vs_arpack_on_slab_geometry():
+    """An independent library (ARPACK through scipy) on a LinearOperator."""
+    grid = (24, 24, 36)
+    box = tuple(n * synth.H_SPACING for n in grid)
+    el = synth.slab_batch(1, grid=grid, n_states=12, n_atoms=6)[0]
+    op, res = _run(el, 1e-9)
+    A = ssl.LinearOperator((op.ng, op.ng), matvec=lambda v: op.apply(v.ravel()), dtype=float)
+    w = np.sort(ssl.eigsh(A, k=12, which="SA", tol=1e-13, maxiter=20000,
+                          v0=np.ones(op.ng))[0])
+    assert res.converged
+    assert np.abs(res.theta - w).max() < 1e-10
+
+
+def test_rank_deficient_initial_guess_breaks_down():
+    el = synth.single_element(seed=0, grid=(12, 12, 12), n_states=6, n_atoms=2)
+    X0 = el.X0.copy()
+    X0[:, 3] = X0[:, 1]
+    with pytest.raises(lob.Breakdown):
+        _run(el, 1e-8, X0=X0)
+
+
+def test_iteration_cap_reports_not_converged():
+    el = synth.single_element(seed=0, grid=(12, 12, 12), n_states=6, n_atoms=2)
+    _, res = _run(el, 1e-10, max_iter=2)
+    assert res.iters == 2 and not res.converged
+    assert res.resid.max() > 1e-10
+
+
+def test_warm_start_converges_immediately():
+    el = synth.single_element(seed=4, grid=(12, 12, 12), n_states=6, n_atoms=2)
+    _, res = _run(el, 1e-9)
+    _, res2 = _run(el, 1e-8, X0=res.X)
+    assert res2.iters == 0 and res2.converged
+    assert np.abs(res2.theta - res.theta).max() < 1e-12
+
+
+def test_solve_element_normalisation():
+    el = synth.single_element(seed=2, grid=(12, 12, 12), n_states=8, n_atoms=3)
+    out = solve_element(el, tol=1e-9)
+    dv = el.dv
+    psi = out["eigvecs"]
+    assert np.abs(dv * psi.T @ psi - np.eye(8)).max() < 1e-12
+    phi = out["albs"]
+    assert np.abs(dv * phi.T @ phi - np.eye(el.n_alb)).max() < 1e-12
