@@ -1,0 +1,203 @@
+/*
+ * dgdft_alb.h -- C ABI of the MI355X library for DGDFT's adaptive-local-basis
+ * (ALB) generation step.
+ *
+ * What the library computes (Hu, Lin, Yang, "DGDFT: a massively parallel
+ * method for large scale density functional theory calculations"):
+ *
+ *   For every extended element Q_K of a batch, the lowest J_K eigenpairs of
+ *   the local Kohn-Sham operator  -1/2 Laplacian + V_eff^Q + V_nl^Q  with the
+ *   normalisation  integral over Q_K of psi_j psi_j' = delta  (Sec. II.A,
+ *   Eq. localproblem), discretised by planewaves on the periodic box of Q_K
+ *   (Sec. II.B, grid rule Eq. Ngecut) and solved by Teter-preconditioned
+ *   LOBPCG (Sec. II.B, "Generation of the ALB functions"); the nonlocal part
+ *   is of Kleinman-Bylander form  sum_p gamma_p |b_p><b_p|  (Eq. DGvar).
+ *   The eigenvectors are then restricted to the element E_K and
+ *   orthonormalised (Sec. II.A after Eq. localproblem; Eq. orthonormal), here
+ *   as an SVD truncation to n_alb functions.
+ *
+ * Conventions shared by every entry point
+ *   - Grids are flattened x fastest: flat = i + n1*(j + n2*k).
+ *   - Block matrices are column-major, one orbital per column, leading
+ *     dimension = rows (no padding at the ABI).
+ *   - Batched arrays are the per-element arrays concatenated in element order.
+ *   - Units: Hartree atomic units (bohr, Ha).  All floating point is FP64 at
+ *     the ABI.
+ *   - "device" pointers are HIP device memory of the device current at
+ *     dgdft_alb_create; "host" pointers are ordinary host memory.
+ *   - Work is enqueued on the caller's hipStream_t (passed as void*; NULL =
+ *     the null stream).  Entry points that return results to the host
+ *     (status, stats) synchronise that stream before returning.
+ *   - No entry point aborts or throws; failures return a negative status and
+ *     leave a message for dgdft_alb_last_error.
+ *   - One handle must not be used from two threads at once; distinct handles
+ *     are independent.
+ */
+#ifndef DGDFT_ALB_H
+#define DGDFT_ALB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define DGDFT_OK               0   /* success                                     */
+#define DGDFT_NOT_CONVERGED    1   /* warning: outputs written, some element did  *
+                                    * not reach tol within max_iter (see stats)   */
+#define DGDFT_EINVAL          -1   /* bad argument: null pointer, bad shape,      *
+                                    * non-finite input, box outside the grid ...  */
+#define DGDFT_EUNSUPPORTED    -2   /* grid edge with a prime factor > 5, plane or *
+                                    * pencil tile above the LDS limit, J > 1024   */
+#define DGDFT_ENOMEM          -3   /* device allocation failed                    */
+#define DGDFT_EHIP            -4   /* HIP runtime error (message in last_error)   */
+#define DGDFT_EBREAKDOWN      -5   /* initial block rank deficient (CholQR)       */
+
+#define DGDFT_PREC_FP64        0
+#define DGDFT_PREC_MIXED       1   /* FP32 FFT/pointwise; reserved, see design    */
+
+#define DGDFT_PRECOND_TETER    0
+#define DGDFT_PRECOND_NONE     2   /* identity (for tests)                        */
+
+typedef struct dgdft_alb dgdft_alb;   /* opaque handle */
+
+/* Options for dgdft_alb_create.  Zero-initialise, then set fields; a NULL
+ * options pointer means all defaults.  Array fields are host pointers with
+ * one entry (or three, for boxes) per element, copied at create. */
+typedef struct dgdft_alb_opts {
+    int32_t precision;        /* DGDFT_PREC_*, default FP64                        */
+    int32_t precond;          /* DGDFT_PRECOND_*, default TETER                    */
+    double  tol;              /* residual tolerance, default 1e-8 (0 = default)   *
+                               * converged iff max_i ||H x_i - theta_i x_i||_2     *
+                               * <= tol for unit x_i, in FP64                      */
+    int32_t max_iter;         /* LOBPCG iteration cap, default 500 (0 = default)  */
+    int32_t poll_every;       /* host convergence poll period in iterations,      *
+                               * default 1                                         */
+    const int32_t* elem_lo;   /* [n_elem][3] restriction box, half-open; NULL =   */
+    const int32_t* elem_hi;   /*   central floor(n/3) points per axis             */
+    const int32_t* n_alb;     /* [n_elem] ALBs per element; NULL = J/2            */
+} dgdft_alb_opts;
+
+/* Kleinman-Bylander projectors of the whole batch, CSR by projector
+ * (the b_{I,l}, gamma_{I,l} of Eq. DGvar).  Projector p of element e covers
+ * idx/val[ptr[p] .. ptr[p+1]); projectors are numbered element after element.
+ *   n_proj  host   [n_elem]          projectors per element (may be 0)
+ *   gamma   device [sum n_proj]      coupling constants (Ha)
+ *   ptr     device [sum n_proj + 1]  offsets into idx/val (ptr[0] = 0)
+ *   idx     device [nnz]             flat grid index within the element's grid
+ *   val     device [nnz]             b_p sampled on the grid, normalised so that
+ *                                    dV * sum val^2 = 1 (bohr^-3/2)
+ * The library copies these arrays to the host once per dgdft_alb_solve /
+ * dgdft_alb_set_potential and re-lays them out for its kernels. */
+typedef struct dgdft_kb {
+    const int32_t* n_proj;
+    const double*  gamma;
+    const int64_t* ptr;
+    const int32_t* idx;
+    const double*  val;
+} dgdft_kb;
+
+/* Per-element results of dgdft_alb_solve (host array, one per element). */
+typedef struct dgdft_alb_stats {
+    int32_t iters;            /* LOBPCG iterations performed                       */
+    int32_t converged;        /* 1 iff the final FP64 residual max <= tol          */
+    double  max_res;          /* final max_i residual (FP64)                       */
+    int32_t n_chol_fallback;  /* W orthonormalisations that fell back to SVQB      */
+    int32_t n_rr_fallback;    /* Rayleigh-Ritz steps with a rank-deficient basis   */
+    int32_t n_p_drop;         /* iterations that restarted without P               */
+    int32_t reserved;
+} dgdft_alb_stats;
+
+/* Create a handle for a batch of n_elem extended elements.
+ *   grid     host [n_elem][3]  grid points per axis; each edge >= 2 with prime
+ *                              factors in {2,3,5}
+ *   box      host [n_elem][3]  box lengths L_d (bohr), > 0
+ *   n_states host [n_elem]     J_K, 1 <= J_K <= min(N_g, 1024)
+ *   opts     host or NULL
+ * Allocates the device workspace for the whole batch on the current device.
+ * On failure *out is NULL and dgdft_alb_last_error(NULL) explains. */
+int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box,
+                         int32_t n_elem, const int32_t* n_states,
+                         const dgdft_alb_opts* opts);
+
+/* Release everything the handle owns.  NULL is a no-op. */
+void dgdft_alb_destroy(dgdft_alb* h);
+
+/* Sizes and offsets of element `elem` in the concatenated arrays.
+ * Any output pointer may be NULL.  offsets (if non-NULL) receives 4 values:
+ * offset of the element in V/eigvecs rows-space (sum of N_g of earlier
+ * elements), in eigvecs (sum N_g*J), in eigvals (sum J), in albs (sum N_E*n_alb).
+ */
+int32_t dgdft_alb_sizes(const dgdft_alb* h, int32_t elem, int64_t* ng, int64_t* ne,
+                        int32_t* n_states, int32_t* n_alb, int64_t* offsets);
+
+/* Load the restricted potentials of all elements (V_eff^Q and V_nl^Q of
+ * Sec. II.A).  V: device [sum N_g] (Ha); kb as above (n_proj may be NULL for
+ * no projectors).  Validates finiteness; the data are copied, so the caller
+ * may free them afterwards. */
+int32_t dgdft_alb_set_potential(dgdft_alb* h, const double* V, const dgdft_kb* kb,
+                                void* stream);
+
+/* Solve every element: LOBPCG from X0 to the tolerance, final FP64 check,
+ * then restriction + SVD truncation (Sec. II.A-B).
+ *   V, kb    as in dgdft_alb_set_potential; V == NULL keeps the loaded ones
+ *   X0       device [sum N_g*J] initial guesses (full column rank), read only
+ *   eigvals  device [sum J]        ascending per element (Ha)
+ *   eigvecs  device [sum N_g*J] or NULL; dV * sum psi^2 = 1 (Eq. localproblem)
+ *   albs     device [sum N_E*n_alb] or NULL; dV * sum_E phi^2 = 1, descending
+ *            singular value, largest-|entry| positive (Eq. orthonormal)
+ *   sigma    device [sum n_alb] or NULL; singular values of the restricted
+ *            unit eigenvectors
+ *   stats    host [n_elem] or NULL
+ * Returns DGDFT_OK, DGDFT_NOT_CONVERGED (outputs still written) or an error.
+ * Synchronises `stream` before returning. */
+int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb,
+                        const double* X0, double* eigvals, double* eigvecs,
+                        double* albs, double* sigma, dgdft_alb_stats* stats,
+                        void* stream);
+
+/* Apply the discrete operator of element `elem` (loaded potential) to ncols
+ * unit-basis columns: HX = (F^-1 diag(|G|^2/2) F + diag(V) +
+ * sum_p gamma_p beta_p beta_p^T) X with beta_p = sqrt(dV) b_p
+ * (Eq. localproblem with the KB term of Eq. DGvar; the operation-1 of the
+ * LOBPCG list in Sec. II.B).  X, HX: device [N_g*ncols]; 1 <= ncols <= J. */
+int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* HX,
+                          int32_t ncols, void* stream);
+
+/* Teter preconditioner of element `elem` (Sec. II.B; Payne, Teter, Allan et
+ * al.): W_i = F^-1 K(|G|^2/2 / T_i) F R_i with T_i = the kinetic energy of the
+ * unit vector X_i, floored at (2 pi / L_max)^2 / 2, and
+ * K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4).
+ * R, X, W: device [N_g*ncols]; W may equal R. */
+int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R,
+                               const double* X, double* W, int32_t ncols, void* stream);
+
+/* Batched FP64 symmetric eigensolver used for the Rayleigh-Ritz step
+ * (operation 4 of the LOBPCG list in Sec. II.B): for each of `count` n x n
+ * matrices A (device, column-major, lda = n, only the upper triangle read),
+ * w = eigenvalues ascending (device [count*n]) and Z = the first k unit
+ * eigenvectors (device [count*n*k]).  n <= 3072. */
+int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A,
+                         double* w, double* Z, void* stream);
+
+/* Batched tall-skinny FP64 product on matrix cores (operations 2 and 3 of the
+ * LOBPCG list in Sec. II.B), exported for tests:
+ *   trans == 1: C (m x n) = A^T B with A (K x m), B (K x n)
+ *   trans == 0: C (K x n) = alpha A B + beta C with A (K x m), B (m x n)
+ * all column-major with leading dimension = rows, `count` independent
+ * problems laid out back to back.  Device pointers. */
+int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m,
+                           int32_t n, double alpha, const double* A, const double* B,
+                           double beta, double* C, void* stream);
+
+/* Message of the last failure on h (NULL: of the last failed create). */
+const char* dgdft_alb_last_error(const dgdft_alb* h);
+
+/* Static description of a status code. */
+const char* dgdft_strerror(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGDFT_ALB_H */

@@ -1,0 +1,301 @@
+"""ctypes binding of libdgdft_alb.so (argument marshalling only).
+
+Device buffers are torch tensors on the current HIP device; their data_ptr()
+and torch's current stream are handed to the C ABI.  Names follow the C
+entry points (dgdft_alb_create -> ALB(...), dgdft_alb_solve -> ALB.solve, ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgdft_alb.so")
+
+EXPORTS = (
+    "dgdft_alb_create", "dgdft_alb_destroy", "dgdft_alb_sizes", "dgdft_alb_set_potential",
+    "dgdft_alb_solve", "dgdft_alb_apply_h", "dgdft_alb_precondition", "dgdft_small_syev",
+    "dgdft_gemm_batched", "dgdft_alb_last_error", "dgdft_strerror",
+)
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM",
+          -4: "EHIP", -5: "EBREAKDOWN"}
+PRECOND = {"teter": 0, "none": 2}
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+class DGDFTError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("poll_every", C.c_int32),
+                ("elem_lo", C.POINTER(C.c_int32)), ("elem_hi", C.POINTER(C.c_int32)),
+                ("n_alb", C.POINTER(C.c_int32))]
+
+
+class KB(C.Structure):
+    _fields_ = [("n_proj", C.POINTER(C.c_int32)), ("gamma", C.c_void_p), ("ptr", C.c_void_p),
+                ("idx", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("max_res", C.c_double),
+                ("n_chol_fallback", C.c_int32), ("n_rr_fallback", C.c_int32),
+                ("n_p_drop", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load the in-tree library; raise LibraryMissing if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    lib.dgdft_alb_create.argtypes = [P(vp), P(i32), P(dbl), i32, P(i32), P(Opts)]
+    lib.dgdft_alb_create.restype = i32
+    lib.dgdft_alb_destroy.argtypes = [vp]
+    lib.dgdft_alb_destroy.restype = None
+    lib.dgdft_alb_sizes.argtypes = [vp, i32, P(i64), P(i64), P(i32), P(i32), P(i64)]
+    lib.dgdft_alb_sizes.restype = i32
+    lib.dgdft_alb_set_potential.argtypes = [vp, vp, P(KB), vp]
+    lib.dgdft_alb_set_potential.restype = i32
+    lib.dgdft_alb_solve.argtypes = [vp, vp, P(KB), vp, vp, vp, vp, vp, P(Stats), vp]
+    lib.dgdft_alb_solve.restype = i32
+    lib.dgdft_alb_apply_h.argtypes = [vp, i32, vp, vp, i32, vp]
+    lib.dgdft_alb_apply_h.restype = i32
+    lib.dgdft_alb_precondition.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+    lib.dgdft_alb_precondition.restype = i32
+    lib.dgdft_small_syev.argtypes = [i32, i32, i32, vp, vp, vp, vp]
+    lib.dgdft_small_syev.restype = i32
+    lib.dgdft_gemm_batched.argtypes = [i32, i32, i64, i32, i32, dbl, vp, vp, dbl, vp, vp]
+    lib.dgdft_gemm_batched.restype = i32
+    lib.dgdft_alb_last_error.argtypes = [vp]
+    lib.dgdft_alb_last_error.restype = C.c_char_p
+    lib.dgdft_strerror.argtypes = [i32]
+    lib.dgdft_strerror.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+class ALB:
+    """Handle over dgdft_alb_create for a batch of extended elements.
+
+    grids: (n_elem, 3) ints; boxes: (n_elem, 3) bohr; n_states: (n_elem,).
+    """
+
+    def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
+                 elem_hi=None, n_alb=None, precond="teter"):
+        import torch  # noqa: F401  (device memory and streams)
+        self.lib = load_library()
+        self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
+        self.n_elem = self.grids.shape[0]
+        boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
+        self._keep = []
+        o = Opts()
+        o.precision = 0
+        o.precond = PRECOND[precond]
+        o.tol = tol
+        o.max_iter = max_iter
+        o.poll_every = 1
+        if elem_lo is not None:
+            lo, plo = _i32(np.asarray(elem_lo).reshape(-1))
+            hi, phi = _i32(np.asarray(elem_hi).reshape(-1))
+            self._keep += [lo, hi]
+            o.elem_lo, o.elem_hi = plo, phi
+        if n_alb is not None:
+            na, pna = _i32(n_alb)
+            self._keep.append(na)
+            o.n_alb = pna
+        g, pg = _i32(self.grids.reshape(-1))
+        ns, pns = _i32(n_states)
+        h = C.c_void_p()
+        rc = self.lib.dgdft_alb_create(C.byref(h), pg, boxes.ctypes.data_as(C.POINTER(C.c_double)),
+                                       self.n_elem, pns, C.byref(o))
+        if rc != 0:
+            raise DGDFTError(rc, self.lib.dgdft_alb_last_error(None).decode())
+        self.h = h
+        self.sizes = [self._sizes(e) for e in range(self.n_elem)]
+
+    # ---------------------------------------------------------------- ABI
+    def _check(self, rc, allow=(0,)):
+        if rc not in allow:
+            raise DGDFTError(rc, self.lib.dgdft_alb_last_error(self.h).decode())
+        return rc
+
+    def _sizes(self, e):
+        ng, ne = C.c_int64(), C.c_int64()
+        J, na = C.c_int32(), C.c_int32()
+        off = (C.c_int64 * 4)()
+        self._check(self.lib.dgdft_alb_sizes(self.h, e, C.byref(ng), C.byref(ne), C.byref(J),
+                                             C.byref(na), off))
+        return dict(ng=ng.value, ne=ne.value, J=J.value, n_alb=na.value, off_ng=off[0],
+                    off_ngj=off[1], off_j=off[2], off_alb=off[3])
+
+    def totals(self):
+        s = self.sizes
+        return (sum(x["ng"] for x in s), sum(x["ng"] * x["J"] for x in s),
+                sum(x["J"] for x in s), sum(x["ne"] * x["n_alb"] for x in s),
+                sum(x["n_alb"] for x in s))
+
+    @staticmethod
+    def kb_batch(kbs, device):
+        """Concatenate per-element CSR projector tables into the batch form."""
+        import torch
+        n_proj = np.array([k.gamma.shape[0] for k in kbs], dtype=np.int32)
+        gam = np.concatenate([k.gamma for k in kbs]) if len(kbs) else np.zeros(0)
+        ptrs, idxs, vals = [np.zeros(1, np.int64)], [], []
+        base = 0
+        for k in kbs:
+            ptrs.append(np.asarray(k.ptr[1:], dtype=np.int64) + base)
+            base += int(k.ptr[-1])
+            idxs.append(np.asarray(k.idx, dtype=np.int32))
+            vals.append(np.asarray(k.val, dtype=np.float64))
+        t = dict(
+            n_proj=n_proj,
+            gamma=torch.from_numpy(np.ascontiguousarray(gam, dtype=np.float64)).to(device),
+            ptr=torch.from_numpy(np.concatenate(ptrs)).to(device),
+            idx=torch.from_numpy(np.concatenate(idxs) if idxs else np.zeros(0, np.int32)).to(device),
+            val=torch.from_numpy(np.concatenate(vals) if vals else np.zeros(0)).to(device),
+        )
+        return t
+
+    def _kb_struct(self, kbt):
+        k = KB()
+        if kbt is None:
+            return None
+        npj, p = _i32(kbt["n_proj"])
+        self._kbkeep = (npj, kbt)
+        k.n_proj = p
+        k.gamma = kbt["gamma"].data_ptr() if kbt["gamma"].numel() else None
+        k.ptr = kbt["ptr"].data_ptr()
+        k.idx = kbt["idx"].data_ptr() if kbt["idx"].numel() else None
+        k.val = kbt["val"].data_ptr() if kbt["val"].numel() else None
+        return k
+
+    def set_potential(self, V, kbt):
+        k = self._kb_struct(kbt)
+        self._check(self.lib.dgdft_alb_set_potential(self.h, _ptr(V), C.byref(k) if k else None,
+                                                     _stream()))
+
+    def solve(self, V, kbt, X0, want_vecs=True, want_albs=True):
+        import torch
+        sng, sngj, sj, salb, snalb = self.totals()
+        dev = X0.device
+        vals = torch.empty(sj, dtype=torch.float64, device=dev)
+        vecs = torch.empty(sngj, dtype=torch.float64, device=dev) if want_vecs else None
+        albs = torch.empty(salb, dtype=torch.float64, device=dev) if want_albs else None
+        sig = torch.empty(max(snalb, 1), dtype=torch.float64, device=dev)
+        st = (Stats * self.n_elem)()
+        k = self._kb_struct(kbt) if V is not None else None
+        rc = self.lib.dgdft_alb_solve(self.h, _ptr(V), C.byref(k) if k else None, _ptr(X0),
+                                      _ptr(vals), _ptr(vecs), _ptr(albs), _ptr(sig), st, _stream())
+        self._check(rc, allow=(0, 1))
+        stats = [dict(iters=s.iters, converged=bool(s.converged), max_res=s.max_res,
+                      n_chol_fallback=s.n_chol_fallback, n_rr_fallback=s.n_rr_fallback,
+                      n_p_drop=s.n_p_drop, n_ql_fail=s.reserved) for s in st]
+        return dict(status=rc, eigvals=vals, eigvecs=vecs, albs=albs, sigma=sig[:snalb],
+                    stats=stats)
+
+    def split(self, out, e):
+        """Per-element views (eigvals, eigvecs (Ng x J), albs (NE x n_alb), sigma)."""
+        s = self.sizes[e]
+        J, ng, ne, na = s["J"], s["ng"], s["ne"], s["n_alb"]
+        off_nalb = sum(x["n_alb"] for x in self.sizes[:e])
+        r = dict(eigvals=out["eigvals"][s["off_j"]:s["off_j"] + J])
+        if out["eigvecs"] is not None:
+            r["eigvecs"] = out["eigvecs"][s["off_ngj"]:s["off_ngj"] + ng * J].view(J, ng).T
+        if out["albs"] is not None:
+            r["albs"] = out["albs"][s["off_alb"]:s["off_alb"] + ne * na].view(na, ne).T
+        r["sigma"] = out["sigma"][off_nalb:off_nalb + na]
+        return r
+
+    def apply_h(self, e, X):
+        """X: (ncols, Ng) contiguous device tensor (column-major Ng x ncols)."""
+        import torch
+        HX = torch.empty_like(X)
+        self._check(self.lib.dgdft_alb_apply_h(self.h, e, _ptr(X), _ptr(HX), X.shape[0], _stream()))
+        return HX
+
+    def precondition(self, e, R, X):
+        import torch
+        W = torch.empty_like(R)
+        self._check(self.lib.dgdft_alb_precondition(self.h, e, _ptr(R), _ptr(X), _ptr(W),
+                                                    R.shape[0], _stream()))
+        return W
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dgdft_alb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def small_syev(A, k):
+    """A: (count, n, n) device float64 (upper triangle read, column-major per
+    matrix); returns w (count, n) ascending and Z (count, k, n) (columns)."""
+    import torch
+    lib = load_library()
+    count, n, _ = A.shape
+    A = A.contiguous()
+    w = torch.empty(count, n, dtype=torch.float64, device=A.device)
+    Z = torch.empty(count, k, n, dtype=torch.float64, device=A.device)
+    rc = lib.dgdft_small_syev(count, n, k, _ptr(A), _ptr(w), _ptr(Z), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return w, Z
+
+
+def gemm_batched(trans, A, B, alpha=1.0, beta=0.0, Cin=None):
+    """Column-major batched products on the library's MFMA kernels.
+    A: (count, m, K) device tensor = column-major K x m per problem.
+    trans=1: B (count, n, K) -> C (count, n, m) = column-major (A^T B) m x n.
+    trans=0: B (count, n, m) (column-major m x n) -> C (count, n, K) = alpha A B + beta C."""
+    import torch
+    lib = load_library()
+    count, m, K = A.shape
+    n = B.shape[1]
+    if trans:
+        Cout = torch.empty(count, n, m, dtype=torch.float64, device=A.device)
+    else:
+        Cout = (Cin.clone() if Cin is not None else
+                torch.zeros(count, n, K, dtype=torch.float64, device=A.device))
+    Ac, Bc = A.contiguous(), B.contiguous()
+    rc = lib.dgdft_gemm_batched(int(trans), count, K, m, n, alpha, _ptr(Ac), _ptr(Bc), beta,
+                                _ptr(Cout), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return Cout

@@ -1,0 +1,189 @@
+// Shared device-side definitions of the ALB-generation library: the per-element
+// descriptor that every batched kernel reads, block-slot numbering, and the
+// work decomposition (a prefix array over active elements).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dg {
+
+// Block slots of an element: N_g x J column-major FP64 blocks.  X/HX/P/HP are
+// double-buffered (current / next iterate); W holds the residual and then the
+// preconditioned, projected search direction; W2 its orthonormalised form; HW
+// = H W2.  U0..U2 are bound to caller buffers by the test entry points.
+enum Slot {
+  S_X0 = 0, S_X1, S_HX0, S_HX1, S_P0, S_P1, S_HP0, S_HP1,
+  S_W, S_W2, S_HW, S_U0, S_U1, S_U2, NSLOT
+};
+
+constexpr int MAX_RADICES = 10;
+constexpr int KB_GMAX = 8;   // projectors sharing one support, per group
+
+struct Elem {
+  int n1, n2, n3, J;
+  int ng;                    // n1*n2*n3
+  int ld;                    // leading dimension of blocks (= ng)
+  int n_proj, n_grp;
+  int nalb, ne;              // ALBs, points of the restriction box
+  int lo[3], hi[3];
+  int nrad[3];
+  int rad[3][MAX_RADICES];   // radix sequence per axis (Stockham order)
+  double L[3];
+  double dv, tfloor;
+  double* blk[NSLOT];
+  double* V;                 // ng
+  double2* zscr;             // FFT scratch: ceil(J/2) * ng complex
+  const double2* tw[3];      // exp(-2 pi i t / n_d), t < n_d
+  double* theta;             // J   Ritz values
+  double* resid;             // J   residual norms
+  double* xhx;               // J   x_i . (HX)_i
+  double* vx;                // J   sum V x_i^2
+  double* tkin;              // J   band kinetic energies
+  double* proj;              // n_proj x J   beta^T (column block) scratch
+  double* projx;             // n_proj x J   beta^T X
+  const double* gamma;       // n_proj
+  const int* grp_ptr;        // n_grp+1: support points of group g
+  const int* grp_p0;         // first projector of group g
+  const int* grp_np;         // projectors in group g (<= KB_GMAX)
+  const int* grp_idx;        // flat grid index per support point
+  const double* grp_val;     // per point, grp_np values (beta = sqrt(dV) b)
+  const int* kbt_ptr;        // ng+1: projector entries touching point r
+  const int* kbt_p;          // projector id
+  const double* kbt_c;       // gamma_p * beta_p(r)
+  double* small;             // per-element small dense workspace
+  double* gpart;             // Gram split-K partial sums
+  long long small_stride;    // doubles per n x n matrix in `small`
+  int* fl;                   // FL_COUNT status words, read back by the host
+  long long off_ng, off_ngj, off_j, off_alb, off_nalb;   // offsets in batch arrays
+};
+
+// Status words written by the device (one group per element).  The host
+// never uploads these, so device-side state survives descriptor updates.
+enum Flag {
+  FL_HASP = 0,        // search-direction block P present in this iteration
+  FL_PAR,             // which buffer of each X/HX/P/HP pair is current
+  FL_HASP_NEXT,       // P present in the next iteration
+  FL_W_SVQB,          // W orthonormalisations that fell back to SVQB
+  FL_RR_FALLBACK,     // Rayleigh-Ritz on a rank-deficient basis
+  FL_P_DROP,          // iterations restarted without P
+  FL_BREAKDOWN,       // unrecoverable rank deficiency
+  FL_QL_FAIL,         // tridiagonal QL did not converge
+  FL_NONFINITE,       // non-finite input seen
+  FL_COUNT = 10
+};
+
+// Virtual slots resolved per element through its buffer parity:
+// VS_X = current X, VS_XN = next X, and likewise for HX, P, HP.
+enum VSlot { VS_BASE = 32, VS_X = 32, VS_XN, VS_HX, VS_HXN, VS_P, VS_PN, VS_HP, VS_HPN };
+
+__host__ __device__ inline double* bp(const Elem& e, int slot) {
+  if (slot < VS_BASE) return e.blk[slot];
+  int v = slot - VS_BASE;
+  return e.blk[2 * (v >> 1) + ((v & 1) ^ e.fl[FL_PAR])];
+}
+
+__device__ inline int has_p(const Elem& e) { return e.fl[FL_HASP]; }
+
+// Column c (0 <= c < nblk*J) of a virtual concatenation of element blocks.
+// `slots` lists block slots; a slot < 0 means "skip".
+struct Opnd {
+  int nblk;
+  int slot[6];
+  int optP[6];   // 1: block present only if the element has P
+  int ncols;     // >= 0: explicit column count (single block, ld = e.ld)
+};
+
+__device__ inline int opnd_cols(const Opnd& o, const Elem& e) {
+  if (o.ncols >= 0) return o.ncols;
+  int n = 0;
+  for (int i = 0; i < o.nblk; ++i) n += (o.optP[i] && !has_p(e)) ? 0 : 1;
+  return n * e.J;
+}
+
+// Resolve the block pointer holding column c; returns column pointer.
+__device__ inline double* opnd_col(const Opnd& o, const Elem& e, int c) {
+  if (o.ncols >= 0) return bp(e, o.slot[0]) + (long long)c * e.ld;
+  int b = c / e.J, r = c - b * e.J;
+  int k = -1;
+  for (int i = 0; i < o.nblk; ++i) {
+    if (o.optP[i] && !has_p(e)) continue;
+    if (++k == b) return bp(e, o.slot[i]) + (long long)r * e.ld;
+  }
+  return nullptr;
+}
+
+__host__ __device__ inline int host_opnd_cols(const Opnd& o, int hasP, int J) {
+  if (o.ncols >= 0) return o.ncols;
+  int n = 0;
+  int nblk = o.nblk;
+  const int* optP = o.optP;
+  for (int i = 0; i < nblk; ++i) n += (optP[i] && !hasP) ? 0 : 1;
+  return n * J;
+}
+
+
+
+// Offsets (in matrices of size small_stride) inside the small workspace.
+enum SmallMat {
+  SM_G = 0,   // Gram results (general)
+  SM_M,       // S^T S
+  SM_H,       // S^T H S
+  SM_A,       // working matrix
+  SM_U,       // eigenvector accumulator
+  SM_L,       // Cholesky factor / inverse
+  SM_C,       // coefficients [C | D]  (n x 2J)
+  SM_T,       // orthonormalising transform
+  SM_Z,       // eigenvectors (n x J)
+  SM_V,       // vectors d, e, w, ... (a few columns of length n)
+  SM_COUNT
+};
+
+__host__ __device__ inline double* sm(const Elem& e, int which) {
+  return e.small + (long long)which * e.small_stride;
+}
+
+// Find the position of blockIdx-linear work item `b` among active elements:
+// prefix[0..na] holds cumulative work counts.  Returns index into `active`.
+__device__ inline int find_elem(const int* __restrict__ prefix, int na, int b) {
+  int lo = 0, hi = na;  // invariant: prefix[lo] <= b < prefix[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---- work decomposition shared by host (counts) and device (decode) ----
+constexpr int GT = 64;            // GEMM tile edge (rows and columns)
+constexpr int GRAM_MAXCHUNK = 8;
+
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+__host__ __device__ inline int gram_nchunk(int K) {
+  int c = cdiv(K, 4096);
+  return c < 1 ? 1 : (c > GRAM_MAXCHUNK ? GRAM_MAXCHUNK : c);
+}
+// chunk length, a multiple of 16
+__host__ __device__ inline int gram_chunklen(int K, int nchunk) { return cdiv(cdiv(K, nchunk), 16) * 16; }
+
+__host__ __device__ inline int gram_tiles(int m, int n, int upper) {
+  int tm = cdiv(m, GT), tn = cdiv(n, GT);
+  if (!upper) return tm * tn;
+  int c = 0;
+  for (int i = 0; i < tm; ++i) c += (tn - i > 0) ? tn - i : 0;
+  return c;
+}
+
+__host__ __device__ inline void gram_tile_decode(int t, int m, int n, int upper, int* ti, int* tj) {
+  int tm = cdiv(m, GT), tn = cdiv(n, GT);
+  if (!upper) { *ti = t / tn; *tj = t % tn; return; }
+  for (int i = 0; i < tm; ++i) {
+    int row = tn - i;
+    if (row <= 0) break;
+    if (t < row) { *ti = i; *tj = i + t; return; }
+    t -= row;
+  }
+  *ti = 0; *tj = 0;
+}
+
+}  // namespace dg

@@ -1,0 +1,1055 @@
+// Host engine and C ABI of the ALB-generation library (one translation unit
+// with the kernels).  The engine owns the per-element buffers, lays out the
+// inputs, and drives the batched LOBPCG: every launch covers all active
+// elements at once (work items located through a prefix array over the
+// active list), the host polls residuals and status words once per
+// iteration, and converged elements leave the active list.
+//
+// Method (Hu, Lin, Yang, Sec. II.A-B): per extended element, the lowest J
+// eigenpairs of the planewave-discretised local operator by Teter-
+// preconditioned LOBPCG, then restriction to the element and SVD truncation.
+#include "fft.hip"
+#include "gemm.hip"
+#include "lobpcg.hip"
+
+#include "../../include/dgdft_alb.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct HipFail {
+  hipError_t code;
+  std::string what;
+};
+
+#define HCHECK(call)                                                                  \
+  do {                                                                                \
+    hipError_t _e = (call);                                                           \
+    if (_e != hipSuccess) throw HipFail{_e, std::string(#call) + ": " + hipGetErrorString(_e)}; \
+  } while (0)
+
+struct Status {
+  int32_t code;
+  std::string msg;
+};
+
+constexpr int PREFIX_RING = 96;   // prefix arrays between two host polls
+
+}  // namespace
+
+struct dgdft_alb {
+  int dev = 0;
+  int n = 0;                       // elements
+  dgdft_alb_opts opts{};
+  std::vector<Elem> eh;            // host mirror of descriptors
+  Elem* ed = nullptr;              // device descriptors
+  std::vector<void*> elem_mem;     // one allocation per element
+  // batch arenas
+  double* vec_arena = nullptr;     // theta, resid, xhx, vx, tkin (5 * sumJ)
+  int* fl_arena = nullptr;         // n * FL_COUNT
+  double2* tw_arena = nullptr;
+  void* kb_arena = nullptr;        // KB layout of the loaded potential
+  size_t kb_cap = 0;
+  double* proj_arena = nullptr;    // proj + projx
+  size_t proj_cap = 0;
+  int* d_flag = nullptr;           // scratch flag for input checks
+  // prefix ring
+  int* ring_d = nullptr;
+  int* ring_h = nullptr;           // pinned
+  int ring_stride = 0, ring_pos = 0;
+  int* d_active_all = nullptr;
+  // host readback (pinned)
+  double* h_resid = nullptr;
+  int* h_fl = nullptr;
+  long long sumJ = 0, sumNg = 0, sumNgJ = 0, sumAlb = 0, sumNalb = 0;
+  bool potential_loaded = false;
+  std::string err;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+
+  // ---------------------------------------------------------------------
+  struct Prefix {
+    const int* active;
+    const int* prefix;
+    int na;
+    int total;
+  };
+
+  void ring_reset() { ring_pos = 0; }
+
+  // Upload `active` and per-element work counts; returns device pointers.
+  template <class F>
+  Prefix make_prefix(const std::vector<int>& act, F work) {
+    if (ring_pos >= PREFIX_RING) throw HipFail{hipErrorUnknown, "prefix ring exhausted"};
+    int* hp = ring_h + (size_t)ring_pos * ring_stride;
+    int* dp = ring_d + (size_t)ring_pos * ring_stride;
+    ++ring_pos;
+    int na = (int)act.size();
+    int* ha = hp;              // active ids
+    int* hpre = hp + n;        // prefix
+    hpre[0] = 0;
+    for (int i = 0; i < na; ++i) {
+      ha[i] = act[i];
+      hpre[i + 1] = hpre[i] + work(act[i]);
+    }
+    HCHECK(hipMemcpyAsync(dp, hp, sizeof(int) * (size_t)(n + na + 1), hipMemcpyHostToDevice, stream));
+    return Prefix{dp, dp + n, na, hpre[na]};
+  }
+
+  int hasP_host(int e) const { return h_fl[(size_t)e * FL_COUNT + FL_HASP]; }
+
+  // -------------------------------------------------------------- launches
+  void op_apply(const std::vector<int>& act, int in_slot, int out_slot, int col0, int ncols_fixed) {
+    // ncols_fixed < 0: all J columns
+    auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
+    launch_kbproj(act, in_slot, col0, ncols_fixed, 0);
+    auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
+    hipLaunchKernelGGL(dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
+                       P1.prefix, P1.na, in_slot, col0, ncols_fixed);
+    auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
+    hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
+                       P2.prefix, P2.na, col0, ncols_fixed, 0);
+    hipLaunchKernelGGL(dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
+                       P1.prefix, P1.na, in_slot, out_slot, col0, ncols_fixed, 0);
+    HCHECK(hipGetLastError());
+  }
+
+  void launch_kbproj(const std::vector<int>& act, int slot, int col0, int ncols_fixed, int to_projx) {
+    auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
+    auto P = make_prefix(act, [&](int e) { return eh[e].n_grp * nc(e); });
+    if (P.total == 0) return;
+    hipLaunchKernelGGL(dg_kb_project, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
+                       P.na, slot, col0, ncols_fixed, to_projx);
+    HCHECK(hipGetLastError());
+  }
+
+  void precondition(const std::vector<int>& act, int slot, int col0, int ncols_fixed) {
+    auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
+    auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
+    hipLaunchKernelGGL(dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
+                       P1.prefix, P1.na, slot, col0, ncols_fixed);
+    auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
+    hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
+                       P2.prefix, P2.na, col0, ncols_fixed, opts.precond == DGDFT_PRECOND_NONE ? 2 : 1);
+    hipLaunchKernelGGL(dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
+                       P1.prefix, P1.na, slot, slot, col0, ncols_fixed, 1);
+    HCHECK(hipGetLastError());
+  }
+
+  static Opnd opnd(std::initializer_list<int> slots, std::initializer_list<int> optp = {}) {
+    Opnd o{};
+    o.nblk = 0;
+    o.ncols = -1;
+    for (int s : slots) o.slot[o.nblk++] = s;
+    int i = 0;
+    for (int f : optp) o.optP[i++] = f;
+    return o;
+  }
+
+  int cols_host(const Opnd& o, int e) const { return host_opnd_cols(o, hasP_host(e), eh[e].J); }
+
+  void gram(const std::vector<int>& act, const GramArgs& g) {
+    auto K = [&](int e) { return g.use_ne ? eh[e].ne : eh[e].ng; };
+    auto P = make_prefix(act, [&](int e) {
+      int m = cols_host(g.A, e), c = 0;
+      for (int j = 0; j < g.njob; ++j) c += gram_tiles(m, cols_host(g.B[j], e), g.upper);
+      return c * gram_nchunk(K(e));
+    });
+    if (P.total == 0) return;
+    hipLaunchKernelGGL(dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, g);
+    auto R = make_prefix(act, [&](int e) {
+      int m = cols_host(g.A, e), c = 0;
+      for (int j = 0; j < g.njob; ++j) c += cdiv(m * cols_host(g.B[j], e), 256);
+      return c;
+    });
+    hipLaunchKernelGGL(dg_gram_reduce, dim3(R.total), dim3(256), 0, stream, ed, R.active, R.prefix,
+                       R.na, g);
+    HCHECK(hipGetLastError());
+  }
+
+  void update(const std::vector<int>& act, const UpdArgs& u) {
+    auto P = make_prefix(act, [&](int e) {
+      int K = u.use_ne ? eh[e].ne : eh[e].ng;
+      int nc = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
+      return u.njob * cdiv(K, GT) * cdiv(nc, GT);
+    });
+    if (P.total == 0) return;
+    hipLaunchKernelGGL(dg_update, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, u);
+    HCHECK(hipGetLastError());
+  }
+
+  void per_elem_cols(const std::vector<int>& act, int which, int a0, int a1, int a2, double* o1,
+                     double* o2) {
+    auto P = make_prefix(act, [&](int e) { return which == 2 ? eh[e].nalb : eh[e].J; });
+    if (P.total == 0) return;
+    switch (which) {
+      case 0:
+        hipLaunchKernelGGL(dg_resid, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na,
+                           a0, a1, a2, 1);
+        break;
+      case 1:
+        hipLaunchKernelGGL(dg_resid, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na,
+                           a0, a1, a2, 0);
+        break;
+      case 2:
+        hipLaunchKernelGGL(dg_pack_albs, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
+                           P.na, a0, o1);
+        break;
+      case 3:
+        hipLaunchKernelGGL(dg_pack_eig, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
+                           P.na, a0, o1, o2);
+        break;
+      case 4:
+        hipLaunchKernelGGL(dg_gather_box, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
+                           P.na, a0, a1);
+        break;
+    }
+    HCHECK(hipGetLastError());
+  }
+
+  void per_elem(const std::vector<int>& act, int which, int arg, double* out = nullptr) {
+    auto P = make_prefix(act, [&](int) { return 1; });
+    if (P.na == 0) return;
+    switch (which) {
+      case 0:
+        hipLaunchKernelGGL(dg_cholqr, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
+        break;
+      case 1:
+        hipLaunchKernelGGL(dg_rr, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
+        break;
+      case 2:
+        hipLaunchKernelGGL(dg_teter_energy, dim3(P.na), dim3(256), 0, stream, ed, P.active, P.na);
+        break;
+      case 3:
+        hipLaunchKernelGGL(dg_advance, dim3(cdiv(P.na, 256)), dim3(256), 0, stream, ed, P.active, P.na);
+        break;
+      case 4:
+        hipLaunchKernelGGL(dg_alb_coeffs, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active,
+                           P.na, out);
+        break;
+    }
+    HCHECK(hipGetLastError());
+  }
+
+  // Poll: residual norms and status words to the host.
+  void poll() {
+    HCHECK(hipMemcpyAsync(h_resid, vec_arena + sumJ, sizeof(double) * sumJ, hipMemcpyDeviceToHost, stream));
+    HCHECK(hipMemcpyAsync(h_fl, fl_arena, sizeof(int) * (size_t)n * FL_COUNT, hipMemcpyDeviceToHost, stream));
+    HCHECK(hipStreamSynchronize(stream));
+    ring_reset();
+  }
+
+  double max_res(int e) const {
+    double m = 0.0;
+    for (int j = 0; j < eh[e].J; ++j) m = std::max(m, h_resid[eh[e].off_j + j]);
+    return m;
+  }
+
+  void upload_elems() {
+    HCHECK(hipMemcpyAsync(ed, eh.data(), sizeof(Elem) * (size_t)n, hipMemcpyHostToDevice, stream));
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+bool factor_radices(int n, int* rad, int* nrad) {
+  int k = 0;
+  for (int r : {4, 2, 3, 5}) {
+    while (n % r == 0) {
+      if (k >= MAX_RADICES) return false;
+      rad[k++] = r;
+      n /= r;
+    }
+  }
+  *nrad = k;
+  return n == 1;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Status fail(int32_t c, const std::string& m) { return Status{c, m}; }
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char* dgdft_strerror(int32_t s) {
+  switch (s) {
+    case DGDFT_OK: return "success";
+    case DGDFT_NOT_CONVERGED: return "not converged within max_iter";
+    case DGDFT_EINVAL: return "invalid argument";
+    case DGDFT_EUNSUPPORTED: return "unsupported size";
+    case DGDFT_ENOMEM: return "device out of memory";
+    case DGDFT_EHIP: return "HIP runtime error";
+    case DGDFT_EBREAKDOWN: return "initial block is rank deficient";
+    default: return "unknown status";
+  }
+}
+
+const char* dgdft_alb_last_error(const dgdft_alb* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+void dgdft_alb_destroy(dgdft_alb* h) {
+  if (!h) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(h->dev);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (void* p : h->elem_mem) (void)hipFree(p);
+  (void)hipFree(h->ed);
+  (void)hipFree(h->vec_arena);
+  (void)hipFree(h->fl_arena);
+  (void)hipFree(h->tw_arena);
+  (void)hipFree(h->kb_arena);
+  (void)hipFree(h->proj_arena);
+  (void)hipFree(h->d_flag);
+  (void)hipFree(h->ring_d);
+  (void)hipHostFree(h->ring_h);
+  (void)hipHostFree(h->h_resid);
+  (void)hipHostFree(h->h_fl);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  (void)hipSetDevice(cur);
+  delete h;
+}
+
+int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box, int32_t n_elem,
+                         const int32_t* n_states, const dgdft_alb_opts* opts) {
+  if (!out) { g_create_error = "out is NULL"; return DGDFT_EINVAL; }
+  *out = nullptr;
+  if (!grid || !box || !n_states || n_elem <= 0) {
+    g_create_error = "grid, box, n_states must be non-NULL and n_elem > 0";
+    return DGDFT_EINVAL;
+  }
+  dgdft_alb* h = new dgdft_alb();
+  if (opts) h->opts = *opts;
+  if (h->opts.tol <= 0.0) h->opts.tol = 1e-8;
+  if (h->opts.max_iter <= 0) h->opts.max_iter = 500;
+  if (h->opts.poll_every <= 0) h->opts.poll_every = 1;
+  if (h->opts.precision != DGDFT_PREC_FP64) {
+    g_create_error = "only DGDFT_PREC_FP64 is implemented";
+    delete h;
+    return DGDFT_EUNSUPPORTED;
+  }
+  h->n = n_elem;
+  h->eh.assign(n_elem, Elem{});
+  // ---- validate shapes, fill host descriptors
+  long long offng = 0, offngj = 0, offj = 0, offalb = 0, offnalb = 0;
+  for (int e = 0; e < n_elem; ++e) {
+    Elem& E = h->eh[e];
+    E.n1 = grid[3 * e]; E.n2 = grid[3 * e + 1]; E.n3 = grid[3 * e + 2];
+    E.J = n_states[e];
+    char buf[256];
+    for (int d = 0; d < 3; ++d) {
+      int nd = grid[3 * e + d];
+      if (nd < 2 || !(box[3 * e + d] > 0.0) || !std::isfinite(box[3 * e + d])) {
+        snprintf(buf, sizeof buf, "element %d: grid edges must be >= 2 and box lengths > 0", e);
+        g_create_error = buf; delete h; return DGDFT_EINVAL;
+      }
+      if (!factor_radices(nd, E.rad[d], &E.nrad[d])) {
+        snprintf(buf, sizeof buf, "element %d: grid edge %d has a prime factor > 5", e, nd);
+        g_create_error = buf; delete h; return DGDFT_EUNSUPPORTED;
+      }
+      E.L[d] = box[3 * e + d];
+    }
+    long long ng = (long long)E.n1 * E.n2 * E.n3;
+    if (ng > (1LL << 30)) { g_create_error = "grid too large"; delete h; return DGDFT_EUNSUPPORTED; }
+    if ((long long)E.n1 * E.n2 > FFT_MAXPTS || 2LL * E.n1 * E.n3 > FFT_MAXPTS) {
+      snprintf(buf, sizeof buf, "element %d: n1*n2 and 2*n1*n3 must be <= %d", e, FFT_MAXPTS);
+      g_create_error = buf; delete h; return DGDFT_EUNSUPPORTED;
+    }
+    E.ng = (int)ng;
+    E.ld = E.ng;
+    if (E.J < 1 || E.J > E.ng) {
+      snprintf(buf, sizeof buf, "element %d: n_states must be in [1, N_g]", e);
+      g_create_error = buf; delete h; return DGDFT_EINVAL;
+    }
+    if (E.J > 1024) { g_create_error = "n_states > 1024"; delete h; return DGDFT_EUNSUPPORTED; }
+    for (int d = 0; d < 3; ++d) {
+      int nd = grid[3 * e + d];
+      if (h->opts.elem_lo && h->opts.elem_hi) {
+        E.lo[d] = h->opts.elem_lo[3 * e + d];
+        E.hi[d] = h->opts.elem_hi[3 * e + d];
+      } else {
+        int m = nd / 3;
+        E.lo[d] = (nd - m) / 2;
+        E.hi[d] = E.lo[d] + m;
+      }
+      if (E.lo[d] < 0 || E.hi[d] > nd || E.lo[d] >= E.hi[d]) {
+        snprintf(buf, sizeof buf, "element %d: restriction box outside the grid or empty", e);
+        g_create_error = buf; delete h; return DGDFT_EINVAL;
+      }
+    }
+    E.ne = (E.hi[0] - E.lo[0]) * (E.hi[1] - E.lo[1]) * (E.hi[2] - E.lo[2]);
+    E.nalb = h->opts.n_alb ? h->opts.n_alb[e] : E.J / 2;
+    if (E.nalb < 1 || E.nalb > std::min(E.ne, E.J)) {
+      snprintf(buf, sizeof buf, "element %d: n_alb must be in [1, min(N_E, J)]", e);
+      g_create_error = buf; delete h; return DGDFT_EINVAL;
+    }
+    E.dv = E.L[0] * E.L[1] * E.L[2] / (double)E.ng;
+    double lmax = std::max(E.L[0], std::max(E.L[1], E.L[2]));
+    E.tfloor = 0.5 * (2.0 * M_PI / lmax) * (2.0 * M_PI / lmax);
+    E.off_ng = offng; E.off_ngj = offngj; E.off_j = offj; E.off_alb = offalb; E.off_nalb = offnalb;
+    offng += E.ng; offngj += (long long)E.ng * E.J; offj += E.J;
+    offalb += (long long)E.ne * E.nalb; offnalb += E.nalb;
+  }
+  h->sumNg = offng; h->sumNgJ = offngj; h->sumJ = offj; h->sumAlb = offalb; h->sumNalb = offnalb;
+  try {
+    HCHECK(hipGetDevice(&h->dev));
+    HCHECK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+    h->stream = h->own_stream;
+    // ---- per-element memory
+    for (int e = 0; e < n_elem; ++e) {
+      Elem& E = h->eh[e];
+      size_t blk = align256(sizeof(double) * (size_t)E.ld * E.J);
+      size_t nmax = 3 * (size_t)E.J;
+      size_t stride = std::max(nmax * nmax, 16 * nmax);
+      size_t sz = blk * (NSLOT - 3) + align256(sizeof(double2) * (size_t)cdiv(E.J, 2) * E.ng) +
+                  align256(sizeof(double) * E.ng) + align256(sizeof(double) * stride * SM_COUNT) +
+                  align256(sizeof(double) * 2 * GRAM_MAXCHUNK * nmax * nmax);
+      void* mem = nullptr;
+      hipError_t st = hipMalloc(&mem, sz);
+      if (st != hipSuccess) {
+        g_create_error = "device allocation of the element workspace failed";
+        dgdft_alb_destroy(h);
+        return DGDFT_ENOMEM;
+      }
+      h->elem_mem.push_back(mem);
+      char* p = (char*)mem;
+      for (int s = 0; s < NSLOT - 3; ++s) { E.blk[s] = (double*)p; p += blk; }
+      E.zscr = (double2*)p; p += align256(sizeof(double2) * (size_t)cdiv(E.J, 2) * E.ng);
+      E.V = (double*)p; p += align256(sizeof(double) * E.ng);
+      E.small = (double*)p; E.small_stride = (long long)stride;
+      p += align256(sizeof(double) * stride * SM_COUNT);
+      E.gpart = (double*)p;
+    }
+    HCHECK(hipMalloc(&h->vec_arena, sizeof(double) * 5 * h->sumJ));
+    HCHECK(hipMalloc(&h->fl_arena, sizeof(int) * (size_t)n_elem * FL_COUNT));
+    HCHECK(hipMemset(h->fl_arena, 0, sizeof(int) * (size_t)n_elem * FL_COUNT));
+    HCHECK(hipMalloc(&h->d_flag, sizeof(int)));
+    // twiddles
+    long long ntw = 0;
+    for (auto& E : h->eh) ntw += E.n1 + E.n2 + E.n3;
+    HCHECK(hipMalloc(&h->tw_arena, sizeof(double2) * ntw));
+    std::vector<double2> tw(ntw);
+    long long o = 0;
+    for (int e = 0; e < n_elem; ++e) {
+      Elem& E = h->eh[e];
+      int nd3[3] = {E.n1, E.n2, E.n3};
+      for (int d = 0; d < 3; ++d) {
+        for (int t = 0; t < nd3[d]; ++t) {
+          double a = 2.0 * M_PI * (double)t / (double)nd3[d];
+          tw[o + t] = make_double2(std::cos(a), -std::sin(a));
+        }
+        E.tw[d] = h->tw_arena + o;
+        o += nd3[d];
+      }
+      E.theta = h->vec_arena + E.off_j;
+      E.resid = h->vec_arena + h->sumJ + E.off_j;
+      E.xhx = h->vec_arena + 2 * h->sumJ + E.off_j;
+      E.vx = h->vec_arena + 3 * h->sumJ + E.off_j;
+      E.tkin = h->vec_arena + 4 * h->sumJ + E.off_j;
+      E.fl = h->fl_arena + (size_t)e * FL_COUNT;
+    }
+    HCHECK(hipMemcpy(h->tw_arena, tw.data(), sizeof(double2) * ntw, hipMemcpyHostToDevice));
+    HCHECK(hipMalloc(&h->ed, sizeof(Elem) * n_elem));
+    h->ring_stride = 2 * n_elem + 8;
+    HCHECK(hipMalloc(&h->ring_d, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING));
+    HCHECK(hipHostMalloc(&h->ring_h, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING));
+    HCHECK(hipHostMalloc(&h->h_resid, sizeof(double) * h->sumJ));
+    HCHECK(hipHostMalloc(&h->h_fl, sizeof(int) * (size_t)n_elem * FL_COUNT));
+    memset(h->h_fl, 0, sizeof(int) * (size_t)n_elem * FL_COUNT);
+    h->upload_elems();
+    HCHECK(hipStreamSynchronize(h->stream));
+  } catch (HipFail& f) {
+    g_create_error = f.what;
+    dgdft_alb_destroy(h);
+    return f.code == hipErrorOutOfMemory ? DGDFT_ENOMEM : DGDFT_EHIP;
+  }
+  *out = h;
+  return DGDFT_OK;
+}
+
+int32_t dgdft_alb_sizes(const dgdft_alb* h, int32_t elem, int64_t* ng, int64_t* ne, int32_t* n_states,
+                        int32_t* n_alb, int64_t* offsets) {
+  if (!h || elem < 0 || elem >= h->n) return DGDFT_EINVAL;
+  const Elem& E = h->eh[elem];
+  if (ng) *ng = E.ng;
+  if (ne) *ne = E.ne;
+  if (n_states) *n_states = E.J;
+  if (n_alb) *n_alb = E.nalb;
+  if (offsets) {
+    offsets[0] = E.off_ng;
+    offsets[1] = E.off_ngj;
+    offsets[2] = E.off_j;
+    offsets[3] = E.off_alb;
+  }
+  return DGDFT_OK;
+}
+
+static Status set_potential_impl(dgdft_alb* h, const double* V, const dgdft_kb* kb, hipStream_t s) {
+  const int n = h->n;
+  // ---- finiteness of V on the device
+  HCHECK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(dg_check_finite, dim3(1024), dim3(256), 0, s, V, (long long)h->sumNg, h->d_flag);
+  HCHECK(hipGetLastError());
+  int bad = 0;
+  HCHECK(hipMemcpyAsync(&bad, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  if (bad) return fail(DGDFT_EINVAL, "V contains non-finite values");
+  for (int e = 0; e < n; ++e)
+    HCHECK(hipMemcpyAsync(h->eh[e].V, V + h->eh[e].off_ng, sizeof(double) * h->eh[e].ng,
+                          hipMemcpyDeviceToDevice, s));
+  // ---- KB projectors: copy to host, validate, group by shared support
+  std::vector<int> nproj(n, 0);
+  long long np_tot = 0;
+  if (kb && kb->n_proj) {
+    for (int e = 0; e < n; ++e) {
+      nproj[e] = kb->n_proj[e];
+      if (nproj[e] < 0) return fail(DGDFT_EINVAL, "negative projector count");
+      np_tot += nproj[e];
+    }
+  }
+  std::vector<double> gam(np_tot);
+  std::vector<int64_t> ptr(np_tot + 1, 0);
+  std::vector<int32_t> idx;
+  std::vector<double> val;
+  if (np_tot > 0) {
+    if (!kb->gamma || !kb->ptr || !kb->idx || !kb->val) return fail(DGDFT_EINVAL, "KB arrays are NULL");
+    HCHECK(hipMemcpyAsync(gam.data(), kb->gamma, sizeof(double) * np_tot, hipMemcpyDeviceToHost, s));
+    HCHECK(hipMemcpyAsync(ptr.data(), kb->ptr, sizeof(int64_t) * (np_tot + 1), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    long long nnz = ptr[np_tot];
+    if (ptr[0] != 0 || nnz < 0) return fail(DGDFT_EINVAL, "KB ptr must start at 0");
+    for (long long p = 0; p < np_tot; ++p)
+      if (ptr[p + 1] < ptr[p]) return fail(DGDFT_EINVAL, "KB ptr is not monotone");
+    idx.resize(nnz);
+    val.resize(nnz);
+    if (nnz) {
+      HCHECK(hipMemcpyAsync(idx.data(), kb->idx, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+      HCHECK(hipMemcpyAsync(val.data(), kb->val, sizeof(double) * nnz, hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+    }
+    for (double g : gam)
+      if (!std::isfinite(g)) return fail(DGDFT_EINVAL, "KB gamma contains non-finite values");
+    for (double v : val)
+      if (!std::isfinite(v)) return fail(DGDFT_EINVAL, "KB val contains non-finite values");
+  }
+  // layout per element: groups, points, values (KB_GMAX per point), transposed CSR
+  struct Lay {
+    std::vector<int> gptr, gp0, gnp, gidx, tptr, tp;
+    std::vector<double> gval, tc;
+  };
+  std::vector<Lay> lay(n);
+  size_t kb_bytes = 0, proj_doubles = 0;
+  long long pbase = 0;
+  for (int e = 0; e < n; ++e) {
+    Elem& E = h->eh[e];
+    Lay& L = lay[e];
+    const double sq = std::sqrt(E.dv);
+    int P = nproj[e];
+    L.gptr.push_back(0);
+    for (int p = 0; p < P;) {
+      long long a0 = ptr[pbase + p], a1 = ptr[pbase + p + 1];
+      for (long long k = a0; k < a1; ++k)
+        if (idx[k] < 0 || idx[k] >= E.ng) return fail(DGDFT_EINVAL, "KB idx outside the grid");
+      int q = p + 1;
+      while (q < P && q - p < KB_GMAX) {
+        long long b0 = ptr[pbase + q], b1 = ptr[pbase + q + 1];
+        if (b1 - b0 != a1 - a0 || !std::equal(idx.begin() + b0, idx.begin() + b1, idx.begin() + a0)) break;
+        ++q;
+      }
+      L.gp0.push_back(p);
+      L.gnp.push_back(q - p);
+      for (long long k = a0; k < a1; ++k) {
+        L.gidx.push_back(idx[k]);
+        for (int g = 0; g < KB_GMAX; ++g) {
+          double v = 0.0;
+          if (g < q - p) v = sq * val[ptr[pbase + p + g] + (k - a0)];
+          L.gval.push_back(v);
+        }
+      }
+      L.gptr.push_back((int)L.gidx.size());
+      p = q;
+    }
+    // transposed CSR: entries (projector, gamma_p * beta_p(r)) per grid point
+    if (P > 0) {
+      L.tptr.assign(E.ng + 1, 0);
+      for (int p = 0; p < P; ++p)
+        for (long long k = ptr[pbase + p]; k < ptr[pbase + p + 1]; ++k) L.tptr[idx[k] + 1]++;
+      for (int r = 0; r < E.ng; ++r) L.tptr[r + 1] += L.tptr[r];
+      L.tp.resize(L.tptr[E.ng]);
+      L.tc.resize(L.tptr[E.ng]);
+      std::vector<int> fillpos(L.tptr.begin(), L.tptr.end() - 1);
+      for (int p = 0; p < P; ++p)
+        for (long long k = ptr[pbase + p]; k < ptr[pbase + p + 1]; ++k) {
+          int at = fillpos[idx[k]]++;
+          L.tp[at] = p;
+          L.tc[at] = gam[pbase + p] * sq * val[k];
+        }
+    }
+    kb_bytes += align256(sizeof(int) * L.gptr.size()) + 2 * align256(sizeof(int) * L.gp0.size()) +
+                align256(sizeof(int) * L.gidx.size()) + align256(sizeof(double) * L.gval.size()) +
+                align256(sizeof(int) * L.tptr.size()) + align256(sizeof(int) * L.tp.size()) +
+                align256(sizeof(double) * L.tc.size()) + align256(sizeof(double) * P);
+    proj_doubles += 2 * (size_t)P * E.J;
+    pbase += P;
+  }
+  HCHECK(hipStreamSynchronize(s));
+  if (kb_bytes > h->kb_cap) {
+    HCHECK(hipFree(h->kb_arena));
+    h->kb_arena = nullptr;
+    HCHECK(hipMalloc(&h->kb_arena, kb_bytes));
+    h->kb_cap = kb_bytes;
+  }
+  if (proj_doubles * sizeof(double) > h->proj_cap) {
+    HCHECK(hipFree(h->proj_arena));
+    h->proj_arena = nullptr;
+    HCHECK(hipMalloc(&h->proj_arena, std::max<size_t>(proj_doubles, 1) * sizeof(double)));
+    h->proj_cap = proj_doubles * sizeof(double);
+  }
+  // upload (synchronous copies from pageable host vectors)
+  char* p = (char*)h->kb_arena;
+  double* pj = h->proj_arena;
+  pbase = 0;
+  auto put = [&](const void* src, size_t bytes) -> void* {
+    void* dst = p;
+    if (bytes) HCHECK(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    p += align256(bytes);
+    return dst;
+  };
+  for (int e = 0; e < n; ++e) {
+    Elem& E = h->eh[e];
+    Lay& L = lay[e];
+    int P = nproj[e];
+    E.n_proj = P;
+    E.n_grp = (int)L.gp0.size();
+    E.grp_ptr = (const int*)put(L.gptr.data(), sizeof(int) * L.gptr.size());
+    E.grp_p0 = (const int*)put(L.gp0.data(), sizeof(int) * L.gp0.size());
+    E.grp_np = (const int*)put(L.gnp.data(), sizeof(int) * L.gnp.size());
+    E.grp_idx = (const int*)put(L.gidx.data(), sizeof(int) * L.gidx.size());
+    E.grp_val = (const double*)put(L.gval.data(), sizeof(double) * L.gval.size());
+    if (P > 0) {
+      E.kbt_ptr = (const int*)put(L.tptr.data(), sizeof(int) * L.tptr.size());
+      E.kbt_p = (const int*)put(L.tp.data(), sizeof(int) * L.tp.size());
+      E.kbt_c = (const double*)put(L.tc.data(), sizeof(double) * L.tc.size());
+    } else {
+      E.kbt_ptr = nullptr; E.kbt_p = nullptr; E.kbt_c = nullptr;
+    }
+    E.gamma = (const double*)put(gam.data() + pbase, sizeof(double) * P);
+    E.proj = pj; pj += (size_t)P * E.J;
+    E.projx = pj; pj += (size_t)P * E.J;
+    pbase += P;
+  }
+  h->upload_elems();
+  HCHECK(hipStreamSynchronize(s));
+  h->potential_loaded = true;
+  return fail(DGDFT_OK, "");
+}
+
+int32_t dgdft_alb_set_potential(dgdft_alb* h, const double* V, const dgdft_kb* kb, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!V) { h->err = "V is NULL"; return DGDFT_EINVAL; }
+  h->stream = stream ? (hipStream_t)stream : h->stream;
+  try {
+    Status st = set_potential_impl(h, V, kb, h->stream);
+    if (st.code != DGDFT_OK) h->err = st.msg;
+    return st.code;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return f.code == hipErrorOutOfMemory ? DGDFT_ENOMEM : DGDFT_EHIP;
+  }
+}
+
+static std::vector<int> all_elems(int n) {
+  std::vector<int> a(n);
+  for (int i = 0; i < n; ++i) a[i] = i;
+  return a;
+}
+
+// Rayleigh-Ritz on the current X alone and rotation of X, HX (initial and
+// final steps), then the residual norms.
+static void rr_on_x(dgdft_alb* h, const std::vector<int>& act) {
+  GramArgs g{};
+  g.A = dgdft_alb::opnd({VS_X});
+  g.B[0] = dgdft_alb::opnd({VS_X});
+  g.B[1] = dgdft_alb::opnd({VS_HX});
+  g.njob = 2; g.out_mat[0] = SM_M; g.out_mat[1] = SM_H; g.upper = 1;
+  h->gram(act, g);
+  h->per_elem(act, 1, 1);
+  UpdArgs u{};
+  u.A[0] = dgdft_alb::opnd({VS_X});
+  u.A[1] = dgdft_alb::opnd({VS_HX});
+  u.Y[0] = dgdft_alb::opnd({VS_XN});
+  u.Y[1] = dgdft_alb::opnd({VS_HXN});
+  u.njob = 2; u.cmat = SM_C; u.ccol0 = 0; u.ncol = -1; u.alpha = 1.0; u.beta = 0.0;
+  h->update(act, u);
+  h->per_elem(act, 3, 0);   // advance: X <- X C etc. become current; hasP <- 0
+}
+
+static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double* eigvecs, double* albs,
+                         double* sigma, dgdft_alb_stats* stats) {
+  const int n = h->n;
+  hipStream_t s = h->stream;
+  h->ring_reset();
+  // ---- X0 finiteness
+  HCHECK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+  hipLaunchKernelGGL(dg_check_finite, dim3(1024), dim3(256), 0, s, X0, (long long)h->sumNgJ, h->d_flag);
+  int bad = 0;
+  HCHECK(hipMemcpyAsync(&bad, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  if (bad) return fail(DGDFT_EINVAL, "X0 contains non-finite values");
+  HCHECK(hipMemsetAsync(h->fl_arena, 0, sizeof(int) * (size_t)n * FL_COUNT, s));
+  memset(h->h_fl, 0, sizeof(int) * (size_t)n * FL_COUNT);
+  std::vector<int> all = all_elems(n);
+  // ---- initial block: X = X0 T with T from a scaled CholQR of X0
+  {
+    auto P = h->make_prefix(all, [&](int e) { return h->eh[e].J; });
+    hipLaunchKernelGGL(dg_load_block, dim3(P.total), dim3(256), 0, s, h->ed, P.active, P.prefix, P.na,
+                       X0, (int)S_W, 1.0);
+    HCHECK(hipGetLastError());
+  }
+  GramArgs gw{};
+  gw.A = dgdft_alb::opnd({S_W});
+  gw.B[0] = dgdft_alb::opnd({S_W});
+  gw.njob = 1; gw.out_mat[0] = SM_G; gw.upper = 1;
+  h->gram(all, gw);
+  h->per_elem(all, 0, 1);
+  h->poll();
+  for (int e = 0; e < n; ++e)
+    if (h->h_fl[(size_t)e * FL_COUNT + FL_BREAKDOWN]) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "element %d: initial guess X0 is rank deficient", e);
+      return fail(DGDFT_EBREAKDOWN, buf);
+    }
+  UpdArgs ux{};
+  ux.A[0] = dgdft_alb::opnd({S_W});
+  ux.Y[0] = dgdft_alb::opnd({VS_X});
+  ux.njob = 1; ux.cmat = SM_T; ux.ncol = -1; ux.alpha = 1.0; ux.beta = 0.0;
+  h->update(all, ux);
+  h->op_apply(all, VS_X, VS_HX, 0, -1);
+  rr_on_x(h, all);
+
+  std::vector<int> iters(n, 0), done(n, 0);
+  std::vector<int> act = all;
+  const double tol = h->opts.tol;
+  int max_iter = h->opts.max_iter;
+  for (;;) {
+    h->per_elem_cols(act, 0, VS_X, VS_HX, S_W, nullptr, nullptr);   // R -> W, norms
+    h->poll();
+    std::vector<int> next;
+    for (int e : act) {
+      if (h->max_res(e) <= tol || iters[e] >= max_iter) done[e] = 1;
+      else next.push_back(e);
+    }
+    act.swap(next);
+    if (act.empty()) break;
+    // Teter: band kinetic energies, then W = K(R)
+    h->launch_kbproj(act, VS_X, 0, -1, 1);
+    h->per_elem(act, 2, 0);
+    h->precondition(act, S_W, 0, -1);
+    // W <- W - [X P]([X P]^T W)
+    GramArgs g1{};
+    g1.A = dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
+    g1.B[0] = dgdft_alb::opnd({S_W});
+    g1.njob = 1; g1.out_mat[0] = SM_G; g1.upper = 0;
+    h->gram(act, g1);
+    UpdArgs u1{};
+    u1.A[0] = g1.A;
+    u1.Y[0] = dgdft_alb::opnd({S_W});
+    u1.njob = 1; u1.cmat = SM_G; u1.ncol = -1; u1.alpha = -1.0; u1.beta = 1.0;
+    h->update(act, u1);
+    // W2 = W T (CholQR / SVQB)
+    h->gram(act, gw);
+    h->per_elem(act, 0, 0);
+    UpdArgs u2{};
+    u2.A[0] = dgdft_alb::opnd({S_W});
+    u2.Y[0] = dgdft_alb::opnd({S_W2});
+    u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = 1.0; u2.beta = 0.0;
+    h->update(act, u2);
+    // HW
+    h->op_apply(act, S_W2, S_HW, 0, -1);
+    // Rayleigh-Ritz on S = [X P W2]
+    GramArgs g3{};
+    g3.A = dgdft_alb::opnd({VS_X, VS_P, S_W2}, {0, 1, 0});
+    g3.B[0] = g3.A;
+    g3.B[1] = dgdft_alb::opnd({VS_HX, VS_HP, S_HW}, {0, 1, 0});
+    g3.njob = 2; g3.out_mat[0] = SM_M; g3.out_mat[1] = SM_H; g3.upper = 1;
+    h->gram(act, g3);
+    h->per_elem(act, 1, 0);
+    UpdArgs u3{};
+    u3.A[0] = g3.A;
+    u3.A[1] = g3.B[1];
+    u3.Y[0] = dgdft_alb::opnd({VS_XN, VS_PN});
+    u3.Y[1] = dgdft_alb::opnd({VS_HXN, VS_HPN});
+    u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
+    h->update(act, u3);
+    h->per_elem(act, 3, 0);
+    for (int e : act) iters[e]++;
+  }
+  // ---- final FP64 check on every element: fresh HX, RR on X, residuals
+  h->ring_reset();
+  h->op_apply(all, VS_X, VS_HX, 0, -1);
+  // RR on X needs hasP = 0 for the operand layout; it reads only X/HX
+  rr_on_x(h, all);
+  h->per_elem_cols(all, 1, VS_X, VS_HX, S_W, nullptr, nullptr);
+  h->poll();
+  // ---- restriction + SVD truncation
+  h->per_elem_cols(all, 4, VS_X, S_W, 0, nullptr, nullptr);
+  GramArgs ga{};
+  ga.A = dgdft_alb::opnd({S_W});
+  ga.B[0] = ga.A;
+  ga.njob = 1; ga.out_mat[0] = SM_G; ga.upper = 1; ga.use_ne = 1;
+  h->gram(all, ga);
+  double* sig = sigma;
+  double* sig_tmp = nullptr;
+  if (!sig) {
+    HCHECK(hipMalloc(&sig_tmp, sizeof(double) * std::max<long long>(h->sumNalb, 1)));
+    sig = sig_tmp;
+  }
+  h->per_elem(all, 4, 0, sig);
+  if (albs) {
+    // ALB = Psi_E T -> W2 rows 0..N_E-1, columns 0..n_alb-1; then sign + pack
+    UpdArgs ua{};
+    ua.A[0] = dgdft_alb::opnd({S_W});
+    ua.Y[0] = dgdft_alb::opnd({S_W2});
+    ua.njob = 1; ua.cmat = SM_T; ua.alpha = 1.0; ua.beta = 0.0; ua.use_ne = 1;
+    ua.ncol = -2;   // each element's n_alb
+    h->update(all, ua);
+    h->per_elem_cols(all, 2, S_W2, 0, 0, albs, nullptr);
+  }
+  h->per_elem_cols(all, 3, VS_X, 0, 0, eigvals, eigvecs);
+  HCHECK(hipStreamSynchronize(s));
+  if (sig_tmp) (void)hipFree(sig_tmp);
+  // ---- stats
+  int any_nc = 0;
+  for (int e = 0; e < n; ++e) {
+    double mr = h->max_res(e);
+    int conv = mr <= tol;
+    any_nc |= !conv;
+    if (stats) {
+      const int* f = h->h_fl + (size_t)e * FL_COUNT;
+      stats[e].iters = iters[e];
+      stats[e].converged = conv;
+      stats[e].max_res = mr;
+      stats[e].n_chol_fallback = f[FL_W_SVQB];
+      stats[e].n_rr_fallback = f[FL_RR_FALLBACK];
+      stats[e].n_p_drop = f[FL_P_DROP];
+      stats[e].reserved = f[FL_QL_FAIL];
+    }
+  }
+  return fail(any_nc ? DGDFT_NOT_CONVERGED : DGDFT_OK, any_nc ? "some element did not converge" : "");
+}
+
+int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb, const double* X0,
+                        double* eigvals, double* eigvecs, double* albs, double* sigma,
+                        dgdft_alb_stats* stats, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!X0 || !eigvals) { h->err = "X0 and eigvals must be non-NULL"; return DGDFT_EINVAL; }
+  if (stream) h->stream = (hipStream_t)stream;
+  try {
+    if (V) {
+      Status st = set_potential_impl(h, V, kb, h->stream);
+      if (st.code != DGDFT_OK) { h->err = st.msg; return st.code; }
+    } else if (!h->potential_loaded) {
+      h->err = "no potential loaded (pass V or call dgdft_alb_set_potential)";
+      return DGDFT_EINVAL;
+    }
+    Status st = solve_impl(h, X0, eigvals, eigvecs, albs, sigma, stats);
+    h->err = st.msg;
+    return st.code;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return f.code == hipErrorOutOfMemory ? DGDFT_ENOMEM : DGDFT_EHIP;
+  }
+}
+
+// Bind caller buffers to the user slots of one element.
+static void bind_user(dgdft_alb* h, int elem, const double* a, const double* b, const double* c) {
+  Elem& E = h->eh[elem];
+  E.blk[S_U0] = const_cast<double*>(a);
+  E.blk[S_U1] = const_cast<double*>(b);
+  E.blk[S_U2] = const_cast<double*>(c);
+  HCHECK(hipMemcpyAsync(h->ed + elem, &E, sizeof(Elem), hipMemcpyHostToDevice, h->stream));
+}
+
+int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* HX, int32_t ncols,
+                          void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (elem < 0 || elem >= h->n || !X || !HX || ncols < 1 || ncols > h->eh[elem].J) {
+    h->err = "apply_h: bad element, pointer or ncols";
+    return DGDFT_EINVAL;
+  }
+  if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
+  if (stream) h->stream = (hipStream_t)stream;
+  try {
+    h->ring_reset();
+    bind_user(h, elem, X, HX, nullptr);
+    std::vector<int> one{elem};
+    h->op_apply(one, S_U0, S_U1, 0, ncols);
+    HCHECK(hipStreamSynchronize(h->stream));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R, const double* X, double* W,
+                               int32_t ncols, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (elem < 0 || elem >= h->n || !R || !X || !W || ncols < 1 || ncols > h->eh[elem].J) {
+    h->err = "precondition: bad element, pointer or ncols";
+    return DGDFT_EINVAL;
+  }
+  if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
+  if (stream) h->stream = (hipStream_t)stream;
+  try {
+    h->ring_reset();
+    Elem& E = h->eh[elem];
+    if (W != R) HCHECK(hipMemcpyAsync(W, R, sizeof(double) * (size_t)E.ng * ncols, hipMemcpyDeviceToDevice, h->stream));
+    // HX into the solver's HW block, then x.hx, V x.x and beta^T x give T_i
+    bind_user(h, elem, X, W, E.blk[S_HW]);
+    std::vector<int> one{elem};
+    h->op_apply(one, S_U0, S_U2, 0, ncols);
+    {
+      auto P = h->make_prefix(one, [&](int) { return ncols; });
+      hipLaunchKernelGGL(dg_resid, dim3(P.total), dim3(256), 0, h->stream, h->ed, P.active, P.prefix,
+                         P.na, (int)S_U0, (int)S_U2, (int)S_U2, 0);
+    }
+    h->launch_kbproj(one, S_U0, 0, ncols, 1);
+    h->per_elem(one, 2, 0);
+    h->precondition(one, S_U1, 0, ncols);
+    HCHECK(hipStreamSynchronize(h->stream));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------- test entries
+namespace {
+struct TmpDev {
+  std::vector<void*> p;
+  ~TmpDev() {
+    for (void* q : p) (void)hipFree(q);
+  }
+  template <class T> T* alloc(size_t count) {
+    void* q = nullptr;
+    HCHECK(hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T)));
+    p.push_back(q);
+    return (T*)q;
+  }
+};
+}  // namespace
+
+extern "C" {
+
+int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A, double* w, double* Z,
+                         void* stream) {
+  if (count < 1 || n < 1 || n > 3072 || k < 1 || k > n || !A || !w || !Z) {
+    g_create_error = "small_syev: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    TmpDev t;
+    double* work = t.alloc<double>((size_t)count * (2 * (size_t)n * n + 8 * (size_t)n));
+    hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work);
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(s));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    g_create_error = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, int32_t n, double alpha,
+                           const double* A, const double* B, double beta, double* C, void* stream) {
+  if (count < 1 || K < 1 || K > (1LL << 30) || m < 1 || n < 1 || !A || !B || !C ||
+      (trans != 0 && trans != 1) || (long long)m * n > (1LL << 30)) {
+    g_create_error = "gemm_batched: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    TmpDev t;
+    std::vector<Elem> eh(count);
+    const int nch = gram_nchunk((int)K);
+    double* gp = trans ? t.alloc<double>((size_t)count * nch * m * n) : nullptr;
+    for (int i = 0; i < count; ++i) {
+      Elem& e = eh[i];
+      e.ng = e.ld = (int)K;
+      e.J = std::max(m, n);
+      if (trans) {
+        e.blk[S_U0] = const_cast<double*>(A) + (size_t)i * K * m;
+        e.blk[S_U1] = const_cast<double*>(B) + (size_t)i * K * n;
+        e.small = C + (size_t)i * m * n;
+        e.gpart = gp + (size_t)i * nch * m * n;
+      } else {
+        e.blk[S_U0] = const_cast<double*>(A) + (size_t)i * K * m;
+        e.small = const_cast<double*>(B) + (size_t)i * m * n;
+        e.blk[S_U2] = C + (size_t)i * K * n;
+      }
+      e.small_stride = 0;
+    }
+    Elem* ed = t.alloc<Elem>(count);
+    HCHECK(hipMemcpy(ed, eh.data(), sizeof(Elem) * count, hipMemcpyHostToDevice));
+    std::vector<int> act(count), pre(count + 1, 0), pre2(count + 1, 0);
+    Opnd oa{}, ob{}, oc{};
+    oa.nblk = ob.nblk = oc.nblk = 1;
+    oa.slot[0] = S_U0; oa.ncols = m;
+    ob.slot[0] = S_U1; ob.ncols = n;
+    oc.slot[0] = S_U2; oc.ncols = n;
+    for (int i = 0; i < count; ++i) {
+      act[i] = i;
+      if (trans) {
+        pre[i + 1] = pre[i] + gram_tiles(m, n, 0) * nch;
+        pre2[i + 1] = pre2[i] + cdiv(m * n, 256);
+      } else {
+        pre[i + 1] = pre[i] + cdiv((int)K, GT) * cdiv(n, GT);
+      }
+    }
+    int* d_act = t.alloc<int>(count);
+    int* d_pre = t.alloc<int>(count + 1);
+    int* d_pre2 = t.alloc<int>(count + 1);
+    HCHECK(hipMemcpy(d_act, act.data(), sizeof(int) * count, hipMemcpyHostToDevice));
+    HCHECK(hipMemcpy(d_pre, pre.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice));
+    HCHECK(hipMemcpy(d_pre2, pre2.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice));
+    if (trans) {
+      GramArgs g{};
+      g.A = oa; g.B[0] = ob; g.njob = 1; g.out_mat[0] = 0; g.upper = 0;
+      hipLaunchKernelGGL(dg_gram, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, g);
+      hipLaunchKernelGGL(dg_gram_reduce, dim3(pre2[count]), dim3(256), 0, s, ed, d_act, d_pre2, count, g);
+    } else {
+      UpdArgs u{};
+      u.A[0] = oa; u.Y[0] = oc; u.njob = 1; u.cmat = 0; u.ccol0 = 0; u.ncol = n;
+      u.alpha = alpha; u.beta = beta;
+      hipLaunchKernelGGL(dg_update, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, u);
+    }
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(s));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    g_create_error = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+}  // extern "C"

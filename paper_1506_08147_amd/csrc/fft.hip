@@ -1,0 +1,357 @@
+// Batched 3D FFT pipeline for the local operator and the Teter preconditioner.
+//
+// Operation 1 of the LOBPCG list in Sec. II.B applies the local Hamiltonian:
+// the Laplacian through the FFT, the local potential pointwise and the KB
+// projectors.  Operation 5 applies the Teter preconditioner, diagonal in G.
+// Both act on real columns with a real, even diagonal in G, so two real
+// columns a, b are packed as z = a + i b and share one complex transform.
+//
+// Three passes per transform pair, each one read + one write of the packed
+// column through HBM (intermediates are one complex scratch per pair):
+//   fft_xy  : load an xy-plane of (a, b) into LDS, FFT along x then y, store
+//   fft_z   : load the z-pencils of row pair (m2, -m2), FFT along z, apply
+//             the G-space diagonal (kinetic |G|^2/2, or Teter with the mixing
+//             needed when a and b carry different K), inverse FFT along z
+//   fft_xyi : inverse FFT along y then x, scale 1/N, and the epilogue: for the
+//             operator HX = T x + V x + sum_p gamma_p beta_p (beta_p^T x)
+//             (V and the KB scatter fused), for the preconditioner the result
+//
+// 1D transforms are mixed-radix Stockham (radices 4, 2, 3, 5) in LDS with
+// register staging: every thread reads all its butterfly inputs of a stage,
+// the workgroup synchronises, then every thread writes its outputs, so one
+// LDS buffer suffices.  Twiddles come from a per-axis table exp(-2 pi i t/n).
+#include "common.h"
+
+namespace dg {
+
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_MAXPTS = 6144;        // points of one LDS tile (96 KiB)
+constexpr int FFT_PTS_PER_THREAD = FFT_MAXPTS / FFT_THREADS;   // 24
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+// i*sign*z
+__device__ __forceinline__ double2 cisgn(double2 z, double sgn) { return make_double2(-sgn * z.y, sgn * z.x); }
+
+template <int R> __device__ __forceinline__ void dft(double2* v, double sgn);
+
+template <> __device__ __forceinline__ void dft<2>(double2* v, double) {
+  double2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <> __device__ __forceinline__ void dft<3>(double2* v, double sgn) {
+  const double h = 0.86602540378443864676;   // sin(2 pi / 3)
+  double2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+  double2 m = csub(v[0], cscale(s, 0.5));
+  double2 r = cisgn(cscale(d, h), sgn);
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(m, r);
+  v[2] = csub(m, r);
+}
+
+template <> __device__ __forceinline__ void dft<4>(double2* v, double sgn) {
+  double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+  double2 s13 = cadd(v[1], v[3]), d13 = cisgn(csub(v[1], v[3]), sgn);
+  v[0] = cadd(s02, s13);
+  v[2] = csub(s02, s13);
+  v[1] = cadd(d02, d13);
+  v[3] = csub(d02, d13);
+}
+
+template <> __device__ __forceinline__ void dft<5>(double2* v, double sgn) {
+  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+  double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  double2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+  double2 a = v[0];
+  double2 m1 = cadd(a, cadd(cscale(t1, c1), cscale(t2, c2)));
+  double2 m2 = cadd(a, cadd(cscale(t1, c2), cscale(t2, c1)));
+  double2 r1 = cisgn(cadd(cscale(t3, s1), cscale(t4, s2)), sgn);
+  double2 r2 = cisgn(csub(cscale(t3, s2), cscale(t4, s1)), sgn);
+  v[0] = cadd(a, cadd(t1, t2));
+  v[1] = cadd(m1, r1);
+  v[4] = csub(m1, r1);
+  v[2] = cadd(m2, r2);
+  v[3] = csub(m2, r2);
+}
+
+// One Stockham stage of radix R on `nlines` lines of length n stored in LDS
+// at buf[line*lstride + m*estride].  Ns = product of the radices done so far.
+template <int R>
+__device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstride, int estride,
+                                      int Ns, const double2* __restrict__ tw, double sgn) {
+  constexpr int MAXK = (FFT_MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
+  const int nb = n / R;
+  const int total = nb * nlines;
+  double2 v[MAXK][R];
+#pragma unroll
+  for (int q = 0; q < MAXK; ++q) {
+    int b = threadIdx.x + q * FFT_THREADS;
+    if (b < total) {
+      int line = b / nb, j = b - line * nb;
+      int base = line * lstride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[base + (j + r * nb) * estride];
+    }
+  }
+  __syncthreads();
+  const int step = n / (Ns * R);
+#pragma unroll
+  for (int q = 0; q < MAXK; ++q) {
+    int b = threadIdx.x + q * FFT_THREADS;
+    if (b < total) {
+      int line = b / nb, j = b - line * nb;
+      int k = j % Ns;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        double2 w = tw[k * r * step];
+        if (sgn > 0) w.y = -w.y;
+        v[q][r] = cmul(v[q][r], w);
+      }
+      dft<R>(v[q], sgn);
+      int o = (j / Ns) * Ns * R + k;
+      int base = line * lstride;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + (o + r * Ns) * estride] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+__device__ void fft_lines(double2* buf, int n, int nlines, int lstride, int estride,
+                          const int* rad, int nrad, const double2* __restrict__ tw, double sgn) {
+  int Ns = 1;
+  for (int s = 0; s < nrad; ++s) {
+    int R = rad[s];
+    switch (R) {
+      case 4: stage<4>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 2: stage<2>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 3: stage<3>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      default: stage<5>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+    }
+    Ns *= R;
+  }
+}
+
+__device__ __forceinline__ int freq(int k, int n) { return k <= n / 2 ? k : k - n; }
+
+__device__ __forceinline__ double teter_k(double x) {
+  double num = 27.0 + x * (18.0 + x * (12.0 + x * 8.0));
+  return num / (num + 16.0 * x * x * x * x);
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: xy-plane forward transform.  Work item (pair q, plane z).
+// Columns col0 + 2q and col0 + 2q + 1 (if < col0 + ncols) of block `slot`;
+// ncols < 0 means all J columns of the element (here and below).
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, int slot, int col0, int ncols) {
+  __shared__ double2 buf[FFT_MAXPTS];
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int w = b - prefix[ai];
+  int q = w / e.n3, z = w - q * e.n3;
+  int n1 = e.n1, n2 = e.n2, np = n1 * n2;
+  const int nc = ncols < 0 ? e.J : ncols;
+  int ca = col0 + 2 * q, cb = ca + 1;
+  bool hasb = cb < col0 + nc;
+  const double* A = bp(e, slot) + (long long)ca * e.ld + (long long)z * np;
+  const double* B = bp(e, slot) + (long long)cb * e.ld + (long long)z * np;
+  for (int p = threadIdx.x; p < np; p += FFT_THREADS)
+    buf[p] = make_double2(A[p], hasb ? B[p] : 0.0);
+  __syncthreads();
+  fft_lines(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], -1.0);
+  fft_lines(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], -1.0);
+  double2* Z = e.zscr + (long long)q * e.ng + (long long)z * np;
+  for (int p = threadIdx.x; p < np; p += FFT_THREADS) Z[p] = buf[p];
+}
+
+// Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
+// (pair q, row pair m2 in [0, n2/2]).  mode 0: kinetic |G|^2/2.  mode 1:
+// Teter with band kinetic energies tkin[col].  mode 2: identity.
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+         int na, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_MAXPTS];
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int w = b - prefix[ai];
+  int nrp = e.n2 / 2 + 1;
+  int q = w / nrp, m2 = w - q * nrp;
+  int n1 = e.n1, n2 = e.n2, n3 = e.n3;
+  int ra = m2, rb = (n2 - m2) % n2;
+  int nrows = (ra == rb) ? 1 : 2;
+  int width = nrows * n1;            // lines per z-slice, contiguous in LDS
+  int npts = width * n3;
+  double2* Z = e.zscr + (long long)q * e.ng;
+  // LDS layout: buf[z*width + slot*n1 + x]
+  for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
+    int z = p / width, r = p - z * width;
+    int s = r / n1, x = r - s * n1;
+    int row = s ? rb : ra;
+    buf[p] = Z[(long long)z * n1 * n2 + row * n1 + x];
+  }
+  __syncthreads();
+  fft_lines(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], -1.0);
+
+  const double g1 = 2.0 * M_PI / e.L[0], g2 = 2.0 * M_PI / e.L[1], g3 = 2.0 * M_PI / e.L[2];
+  if (mode == 0) {
+    for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
+      int z = p / width, r = p - z * width;
+      int s = r / n1, x = r - s * n1;
+      int row = s ? rb : ra;
+      double k1 = g1 * freq(x, n1), k2 = g2 * freq(row, n2), k3 = g3 * freq(z, n3);
+      buf[p] = cscale(buf[p], 0.5 * (k1 * k1 + k2 * k2 + k3 * k3));
+    }
+    __syncthreads();
+  } else if (mode == 1) {
+    const int nc = ncols < 0 ? e.J : ncols;
+    int ca = col0 + 2 * q, cb = ca + 1;
+    bool hasb = cb < col0 + nc;
+    double Ta = e.tkin[ca], Tb = hasb ? e.tkin[cb] : Ta;
+    double2 nv[FFT_PTS_PER_THREAD];
+#pragma unroll
+    for (int u = 0; u < FFT_PTS_PER_THREAD; ++u) {
+      int p = threadIdx.x + u * FFT_THREADS;
+      if (p < npts) {
+        int z = p / width, r = p - z * width;
+        int s = r / n1, x = r - s * n1;
+        int row = s ? rb : ra;
+        double k1 = g1 * freq(x, n1), k2 = g2 * freq(row, n2), k3 = g3 * freq(z, n3);
+        double t = 0.5 * (k1 * k1 + k2 * k2 + k3 * k3);
+        double Ka = teter_k(t / Ta), Kb = teter_k(t / Tb);
+        // mirror point (-m1, -m2, -m3): the other row slot (or the same)
+        int zm = (n3 - z) % n3, xm = (n1 - x) % n1;
+        int sm = (nrows == 2) ? 1 - s : 0;
+        double2 zp = buf[p], zmr = buf[zm * width + sm * n1 + xm];
+        double hs = 0.5 * (Ka + Kb), hd = 0.5 * (Ka - Kb);
+        nv[u] = make_double2(hs * zp.x + hd * zmr.x, hs * zp.y - hd * zmr.y);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < FFT_PTS_PER_THREAD; ++u) {
+      int p = threadIdx.x + u * FFT_THREADS;
+      if (p < npts) buf[p] = nv[u];
+    }
+    __syncthreads();
+  }
+  fft_lines(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], 1.0);
+  for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
+    int z = p / width, r = p - z * width;
+    int s = r / n1, x = r - s * n1;
+    int row = s ? rb : ra;
+    Z[(long long)z * n1 * n2 + row * n1 + x] = buf[p];
+  }
+}
+
+// Pass 3: inverse xy transform and epilogue.  Work item (pair q, plane z).
+// mode 0 (operator): out = T x + V x + KB, reading x from block `in_slot`
+//   and the projections beta^T x from e.proj (n_proj x ncols).
+// mode 1 (plain): out = result (preconditioner; out may equal in).
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_MAXPTS];
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int w = b - prefix[ai];
+  int q = w / e.n3, z = w - q * e.n3;
+  int n1 = e.n1, n2 = e.n2, np = n1 * n2;
+  const double2* Z = e.zscr + (long long)q * e.ng + (long long)z * np;
+  for (int p = threadIdx.x; p < np; p += FFT_THREADS) buf[p] = Z[p];
+  __syncthreads();
+  fft_lines(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], 1.0);
+  fft_lines(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], 1.0);
+  const double sc = 1.0 / (double)e.ng;
+  const int nc = ncols < 0 ? e.J : ncols;
+  int ca = col0 + 2 * q, cb = ca + 1;
+  bool hasb = cb < col0 + nc;
+  long long off = (long long)z * np;
+  double* OA = bp(e, out_slot) + (long long)ca * e.ld + off;
+  double* OB = bp(e, out_slot) + (long long)cb * e.ld + off;
+  if (mode == 0) {
+    const double* IA = bp(e, in_slot) + (long long)ca * e.ld + off;
+    const double* IB = bp(e, in_slot) + (long long)cb * e.ld + off;
+    const double* V = e.V + off;
+    const int* kp = e.kbt_ptr;
+    const double* pa = e.proj + (long long)(ca - col0) * e.n_proj;
+    const double* pb = e.proj + (long long)(cb - col0) * e.n_proj;
+    for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
+      double2 r = buf[p];
+      double v = V[p];
+      double ya = sc * r.x + v * IA[p];
+      double yb = hasb ? sc * r.y + v * IB[p] : 0.0;
+      if (kp) {
+        int g = (int)(off + p);
+        for (int t = kp[g]; t < kp[g + 1]; ++t) {
+          int pr = e.kbt_p[t];
+          double c = e.kbt_c[t];
+          ya += c * pa[pr];
+          if (hasb) yb += c * pb[pr];
+        }
+      }
+      OA[p] = ya;
+      if (hasb) OB[p] = yb;
+    }
+  } else {
+    for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
+      double2 r = buf[p];
+      OA[p] = sc * r.x;
+      if (hasb) OB[p] = sc * r.y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// KB projections: out[p + n_proj*(c - col0)] = beta_p^T x_c for projector
+// groups sharing one support.  Work item (group g, column c).
+extern "C" __global__ void __launch_bounds__(256)
+dg_kb_project(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, int slot, int col0, int ncols, int to_projx) {
+  __shared__ double red[KB_GMAX][4];
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int w = b - prefix[ai];
+  const int nc = ncols < 0 ? e.J : ncols;
+  int g = w / nc, c = col0 + (w - g * nc);
+  int p0 = e.grp_p0[g], npg = e.grp_np[g];
+  int s0 = e.grp_ptr[g], s1 = e.grp_ptr[g + 1];
+  const double* x = bp(e, slot) + (long long)c * e.ld;
+  double acc[KB_GMAX];
+#pragma unroll
+  for (int k = 0; k < KB_GMAX; ++k) acc[k] = 0.0;
+  for (int s = s0 + threadIdx.x; s < s1; s += 256) {
+    double xv = x[e.grp_idx[s]];
+    const double* vv = e.grp_val + (long long)s * KB_GMAX;
+#pragma unroll
+    for (int k = 0; k < KB_GMAX; ++k) acc[k] += vv[k] * xv;
+  }
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KB_GMAX; ++k) {
+    double v = acc[k];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) red[k][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < npg) {
+    int k = threadIdx.x;
+    double s = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+    double* out = to_projx ? e.projx : e.proj;
+    out[(p0 + k) + (long long)e.n_proj * (c - col0)] = s;
+  }
+}
+
+}  // namespace dg

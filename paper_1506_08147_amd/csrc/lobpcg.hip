@@ -1,0 +1,422 @@
+// Per-element LOBPCG kernels other than the operator and the block products:
+// residuals and their norms, the band kinetic energies of the Teter
+// preconditioner, block orthonormalisation coefficients (CholQR / SVQB),
+// the Rayleigh-Ritz step with the next search direction, and the final
+// restriction + SVD truncation to ALBs (Sec. II.A after Eq. localproblem,
+// Sec. II.B "Generation of the ALB functions").
+//
+// Small dense work (size J or 3J) runs one workgroup per element on the
+// cooperative routines of small_dense.h, all FP64.
+#include "common.h"
+#include "small_dense.h"
+
+namespace dg {
+
+constexpr double CHOL_TOL = 1e-10;   // smallest admissible pivot of a unit-diagonal Gram
+constexpr int SMALL_THREADS = 1024;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// R = HX - X diag(theta) into block `out_slot`; resid = ||R_j||, xhx = x_j.hx_j,
+// vx = sum V x_j^2.  Work item: (element, column j).
+extern "C" __global__ void __launch_bounds__(256)
+dg_resid(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+         int na, int xs, int hxs, int out_slot, int write_r) {
+  __shared__ double red[3][4];
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int j = b - prefix[ai];
+  const double* x = bp(e, xs) + (long long)j * e.ld;
+  const double* hx = bp(e, hxs) + (long long)j * e.ld;
+  double* r = bp(e, out_slot) + (long long)j * e.ld;
+  const double th = e.theta[j];
+  double s0 = 0, s1 = 0, s2 = 0;
+  for (int i = threadIdx.x; i < e.ng; i += 256) {
+    double xv = x[i], hv = hx[i];
+    double rv = hv - th * xv;
+    if (write_r) r[i] = rv;
+    s0 += rv * rv;
+    s1 += xv * hv;
+    s2 += e.V[i] * xv * xv;
+  }
+  s0 = wave_sum(s0); s1 = wave_sum(s1); s2 = wave_sum(s2);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) { red[0][w] = s0; red[1][w] = s1; red[2][w] = s2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    e.resid[j] = sqrt(red[0][0] + red[0][1] + red[0][2] + red[0][3]);
+    e.xhx[j] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    e.vx[j] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  }
+}
+
+// Band kinetic energy of the unit Ritz vector x_j from quantities already at
+// hand: T_j = x_j^T H x_j - sum V x_j^2 - sum_p gamma_p (beta_p^T x_j)^2,
+// floored at the smallest nonzero planewave energy.  One workgroup per element.
+extern "C" __global__ void __launch_bounds__(256)
+dg_teter_energy(Elem* __restrict__ E, const int* __restrict__ active, int na) {
+  const Elem& e = E[active[blockIdx.x]];
+  for (int j = threadIdx.x; j < e.J; j += 256) {
+    double t = e.xhx[j] - e.vx[j];
+    for (int p = 0; p < e.n_proj; ++p) {
+      double b = e.projx[p + (long long)e.n_proj * j];
+      t -= e.gamma[p] * b * b;
+    }
+    e.tkin[j] = fmax(t, e.tfloor);
+  }
+}
+
+// Orthonormalising transform of a block Y with Gram G = Y^T Y (J x J, upper
+// triangle in SM_G): T = D^-1 L^-T from a Cholesky of the unit-diagonal
+// D^-1 G D^-1 = L L^T (CholQR), or, if a pivot falls below CHOL_TOL, the
+// eigenvalue form T = D^-1 U Lambda^-1/2 with Lambda clamped (SVQB).
+// Output T in SM_T (ld J).  init = 1: a fallback marks breakdown instead.
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  const Elem& e = E[active[blockIdx.x]];
+  const int n = e.J;
+  double* G = sm(e, SM_G);
+  double* Ls = sm(e, SM_L);
+  double* Tm = sm(e, SM_T);
+  double* vec = sm(e, SM_V);
+  double* dm = vec + 6 * n;
+  sym_from_upper(t, G, n, n);
+  for (int i = t.tid(); i < n; i += t.nt()) {
+    double d = sqrt(fmax(G[i + (long long)n * i], 0.0));
+    dm[i] = d > 0.0 ? d : 1.0;
+  }
+  t.sync();
+  for (int p = t.tid(); p < n * n; p += t.nt()) {
+    int i = p % n, j = p / n;
+    Ls[p] = G[p] / (dm[i] * dm[j]);
+  }
+  t.sync();
+  int ok = chol_lower(t, Ls, n, n, CHOL_TOL);
+  if (ok) {
+    double* Li = sm(e, SM_A);
+    tri_inv_lower(t, Ls, n, Li, n, n);
+    for (int p = t.tid(); p < n * n; p += t.nt()) {
+      int i = p % n, j = p / n;
+      Tm[p] = Li[j + (long long)n * i] / dm[i];
+    }
+    t.sync();
+    return;
+  }
+  if (t.tid() == 0) {
+    if (init) e.fl[FL_BREAKDOWN] = 1;
+    else e.fl[FL_W_SVQB] += 1;
+  }
+  // SVQB: eigen-decomposition of the scaled Gram, clamped spectrum
+  for (int p = t.tid(); p < n * n; p += t.nt()) {
+    int i = p % n, j = p / n;
+    Ls[p] = G[p] / (dm[i] * dm[j]);
+  }
+  t.sync();
+  double* w = vec + 7 * n;
+  double* Z = sm(e, SM_Z);
+  int qok = syev(t, Ls, n, n, w, Z, n, n, sm(e, SM_U), vec);
+  if (!qok && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
+  double lmax = w[n - 1] > 1e-300 ? w[n - 1] : 1e-300;
+  for (int p = t.tid(); p < n * n; p += t.nt()) {
+    int i = p % n, j = p / n;
+    double l = fmax(w[j], CHOL_TOL * lmax);
+    Tm[p] = Z[p] / (sqrt(l) * dm[i]);
+  }
+  t.sync();
+}
+
+// Rayleigh-Ritz on S = [X P W] (k blocks: 1 for the initial/final step on X,
+// 2 without P, 3 with P): lowest J of Hh c = theta M c with Hh = S^T HS and
+// M = S^T S (upper triangles in SM_H, SM_M, ld n = kJ).  Writes theta, the
+// coefficients C (n x J) into SM_C[:, 0:J] and, for k > 1, the next search
+// direction D (n x J) into SM_C[:, J:2J]: the part of S [0; C_P; C_W] that is
+// M-orthogonal to S C, normalised through a scaled Cholesky of its M-Gram.
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_rr(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  const Elem& e = E[active[blockIdx.x]];
+  const int J = e.J;
+  const int kb = single ? 1 : (has_p(e) ? 3 : 2);
+  const int n = kb * J;
+  double* H = sm(e, SM_H);
+  double* M = sm(e, SM_M);
+  double* A = sm(e, SM_A);
+  double* Lm = sm(e, SM_L);
+  double* U = sm(e, SM_U);
+  double* Cm = sm(e, SM_C);
+  double* Tm = sm(e, SM_T);
+  double* Z = sm(e, SM_Z);
+  double* vec = sm(e, SM_V);
+  double* dm = vec + 6 * n;
+  double* w = vec + 7 * n;
+  sym_from_upper(t, H, n, n);
+  sym_from_upper(t, M, n, n);
+  for (int i = t.tid(); i < n; i += t.nt()) {
+    double d = sqrt(fmax(M[i + (long long)n * i], 0.0));
+    dm[i] = d > 0.0 ? d : 1.0;
+  }
+  t.sync();
+  for (int p = t.tid(); p < n * n; p += t.nt()) {
+    int i = p % n, j = p / n;
+    Lm[p] = M[p] / (dm[i] * dm[j]);
+    A[p] = H[p] / (dm[i] * dm[j]);       // D^-1 Hh D^-1
+  }
+  t.sync();
+  int ok = chol_lower(t, Lm, n, n, CHOL_TOL);
+  int nk = n;
+  if (ok) {
+    // T = D^-1 L^-T; A' = L^-1 (D^-1 Hh D^-1) L^-T
+    tri_inv_lower(t, Lm, n, Tm, n, n);                    // Tm = L^-1 (lower)
+    gemm(t, 0, 0, n, n, n, 1.0, Tm, n, A, n, 0.0, U, n);  // U = L^-1 A
+    gemm(t, 0, 1, n, n, n, 1.0, U, n, Tm, n, 0.0, A, n);  // A = U L^-T
+    int qok = syev(t, A, n, n, w, Z, n, J, U, vec);
+    if (!qok && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
+    // C = D^-1 L^-T Y
+    gemm(t, 1, 0, n, J, n, 1.0, Tm, n, Z, n, 0.0, Cm, n);
+    for (int p = t.tid(); p < n * J; p += t.nt()) Cm[p] /= dm[p % n];
+    t.sync();
+  } else {
+    if (t.tid() == 0) e.fl[FL_RR_FALLBACK] += 1;
+    // reduce to the eigenvectors of D^-1 M D^-1 above CHOL_TOL * max
+    for (int p = t.tid(); p < n * n; p += t.nt()) {
+      int i = p % n, j = p / n;
+      Lm[p] = M[p] / (dm[i] * dm[j]);
+    }
+    t.sync();
+    double* wm = vec + 8 * n;
+    int qok = syev(t, Lm, n, n, wm, Z, n, n, U, vec);
+    if (!qok && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
+    double lmax = wm[n - 1];
+    int first = n;
+    for (int i = 0; i < n; ++i)
+      if (wm[i] > CHOL_TOL * lmax) { first = i; break; }
+    nk = n - first;
+    if (nk < J) {
+      if (t.tid() == 0) e.fl[FL_BREAKDOWN] = 1;
+      nk = J < n ? J : n;
+      first = n - nk;
+    }
+    // T (n x nk) = D^-1 V_k Lambda_k^-1/2
+    for (int p = t.tid(); p < n * nk; p += t.nt()) {
+      int i = p % n, j = p / n;
+      double l = fmax(wm[first + j], 1e-300);
+      Tm[p] = Z[i + (long long)n * (first + j)] / (sqrt(l) * dm[i]);
+    }
+    t.sync();
+    gemm(t, 0, 0, n, nk, n, 1.0, H, n, Tm, n, 0.0, U, n);     // U = Hh T
+    gemm(t, 1, 0, nk, nk, n, 1.0, Tm, n, U, n, 0.0, A, nk);   // A = T^T Hh T
+    sym_from_upper(t, A, nk, nk);
+    int q2 = syev(t, A, nk, nk, w, Z, nk, J, U, vec);
+    if (!q2 && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
+    gemm(t, 0, 0, n, J, nk, 1.0, Tm, n, Z, nk, 0.0, Cm, n);   // C = T Y
+  }
+  for (int j = t.tid(); j < J; j += t.nt()) e.theta[j] = w[j];
+  t.sync();
+  if (kb == 1) {
+    if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 0;
+    return;
+  }
+  // ---- next search direction ----
+  double* Ez = Z;                        // n x J
+  double* Dn = Cm + (long long)n * J;    // output block of SM_C
+  for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] = (p % n) < J ? 0.0 : Cm[p];
+  t.sync();
+  gemm(t, 0, 0, n, J, n, 1.0, M, n, Ez, n, 0.0, U, n);        // U = M E
+  gemm(t, 1, 0, J, J, n, 1.0, Cm, n, U, n, 0.0, A, J);        // A = C^T M E
+  gemm(t, 0, 0, n, J, J, -1.0, Cm, n, A, J, 1.0, Ez, n);      // E <- E - C A
+  gemm(t, 0, 0, n, J, n, 1.0, M, n, Ez, n, 0.0, U, n);        // U = M D
+  gemm(t, 1, 0, J, J, n, 1.0, Ez, n, U, n, 0.0, A, J);        // A = D^T M D
+  for (int p = t.tid(); p < J * J; p += t.nt()) {
+    int i = p % J, j = p / J;
+    if (i > j) A[p] = A[j + (long long)J * i];
+  }
+  t.sync();
+  for (int i = t.tid(); i < J; i += t.nt()) dm[i] = sqrt(fmax(A[i + (long long)J * i], 0.0));
+  t.sync();
+  int dpos = 1;
+  for (int i = 0; i < J; ++i) dpos &= dm[i] > 0.0;
+  int pok = 0;
+  if (dpos) {
+    for (int p = t.tid(); p < J * J; p += t.nt()) {
+      int i = p % J, j = p / J;
+      A[p] /= dm[i] * dm[j];
+    }
+    t.sync();
+    pok = chol_lower(t, A, J, J, CHOL_TOL);
+  }
+  if (pok) {
+    tri_inv_lower(t, A, J, Lm, J, J);                          // Lm = L^-1
+    for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] /= dm[p / n];
+    t.sync();
+    gemm(t, 0, 1, n, J, J, 1.0, Ez, n, Lm, J, 0.0, Dn, n);     // D = E D^-1 L^-T
+    if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 1;
+  } else {
+    for (int p = t.tid(); p < n * J; p += t.nt()) Dn[p] = 0.0;
+    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 0; e.fl[FL_P_DROP] += 1; }
+  }
+  t.sync();
+}
+
+// End of an iteration: next buffers become current, P presence follows the
+// decision of the last Rayleigh-Ritz step.
+extern "C" __global__ void dg_advance(Elem* __restrict__ E, const int* __restrict__ active, int na) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) {
+    const Elem& e = E[active[i]];
+    e.fl[FL_HASP] = e.fl[FL_HASP_NEXT];
+    e.fl[FL_PAR] ^= 1;
+  }
+}
+
+// Rows of the restriction box E_K of column j of block `src` into block `dst`
+// (rows 0..N_E-1).  Work item (element, column).
+extern "C" __global__ void __launch_bounds__(256)
+dg_gather_box(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, int src, int dst) {
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int j = b - prefix[ai];
+  int b1 = e.hi[0] - e.lo[0], b2 = e.hi[1] - e.lo[1];
+  const double* x = bp(e, src) + (long long)j * e.ld;
+  double* y = bp(e, dst) + (long long)j * e.ld;
+  for (int r = threadIdx.x; r < e.ne; r += 256) {
+    int i = r % b1, q = r / b1;
+    int jj = q % b2, kk = q / b2;
+    y[r] = x[(e.lo[0] + i) + e.n1 * ((e.lo[1] + jj) + e.n2 * (e.lo[2] + kk))];
+  }
+}
+
+// SVD truncation through the Gram of the restricted unit eigenvectors:
+// G = Psi_E^T Psi_E = V S^2 V^T (SM_G, upper); the n_alb largest give
+// sigma (descending) and T = V S^-1 / sqrt(dV) (J x n_alb, SM_T), so that
+// Psi_E T are the ALBs in the dV sum phi^2 = 1 normalisation.
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_alb_coeffs(Elem* __restrict__ E, const int* __restrict__ active, int na, double* sigma) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  const Elem& e = E[active[blockIdx.x]];
+  const int n = e.J, na_ = e.nalb;
+  double* G = sm(e, SM_G);
+  double* A = sm(e, SM_A);
+  double* Z = sm(e, SM_Z);
+  double* vec = sm(e, SM_V);
+  double* w = vec + 7 * n;
+  sym_from_upper(t, G, n, n);
+  copy_mat(t, G, n, A, n, n, n);
+  int ok = syev(t, A, n, n, w, Z, n, n, sm(e, SM_U), vec);
+  if (!ok && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
+  double* Tm = sm(e, SM_T);
+  const double isdv = 1.0 / sqrt(e.dv);
+  for (int p = t.tid(); p < n * na_; p += t.nt()) {
+    int i = p % n, c = p / n;
+    int src = n - 1 - c;
+    double s = sqrt(fmax(w[src], 0.0));
+    Tm[p] = s > 0.0 ? Z[i + (long long)n * src] * isdv / s : 0.0;
+  }
+  for (int c = t.tid(); c < na_; c += t.nt()) sigma[e.off_nalb + c] = sqrt(fmax(w[n - 1 - c], 0.0));
+  t.sync();
+}
+
+// ALB column c of block `src` (rows 0..N_E-1) -> output, sign such that the
+// largest-magnitude entry is positive.  Work item (element, ALB).
+extern "C" __global__ void __launch_bounds__(256)
+dg_pack_albs(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+             int na, int src, double* out) {
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int c = b - prefix[ai];
+  const double* x = bp(e, src) + (long long)c * e.ld;
+  double best = -1.0;
+  int bidx = 0x7fffffff;
+  for (int r = threadIdx.x; r < e.ne; r += 256) {
+    double a = fabs(x[r]);
+    if (a > best) { best = a; bidx = r; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    double ob = __shfl_xor(best, o, 64);
+    int oi = __shfl_xor(bidx, o, 64);
+    if (ob > best || (ob == best && oi < bidx)) { best = ob; bidx = oi; }
+  }
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) { bv[w] = best; bi[w] = bidx; }
+  __syncthreads();
+  double gb = bv[0];
+  int gi = bi[0];
+  for (int k = 1; k < 4; ++k)
+    if (bv[k] > gb || (bv[k] == gb && bi[k] < gi)) { gb = bv[k]; gi = bi[k]; }
+  double sgn = (gi < e.ne && x[gi] < 0.0) ? -1.0 : 1.0;
+  double* y = out + e.off_alb + (long long)c * e.ne;
+  for (int r = threadIdx.x; r < e.ne; r += 256) y[r] = sgn * x[r];
+}
+
+// Eigenpairs to the output: eigvals, eigvecs = X / sqrt(dV) (psi
+// normalisation of Eq. localproblem).  Work item (element, column).
+extern "C" __global__ void __launch_bounds__(256)
+dg_pack_eig(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+            int na, int xs, double* vals, double* vecs) {
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int j = b - prefix[ai];
+  if (threadIdx.x == 0) vals[e.off_j + j] = e.theta[j];
+  if (!vecs) return;
+  const double s = 1.0 / sqrt(e.dv);
+  const double* x = bp(e, xs) + (long long)j * e.ld;
+  double* y = vecs + e.off_ngj + (long long)j * e.ng;
+  for (int r = threadIdx.x; r < e.ng; r += 256) y[r] = s * x[r];
+}
+
+// Copy a batch-concatenated input (rows per element = N_g, J columns) into
+// block `dst` of every element, scaled by `scale`.  Work item (element, column).
+extern "C" __global__ void __launch_bounds__(256)
+dg_load_block(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, const double* src, int dst, double scale) {
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const Elem& e = E[active[ai]];
+  int j = b - prefix[ai];
+  const double* x = src + e.off_ngj + (long long)j * e.ng;
+  double* y = bp(e, dst) + (long long)j * e.ld;
+  for (int r = threadIdx.x; r < e.ng; r += 256) y[r] = scale * x[r];
+}
+
+// Any non-finite value in a[0..n) sets *flag.
+extern "C" __global__ void __launch_bounds__(256)
+dg_check_finite(const double* __restrict__ a, long long n, int* flag) {
+  long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  long long stride = (long long)gridDim.x * 256;
+  int bad = 0;
+  for (; i < n; i += stride) bad |= !isfinite(a[i]);
+  if (bad) atomicOr(flag, 1);
+}
+
+}  // namespace dg
+
+namespace dg {
+// Batched symmetric eigensolver for tests: matrix b of A (n x n, upper
+// triangle read) -> w[b*n ..] ascending, Z[b*n*k ..] first k eigenvectors.
+// work: per matrix 2 n^2 + 8 n doubles.
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, double* work) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  long long b = blockIdx.x;
+  double* Aw = work + b * (2LL * n * n + 8LL * n);
+  double* U = Aw + (long long)n * n;
+  double* vec = U + (long long)n * n;
+  copy_mat(t, A + b * n * n, n, Aw, n, n, n);
+  sym_from_upper(t, Aw, n, n);
+  syev(t, Aw, n, n, w + b * n, Z + b * n * k, n, k, U, vec);
+}
+}  // namespace dg
