@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of ALB generation on one MI355X.
+
+A step is one whole pass of the method over one batch of extended elements:
+loading the potentials, LOBPCG from the seeded initial guesses to the
+residual tolerance, the final FP64 check, and restriction + SVD truncation to
+ALBs (all through the C ABI).  The metric is converged element eigensolves
+per second.
+
+Default workload: 64 extended elements of a synthetic 2D slab, 36x36x60 grid
+(h = 10/24 bohr, vacuum along z), ~20 Gaussian-well atoms with 4 KB
+projectors each, 128 states, residual 1e-6, element box 12x12x60, 64 ALBs.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line (rank 0).  One GPU only.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged element eigensolves/s at residual 1e-6: plain FP64 vs mixed+learned"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name, n_elem):
+    import synth
+    if name == "slab":
+        els = synth.slab_batch(n_elem or 64)
+        desc = dict(workload="slab_36x36x60_J128", elements=len(els), grid=[36, 36, 60],
+                    n_states=128, atoms_per_element=20, n_alb=64, element_box=[12, 12, 60])
+    elif name == "one":
+        els = [synth.single_element(seed=s) for s in range(n_elem or 1)]
+        desc = dict(workload="cube_24^3_J32", elements=len(els), grid=[24, 24, 24], n_states=32,
+                    atoms_per_element=8, n_alb=16)
+    else:
+        els = synth.uneven_batch(n_elem or 200)
+        desc = dict(workload="uneven_edges_24-48_J64-256", elements=len(els))
+    return els, desc
+
+
+def cpu_baseline(el, gpu_iters, iters_sample):
+    """The oracle on one element of the same workload: a run stopped after 0
+    and after `iters_sample` iterations gives the set-up + final cost and the
+    cost per iteration; one converged solve is extrapolated to the iteration
+    count the element needs (`gpu_iters`), plus the ALB step."""
+    import numpy as np
+    from oracle import alb, lobpcg as lob, teter
+    from oracle.hamiltonian import FFT_WORKERS, Operator
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    op = Operator(el.grid, el.box, el.V, el.kb)
+    pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
+
+    def run(k):
+        t = time.perf_counter()
+        res = lob.lobpcg(op.apply, pre, el.X0, 1e-6, k)
+        return time.perf_counter() - t, res
+
+    t0, res0 = run(0)
+    tk, _ = run(iters_sample)
+    per_it = max(tk - t0, 0.0) / iters_sample
+    t = time.perf_counter()
+    alb.restrict_svd(res0.X, op.grid, el.elem_lo, el.elem_hi, op.dv, el.n_alb)
+    t_alb = time.perf_counter() - t
+    est = t0 + gpu_iters * per_it + t_alb
+    return dict(value=1.0 / est, unit="elements/s", cores=int(max(FFT_WORKERS, blas)),
+                kind="oracle",
+                sample=(f"element 0 of the workload: oracle LOBPCG run for 0 and {iters_sample} "
+                        f"iterations ({t0:.1f} s, {tk:.1f} s), {per_it:.2f} s/iteration, "
+                        f"extrapolated to the {gpu_iters} iterations this element needs "
+                        f"+ ALB step ({t_alb:.2f} s): {est:.1f} s per converged element"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="slab", choices=["slab", "one", "uneven"])
+    ap.add_argument("--elements", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(extended elements shard across GPUs with no communication; see the design "
+              "notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1506_08147_amd import ALB
+
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    els, desc = workload(args.workload, args.elements)
+    log(f"inputs generated: {len(els)} elements in {time.perf_counter() - t:.1f} s")
+    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
+    kbt = ALB.kb_batch([e.kb for e in els], dev)
+    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
+    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=args.tol,
+            max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+            n_alb=[e.n_alb for e in els])
+    torch.cuda.synchronize()
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        out = h.solve(V, kbt, X0)
+        log(f"warmup {w}: {time.perf_counter() - t:.2f} s")
+    h.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_conv = 0
+    for s in range(args.steps):
+        out = h.solve(V, kbt, X0)
+        n_conv += sum(1 for st in out["stats"] if st["converged"])
+        log(f"step {s}: done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ks = h.kernel_stats()
+    stats = out["stats"]
+    iters = [st["iters"] for st in stats]
+    ms_step = 1e3 * elapsed / args.steps
+
+    # roofline of the dominant kernel class (largest time in the timed region)
+    dom = max((k for k in ks if k not in ("other",)), key=lambda k: ks[k]["ms"])
+    d = ks[dom]
+    per_launch_ms = d["ms"] / max(d["launches"], 1)
+    if d["flops"] > 0:
+        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / PEAK_FP64_TFLOPS, 4), traffic=None)
+    else:
+        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
+    roof.update(kernel=dom, launches=d["launches"], avg_launch_ms=round(per_launch_ms, 4),
+                algorithmic_flops_per_launch=d["flops"] / max(d["launches"], 1),
+                algorithmic_bytes_per_launch=d["bytes"] / max(d["launches"], 1))
+    kernels = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3), launches=v["launches"],
+                       tflops=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] else 0,
+                       gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else 0)
+               for k, v in ks.items() if v["launches"]}
+    line = dict(metric=METRIC, value=round(n_conv / elapsed, 4), unit="elements/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+                data="synthetic", config=dict(desc, tol=args.tol, precision="fp64",
+                                              preconditioner="teter"),
+                roofline=roof, kernels=kernels,
+                iterations=dict(mean=float(np.mean(iters)), min=int(min(iters)), max=int(max(iters))),
+                converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}")
+    h.close()
+    if args.cpu_baseline:
+        log("timing the oracle sample on the host")
+        line["cpu_baseline"] = cpu_baseline(els[0], stats[0]["iters"], args.cpu_iters)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

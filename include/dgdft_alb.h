@@ -177,9 +177,12 @@ int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R,
  * (operation 4 of the LOBPCG list in Sec. II.B): for each of `count` n x n
  * matrices A (device, column-major, lda = n, only the upper triangle read),
  * w = eigenvalues ascending (device [count*n]) and Z = the first k unit
- * eigenvectors (device [count*n*k]).  n <= 3072. */
+ * eigenvectors (device [count*n*k]).  n <= 3072.
+ * method 0: Householder tridiagonalisation, bisection and inverse iteration
+ *           for the k lowest only (w[0..k) written per matrix) -- the path of
+ *           the solver; method 1: implicit QL on the whole spectrum. */
 int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A,
-                         double* w, double* Z, void* stream);
+                         double* w, double* Z, int32_t method, void* stream);
 
 /* Batched tall-skinny FP64 product on matrix cores (operations 2 and 3 of the
  * LOBPCG list in Sec. II.B), exported for tests:
@@ -190,6 +193,37 @@ int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A,
 int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m,
                            int32_t n, double alpha, const double* A, const double* B,
                            double beta, double* C, void* stream);
+
+/* ---- per-kernel timing (diagnostics) ---------------------------------
+ * When enabled, every launch of the listed kernel classes is bracketed by
+ * HIP events on the launch stream; durations are accumulated at the host
+ * polls.  Algorithmic work per launch: Gram products count 2 K m n flops
+ * (K m (m+1) for the symmetric, upper-triangle products) and 8 K (m + n)
+ * bytes; update products 2 K kA n flops and 8 K (kA + n) bytes (+8 K n when
+ * accumulating); FFT passes count the HBM bytes of their input and output. */
+#define DGDFT_K_GRAM         0
+#define DGDFT_K_GRAM_REDUCE  1
+#define DGDFT_K_UPDATE       2
+#define DGDFT_K_FFT_XY_FWD   3
+#define DGDFT_K_FFT_Z        4
+#define DGDFT_K_FFT_XY_INV   5
+#define DGDFT_K_KB_PROJECT   6
+#define DGDFT_K_RESID        7
+#define DGDFT_K_RR           8
+#define DGDFT_K_CHOLQR       9
+#define DGDFT_K_OTHER       10
+#define DGDFT_KCLASS_COUNT  11
+
+/* Enable (1) or disable (0) timing and reset the counters. */
+int32_t dgdft_alb_profile(dgdft_alb* h, int32_t enable);
+
+/* Accumulated launches, milliseconds, algorithmic flops and bytes of one
+ * kernel class since the last dgdft_alb_profile call.  Outputs nullable. */
+int32_t dgdft_alb_kernel_stats(const dgdft_alb* h, int32_t kclass, int64_t* launches,
+                               double* ms, double* flops, double* bytes);
+
+/* Kernel symbol name of a class ("dg_gram", ...). */
+const char* dgdft_kernel_class_name(int32_t kclass);
 
 /* Message of the last failure on h (NULL: of the last failed create). */
 const char* dgdft_alb_last_error(const dgdft_alb* h);

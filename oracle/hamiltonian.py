@@ -23,8 +23,13 @@ Layout: a column is a flat array of N_g values, x fastest
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import scipy.fft as sfft
+
+# threads of the FFT library (the BLAS pool is set by OMP_NUM_THREADS)
+FFT_WORKERS = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 import scipy.sparse as sp
 
 
@@ -68,7 +73,7 @@ class Operator:
         n1, n2, n3 = self.grid
         m = U.shape[1]
         A = U.T.reshape(m, n3, n2, n1)
-        out = sfft.ifftn(self.t[None] * sfft.fftn(A, axes=(1, 2, 3), workers=-1), axes=(1, 2, 3), workers=-1)
+        out = sfft.ifftn(self.t[None] * sfft.fftn(A, axes=(1, 2, 3), workers=FFT_WORKERS), axes=(1, 2, 3), workers=FFT_WORKERS)
         return np.asfortranarray(out.real.reshape(m, self.ng).T)
 
     def nonlocal_(self, U: np.ndarray) -> np.ndarray:

@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.fft as sfft
 
-from .hamiltonian import kinetic_diagonal
+from .hamiltonian import FFT_WORKERS, kinetic_diagonal
 
 
 def teter_k(x):
@@ -33,7 +33,7 @@ def band_kinetic(X: np.ndarray, grid, box) -> np.ndarray:
     n1, n2, n3 = grid
     m = X.shape[1]
     t = kinetic_diagonal(grid, box)
-    Xh = sfft.fftn(X.T.reshape(m, n3, n2, n1), axes=(1, 2, 3), workers=-1)
+    Xh = sfft.fftn(X.T.reshape(m, n3, n2, n1), axes=(1, 2, 3), workers=FFT_WORKERS)
     ng = n1 * n2 * n3
     return np.einsum("abcd,bcd->a", np.abs(Xh) ** 2, t) / ng
 
@@ -48,6 +48,6 @@ def precondition(R: np.ndarray, X: np.ndarray, grid, box) -> np.ndarray:
     t = kinetic_diagonal(grid, box)
     T = np.maximum(band_kinetic(X, grid, box), kinetic_floor(box))
     K = teter_k(t[None] / T[:, None, None, None])
-    Rh = sfft.fftn(R.T.reshape(m, n3, n2, n1), axes=(1, 2, 3), workers=-1)
-    W = sfft.ifftn(K * Rh, axes=(1, 2, 3), workers=-1).real
+    Rh = sfft.fftn(R.T.reshape(m, n3, n2, n1), axes=(1, 2, 3), workers=FFT_WORKERS)
+    W = sfft.ifftn(K * Rh, axes=(1, 2, 3), workers=FFT_WORKERS).real
     return np.asfortranarray(W.reshape(m, n1 * n2 * n3).T)

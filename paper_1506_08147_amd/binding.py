@@ -17,8 +17,11 @@ LIB_PATH = os.path.join(HERE, "libdgdft_alb.so")
 EXPORTS = (
     "dgdft_alb_create", "dgdft_alb_destroy", "dgdft_alb_sizes", "dgdft_alb_set_potential",
     "dgdft_alb_solve", "dgdft_alb_apply_h", "dgdft_alb_precondition", "dgdft_small_syev",
-    "dgdft_gemm_batched", "dgdft_alb_last_error", "dgdft_strerror",
+    "dgdft_gemm_batched", "dgdft_alb_last_error", "dgdft_strerror", "dgdft_alb_profile",
+    "dgdft_alb_kernel_stats", "dgdft_kernel_class_name",
 )
+KCLASS = ("dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
+          "dg_kb_project", "dg_resid", "dg_rr", "dg_cholqr", "other")
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM",
           -4: "EHIP", -5: "EBREAKDOWN"}
@@ -80,7 +83,7 @@ def load_library():
     lib.dgdft_alb_apply_h.restype = i32
     lib.dgdft_alb_precondition.argtypes = [vp, i32, vp, vp, vp, i32, vp]
     lib.dgdft_alb_precondition.restype = i32
-    lib.dgdft_small_syev.argtypes = [i32, i32, i32, vp, vp, vp, vp]
+    lib.dgdft_small_syev.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp]
     lib.dgdft_small_syev.restype = i32
     lib.dgdft_gemm_batched.argtypes = [i32, i32, i64, i32, i32, dbl, vp, vp, dbl, vp, vp]
     lib.dgdft_gemm_batched.restype = i32
@@ -88,6 +91,12 @@ def load_library():
     lib.dgdft_alb_last_error.restype = C.c_char_p
     lib.dgdft_strerror.argtypes = [i32]
     lib.dgdft_strerror.restype = C.c_char_p
+    lib.dgdft_alb_profile.argtypes = [vp, i32]
+    lib.dgdft_alb_profile.restype = i32
+    lib.dgdft_alb_kernel_stats.argtypes = [vp, i32, P(i64), P(dbl), P(dbl), P(dbl)]
+    lib.dgdft_alb_kernel_stats.restype = i32
+    lib.dgdft_kernel_class_name.argtypes = [i32]
+    lib.dgdft_kernel_class_name.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -252,6 +261,20 @@ class ALB:
                                                     R.shape[0], _stream()))
         return W
 
+    def profile(self, enable=True):
+        """Enable per-kernel HIP-event timing and reset the counters."""
+        self._check(self.lib.dgdft_alb_profile(self.h, int(enable)))
+
+    def kernel_stats(self):
+        out = {}
+        for k in range(len(KCLASS)):
+            n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            self._check(self.lib.dgdft_alb_kernel_stats(self.h, k, C.byref(n), C.byref(ms),
+                                                        C.byref(fl), C.byref(by)))
+            out[self.lib.dgdft_kernel_class_name(k).decode()] = dict(
+                launches=n.value, ms=ms.value, flops=fl.value, bytes=by.value)
+        return out
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.dgdft_alb_destroy(self.h)
@@ -264,7 +287,7 @@ class ALB:
             pass
 
 
-def small_syev(A, k):
+def small_syev(A, k, method=0):
     """A: (count, n, n) device float64 (upper triangle read, column-major per
     matrix); returns w (count, n) ascending and Z (count, k, n) (columns)."""
     import torch
@@ -273,7 +296,7 @@ def small_syev(A, k):
     A = A.contiguous()
     w = torch.empty(count, n, dtype=torch.float64, device=A.device)
     Z = torch.empty(count, k, n, dtype=torch.float64, device=A.device)
-    rc = lib.dgdft_small_syev(count, n, k, _ptr(A), _ptr(w), _ptr(Z), _stream())
+    rc = lib.dgdft_small_syev(count, n, k, _ptr(A), _ptr(w), _ptr(Z), int(method), _stream())
     if rc != 0:
         raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
     return w, Z

@@ -82,7 +82,7 @@ __host__ __device__ inline double* bp(const Elem& e, int slot) {
   return e.blk[2 * (v >> 1) + ((v & 1) ^ e.fl[FL_PAR])];
 }
 
-__device__ inline int has_p(const Elem& e) { return e.fl[FL_HASP]; }
+__host__ __device__ inline int has_p(const Elem& e) { return e.fl[FL_HASP]; }
 
 // Column c (0 <= c < nblk*J) of a virtual concatenation of element blocks.
 // `slots` lists block slots; a slot < 0 means "skip".
@@ -135,6 +135,8 @@ enum SmallMat {
   SM_T,       // orthonormalising transform
   SM_Z,       // eigenvectors (n x J)
   SM_V,       // vectors d, e, w, ... (a few columns of length n)
+  SM_W0,      // eigensolver workspace (two consecutive matrices)
+  SM_W1,
   SM_COUNT
 };
 

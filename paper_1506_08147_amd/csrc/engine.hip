@@ -77,6 +77,57 @@ struct dgdft_alb {
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
 
+  // ---- per-kernel-class timing with HIP events on the launch stream
+  struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<ProfRec> recs;
+  long long k_n[DGDFT_KCLASS_COUNT] = {};
+  double k_ms[DGDFT_KCLASS_COUNT] = {}, k_flops[DGDFT_KCLASS_COUNT] = {},
+         k_bytes[DGDFT_KCLASS_COUNT] = {};
+  int cur_kid = -1;
+  double cur_flops = 0, cur_bytes = 0;
+  hipEvent_t cur_a = nullptr;
+
+  hipEvent_t ev() {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t e;
+      HCHECK(hipEventCreate(&e));
+      ev_pool.push_back(e);
+    }
+    return ev_pool[ev_used++];
+  }
+  void pbeg(int kid, double flops, double bytes) {
+    if (!prof) return;
+    cur_kid = kid; cur_flops = flops; cur_bytes = bytes;
+    cur_a = ev();
+    HCHECK(hipEventRecord(cur_a, stream));
+  }
+  void pend() {
+    if (!prof) return;
+    hipEvent_t b = ev();
+    HCHECK(hipEventRecord(b, stream));
+    recs.push_back(ProfRec{cur_kid, cur_a, b, cur_flops, cur_bytes});
+  }
+  // after a stream synchronisation
+  void flush_prof() {
+    for (auto& r : recs) {
+      float ms = 0.f;
+      HCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      k_n[r.kid] += 1;
+      k_ms[r.kid] += ms;
+      k_flops[r.kid] += r.flops;
+      k_bytes[r.kid] += r.bytes;
+    }
+    recs.clear();
+    ev_used = 0;
+  }
+
   // ---------------------------------------------------------------------
   struct Prefix {
     const int* active;
@@ -114,13 +165,21 @@ struct dgdft_alb {
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
     launch_kbproj(act, in_slot, col0, ncols_fixed, 0);
     auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
+    double pts = 0;   // grid points x column pairs
+    for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
+    pbeg(DGDFT_K_FFT_XY_FWD, 0, 32.0 * pts);
     hipLaunchKernelGGL(dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
                        P1.prefix, P1.na, in_slot, col0, ncols_fixed);
+    pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
+    pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
     hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
                        P2.prefix, P2.na, col0, ncols_fixed, 0);
+    pend();
+    pbeg(DGDFT_K_FFT_XY_INV, 0, 56.0 * pts);
     hipLaunchKernelGGL(dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
                        P1.prefix, P1.na, in_slot, out_slot, col0, ncols_fixed, 0);
+    pend();
     HCHECK(hipGetLastError());
   }
 
@@ -128,21 +187,31 @@ struct dgdft_alb {
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
     auto P = make_prefix(act, [&](int e) { return eh[e].n_grp * nc(e); });
     if (P.total == 0) return;
+    pbeg(DGDFT_K_KB_PROJECT, 0, 0);
     hipLaunchKernelGGL(dg_kb_project, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
                        P.na, slot, col0, ncols_fixed, to_projx);
+    pend();
     HCHECK(hipGetLastError());
   }
 
   void precondition(const std::vector<int>& act, int slot, int col0, int ncols_fixed) {
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
     auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
+    double pts = 0;
+    for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
+    pbeg(DGDFT_K_FFT_XY_FWD, 0, 32.0 * pts);
     hipLaunchKernelGGL(dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
                        P1.prefix, P1.na, slot, col0, ncols_fixed);
+    pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
+    pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
     hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
                        P2.prefix, P2.na, col0, ncols_fixed, opts.precond == DGDFT_PRECOND_NONE ? 2 : 1);
+    pend();
+    pbeg(DGDFT_K_FFT_XY_INV, 0, 32.0 * pts);
     hipLaunchKernelGGL(dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
                        P1.prefix, P1.na, slot, slot, col0, ncols_fixed, 1);
+    pend();
     HCHECK(hipGetLastError());
   }
 
@@ -166,14 +235,29 @@ struct dgdft_alb {
       return c * gram_nchunk(K(e));
     });
     if (P.total == 0) return;
+    double fl = 0, by = 0;
+    for (int e : act) {
+      double K = g.use_ne ? eh[e].ne : eh[e].ng;
+      int m = cols_host(g.A, e);
+      by += 8.0 * K * m;
+      for (int j = 0; j < g.njob; ++j) {
+        int nn = cols_host(g.B[j], e);
+        fl += g.upper ? K * m * (double)(m + 1) : 2.0 * K * m * nn;
+        by += 8.0 * K * nn;
+      }
+    }
+    pbeg(DGDFT_K_GRAM, fl, by);
     hipLaunchKernelGGL(dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, g);
+    pend();
     auto R = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
       for (int j = 0; j < g.njob; ++j) c += cdiv(m * cols_host(g.B[j], e), 256);
       return c;
     });
+    pbeg(DGDFT_K_GRAM_REDUCE, 0, 0);
     hipLaunchKernelGGL(dg_gram_reduce, dim3(R.total), dim3(256), 0, stream, ed, R.active, R.prefix,
                        R.na, g);
+    pend();
     HCHECK(hipGetLastError());
   }
 
@@ -184,7 +268,17 @@ struct dgdft_alb {
       return u.njob * cdiv(K, GT) * cdiv(nc, GT);
     });
     if (P.total == 0) return;
+    double fl = 0, by = 0;
+    for (int e : act) {
+      double K = u.use_ne ? eh[e].ne : eh[e].ng;
+      int kA = cols_host(u.A[0], e);
+      int nc = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
+      fl += u.njob * 2.0 * K * kA * nc;
+      by += u.njob * 8.0 * K * (kA + nc * (u.beta != 0.0 ? 2 : 1));
+    }
+    pbeg(DGDFT_K_UPDATE, fl, by);
     hipLaunchKernelGGL(dg_update, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, u);
+    pend();
     HCHECK(hipGetLastError());
   }
 
@@ -192,6 +286,9 @@ struct dgdft_alb {
                      double* o2) {
     auto P = make_prefix(act, [&](int e) { return which == 2 ? eh[e].nalb : eh[e].J; });
     if (P.total == 0) return;
+    double pts = 0;
+    for (int e : act) pts += (double)eh[e].J * eh[e].ng;
+    if (which <= 1) pbeg(DGDFT_K_RESID, 0, (which == 0 ? 32.0 : 24.0) * pts);
     switch (which) {
       case 0:
         hipLaunchKernelGGL(dg_resid, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na,
@@ -214,12 +311,15 @@ struct dgdft_alb {
                            P.na, a0, a1);
         break;
     }
+    if (which <= 1) pend();
     HCHECK(hipGetLastError());
   }
 
   void per_elem(const std::vector<int>& act, int which, int arg, double* out = nullptr) {
     auto P = make_prefix(act, [&](int) { return 1; });
     if (P.na == 0) return;
+    int kid = which == 0 ? DGDFT_K_CHOLQR : which == 1 ? DGDFT_K_RR : DGDFT_K_OTHER;
+    pbeg(kid, 0, 0);
     switch (which) {
       case 0:
         hipLaunchKernelGGL(dg_cholqr, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
@@ -238,6 +338,7 @@ struct dgdft_alb {
                            P.na, out);
         break;
     }
+    pend();
     HCHECK(hipGetLastError());
   }
 
@@ -247,6 +348,7 @@ struct dgdft_alb {
     HCHECK(hipMemcpyAsync(h_fl, fl_arena, sizeof(int) * (size_t)n * FL_COUNT, hipMemcpyDeviceToHost, stream));
     HCHECK(hipStreamSynchronize(stream));
     ring_reset();
+    flush_prof();
   }
 
   double max_res(int e) const {
@@ -320,6 +422,7 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   (void)hipHostFree(h->ring_h);
   (void)hipHostFree(h->h_resid);
   (void)hipHostFree(h->h_fl);
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   (void)hipSetDevice(cur);
   delete h;
@@ -415,7 +518,7 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       Elem& E = h->eh[e];
       size_t blk = align256(sizeof(double) * (size_t)E.ld * E.J);
       size_t nmax = 3 * (size_t)E.J;
-      size_t stride = std::max(nmax * nmax, 16 * nmax);
+      size_t stride = nmax * nmax + 64 * (size_t)E.J;
       size_t sz = blk * (NSLOT - 3) + align256(sizeof(double2) * (size_t)cdiv(E.J, 2) * E.ng) +
                   align256(sizeof(double) * E.ng) + align256(sizeof(double) * stride * SM_COUNT) +
                   align256(sizeof(double) * 2 * GRAM_MAXCHUNK * nmax * nmax);
@@ -832,6 +935,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   }
   h->per_elem_cols(all, 3, VS_X, 0, 0, eigvals, eigvecs);
   HCHECK(hipStreamSynchronize(s));
+  h->flush_prof();
   if (sig_tmp) (void)hipFree(sig_tmp);
   // ---- stats
   int any_nc = 0;
@@ -942,6 +1046,37 @@ int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R, cons
 
 }  // extern "C"
 
+extern "C" {
+
+int32_t dgdft_alb_profile(dgdft_alb* h, int32_t enable) {
+  if (!h) return DGDFT_EINVAL;
+  h->prof = enable != 0;
+  for (int k = 0; k < DGDFT_KCLASS_COUNT; ++k) {
+    h->k_n[k] = 0;
+    h->k_ms[k] = h->k_flops[k] = h->k_bytes[k] = 0.0;
+  }
+  return DGDFT_OK;
+}
+
+int32_t dgdft_alb_kernel_stats(const dgdft_alb* h, int32_t kclass, int64_t* launches, double* ms,
+                               double* flops, double* bytes) {
+  if (!h || kclass < 0 || kclass >= DGDFT_KCLASS_COUNT) return DGDFT_EINVAL;
+  if (launches) *launches = h->k_n[kclass];
+  if (ms) *ms = h->k_ms[kclass];
+  if (flops) *flops = h->k_flops[kclass];
+  if (bytes) *bytes = h->k_bytes[kclass];
+  return DGDFT_OK;
+}
+
+const char* dgdft_kernel_class_name(int32_t kclass) {
+  static const char* names[DGDFT_KCLASS_COUNT] = {
+      "dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
+      "dg_kb_project", "dg_resid", "dg_rr", "dg_cholqr", "other"};
+  return (kclass >= 0 && kclass < DGDFT_KCLASS_COUNT) ? names[kclass] : "";
+}
+
+}  // extern "C"
+
 // ----------------------------------------------------------- test entries
 namespace {
 struct TmpDev {
@@ -961,16 +1096,19 @@ struct TmpDev {
 extern "C" {
 
 int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A, double* w, double* Z,
-                         void* stream) {
-  if (count < 1 || n < 1 || n > 3072 || k < 1 || k > n || !A || !w || !Z) {
+                         int32_t method, void* stream) {
+  if (count < 1 || n < 1 || n > 3072 || k < 1 || k > n || !A || !w || !Z || method < 0 ||
+      method > 1) {
     g_create_error = "small_syev: bad arguments";
     return DGDFT_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
   try {
     TmpDev t;
-    double* work = t.alloc<double>((size_t)count * (2 * (size_t)n * n + 8 * (size_t)n));
-    hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work);
+    double* work = t.alloc<double>((size_t)count * (2 * (size_t)n * n + 8 * (size_t)n +
+                                                    6 * (size_t)n * k));
+    hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
+                       method);
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(s));
     return DGDFT_OK;

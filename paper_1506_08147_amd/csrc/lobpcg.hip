@@ -406,17 +406,24 @@ dg_check_finite(const double* __restrict__ a, long long n, int* flag) {
 namespace dg {
 // Batched symmetric eigensolver for tests: matrix b of A (n x n, upper
 // triangle read) -> w[b*n ..] ascending, Z[b*n*k ..] first k eigenvectors.
-// work: per matrix 2 n^2 + 8 n doubles.
+// method 0: Householder + bisection + inverse iteration (lowest k only);
+// method 1: Householder + implicit QL on the whole spectrum.
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
-dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, double* work) {
+dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, double* work,
+              int method) {
   __shared__ double red[32];
+  __shared__ double lds[8192];
   DevTeam t{red};
   long long b = blockIdx.x;
-  double* Aw = work + b * (2LL * n * n + 8LL * n);
+  double* Aw = work + b * (2LL * n * n + 8LL * n + 6LL * n * k);
   double* U = Aw + (long long)n * n;
   double* vec = U + (long long)n * n;
   copy_mat(t, A + b * n * n, n, Aw, n, n, n);
   sym_from_upper(t, Aw, n, n);
-  syev(t, Aw, n, n, w + b * n, Z + b * n * k, n, k, U, vec);
+  if (method == 1) {
+    syev(t, Aw, n, n, w + b * n, Z + b * n * k, n, k, U, vec);
+  } else {
+    syev_lowest(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, 8192);
+  }
 }
 }  // namespace dg

@@ -23,6 +23,7 @@
 namespace dg {
 
 struct HostTeam {
+  static constexpr bool is_device = false;
   double red[1];
   int tid() const { return 0; }
   int nt() const { return 1; }
@@ -32,6 +33,7 @@ struct HostTeam {
 };
 
 struct DevTeam {
+  static constexpr bool is_device = true;
   double* red;   // LDS scratch, >= 32 doubles
   __device__ int tid() const { return threadIdx.x; }
   __device__ int nt() const { return blockDim.x; }
@@ -337,6 +339,419 @@ __host__ __device__ int syev(T& t, double* A, int lda, int n, double* w, double*
     t.sync();
   }
   return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Faster pieces for the Rayleigh-Ritz step (lowest k of n eigenpairs).
+
+// C = alpha op(A) op(B) + beta C on the matrix cores: every wave owns 16 x 16
+// output tiles and stages 16 x 16 operand tiles through its own LDS region
+// (lds: 512 doubles per wave).  Host teams use the scalar product.
+typedef double dg_dbl4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__host__ __device__ void gemm_fast(T& t, int ta, int tb, int m, int n, int k, double alpha,
+                                   const double* A, int lda, const double* B, int ldb, double beta,
+                                   double* C, int ldc, double* lds) {
+  if constexpr (!T::is_device) {
+    gemm(t, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  } else {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double* As = lds + wv * 512;
+    double* Bs = As + 256;
+    const int ntm = (m + 15) / 16, ntn = (n + 15) / 16;
+    for (int tile = wv; tile < ntm * ntn; tile += nw) {
+      const int i0 = (tile % ntm) * 16, j0 = (tile / ntm) * 16;
+      dg_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < k; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int e = lane + 64 * q;
+          int a1 = e & 15, a2 = e >> 4;   // a1 fastest in memory
+          // A_op tile (ii, kk)
+          int ii = ta ? a2 : a1, kk = ta ? a1 : a2;
+          double av = 0.0;
+          if (i0 + ii < m && k0 + kk < k)
+            av = ta ? A[(long long)(k0 + kk) + (long long)lda * (i0 + ii)]
+                    : A[(long long)(i0 + ii) + (long long)lda * (k0 + kk)];
+          As[kk * 16 + ii] = av;
+          // B_op tile (kk, jj)
+          int jj = tb ? a1 : a2, kb = tb ? a2 : a1;
+          double bv = 0.0;
+          if (j0 + jj < n && k0 + kb < k)
+            bv = tb ? B[(long long)(j0 + jj) + (long long)ldb * (k0 + kb)]
+                    : B[(long long)(k0 + kb) + (long long)ldb * (j0 + jj)];
+          Bs[kb * 16 + jj] = bv;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          double a = As[(ks * 4 + (lane >> 4)) * 16 + (lane & 15)];
+          double b = Bs[(ks * 4 + (lane >> 4)) * 16 + (lane & 15)];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + 4 * r + (lane >> 4), j = j0 + (lane & 15);
+        if (i < m && j < n) {
+          double* c = &IDX(C, ldc, i, j);
+          *c = alpha * acc[r] + (beta != 0.0 ? beta * *c : 0.0);
+        }
+      }
+    }
+    __syncthreads();
+#endif
+  }
+}
+
+// Householder tridiagonalisation reading and updating only the lower
+// triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
+// scratch of n doubles each (LDS on the device).
+template <class T>
+__host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
+                                              double* tau, double* v, double* p) {
+  const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double part = 0.0;
+    for (int i = k + 2 + t.tid(); i < n; i += t.nt()) part += IDX(A, lda, i, k) * IDX(A, lda, i, k);
+    double a2 = t.sum(part);
+    double x0 = IDX(A, lda, k + 1, k);
+    if (a2 == 0.0) {
+      if (t.tid() == 0) { e[k] = x0; tau[k] = 0.0; }
+      t.sync();
+      continue;
+    }
+    double nrm = sqrt(x0 * x0 + a2);
+    double beta = (x0 >= 0.0) ? -nrm : nrm;
+    double v0 = x0 - beta;
+    double tk = 2.0 / (v0 * v0 + a2);
+    for (int i = t.tid(); i < m; i += t.nt()) v[i] = (i == 0) ? v0 : IDX(A, lda, k + 1 + i, k);
+    t.sync();
+    if (t.tid() == 0) { IDX(A, lda, k + 1, k) = v0; e[k] = beta; tau[k] = tk; }
+    // p = A2 v with A2 the trailing block, lower triangle stored:
+    //   rows:    sum_{j <= i} A2[i][j] v[j]       (thread per row, coalesced)
+    for (int i = t.tid(); i < m; i += t.nt()) {
+      double s = 0.0;
+      for (int j = 0; j <= i; ++j) s += IDX(A, lda, k + 1 + i, k + 1 + j) * v[j];
+      p[i] = s;
+    }
+    t.sync();
+    //   columns: sum_{j > i} A2[j][i] v[j]        (wave per column, coalesced)
+    if constexpr (T::is_device) {
+      for (int i = wv; i < m; i += nw) {
+        double s = 0.0;
+        for (int j = i + 1 + lane; j < m; j += 64) s += IDX(A, lda, k + 1 + j, k + 1 + i) * v[j];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) p[i] += s;
+      }
+    } else {
+      for (int i = 0; i < m; ++i)
+        for (int j = i + 1; j < m; ++j) p[i] += IDX(A, lda, k + 1 + j, k + 1 + i) * v[j];
+    }
+    t.sync();
+    double vp = 0.0;
+    for (int i = t.tid(); i < m; i += t.nt()) { p[i] *= tk; vp += v[i] * p[i]; }
+    double K = 0.5 * tk * t.sum(vp);
+    for (int i = t.tid(); i < m; i += t.nt()) p[i] -= K * v[i];   // p := q
+    t.sync();
+    // lower-triangle rank-2 update, wave per column
+    if constexpr (T::is_device) {
+      for (int j = wv; j < m; j += nw) {
+        double vj = v[j], qj = p[j];
+        for (int i = j + lane; i < m; i += 64)
+          IDX(A, lda, k + 1 + i, k + 1 + j) -= v[i] * qj + p[i] * vj;
+      }
+    } else {
+      for (int j = 0; j < m; ++j)
+        for (int i = j; i < m; ++i) IDX(A, lda, k + 1 + i, k + 1 + j) -= v[i] * p[j] + p[i] * v[j];
+    }
+    t.sync();
+  }
+  for (int i = t.tid(); i < n; i += t.nt()) d[i] = IDX(A, lda, i, i);
+  if (t.tid() == 0) {
+    if (n >= 2) e[n - 2] = IDX(A, lda, n - 1, n - 2);
+    if (n >= 1) e[n - 1] = 0.0;
+    if (n >= 2) tau[n - 2] = 0.0;
+  }
+  t.sync();
+}
+
+// Number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence of
+// the LDL^T factorisation of T - x I).
+__host__ __device__ inline int sturm_count(const double* d, const double* e, int n, double x,
+                                           double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// Counter-based pseudo-random start value in [-1, 1) (splitmix64 of a counter).
+__host__ __device__ inline double start_value(unsigned long long c) {
+  unsigned long long z = c + 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Lowest k eigenpairs of the symmetric tridiagonal (d, e): eigenvalues by
+// bisection (one thread per eigenvalue), eigenvectors by inverse iteration
+// with partial-pivoting LU of T - lambda I (one thread per vector), then
+// Gram-Schmidt inside clusters of eigenvalues closer than 1e-5 ||T||.
+// w[0..k) ascending, Y (n x k, ldy).  work: 6 n k doubles (interleaved).
+template <class T>
+__host__ __device__ void tridiag_lowest(T& t, const double* d, const double* e, int n, int k,
+                                        double* w, double* Y, int ldy, double* work, int* cl) {
+  // Gershgorin interval and scale
+  double gl = 1e300, gu = -1e300, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+    if (i < n - 1) emax2 = fmax(emax2, e[i] * e[i]);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = fmax(1e-290, 1e-290 * emax2);
+  gl -= 2.0 * eps * tnorm * n + pivmin;
+  gu += 2.0 * eps * tnorm * n + pivmin;
+  for (int j = t.tid(); j < k; j += t.nt()) {
+    double lo = gl, hi = gu;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
+      if (sturm_count(d, e, n, mid, pivmin) <= j) lo = mid; else hi = mid;
+    }
+    w[j] = 0.5 * (lo + hi);
+  }
+  t.sync();
+  // inverse iteration, work interleaved: element i of thread j at i*k + j
+  for (int j = t.tid(); j < k; j += t.nt()) {
+    double* dd = work;
+    double* du = work + (long long)n * k;
+    double* du2 = work + 2LL * n * k;
+    double* dl = work + 3LL * n * k;
+    double* x = work + 4LL * n * k;
+    double* piv = work + 5LL * n * k;   // 0: no swap, 1: swap
+#define W(a, i) a[(long long)(i) * k + j]
+    const double lam = w[j];
+    const double tiny = eps * tnorm + 1e-290;
+    // LU with partial pivoting of T - lam I (LAPACK gttrf layout)
+    for (int i = 0; i < n; ++i) {
+      W(dd, i) = d[i] - lam;
+      if (i < n - 1) { W(du, i) = e[i]; W(dl, i) = e[i]; }
+      if (i < n - 2) W(du2, i) = 0.0;
+    }
+    for (int i = 0; i < n - 1; ++i) {
+      double a = W(dd, i), b = W(dl, i);
+      if (fabs(a) >= fabs(b)) {
+        if (a == 0.0) { a = tiny; W(dd, i) = a; }
+        double f = b / a;
+        W(dl, i) = f;
+        W(dd, i + 1) -= f * W(du, i);
+        W(piv, i) = 0.0;
+      } else {
+        double f = a / b;
+        W(dd, i) = b;
+        W(dl, i) = f;
+        double tmp = W(du, i);
+        W(du, i) = W(dd, i + 1);
+        W(dd, i + 1) = tmp - f * W(dd, i + 1);
+        if (i < n - 2) {
+          W(du2, i) = W(du, i + 1);
+          W(du, i + 1) = -f * W(du, i + 1);
+        }
+        W(piv, i) = 1.0;
+      }
+    }
+    if (W(dd, n - 1) == 0.0) W(dd, n - 1) = tiny;
+    for (int i = 0; i < n; ++i) W(x, i) = start_value(((unsigned long long)j << 32) + i);
+    for (int it = 0; it < 3; ++it) {
+      // forward: L with row interchanges
+      for (int i = 0; i < n - 1; ++i) {
+        if (W(piv, i) == 0.0) {
+          W(x, i + 1) -= W(dl, i) * W(x, i);
+        } else {
+          double tmp = W(x, i);
+          W(x, i) = W(x, i + 1);
+          W(x, i + 1) = tmp - W(dl, i) * W(x, i);
+        }
+      }
+      // backward: U with two superdiagonals
+      double s = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        double v = W(x, i);
+        if (i + 1 < n) v -= W(du, i) * W(x, i + 1);
+        if (i + 2 < n) v -= W(du2, i) * W(x, i + 2);
+        double di = W(dd, i);
+        if (fabs(di) < tiny) di = di < 0 ? -tiny : tiny;
+        v /= di;
+        W(x, i) = v;
+        s = fmax(s, fabs(v));
+      }
+      double nr = 0.0;
+      for (int i = 0; i < n; ++i) { W(x, i) /= s; nr += W(x, i) * W(x, i); }
+      nr = 1.0 / sqrt(nr);
+      for (int i = 0; i < n; ++i) W(x, i) *= nr;
+    }
+    for (int i = 0; i < n; ++i) IDX(Y, ldy, i, j) = W(x, i);
+#undef W
+  }
+  t.sync();
+  // clusters: cl[j] = first index of the cluster containing j
+  if (t.tid() == 0) {
+    int c0 = 0;
+    for (int j = 0; j < k; ++j) {
+      if (j > 0 && w[j] - w[j - 1] > 1e-5 * tnorm) c0 = j;
+      cl[j] = c0;
+    }
+  }
+  t.sync();
+  // modified Gram-Schmidt inside each cluster: one wave per cluster on the
+  // device, columns in index order
+  if constexpr (T::is_device) {
+    const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+    int cidx = 0;
+    for (int j = 0; j < k; ++j) {
+      if (cl[j] != j) continue;
+      int jend = j + 1;
+      while (jend < k && cl[jend] == j) ++jend;
+      if (jend - j > 1 && (cidx++ % nw) == wv) {
+        for (int a = j; a < jend; ++a) {
+          for (int b = j; b < a; ++b) {
+            double s = 0.0;
+            for (int i = lane; i < n; i += 64) s += IDX(Y, ldy, i, a) * IDX(Y, ldy, i, b);
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            for (int i = lane; i < n; i += 64) IDX(Y, ldy, i, a) -= s * IDX(Y, ldy, i, b);
+          }
+          double s = 0.0;
+          for (int i = lane; i < n; i += 64) s += IDX(Y, ldy, i, a) * IDX(Y, ldy, i, a);
+          for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+          s = 1.0 / sqrt(s);
+          for (int i = lane; i < n; i += 64) IDX(Y, ldy, i, a) *= s;
+        }
+      }
+    }
+  } else {
+    for (int a = 0; a < k; ++a) {
+      for (int b = cl[a]; b < a; ++b) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += IDX(Y, ldy, i, a) * IDX(Y, ldy, i, b);
+        for (int i = 0; i < n; ++i) IDX(Y, ldy, i, a) -= s * IDX(Y, ldy, i, b);
+      }
+      if (cl[a] != a || (a + 1 < k && cl[a + 1] == a)) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += IDX(Y, ldy, i, a) * IDX(Y, ldy, i, a);
+        s = 1.0 / sqrt(s);
+        for (int i = 0; i < n; ++i) IDX(Y, ldy, i, a) *= s;
+      }
+    }
+  }
+  t.sync();
+}
+
+// Z <- H_0 H_1 ... H_{n-3} Z for the reflectors left by the tridiagonalisation
+// (Z is n x k).  Reflectors go through LDS in blocks; on the device each wave
+// holds one column of Z in registers while it applies a block (n <= 768).
+template <class T>
+__host__ __device__ void backtransform(T& t, const double* A, int lda, const double* tau, int n,
+                                       double* Z, int ldz, int k, double* lds, int lds_size) {
+  constexpr int MAXR = 12;   // column entries per lane: n <= 64 * MAXR
+  if constexpr (T::is_device) {
+    if (n <= 64 * MAXR) {
+      const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+      int NB = lds_size / n;
+      NB = NB > 16 ? 16 : NB;
+      for (int kb = n - 3; kb >= 0; kb -= NB) {
+        int kl = kb - NB + 1 > 0 ? kb - NB + 1 : 0;   // reflectors kb, kb-1, ..., kl
+        // stage reflectors: lds[(kk - kl) * n + i] = v_kk[i] (zero above k+1)
+        for (int q = t.tid(); q < (kb - kl + 1) * n; q += t.nt()) {
+          int kk = kl + q / n, i = q % n;
+          lds[q] = (i >= kk + 1) ? A[(long long)i + (long long)lda * kk] : 0.0;
+        }
+        t.sync();
+        for (int j = wv; j < k; j += nw) {
+          double z[MAXR];
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) {
+            int i = lane + 64 * r;
+            z[r] = i < n ? Z[(long long)i + (long long)ldz * j] : 0.0;
+          }
+          for (int kk = kb; kk >= kl; --kk) {
+            double tk = tau[kk];
+            if (tk == 0.0) continue;
+            const double* v = lds + (kk - kl) * n;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+              int i = lane + 64 * r;
+              if (i < n) s += v[i] * z[r];
+            }
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            s *= tk;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+              int i = lane + 64 * r;
+              if (i < n) z[r] -= s * v[i];
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) {
+            int i = lane + 64 * r;
+            if (i < n) Z[(long long)i + (long long)ldz * j] = z[r];
+          }
+        }
+        t.sync();
+      }
+      return;
+    }
+  }
+  // generic path
+  double* cs = lds;
+  for (int kk = n - 3; kk >= 0; --kk) {
+    double tk = tau[kk];
+    if (tk == 0.0) continue;
+    const double* v = &IDX(A, lda, kk + 1, kk);
+    int m = n - kk - 1;
+    for (int j = t.tid(); j < k; j += t.nt()) {
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += v[i] * IDX(Z, ldz, kk + 1 + i, j);
+      cs[j] = tk * s;
+    }
+    t.sync();
+    for (int q = t.tid(); q < m * k; q += t.nt()) {
+      int i = q % m, j = q / m;
+      IDX(Z, ldz, kk + 1 + i, j) -= v[i] * cs[j];
+    }
+    t.sync();
+  }
+}
+
+// Lowest k eigenpairs of the symmetric A (lower triangle read, destroyed):
+// w[0..k) ascending, Z (n x k).  work: 9 n + 6 n k doubles; cl: k ints
+// (global); lds: >= 2n doubles (and >= k for the generic back-transform).
+template <class T>
+__host__ __device__ void syev_lowest(T& t, double* A, int lda, int n, int k, double* w, double* Z,
+                                     int ldz, double* work, int* cl, double* lds, int lds_size) {
+  double* d = work;
+  double* e = work + n;
+  double* tau = work + 2 * n;
+  tridiagonalize_lower(t, A, lda, n, d, e, tau, lds, lds + n);
+  tridiag_lowest(t, d, e, n, k, w, Z, ldz, work + 3 * n, cl);
+  backtransform(t, A, lda, tau, n, Z, ldz, k, lds, lds_size);
 }
 
 }  // namespace dg
