@@ -21,7 +21,7 @@ EXPORTS = (
     "dgdft_alb_kernel_stats", "dgdft_kernel_class_name",
 )
 KCLASS = ("dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
-          "dg_kb_project", "dg_resid", "dg_rr", "dg_cholqr", "other")
+          "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other")
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM",
           -4: "EHIP", -5: "EBREAKDOWN"}

@@ -69,6 +69,7 @@ enum Flag {
   FL_BREAKDOWN,       // unrecoverable rank deficiency
   FL_QL_FAIL,         // tridiagonal QL did not converge
   FL_NONFINITE,       // non-finite input seen
+  FL_RR_PATH,         // 0: Rayleigh-Ritz via Cholesky of M, 1: eigenvector reduction
   FL_COUNT = 10
 };
 

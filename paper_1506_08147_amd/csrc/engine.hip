@@ -325,7 +325,11 @@ struct dgdft_alb {
         hipLaunchKernelGGL(dg_cholqr, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
         break;
       case 1:
-        hipLaunchKernelGGL(dg_rr, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
+        hipLaunchKernelGGL(dg_rr_reduce, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na,
+                           arg);
+        hipLaunchKernelGGL(dg_rr_eig, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
+        hipLaunchKernelGGL(dg_rr_finish, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na,
+                           arg);
         break;
       case 2:
         hipLaunchKernelGGL(dg_teter_energy, dim3(P.na), dim3(256), 0, stream, ed, P.active, P.na);
@@ -1071,7 +1075,7 @@ int32_t dgdft_alb_kernel_stats(const dgdft_alb* h, int32_t kclass, int64_t* laun
 const char* dgdft_kernel_class_name(int32_t kclass) {
   static const char* names[DGDFT_KCLASS_COUNT] = {
       "dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
-      "dg_kb_project", "dg_resid", "dg_rr", "dg_cholqr", "other"};
+      "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other"};
   return (kclass >= 0 && kclass < DGDFT_KCLASS_COUNT) ? names[kclass] : "";
 }
 

@@ -137,8 +137,14 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
 // coefficients C (n x J) into SM_C[:, 0:J] and, for k > 1, the next search
 // direction D (n x J) into SM_C[:, J:2J]: the part of S [0; C_P; C_W] that is
 // M-orthogonal to S C, normalised through a scaled Cholesky of its M-Gram.
+//
+// Three launches per step: dg_rr_reduce forms A = L^-1 D^-1 Hh D^-1 L^-T from
+// a Cholesky factor of the scaled M (or, if M is not numerically SPD,
+// finishes the whole step through an eigenvector-based reduction);
+// dg_rr_eig finds the lowest J eigenpairs of A (Householder, bisection,
+// inverse iteration); dg_rr_finish forms C and the next search direction.
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
-dg_rr(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   __shared__ double red[32];
   DevTeam t{red};
   const Elem& e = E[active[blockIdx.x]];
@@ -176,12 +182,8 @@ dg_rr(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) 
     tri_inv_lower(t, Lm, n, Tm, n, n);                    // Tm = L^-1 (lower)
     gemm(t, 0, 0, n, n, n, 1.0, Tm, n, A, n, 0.0, U, n);  // U = L^-1 A
     gemm(t, 0, 1, n, n, n, 1.0, U, n, Tm, n, 0.0, A, n);  // A = U L^-T
-    int qok = syev(t, A, n, n, w, Z, n, J, U, vec);
-    if (!qok && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
-    // C = D^-1 L^-T Y
-    gemm(t, 1, 0, n, J, n, 1.0, Tm, n, Z, n, 0.0, Cm, n);
-    for (int p = t.tid(); p < n * J; p += t.nt()) Cm[p] /= dm[p % n];
-    t.sync();
+    if (t.tid() == 0) e.fl[FL_RR_PATH] = 0;
+    return;
   } else {
     if (t.tid() == 0) e.fl[FL_RR_FALLBACK] += 1;
     // reduce to the eigenvectors of D^-1 M D^-1 above CHOL_TOL * max
@@ -218,6 +220,54 @@ dg_rr(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) 
     gemm(t, 0, 0, n, J, nk, 1.0, Tm, n, Z, nk, 0.0, Cm, n);   // C = T Y
   }
   for (int j = t.tid(); j < J; j += t.nt()) e.theta[j] = w[j];
+  if (t.tid() == 0) e.fl[FL_RR_PATH] = 1;
+}
+
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  __shared__ double lds[8192];
+  DevTeam t{red};
+  const Elem& e = E[active[blockIdx.x]];
+  if (e.fl[FL_RR_PATH] != 0) return;
+  const int J = e.J;
+  const int kb = single ? 1 : (has_p(e) ? 3 : 2);
+  const int n = kb * J;
+  double* A = sm(e, SM_A);
+  double* Z = sm(e, SM_Z);
+  double* vec = sm(e, SM_V);
+  double* w = vec + 7 * n;
+  // workspace: SM_U and SM_L (consecutive), free after the reduction
+  syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_U), (int*)(vec + 10 * n), lds, 8192);
+}
+
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_rr_finish(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  const Elem& e = E[active[blockIdx.x]];
+  const int J = e.J;
+  const int kb = single ? 1 : (has_p(e) ? 3 : 2);
+  const int n = kb * J;
+  double* H = sm(e, SM_H);
+  double* M = sm(e, SM_M);
+  double* A = sm(e, SM_A);
+  double* Lm = sm(e, SM_L);
+  double* U = sm(e, SM_U);
+  double* Cm = sm(e, SM_C);
+  double* Tm = sm(e, SM_T);
+  double* Z = sm(e, SM_Z);
+  double* vec = sm(e, SM_V);
+  double* dm = vec + 6 * n;
+  double* w = vec + 7 * n;
+  if (e.fl[FL_RR_PATH] == 0) {
+    // C = D^-1 L^-T Y
+    gemm(t, 1, 0, n, J, n, 1.0, Tm, n, Z, n, 0.0, Cm, n);
+    for (int p = t.tid(); p < n * J; p += t.nt()) Cm[p] /= dm[p % n];
+    t.sync();
+    for (int j = t.tid(); j < J; j += t.nt()) e.theta[j] = w[j];
+  }
+  t.sync();
   t.sync();
   if (kb == 1) {
     if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 0;
