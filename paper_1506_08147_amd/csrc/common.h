@@ -157,7 +157,7 @@ __device__ inline int find_elem(const int* __restrict__ prefix, int na, int b) {
 }
 
 // ---- work decomposition shared by host (counts) and device (decode) ----
-constexpr int GT = 64;            // GEMM tile edge (rows and columns)
+constexpr int GT = 128;           // GEMM workgroup tile edge (rows and columns)
 constexpr int GRAM_MAXCHUNK = 8;
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }

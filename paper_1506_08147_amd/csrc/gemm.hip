@@ -4,7 +4,7 @@
 // with a small C (operation 3); the paper distributes them by row blocks and
 // sums the J x J partial products with MPI_Allreduce.  On one GPU the same
 // split appears as split-K: each workgroup reduces one chunk of the N_g rows
-// into a 64 x 64 tile, and a second kernel sums the chunks in a fixed order
+// into a 128 x 128 tile, and a second kernel sums the chunks in a fixed order
 // (deterministic, no atomics).
 //
 //   dg_gram       partial C = A^T B over one K chunk, A and B virtual
@@ -45,13 +45,23 @@ struct UpdArgs {
 
 __device__ __forceinline__ int rowsK(const Elem& e, int use_ne) { return use_ne ? e.ne : e.ng; }
 
-constexpr int LDSP = GT + 1;   // padded row of a 16 x 64 LDS tile
+// Both products use 128 x 128 workgroup tiles: four waves, each owning a
+// 64 x 64 sub-tile (4 x 4 MFMA blocks, 64 FP64 accumulators per lane).  The
+// K loop runs in stages of 16: operands of stage s+1 are loaded from global
+// memory into registers while stage s is multiplied out of LDS (double
+// buffered, one barrier per stage).  Column pointers of the block operands
+// are resolved once per workgroup into an LDS table.
+constexpr int TT = 128;        // workgroup tile edge
+constexpr int KS = 16;         // K stage
+constexpr int LP = TT + 4;     // padded LDS row (doubles)
 
 extern "C" __global__ void __launch_bounds__(256)
 dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
         int na, GramArgs g) {
-  __shared__ double As[16 * LDSP];
-  __shared__ double Bs[16 * LDSP];
+  __shared__ double As[2][KS * LP];
+  __shared__ double Bs[2][KS * LP];
+  __shared__ const double* colA[TT];
+  __shared__ const double* colB[TT];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
   const Elem& e = E[active[ai]];
@@ -74,57 +84,78 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   gram_tile_decode(tile, m, n, g.upper, &ti, &tj);
   const int kbeg = chunk * clen;
   const int kend = min(K, kbeg + clen);
-
-  // each thread loads 4 (k, col) entries of each tile: col = tid/16 + 16u, k = tid%16
-  const int tk = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  const double* pa[4];
-  const double* pb[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    int ca = ti * GT + tc + 16 * u, cb = tj * GT + tc + 16 * u;
-    pa[u] = ca < m ? opnd_col(g.A, e, ca) : nullptr;
-    pb[u] = cb < n ? opnd_col(B, e, cb) : nullptr;
+  const int tid = threadIdx.x;
+  if (tid < TT) {
+    int c = ti * TT + tid;
+    colA[tid] = c < m ? opnd_col(g.A, e, c) : nullptr;
+  } else {
+    int c = tj * TT + tid - TT;
+    colB[tid - TT] = c < n ? opnd_col(B, e, c) : nullptr;
   }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wi = wv & 1, wj = wv >> 1;
-  dbl4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
-
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    int k = k0 + tk;
+  __syncthreads();
+  // stage loads: k = tid % 16, columns tid/16 + 16u (u < 8)
+  const int lk = tid & 15, lc = tid >> 4;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+    int k = k0 + lk;
     bool kin = k < kend;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      As[tk * LDSP + tc + 16 * u] = (kin && pa[u]) ? pa[u][k] : 0.0;
-      Bs[tk * LDSP + tc + 16 * u] = (kin && pb[u]) ? pb[u][k] : 0.0;
+    for (int u = 0; u < 8; ++u) {
+      const double* pa = colA[lc + 16 * u];
+      const double* pb = colB[lc + 16 * u];
+      ra[u] = (kin && pa) ? pa[k] : 0.0;
+      rb[u] = (kin && pb) ? pb[k] : 0.0;
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      As[buf][lk * LP + lc + 16 * u] = ra[u];
+      Bs[buf][lk * LP + lc + 16 * u] = rb[u];
+    }
+  };
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wi = wv & 1, wj = wv >> 1;
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const int nst = (kend - kbeg + KS - 1) / KS;
+  if (nst > 0) {
+    load(kbeg);
+    store(0);
     __syncthreads();
+  }
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load(kbeg + (st + 1) * KS);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      int kk = ks * 4 + (lane >> 4);
-      double a0 = As[kk * LDSP + wi * 32 + (lane & 15)];
-      double a1 = As[kk * LDSP + wi * 32 + 16 + (lane & 15)];
-      double b0 = Bs[kk * LDSP + wj * 32 + (lane & 15)];
-      double b1 = Bs[kk * LDSP + wj * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      const int kk = ks * 4 + (lane >> 4);
+      double fa[4], fb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa[a] = As[cur][kk * LP + wi * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fb[c] = Bs[cur][kk * LP + wj * 64 + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
     }
+    if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
   }
   double* part = e.gpart + (job ? (long long)nch * m * n0 : 0LL) + (long long)chunk * m * n;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = ti * GT + wi * 32 + a * 16 + 4 * r + (lane >> 4);
-        int j = tj * GT + wj * 32 + c * 16 + (lane & 15);
+        int i = ti * TT + wi * 64 + a * 16 + 4 * r + (lane >> 4);
+        int j = tj * TT + wj * 64 + c * 16 + (lane & 15);
         if (i < m && j < n) part[i + (long long)m * j] = acc[a][c][r];
       }
 }
@@ -156,12 +187,17 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
 
 // Y (K x ncol) = alpha A (K x kA) C (kA x ncol) + beta Y.  Computed as the
 // transposed product so that lanes 0..15 of an accumulator own consecutive
-// rows of Y (coalesced stores).  Work item (job, row tile, column tile).
+// rows of Y (coalesced stores).  Work item (job, row tile, column tile) with
+// 128 x 128 tiles; kA <= UPD_MAXK.
+constexpr int UPD_MAXK = 3 * 1024;
+
 extern "C" __global__ void __launch_bounds__(256)
 dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
           int na, UpdArgs u) {
-  __shared__ double As[16 * LDSP];
-  __shared__ double Cs[16 * LDSP];
+  __shared__ double As[2][KS * LP];
+  __shared__ double Cs[2][KS * LP];
+  __shared__ double* colY[TT];
+  __shared__ const double* colA[UPD_MAXK];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
   const Elem& e = E[active[ai]];
@@ -169,63 +205,82 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   const int K = rowsK(e, u.use_ne);
   const int kA = opnd_cols(u.A[0], e);
   const int ncol = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? e.nalb : opnd_cols(u.Y[0], e));
-  const int ntr = cdiv(K, GT), ntc = cdiv(ncol, GT);
+  const int ntr = cdiv(K, TT), ntc = cdiv(ncol, TT);
   int job = w / (ntr * ntc);
   w -= job * ntr * ntc;
   int tr = w / ntc, tc = w - tr * ntc;
   const Opnd& A = u.A[job];
   const Opnd& Y = u.Y[job];
   const double* C = sm(e, u.cmat) + (long long)u.ccol0 * kA;
-  const int row0 = tr * GT, col0 = tc * GT;
-
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wj = wv & 1, wr = wv >> 1;
-  // A tile load: row = tid % 64, k = tid / 64 + 4u
-  const int lr = threadIdx.x & 63, lk = threadIdx.x >> 6;
-  // C tile load: j = tid / 16 + 16u, k = tid % 16
-  const int ck = threadIdx.x & 15, cj = threadIdx.x >> 4;
-  dbl4 acc[2][2];
+  const int row0 = tr * TT, col0 = tc * TT;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < kA; k += 256) colA[k] = opnd_col(A, e, k);
+  if (tid < TT) colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
+  __syncthreads();
+  // A stage: row = tid % 128, k = tid / 128 + 2u (u < 8)
+  const int ar = tid & 127, ak = tid >> 7;
+  // C stage: k = tid % 16, j = tid / 16 + 16u (u < 8)
+  const int ck = tid & 15, cj = tid >> 4;
+  const bool rin = row0 + ar < K;
+  double ra[8], rc[8];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  const bool rin = row0 + lr < K;
-  for (int k0 = 0; k0 < kA; k0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int k = k0 + lk + 4 * q;
-      double v = 0.0;
-      if (k < kA && rin) v = opnd_col(A, e, k)[row0 + lr];
-      As[(lk + 4 * q) * LDSP + lr] = v;
+    for (int q = 0; q < 8; ++q) {
+      int k = k0 + ak + 2 * q;
+      ra[q] = (k < kA && rin) ? colA[k][row0 + ar] : 0.0;
       int j = col0 + cj + 16 * q;
       int kc = k0 + ck;
-      Cs[ck * LDSP + cj + 16 * q] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
+      rc[q] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      As[buf][(ak + 2 * q) * LP + ar] = ra[q];
+      Cs[buf][ck * LP + cj + 16 * q] = rc[q];
+    }
+  };
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wj = wv & 1, wr = wv >> 1;
+  dbl4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const int nst = cdiv(kA, KS);
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load((st + 1) * KS);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      int kk = ks * 4 + (lane >> 4);
-      double c0 = Cs[kk * LDSP + wj * 32 + (lane & 15)];
-      double c1 = Cs[kk * LDSP + wj * 32 + 16 + (lane & 15)];
-      double a0 = As[kk * LDSP + wr * 32 + (lane & 15)];
-      double a1 = As[kk * LDSP + wr * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(c0, a0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(c0, a1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(c1, a0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(c1, a1, acc[1][1], 0, 0, 0);
+      const int kk = ks * 4 + (lane >> 4);
+      double fc[4], fa[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fc[a] = Cs[cur][kk * LP + wj * 64 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fa[c] = As[cur][kk * LP + wr * 64 + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc[a], fa[c], acc[a][c], 0, 0, 0);
     }
+    if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int j = col0 + wj * 32 + a * 16 + 4 * r + (lane >> 4);
-      if (j >= ncol) continue;
-      double* y = opnd_col(Y, e, j);
+      int jl = wj * 64 + a * 16 + 4 * r + (lane >> 4);
+      double* y = colY[jl];
+      if (!y) continue;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        int row = row0 + wr * 32 + c * 16 + (lane & 15);
+      for (int c = 0; c < 4; ++c) {
+        int row = row0 + wr * 64 + c * 16 + (lane & 15);
         if (row < K) {
           double v = u.alpha * acc[a][c][r];
           if (u.beta != 0.0) v += u.beta * y[row];
