@@ -160,6 +160,12 @@ struct dgdft_alb {
   int hasP_host(int e) const { return h_fl[(size_t)e * FL_COUNT + FL_HASP]; }
 
   // -------------------------------------------------------------- launches
+  bool big_planes(const std::vector<int>& act) const {
+    for (int e : act)
+      if (eh[e].n1 * eh[e].n2 > FFT_XY_SMALL) return true;
+    return false;
+  }
+
   void op_apply(const std::vector<int>& act, int in_slot, int out_slot, int col0, int ncols_fixed) {
     // ncols_fixed < 0: all J columns
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
@@ -167,9 +173,10 @@ struct dgdft_alb {
     auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
     double pts = 0;   // grid points x column pairs
     for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
+    const bool big = big_planes(act);
     pbeg(DGDFT_K_FFT_XY_FWD, 0, 32.0 * pts);
-    hipLaunchKernelGGL(dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
-                       P1.prefix, P1.na, in_slot, col0, ncols_fixed);
+    hipLaunchKernelGGL(big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0,
+                       stream, ed, P1.active, P1.prefix, P1.na, in_slot, col0, ncols_fixed);
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
@@ -177,8 +184,8 @@ struct dgdft_alb {
                        P2.prefix, P2.na, col0, ncols_fixed, 0);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, 56.0 * pts);
-    hipLaunchKernelGGL(dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
-                       P1.prefix, P1.na, in_slot, out_slot, col0, ncols_fixed, 0);
+    hipLaunchKernelGGL(big ? dg_fft_xy_inv_l : dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0,
+                       stream, ed, P1.active, P1.prefix, P1.na, in_slot, out_slot, col0, ncols_fixed, 0);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -199,9 +206,10 @@ struct dgdft_alb {
     auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
     double pts = 0;
     for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
+    const bool big = big_planes(act);
     pbeg(DGDFT_K_FFT_XY_FWD, 0, 32.0 * pts);
-    hipLaunchKernelGGL(dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
-                       P1.prefix, P1.na, slot, col0, ncols_fixed);
+    hipLaunchKernelGGL(big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0,
+                       stream, ed, P1.active, P1.prefix, P1.na, slot, col0, ncols_fixed);
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
@@ -209,8 +217,8 @@ struct dgdft_alb {
                        P2.prefix, P2.na, col0, ncols_fixed, opts.precond == DGDFT_PRECOND_NONE ? 2 : 1);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, 32.0 * pts);
-    hipLaunchKernelGGL(dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active,
-                       P1.prefix, P1.na, slot, slot, col0, ncols_fixed, 1);
+    hipLaunchKernelGGL(big ? dg_fft_xy_inv_l : dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0,
+                       stream, ed, P1.active, P1.prefix, P1.na, slot, slot, col0, ncols_fixed, 1);
     pend();
     HCHECK(hipGetLastError());
   }

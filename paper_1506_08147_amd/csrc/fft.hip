@@ -24,9 +24,16 @@
 
 namespace dg {
 
-constexpr int FFT_THREADS = 256;
-constexpr int FFT_MAXPTS = 6144;        // points of one LDS tile (96 KiB)
-constexpr int FFT_PTS_PER_THREAD = FFT_MAXPTS / FFT_THREADS;   // 24
+constexpr int FFT_THREADS = 512;
+constexpr int FFT_MAXPTS = 4608;        // largest LDS tile (72 KiB): z pencils of a row pair
+constexpr int FFT_XY_SMALL = 2304;      // xy planes up to 48 x 48 use a 36 KiB tile
+
+// Exact division of small unsigned values (b * d < 2^32) by a multiply-high
+// with m = floor((2^32 - 1) / d) + 1; d == 1 handled apart.
+__device__ __forceinline__ unsigned div_magic(unsigned d) { return d == 1u ? 0u : 0xFFFFFFFFu / d + 1u; }
+__device__ __forceinline__ unsigned fdiv(unsigned b, unsigned d, unsigned m) {
+  return d == 1u ? b : __umulhi(b, m);
+}
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -83,18 +90,21 @@ template <> __device__ __forceinline__ void dft<5>(double2* v, double sgn) {
 
 // One Stockham stage of radix R on `nlines` lines of length n stored in LDS
 // at buf[line*lstride + m*estride].  Ns = product of the radices done so far.
-template <int R>
+// MAXPTS bounds the points of the tile, so the register staging is sized at
+// compile time.
+template <int R, int MAXPTS>
 __device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstride, int estride,
                                       int Ns, const double2* __restrict__ tw, double sgn) {
-  constexpr int MAXK = (FFT_MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
-  const int nb = n / R;
-  const int total = nb * nlines;
+  constexpr int MAXK = (MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
+  const unsigned nb = n / R;
+  const unsigned total = nb * nlines;
+  const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
   double2 v[MAXK][R];
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
-    int b = threadIdx.x + q * FFT_THREADS;
+    unsigned b = threadIdx.x + q * FFT_THREADS;
     if (b < total) {
-      int line = b / nb, j = b - line * nb;
+      unsigned line = fdiv(b, nb, m_nb), j = b - line * nb;
       int base = line * lstride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = buf[base + (j + r * nb) * estride];
@@ -104,10 +114,11 @@ __device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstri
   const int step = n / (Ns * R);
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
-    int b = threadIdx.x + q * FFT_THREADS;
+    unsigned b = threadIdx.x + q * FFT_THREADS;
     if (b < total) {
-      int line = b / nb, j = b - line * nb;
-      int k = j % Ns;
+      unsigned line = fdiv(b, nb, m_nb), j = b - line * nb;
+      unsigned jq = fdiv(j, Ns, m_ns);
+      int k = j - jq * Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         double2 w = tw[k * r * step];
@@ -115,7 +126,7 @@ __device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstri
         v[q][r] = cmul(v[q][r], w);
       }
       dft<R>(v[q], sgn);
-      int o = (j / Ns) * Ns * R + k;
+      int o = jq * Ns * R + k;
       int base = line * lstride;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[base + (o + r * Ns) * estride] = v[q][r];
@@ -124,16 +135,18 @@ __device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstri
   __syncthreads();
 }
 
-__device__ void fft_lines(double2* buf, int n, int nlines, int lstride, int estride,
-                          const int* rad, int nrad, const double2* __restrict__ tw, double sgn) {
+template <int MAXPTS>
+__device__ __forceinline__ void fft_lines(double2* buf, int n, int nlines, int lstride, int estride,
+                                          const int* rad, int nrad, const double2* __restrict__ tw,
+                                          double sgn) {
   int Ns = 1;
   for (int s = 0; s < nrad; ++s) {
     int R = rad[s];
     switch (R) {
-      case 4: stage<4>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      case 2: stage<2>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      case 3: stage<3>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      default: stage<5>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 4: stage<4, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 2: stage<2, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 3: stage<3, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      default: stage<5, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
     }
     Ns *= R;
   }
@@ -150,10 +163,11 @@ __device__ __forceinline__ double teter_k(double x) {
 // Pass 1: xy-plane forward transform.  Work item (pair q, plane z).
 // Columns col0 + 2q and col0 + 2q + 1 (if < col0 + ncols) of block `slot`;
 // ncols < 0 means all J columns of the element (here and below).
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
-dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-              int na, int slot, int col0, int ncols) {
-  __shared__ double2 buf[FFT_MAXPTS];
+template <int MAXPTS>
+__device__ __forceinline__ void fft_xy_fwd_body(double2* buf, Elem* __restrict__ E,
+                                                const int* __restrict__ active,
+                                                const int* __restrict__ prefix, int na, int slot,
+                                                int col0, int ncols) {
   int b = blockIdx.x;
   int ai = find_elem(prefix, na, b);
   const Elem& e = E[active[ai]];
@@ -168,10 +182,24 @@ dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* _
   for (int p = threadIdx.x; p < np; p += FFT_THREADS)
     buf[p] = make_double2(A[p], hasb ? B[p] : 0.0);
   __syncthreads();
-  fft_lines(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], -1.0);
-  fft_lines(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], -1.0);
+  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], -1.0);
+  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], -1.0);
   double2* Z = e.zscr + (long long)q * e.ng + (long long)z * np;
   for (int p = threadIdx.x; p < np; p += FFT_THREADS) Z[p] = buf[p];
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, int slot, int col0, int ncols) {
+  __shared__ double2 buf[FFT_XY_SMALL];
+  fft_xy_fwd_body<FFT_XY_SMALL>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_fwd_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int slot, int col0, int ncols) {
+  __shared__ double2 buf[FFT_MAXPTS];
+  fft_xy_fwd_body<FFT_MAXPTS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
 // Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
@@ -201,7 +229,7 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
     buf[p] = Z[(long long)z * n1 * n2 + row * n1 + x];
   }
   __syncthreads();
-  fft_lines(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], -1.0);
+  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], -1.0);
 
   const double g1 = 2.0 * M_PI / e.L[0], g2 = 2.0 * M_PI / e.L[1], g3 = 2.0 * M_PI / e.L[2];
   if (mode == 0) {
@@ -218,9 +246,10 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
     int ca = col0 + 2 * q, cb = ca + 1;
     bool hasb = cb < col0 + nc;
     double Ta = e.tkin[ca], Tb = hasb ? e.tkin[cb] : Ta;
-    double2 nv[FFT_PTS_PER_THREAD];
+    constexpr int PPT = FFT_MAXPTS / FFT_THREADS;
+    double2 nv[PPT];
 #pragma unroll
-    for (int u = 0; u < FFT_PTS_PER_THREAD; ++u) {
+    for (int u = 0; u < PPT; ++u) {
       int p = threadIdx.x + u * FFT_THREADS;
       if (p < npts) {
         int z = p / width, r = p - z * width;
@@ -239,13 +268,13 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < FFT_PTS_PER_THREAD; ++u) {
+    for (int u = 0; u < PPT; ++u) {
       int p = threadIdx.x + u * FFT_THREADS;
       if (p < npts) buf[p] = nv[u];
     }
     __syncthreads();
   }
-  fft_lines(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], 1.0);
+  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], 1.0);
   for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
     int z = p / width, r = p - z * width;
     int s = r / n1, x = r - s * n1;
@@ -258,10 +287,11 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
 // mode 0 (operator): out = T x + V x + KB, reading x from block `in_slot`
 //   and the projections beta^T x from e.proj (n_proj x ncols).
 // mode 1 (plain): out = result (preconditioner; out may equal in).
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
-dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-              int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
-  __shared__ double2 buf[FFT_MAXPTS];
+template <int MAXPTS>
+__device__ __forceinline__ void fft_xy_inv_body(double2* buf, Elem* __restrict__ E,
+                                                const int* __restrict__ active,
+                                                const int* __restrict__ prefix, int na, int in_slot,
+                                                int out_slot, int col0, int ncols, int mode) {
   int b = blockIdx.x;
   int ai = find_elem(prefix, na, b);
   const Elem& e = E[active[ai]];
@@ -271,8 +301,8 @@ dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* _
   const double2* Z = e.zscr + (long long)q * e.ng + (long long)z * np;
   for (int p = threadIdx.x; p < np; p += FFT_THREADS) buf[p] = Z[p];
   __syncthreads();
-  fft_lines(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], 1.0);
-  fft_lines(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], 1.0);
+  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], 1.0);
+  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], 1.0);
   const double sc = 1.0 / (double)e.ng;
   const int nc = ncols < 0 ? e.J : ncols;
   int ca = col0 + 2 * q, cb = ca + 1;
@@ -311,6 +341,20 @@ dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* _
       if (hasb) OB[p] = sc * r.y;
     }
   }
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_XY_SMALL];
+  fft_xy_inv_body<FFT_XY_SMALL>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_inv_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_MAXPTS];
+  fft_xy_inv_body<FFT_MAXPTS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
 // ---------------------------------------------------------------------------

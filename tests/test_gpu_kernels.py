@@ -87,7 +87,7 @@ def _load(h, els, dev):
     h.set_potential(V, ALB.kb_batch([e.kb for e in els], dev))
 
 
-@pytest.mark.parametrize("which", ["one_element", "slab", "odd_grid"])
+@pytest.mark.parametrize("which", ["one_element", "slab", "odd_grid", "big_plane"])
 def test_apply_h_matches_oracle(dev, which):
     if which == "one_element":
         els = [synth.single_element(seed=0)]
@@ -95,9 +95,12 @@ def test_apply_h_matches_oracle(dev, which):
     elif which == "slab":
         els = synth.slab_batch(1, elements=[3])
         cols = 3
-    else:
+    elif which == "odd_grid":
         els = [synth.single_element(seed=4, grid=(20, 30, 18), n_states=6, n_atoms=4)]
         cols = 6
+    else:   # xy plane above 48 x 48 points (large-tile kernels)
+        els = [synth.single_element(seed=6, grid=(60, 48, 12), n_states=5, n_atoms=5)]
+        cols = 5
     # put the element of interest last, behind a different one, to exercise batching
     els = [synth.single_element(seed=9, grid=(12, 12, 12), n_states=4, n_atoms=2)] + els
     h = _handle(els)
