@@ -67,6 +67,14 @@ struct dgdft_alb {
   int* ring_d = nullptr;
   int* ring_h = nullptr;           // pinned
   int ring_stride = 0, ring_pos = 0;
+  // Elements are split into groups iterated on separate streams, so one
+  // group's per-element small-matrix kernels overlap the other group's
+  // block products and transforms.  Group 0 runs on the caller's stream.
+  static constexpr int NGROUP = 2;
+  int cur_g = 0;
+  int g_ring_pos[NGROUP] = {};
+  hipStream_t g_stream[NGROUP] = {};
+  hipEvent_t g_join = nullptr;
   int* d_active_all = nullptr;
   // host readback (pinned)
   double* h_resid = nullptr;
@@ -84,9 +92,9 @@ struct dgdft_alb {
     double flops, bytes;
   };
   bool prof = false;
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> ev_pool[NGROUP];
+  size_t ev_used[NGROUP] = {};
+  std::vector<ProfRec> recs[NGROUP];
   long long k_n[DGDFT_KCLASS_COUNT] = {};
   double k_ms[DGDFT_KCLASS_COUNT] = {}, k_flops[DGDFT_KCLASS_COUNT] = {},
          k_bytes[DGDFT_KCLASS_COUNT] = {};
@@ -95,12 +103,13 @@ struct dgdft_alb {
   hipEvent_t cur_a = nullptr;
 
   hipEvent_t ev() {
-    if (ev_used == ev_pool.size()) {
+    auto& pool = ev_pool[cur_g];
+    if (ev_used[cur_g] == pool.size()) {
       hipEvent_t e;
       HCHECK(hipEventCreate(&e));
-      ev_pool.push_back(e);
+      pool.push_back(e);
     }
-    return ev_pool[ev_used++];
+    return pool[ev_used[cur_g]++];
   }
   void pbeg(int kid, double flops, double bytes) {
     if (!prof) return;
@@ -112,11 +121,11 @@ struct dgdft_alb {
     if (!prof) return;
     hipEvent_t b = ev();
     HCHECK(hipEventRecord(b, stream));
-    recs.push_back(ProfRec{cur_kid, cur_a, b, cur_flops, cur_bytes});
+    recs[cur_g].push_back(ProfRec{cur_kid, cur_a, b, cur_flops, cur_bytes});
   }
-  // after a stream synchronisation
+  // after the current group's stream has been synchronised
   void flush_prof() {
-    for (auto& r : recs) {
+    for (auto& r : recs[cur_g]) {
       float ms = 0.f;
       HCHECK(hipEventElapsedTime(&ms, r.a, r.b));
       k_n[r.kid] += 1;
@@ -124,8 +133,8 @@ struct dgdft_alb {
       k_flops[r.kid] += r.flops;
       k_bytes[r.kid] += r.bytes;
     }
-    recs.clear();
-    ev_used = 0;
+    recs[cur_g].clear();
+    ev_used[cur_g] = 0;
   }
 
   // ---------------------------------------------------------------------
@@ -138,12 +147,20 @@ struct dgdft_alb {
 
   void ring_reset() { ring_pos = 0; }
 
+  void set_group(int g) {
+    g_ring_pos[cur_g] = ring_pos;
+    cur_g = g;
+    ring_pos = g_ring_pos[g];
+    stream = g_stream[g];
+  }
+
   // Upload `active` and per-element work counts; returns device pointers.
   template <class F>
   Prefix make_prefix(const std::vector<int>& act, F work) {
     if (ring_pos >= PREFIX_RING) throw HipFail{hipErrorUnknown, "prefix ring exhausted"};
-    int* hp = ring_h + (size_t)ring_pos * ring_stride;
-    int* dp = ring_d + (size_t)ring_pos * ring_stride;
+    size_t slot = (size_t)cur_g * PREFIX_RING + ring_pos;
+    int* hp = ring_h + slot * ring_stride;
+    int* dp = ring_d + slot * ring_stride;
     ++ring_pos;
     int na = (int)act.size();
     int* ha = hp;              // active ids
@@ -434,7 +451,10 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   (void)hipHostFree(h->ring_h);
   (void)hipHostFree(h->h_resid);
   (void)hipHostFree(h->h_fl);
-  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  for (auto& pool : h->ev_pool)
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  if (h->g_join) (void)hipEventDestroy(h->g_join);
+  if (h->g_stream[1]) (void)hipStreamDestroy(h->g_stream[1]);
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   (void)hipSetDevice(cur);
   delete h;
@@ -525,6 +545,7 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     HCHECK(hipGetDevice(&h->dev));
     HCHECK(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
     h->stream = h->own_stream;
+    h->g_stream[0] = h->own_stream;
     // ---- per-element memory
     for (int e = 0; e < n_elem; ++e) {
       Elem& E = h->eh[e];
@@ -581,8 +602,10 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     HCHECK(hipMemcpy(h->tw_arena, tw.data(), sizeof(double2) * ntw, hipMemcpyHostToDevice));
     HCHECK(hipMalloc(&h->ed, sizeof(Elem) * n_elem));
     h->ring_stride = 2 * n_elem + 8;
-    HCHECK(hipMalloc(&h->ring_d, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING));
-    HCHECK(hipHostMalloc(&h->ring_h, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING));
+    HCHECK(hipMalloc(&h->ring_d, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING * dgdft_alb::NGROUP));
+    HCHECK(hipHostMalloc(&h->ring_h, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING * dgdft_alb::NGROUP));
+    HCHECK(hipStreamCreateWithFlags(&h->g_stream[1], hipStreamNonBlocking));
+    HCHECK(hipEventCreateWithFlags(&h->g_join, hipEventDisableTiming));
     HCHECK(hipHostMalloc(&h->h_resid, sizeof(double) * h->sumJ));
     HCHECK(hipHostMalloc(&h->h_fl, sizeof(int) * (size_t)n_elem * FL_COUNT));
     memset(h->h_fl, 0, sizeof(int) * (size_t)n_elem * FL_COUNT);
@@ -612,6 +635,13 @@ int32_t dgdft_alb_sizes(const dgdft_alb* h, int32_t elem, int64_t* ng, int64_t* 
     offsets[3] = E.off_alb;
   }
   return DGDFT_OK;
+}
+
+// Group 0 runs on the caller's stream (or the handle's own one).
+static void bind_stream(dgdft_alb* h, void* stream) {
+  h->set_group(0);
+  h->g_stream[0] = stream ? (hipStream_t)stream : h->own_stream;
+  h->stream = h->g_stream[0];
 }
 
 static Status set_potential_impl(dgdft_alb* h, const double* V, const dgdft_kb* kb, hipStream_t s) {
@@ -777,7 +807,7 @@ static Status set_potential_impl(dgdft_alb* h, const double* V, const dgdft_kb* 
 int32_t dgdft_alb_set_potential(dgdft_alb* h, const double* V, const dgdft_kb* kb, void* stream) {
   if (!h) return DGDFT_EINVAL;
   if (!V) { h->err = "V is NULL"; return DGDFT_EINVAL; }
-  h->stream = stream ? (hipStream_t)stream : h->stream;
+  bind_stream(h, stream);
   try {
     Status st = set_potential_impl(h, V, kb, h->stream);
     if (st.code != DGDFT_OK) h->err = st.msg;
@@ -814,10 +844,61 @@ static void rr_on_x(dgdft_alb* h, const std::vector<int>& act) {
   h->per_elem(act, 3, 0);   // advance: X <- X C etc. become current; hasP <- 0
 }
 
+// One LOBPCG iteration for the active elements `act` on the current group's
+// stream: Teter preconditioning of the residual in W, projection against
+// [X P], orthonormalisation, H W, Rayleigh-Ritz on [X P W], update, advance.
+static void iterate(dgdft_alb* h, const std::vector<int>& act) {
+  h->launch_kbproj(act, VS_X, 0, -1, 1);
+  h->per_elem(act, 2, 0);
+  h->precondition(act, S_W, 0, -1);
+  // W <- W - [X P]([X P]^T W)
+  GramArgs g1{};
+  g1.A = dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
+  g1.B[0] = dgdft_alb::opnd({S_W});
+  g1.njob = 1; g1.out_mat[0] = SM_G; g1.upper = 0;
+  h->gram(act, g1);
+  UpdArgs u1{};
+  u1.A[0] = g1.A;
+  u1.Y[0] = dgdft_alb::opnd({S_W});
+  u1.njob = 1; u1.cmat = SM_G; u1.ncol = -1; u1.alpha = -1.0; u1.beta = 1.0;
+  h->update(act, u1);
+  // W2 = W T (CholQR / SVQB)
+  GramArgs gw{};
+  gw.A = dgdft_alb::opnd({S_W});
+  gw.B[0] = dgdft_alb::opnd({S_W});
+  gw.njob = 1; gw.out_mat[0] = SM_G; gw.upper = 1;
+  h->gram(act, gw);
+  h->per_elem(act, 0, 0);
+  UpdArgs u2{};
+  u2.A[0] = dgdft_alb::opnd({S_W});
+  u2.Y[0] = dgdft_alb::opnd({S_W2});
+  u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = 1.0; u2.beta = 0.0;
+  h->update(act, u2);
+  // HW
+  h->op_apply(act, S_W2, S_HW, 0, -1);
+  // Rayleigh-Ritz on S = [X P W2]
+  GramArgs g3{};
+  g3.A = dgdft_alb::opnd({VS_X, VS_P, S_W2}, {0, 1, 0});
+  g3.B[0] = g3.A;
+  g3.B[1] = dgdft_alb::opnd({VS_HX, VS_HP, S_HW}, {0, 1, 0});
+  g3.njob = 2; g3.out_mat[0] = SM_M; g3.out_mat[1] = SM_H; g3.upper = 1;
+  h->gram(act, g3);
+  h->per_elem(act, 1, 0);
+  UpdArgs u3{};
+  u3.A[0] = g3.A;
+  u3.A[1] = g3.B[1];
+  u3.Y[0] = dgdft_alb::opnd({VS_XN, VS_PN});
+  u3.Y[1] = dgdft_alb::opnd({VS_HXN, VS_HPN});
+  u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
+  h->update(act, u3);
+  h->per_elem(act, 3, 0);
+}
+
 static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double* eigvecs, double* albs,
                          double* sigma, dgdft_alb_stats* stats) {
   const int n = h->n;
   hipStream_t s = h->stream;
+  for (int g = 0; g < dgdft_alb::NGROUP; ++g) h->g_ring_pos[g] = 0;
   h->ring_reset();
   // ---- X0 finiteness
   HCHECK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
@@ -857,63 +938,43 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   h->op_apply(all, VS_X, VS_HX, 0, -1);
   rr_on_x(h, all);
 
-  std::vector<int> iters(n, 0), done(n, 0);
-  std::vector<int> act = all;
+  std::vector<int> iters(n, 0);
   const double tol = h->opts.tol;
-  int max_iter = h->opts.max_iter;
-  for (;;) {
-    h->per_elem_cols(act, 0, VS_X, VS_HX, S_W, nullptr, nullptr);   // R -> W, norms
-    h->poll();
-    std::vector<int> next;
-    for (int e : act) {
-      if (h->max_res(e) <= tol || iters[e] >= max_iter) done[e] = 1;
-      else next.push_back(e);
-    }
-    act.swap(next);
-    if (act.empty()) break;
-    // Teter: band kinetic energies, then W = K(R)
-    h->launch_kbproj(act, VS_X, 0, -1, 1);
-    h->per_elem(act, 2, 0);
-    h->precondition(act, S_W, 0, -1);
-    // W <- W - [X P]([X P]^T W)
-    GramArgs g1{};
-    g1.A = dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
-    g1.B[0] = dgdft_alb::opnd({S_W});
-    g1.njob = 1; g1.out_mat[0] = SM_G; g1.upper = 0;
-    h->gram(act, g1);
-    UpdArgs u1{};
-    u1.A[0] = g1.A;
-    u1.Y[0] = dgdft_alb::opnd({S_W});
-    u1.njob = 1; u1.cmat = SM_G; u1.ncol = -1; u1.alpha = -1.0; u1.beta = 1.0;
-    h->update(act, u1);
-    // W2 = W T (CholQR / SVQB)
-    h->gram(act, gw);
-    h->per_elem(act, 0, 0);
-    UpdArgs u2{};
-    u2.A[0] = dgdft_alb::opnd({S_W});
-    u2.Y[0] = dgdft_alb::opnd({S_W2});
-    u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = 1.0; u2.beta = 0.0;
-    h->update(act, u2);
-    // HW
-    h->op_apply(act, S_W2, S_HW, 0, -1);
-    // Rayleigh-Ritz on S = [X P W2]
-    GramArgs g3{};
-    g3.A = dgdft_alb::opnd({VS_X, VS_P, S_W2}, {0, 1, 0});
-    g3.B[0] = g3.A;
-    g3.B[1] = dgdft_alb::opnd({VS_HX, VS_HP, S_HW}, {0, 1, 0});
-    g3.njob = 2; g3.out_mat[0] = SM_M; g3.out_mat[1] = SM_H; g3.upper = 1;
-    h->gram(act, g3);
-    h->per_elem(act, 1, 0);
-    UpdArgs u3{};
-    u3.A[0] = g3.A;
-    u3.A[1] = g3.B[1];
-    u3.Y[0] = dgdft_alb::opnd({VS_XN, VS_PN});
-    u3.Y[1] = dgdft_alb::opnd({VS_HXN, VS_HPN});
-    u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
-    h->update(act, u3);
-    h->per_elem(act, 3, 0);
-    for (int e : act) iters[e]++;
+  const int max_iter = h->opts.max_iter;
+  // Split the elements into groups that iterate on their own streams; the
+  // second stream first waits for everything enqueued so far.
+  HCHECK(hipEventRecord(h->g_join, h->g_stream[0]));
+  HCHECK(hipStreamWaitEvent(h->g_stream[1], h->g_join, 0));
+  std::vector<int> act[dgdft_alb::NGROUP];
+  for (int e = 0; e < n; ++e) act[e % dgdft_alb::NGROUP].push_back(e);
+  for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+    if (act[g].empty()) continue;
+    h->set_group(g);
+    h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);   // R -> W, norms
   }
+  for (;;) {
+    bool any = false;
+    for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+      if (act[g].empty()) continue;
+      h->set_group(g);
+      h->poll();
+      std::vector<int> next;
+      for (int e : act[g])
+        if (!(h->max_res(e) <= tol || iters[e] >= max_iter)) next.push_back(e);
+      act[g].swap(next);
+      if (act[g].empty()) continue;
+      any = true;
+      iterate(h, act[g]);
+      for (int e : act[g]) iters[e]++;
+      h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);
+    }
+    if (!any) break;
+  }
+  // join: group 0's stream waits for group 1
+  h->set_group(1);
+  HCHECK(hipEventRecord(h->g_join, h->g_stream[1]));
+  h->set_group(0);
+  HCHECK(hipStreamWaitEvent(h->g_stream[0], h->g_join, 0));
   // ---- final FP64 check on every element: fresh HX, RR on X, residuals
   h->ring_reset();
   h->op_apply(all, VS_X, VS_HX, 0, -1);
@@ -974,7 +1035,7 @@ int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb, const
                         dgdft_alb_stats* stats, void* stream) {
   if (!h) return DGDFT_EINVAL;
   if (!X0 || !eigvals) { h->err = "X0 and eigvals must be non-NULL"; return DGDFT_EINVAL; }
-  if (stream) h->stream = (hipStream_t)stream;
+  bind_stream(h, stream);
   try {
     if (V) {
       Status st = set_potential_impl(h, V, kb, h->stream);
@@ -1009,7 +1070,7 @@ int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* H
     return DGDFT_EINVAL;
   }
   if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
-  if (stream) h->stream = (hipStream_t)stream;
+  bind_stream(h, stream);
   try {
     h->ring_reset();
     bind_user(h, elem, X, HX, nullptr);
@@ -1031,7 +1092,7 @@ int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R, cons
     return DGDFT_EINVAL;
   }
   if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
-  if (stream) h->stream = (hipStream_t)stream;
+  bind_stream(h, stream);
   try {
     h->ring_reset();
     Elem& E = h->eh[elem];
