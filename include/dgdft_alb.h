@@ -212,7 +212,8 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m,
 #define DGDFT_K_RR           8
 #define DGDFT_K_CHOLQR       9
 #define DGDFT_K_OTHER       10
-#define DGDFT_KCLASS_COUNT  11
+#define DGDFT_K_SGEMM       11
+#define DGDFT_KCLASS_COUNT  12
 
 /* Enable (1) or disable (0) timing and reset the counters. */
 int32_t dgdft_alb_profile(dgdft_alb* h, int32_t enable);
@@ -224,6 +225,17 @@ int32_t dgdft_alb_kernel_stats(const dgdft_alb* h, int32_t kclass, int64_t* laun
 
 /* Kernel symbol name of a class ("dg_gram", ...). */
 const char* dgdft_kernel_class_name(int32_t kclass);
+
+/* Batched products of the small Rayleigh-Ritz matrices (operation 4 of the
+ * LOBPCG list in Sec. II.B works on matrices of size n = kb*J), exported for
+ * tests: C = alpha op(A) op(B) + beta C with each dimension d* = 0 -> n,
+ * 1 -> J (dm rows of C, dn columns of C, dk inner), op = transpose when
+ * ta/tb = 1.  `count` problems back to back, each column-major with leading
+ * dimension = rows as stored.  J <= 1024, kb in 1..3.  Device pointers. */
+int32_t dgdft_small_gemm_batched(int32_t ta, int32_t tb, int32_t count, int32_t J,
+                                 int32_t kb, int32_t dm, int32_t dn, int32_t dk,
+                                 double alpha, const double* A, const double* B,
+                                 double beta, double* C, void* stream);
 
 /* Message of the last failure on h (NULL: of the last failed create). */
 const char* dgdft_alb_last_error(const dgdft_alb* h);

@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     DGDFTError,
     gemm_batched,
     load_library,
+    small_gemm_batched,
     small_syev,
     LIB_PATH,
     EXPORTS,

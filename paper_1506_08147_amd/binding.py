@@ -18,10 +18,10 @@ EXPORTS = (
     "dgdft_alb_create", "dgdft_alb_destroy", "dgdft_alb_sizes", "dgdft_alb_set_potential",
     "dgdft_alb_solve", "dgdft_alb_apply_h", "dgdft_alb_precondition", "dgdft_small_syev",
     "dgdft_gemm_batched", "dgdft_alb_last_error", "dgdft_strerror", "dgdft_alb_profile",
-    "dgdft_alb_kernel_stats", "dgdft_kernel_class_name",
+    "dgdft_alb_kernel_stats", "dgdft_kernel_class_name", "dgdft_small_gemm_batched",
 )
 KCLASS = ("dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
-          "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other")
+          "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm")
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM",
           -4: "EHIP", -5: "EBREAKDOWN"}
@@ -95,6 +95,9 @@ def load_library():
     lib.dgdft_alb_profile.restype = i32
     lib.dgdft_alb_kernel_stats.argtypes = [vp, i32, P(i64), P(dbl), P(dbl), P(dbl)]
     lib.dgdft_alb_kernel_stats.restype = i32
+    lib.dgdft_small_gemm_batched.argtypes = [i32, i32, i32, i32, i32, i32, i32, i32, dbl, vp, vp,
+                                             dbl, vp, vp]
+    lib.dgdft_small_gemm_batched.restype = i32
     lib.dgdft_kernel_class_name.argtypes = [i32]
     lib.dgdft_kernel_class_name.restype = C.c_char_p
     _lib = lib
@@ -300,6 +303,20 @@ def small_syev(A, k, method=0):
     if rc != 0:
         raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
     return w, Z
+
+
+def small_gemm_batched(ta, tb, J, kb, dm, dn, dk, A, B, C, alpha=1.0, beta=0.0):
+    """The Rayleigh-Ritz small-matrix product kernel: per problem
+    C = alpha op(A) op(B) + beta C, dims coded 0 -> kb*J, 1 -> J.  A, B, C:
+    (count, cols, rows) device tensors (column-major per problem).  Returns C'."""
+    lib = load_library()
+    Ac, Bc, Cc = A.contiguous(), B.contiguous(), C.clone().contiguous()
+    rc = lib.dgdft_small_gemm_batched(int(ta), int(tb), A.shape[0], int(J), int(kb), int(dm),
+                                      int(dn), int(dk), float(alpha), _ptr(Ac), _ptr(Bc),
+                                      float(beta), _ptr(Cc), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return Cc
 
 
 def gemm_batched(trans, A, B, alpha=1.0, beta=0.0, Cin=None):

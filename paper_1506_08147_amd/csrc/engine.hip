@@ -43,7 +43,7 @@ struct Status {
   std::string msg;
 };
 
-constexpr int PREFIX_RING = 96;   // prefix arrays between two host polls
+constexpr int PREFIX_RING = 160;  // prefix arrays between two host polls
 
 }  // namespace
 
@@ -340,6 +340,73 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
   }
 
+  // One batched small-matrix product (see dg_sgemm): dims/lds coded 0 -> n, 1 -> J.
+  void sgemm(const std::vector<int>& act, int single, int ta, int tb, int ma, int oa, int mb, int ob,
+             int mc, int oc, int dm_, int dn_, int dk_, int la, int lb, int lc, double alpha,
+             double beta, int gate, int gate_pok = 0) {
+    auto P = make_prefix(act, [&](int e) {
+      int J = eh[e].J, n = (single ? 1 : (hasP_host(e) ? 3 : 2)) * J;
+      return cdiv(sg_dim(dm_, n, J), 64) * cdiv(sg_dim(dn_, n, J), 64);
+    });
+    if (P.total == 0) return;
+    SgArgs a{};
+    a.ta = ta; a.tb = tb;
+    a.ma = ma; a.oa = oa; a.mb = mb; a.ob = ob; a.mc = mc; a.oc = oc;
+    a.dm = dm_; a.dn = dn_; a.dk = dk_; a.la = la; a.lb = lb; a.lc = lc;
+    a.alpha = alpha; a.beta = beta; a.gate = gate; a.gate_pok = gate_pok; a.single = single;
+    double fl = 0;
+    for (int e : act) {
+      int J = eh[e].J, n = (single ? 1 : (hasP_host(e) ? 3 : 2)) * J;
+      fl += 2.0 * sg_dim(dm_, n, J) * sg_dim(dn_, n, J) * sg_dim(dk_, n, J);
+    }
+    pbeg(DGDFT_K_SGEMM, fl, 0);
+    hipLaunchKernelGGL(dg_sgemm, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, a);
+    pend();
+    HCHECK(hipGetLastError());
+  }
+
+  void rr_one(const std::vector<int>& act, void (*k)(Elem*, const int*, int, int), int threads,
+              int single) {
+    auto P = make_prefix(act, [&](int) { return 1; });
+    pbeg(DGDFT_K_RR, 0, 0);
+    hipLaunchKernelGGL(k, dim3(P.na), dim3(threads), 0, stream, ed, P.active, P.na, single);
+    pend();
+    HCHECK(hipGetLastError());
+  }
+
+  // Rayleigh-Ritz step (see lobpcg.hip): per-element factorisations and
+  // decisions one workgroup each, products on dg_sgemm.
+  void rr_step(const std::vector<int>& act, int single) {
+    const int N = 0, Jc = 1;
+    rr_one(act, dg_rr_reduce, SMALL_THREADS, single);
+    // path 0: A = L^-1 A L^-T
+    sgemm(act, single, 0, 0, SM_T, 0, SM_A, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
+    sgemm(act, single, 0, 1, SM_U, 0, SM_T, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
+    if (!single) {
+      // path 2: A = Hh - sym(E Hh)
+      sgemm(act, single, 0, 1, SM_L, 0, SM_H, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 2);
+      rr_one(act, dg_rr_form, 256, single);
+    }
+    rr_one(act, dg_rr_eig, SMALL_THREADS, single);
+    // path 0: C = L^-T Y
+    sgemm(act, single, 1, 0, SM_T, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, 1.0, 0.0, 0);
+    if (!single) {
+      // path 2: C = Y - E Y / 2
+      rr_one(act, dg_rr_cinit, 256, single);
+      sgemm(act, single, 0, 0, SM_L, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, -0.5, 1.0, 2);
+    }
+    rr_one(act, dg_rr_post, 256, single);
+    if (single) return;
+    // next search direction: D = E - C (C^T M E), then D <- D (D^T M D)^-1/2 (Cholesky)
+    sgemm(act, single, 0, 0, SM_M, 0, SM_Z, 0, SM_U, 0, N, Jc, N, N, N, N, 1.0, 0.0, -1);
+    sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_A, 0, Jc, Jc, N, N, N, Jc, 1.0, 0.0, -1);
+    sgemm(act, single, 0, 0, SM_C, 0, SM_A, 0, SM_Z, 0, N, Jc, Jc, N, Jc, N, -1.0, 1.0, -1);
+    sgemm(act, single, 0, 0, SM_M, 0, SM_Z, 0, SM_U, 0, N, Jc, N, N, N, N, 1.0, 0.0, -1);
+    sgemm(act, single, 1, 0, SM_Z, 0, SM_U, 0, SM_A, 0, Jc, Jc, N, N, N, Jc, 1.0, 0.0, -1);
+    rr_one(act, dg_rr_dchol, SMALL_THREADS, single);
+    sgemm(act, single, 0, 1, SM_Z, 0, SM_L, 0, SM_C, 1, N, Jc, Jc, N, Jc, N, 1.0, 0.0, -1, 1);
+  }
+
   void per_elem(const std::vector<int>& act, int which, int arg, double* out = nullptr) {
     auto P = make_prefix(act, [&](int) { return 1; });
     if (P.na == 0) return;
@@ -350,12 +417,9 @@ struct dgdft_alb {
         hipLaunchKernelGGL(dg_cholqr, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
         break;
       case 1:
-        hipLaunchKernelGGL(dg_rr_reduce, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na,
-                           arg);
-        hipLaunchKernelGGL(dg_rr_eig, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, arg);
-        hipLaunchKernelGGL(dg_rr_finish, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na,
-                           arg);
-        break;
+        pend();
+        rr_step(act, arg);
+        return;
       case 2:
         hipLaunchKernelGGL(dg_teter_energy, dim3(P.na), dim3(256), 0, stream, ed, P.active, P.na);
         break;
@@ -1144,7 +1208,7 @@ int32_t dgdft_alb_kernel_stats(const dgdft_alb* h, int32_t kclass, int64_t* laun
 const char* dgdft_kernel_class_name(int32_t kclass) {
   static const char* names[DGDFT_KCLASS_COUNT] = {
       "dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
-      "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other"};
+      "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm"};
   return (kclass >= 0 && kclass < DGDFT_KCLASS_COUNT) ? names[kclass] : "";
 }
 
@@ -1183,6 +1247,72 @@ int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A, d
     hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
                        method);
     HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(s));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    g_create_error = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_small_gemm_batched(int32_t ta, int32_t tb, int32_t count, int32_t J, int32_t kb,
+                                 int32_t dm, int32_t dn, int32_t dk, double alpha, const double* A,
+                                 const double* B, double beta, double* C, void* stream) {
+  if (count < 1 || J < 1 || J > 1024 || kb < 1 || kb > 3 || !A || !B || !C || (ta | tb | dm | dn | dk) & ~1) {
+    g_create_error = "small_gemm_batched: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    TmpDev t;
+    const int n = kb * J;
+    auto dim = [&](int c) { return c == 0 ? n : J; };
+    const int M = dim(dm), N = dim(dn), K = dim(dk);
+    const int ra = ta ? K : M, ca = ta ? M : K, rb = tb ? N : K, cb = tb ? K : N;
+    const size_t stride = (size_t)9 * J * J;
+    double* ws = t.alloc<double>((size_t)count * 3 * stride);
+    int* fl = t.alloc<int>((size_t)count * FL_COUNT);
+    std::vector<int> hfl((size_t)count * FL_COUNT, 0);
+    std::vector<Elem> eh(count);
+    for (int i = 0; i < count; ++i) {
+      Elem& e = eh[i];
+      e.J = J;
+      e.small = ws + (size_t)i * 3 * stride;
+      e.small_stride = (long long)stride;
+      e.fl = fl + (size_t)i * FL_COUNT;
+      hfl[(size_t)i * FL_COUNT + FL_HASP] = kb == 3;
+      hfl[(size_t)i * FL_COUNT + FL_HASP_NEXT] = 1;
+      HCHECK(hipMemcpy2DAsync(e.small, sizeof(double) * ra, A + (size_t)i * ra * ca, sizeof(double) * ra,
+                              sizeof(double) * ra, ca, hipMemcpyDeviceToDevice, s));
+      HCHECK(hipMemcpy2DAsync(e.small + stride, sizeof(double) * rb, B + (size_t)i * rb * cb,
+                              sizeof(double) * rb, sizeof(double) * rb, cb, hipMemcpyDeviceToDevice, s));
+      HCHECK(hipMemcpy2DAsync(e.small + 2 * stride, sizeof(double) * M, C + (size_t)i * M * N,
+                              sizeof(double) * M, sizeof(double) * M, N, hipMemcpyDeviceToDevice, s));
+    }
+    HCHECK(hipMemcpyAsync(fl, hfl.data(), sizeof(int) * hfl.size(), hipMemcpyHostToDevice, s));
+    Elem* ed = t.alloc<Elem>(count);
+    HCHECK(hipMemcpyAsync(ed, eh.data(), sizeof(Elem) * count, hipMemcpyHostToDevice, s));
+    std::vector<int> act(count), pre(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+      act[i] = i;
+      pre[i + 1] = pre[i] + cdiv(M, 64) * cdiv(N, 64);
+    }
+    int* d_act = t.alloc<int>(count);
+    int* d_pre = t.alloc<int>(count + 1);
+    HCHECK(hipMemcpyAsync(d_act, act.data(), sizeof(int) * count, hipMemcpyHostToDevice, s));
+    HCHECK(hipMemcpyAsync(d_pre, pre.data(), sizeof(int) * (count + 1), hipMemcpyHostToDevice, s));
+    SgArgs a{};
+    a.ta = ta; a.tb = tb;
+    a.ma = 0; a.mb = 1; a.mc = 2;
+    a.dm = dm; a.dn = dn; a.dk = dk;
+    a.la = ta ? dk : dm; a.lb = tb ? dn : dk; a.lc = dm;
+    a.alpha = alpha; a.beta = beta;
+    a.gate = -1; a.gate_pok = 0; a.single = kb == 1;
+    hipLaunchKernelGGL(dg_sgemm, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, a);
+    HCHECK(hipGetLastError());
+    for (int i = 0; i < count; ++i)
+      HCHECK(hipMemcpy2DAsync(C + (size_t)i * M * N, sizeof(double) * M, eh[i].small + 2 * stride,
+                              sizeof(double) * M, sizeof(double) * M, N, hipMemcpyDeviceToDevice, s));
     HCHECK(hipStreamSynchronize(s));
     return DGDFT_OK;
   } catch (HipFail& f) {

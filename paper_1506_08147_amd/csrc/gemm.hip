@@ -290,4 +290,101 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Products of small per-element matrices (the Rayleigh-Ritz algebra of size
+// n = kJ), spread over many workgroups: C = alpha op(A) op(B) + beta C with
+// all three in the element's small workspace.  Dimensions and leading
+// dimensions are given as codes resolved per element: 0 -> n = kJ (k = 1
+// for the step on X alone, else 2 or 3 by the presence of P), 1 -> J.
+// 64 x 64 tiles, four waves of 32 x 32, 16-deep K stages through LDS.
+struct SgArgs {
+  int ta, tb;
+  int ma, oa, mb, ob, mc, oc;    // small-workspace matrix and column offset (in J)
+  int dm, dn, dk;                // dimension codes
+  int la, lb, lc;                // leading-dimension codes
+  double alpha, beta;
+  int gate;                      // -1: all; else only elements with fl[FL_RR_PATH] == gate
+  int gate_pok;                  // 1: only elements whose next direction is kept
+  int single;
+};
+
+__host__ __device__ inline int sg_dim(int code, int n, int J) { return code == 0 ? n : J; }
+
+extern "C" __global__ void __launch_bounds__(256)
+dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+         int na, SgArgs a) {
+  __shared__ double As[16 * 65];
+  __shared__ double Bs[16 * 65];
+  int blk = blockIdx.x;
+  int ai = find_elem(prefix, na, blk);
+  const Elem& e = E[active[ai]];
+  if (a.gate >= 0 && e.fl[FL_RR_PATH] != a.gate) return;
+  if (a.gate_pok && !e.fl[FL_HASP_NEXT]) return;
+  const int J = e.J;
+  const int n = (a.single ? 1 : (has_p(e) ? 3 : 2)) * J;
+  const int M = sg_dim(a.dm, n, J), N = sg_dim(a.dn, n, J), K = sg_dim(a.dk, n, J);
+  const int lda = sg_dim(a.la, n, J), ldb = sg_dim(a.lb, n, J), ldc = sg_dim(a.lc, n, J);
+  const double* A = sm(e, a.ma) + (long long)a.oa * J * lda;
+  const double* B = sm(e, a.mb) + (long long)a.ob * J * ldb;
+  double* C = sm(e, a.mc) + (long long)a.oc * J * ldc;
+  int w = blk - prefix[ai];
+  const int ntm = cdiv(M, 64);
+  const int i0 = (w % ntm) * 64, j0 = (w / ntm) * 64;
+  if (j0 >= N) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = wv & 1, wj = wv >> 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int el = tid + 256 * q;          // 0..1023 over a 64 x 16 tile
+      int f = el & 63, s16 = el >> 6;  // f: 64-long fast index, s16: 16-long
+      int g = el & 15, s64 = el >> 4;  // g: 16-long fast index, s64: 64-long
+      // op(A) tile (i, kk): contiguous along i when ta == 0, along kk when ta == 1
+      int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
+      double av = 0.0;
+      if (i0 + ii < M && k0 + kk < K)
+        av = a.ta ? A[(k0 + kk) + (long long)lda * (i0 + ii)] : A[(i0 + ii) + (long long)lda * (k0 + kk)];
+      As[kk * 65 + ii] = av;
+      // op(B) tile (kk, jj): contiguous along kk when tb == 0, along jj when tb == 1
+      int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
+      double bv = 0.0;
+      if (j0 + jj < N && k0 + kb < K)
+        bv = a.tb ? B[(j0 + jj) + (long long)ldb * (k0 + kb)] : B[(k0 + kb) + (long long)ldb * (j0 + jj)];
+      Bs[kb * 65 + jj] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      int kk = ks * 4 + (lane >> 4);
+      double a0 = As[kk * 65 + wi * 32 + (lane & 15)];
+      double a1 = As[kk * 65 + wi * 32 + 16 + (lane & 15)];
+      double b0 = Bs[kk * 65 + wj * 32 + (lane & 15)];
+      double b1 = Bs[kk * 65 + wj * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + wi * 32 + x * 16 + 4 * r + (lane >> 4);
+        int j = j0 + wj * 32 + y * 16 + (lane & 15);
+        if (i < M && j < N) {
+          double* c = C + i + (long long)ldc * j;
+          *c = a.alpha * acc[x][y][r] + (a.beta != 0.0 ? a.beta * *c : 0.0);
+        }
+      }
+}
+
 }  // namespace dg

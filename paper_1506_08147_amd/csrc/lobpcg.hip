@@ -133,16 +133,26 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
 
 // Rayleigh-Ritz on S = [X P W] (k blocks: 1 for the initial/final step on X,
 // 2 without P, 3 with P): lowest J of Hh c = theta M c with Hh = S^T HS and
-// M = S^T S (upper triangles in SM_H, SM_M, ld n = kJ).  Writes theta, the
-// coefficients C (n x J) into SM_C[:, 0:J] and, for k > 1, the next search
-// direction D (n x J) into SM_C[:, J:2J]: the part of S [0; C_P; C_W] that is
+// M = S^T S (upper triangles in SM_H, SM_M, ld n = kJ).  Produces theta, the
+// coefficients C (n x J) in SM_C[:, 0:J] and, for k > 1, the next search
+// direction D (n x J) in SM_C[:, J:2J]: the part of S [0; C_P; C_W] that is
 // M-orthogonal to S C, normalised through a scaled Cholesky of its M-Gram.
 //
-// Three launches per step: dg_rr_reduce forms A = L^-1 D^-1 Hh D^-1 L^-T from
-// a Cholesky factor of the scaled M (or, if M is not numerically SPD,
-// finishes the whole step through an eigenvector-based reduction);
-// dg_rr_eig finds the lowest J eigenpairs of A (Householder, bisection,
-// inverse iteration); dg_rr_finish forms C and the next search direction.
+// Launch sequence (host: rr_step).  The per-element decisions and
+// factorisations run one workgroup per element; the products of size n^3,
+// n^2 J and n J^2 run on dg_sgemm over many workgroups.  Reduction paths
+// (fl[FL_RR_PATH]):
+//   2  the blocks of S are orthonormalised as they are built, so M = I + E;
+//      when max|E| <= 1e-8 (and not the step on X alone) the problem is
+//      reduced to first order, T = I - E/2 with T^T M T = I + O(E^2):
+//      A = Hh - sym(E Hh), C = Y - E Y / 2;
+//   0  exact reduction with a Cholesky factor of the scaled M:
+//      A = L^-1 D^-1 Hh D^-1 L^-T, C = D^-1 L^-T Y;
+//   1  M not numerically SPD: reduction to the eigenvectors of the scaled M
+//      above CHOL_TOL times the largest, finished inside dg_rr_reduce.
+// (Y, theta): lowest J eigenpairs of A from dg_rr_eig.
+constexpr double NEAR_ORTHO = 1e-8;
+
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   __shared__ double red[32];
@@ -164,6 +174,23 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   double* w = vec + 7 * n;
   sym_from_upper(t, H, n, n);
   sym_from_upper(t, M, n, n);
+  if (!single) {
+    double em = 0.0;
+    for (int p = t.tid(); p < n * n; p += t.nt()) {
+      int i = p % n, j = p / n;
+      em = fmax(em, fabs(M[p] - (i == j ? 1.0 : 0.0)));
+    }
+    em = t.maxv(em);
+    if (em <= NEAR_ORTHO) {
+      for (int p = t.tid(); p < n * n; p += t.nt()) {
+        int i = p % n, j = p / n;
+        Lm[p] = M[p] - (i == j ? 1.0 : 0.0);      // E
+      }
+      if (t.tid() == 0) e.fl[FL_RR_PATH] = 2;
+      t.sync();
+      return;
+    }
+  }
   for (int i = t.tid(); i < n; i += t.nt()) {
     double d = sqrt(fmax(M[i + (long long)n * i], 0.0));
     dm[i] = d > 0.0 ? d : 1.0;
@@ -178,11 +205,9 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   int ok = chol_lower(t, Lm, n, n, CHOL_TOL);
   int nk = n;
   if (ok) {
-    // T = D^-1 L^-T; A' = L^-1 (D^-1 Hh D^-1) L^-T
-    tri_inv_lower(t, Lm, n, Tm, n, n);                    // Tm = L^-1 (lower)
-    gemm(t, 0, 0, n, n, n, 1.0, Tm, n, A, n, 0.0, U, n);  // U = L^-1 A
-    gemm(t, 0, 1, n, n, n, 1.0, U, n, Tm, n, 0.0, A, n);  // A = U L^-T
+    tri_inv_lower(t, Lm, n, Tm, n, n);   // Tm = L^-1; products follow on dg_sgemm
     if (t.tid() == 0) e.fl[FL_RR_PATH] = 0;
+    t.sync();
     return;
   } else {
     if (t.tid() == 0) e.fl[FL_RR_FALLBACK] += 1;
@@ -223,13 +248,29 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   if (t.tid() == 0) e.fl[FL_RR_PATH] = 1;
 }
 
+// Path 2: A = Hh - (U + U^T)/2 with U = E Hh.
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_form(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  const Elem& e = E[active[blockIdx.x]];
+  if (e.fl[FL_RR_PATH] != 2) return;
+  const int J = e.J;
+  const int n = (single ? 1 : (has_p(e) ? 3 : 2)) * J;
+  const double* H = sm(e, SM_H);
+  const double* U = sm(e, SM_U);
+  double* A = sm(e, SM_A);
+  for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+    int i = p % n, j = p / n;
+    A[p] = H[p] - 0.5 * (U[p] + U[j + (long long)n * i]);
+  }
+}
+
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   __shared__ double red[32];
   __shared__ double lds[8192];
   DevTeam t{red};
   const Elem& e = E[active[blockIdx.x]];
-  if (e.fl[FL_RR_PATH] != 0) return;
+  if (e.fl[FL_RR_PATH] == 1) return;
   const int J = e.J;
   const int kb = single ? 1 : (has_p(e) ? 3 : 2);
   const int n = kb * J;
@@ -237,52 +278,65 @@ dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int sing
   double* Z = sm(e, SM_Z);
   double* vec = sm(e, SM_V);
   double* w = vec + 7 * n;
-  // workspace: SM_U and SM_L (consecutive), free after the reduction
-  syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_U), (int*)(vec + 10 * n), lds, 8192);
+  // workspace: SM_W0 and SM_W1 (consecutive)
+  syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, 8192);
 }
 
-extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
-dg_rr_finish(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
-  __shared__ double red[32];
-  DevTeam t{red};
+// Path 2: C = Y (the E Y / 2 correction follows on dg_sgemm).
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_cinit(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  const Elem& e = E[active[blockIdx.x]];
+  if (e.fl[FL_RR_PATH] != 2) return;
+  const int J = e.J;
+  const int n = (single ? 1 : (has_p(e) ? 3 : 2)) * J;
+  const double* Z = sm(e, SM_Z);
+  double* Cm = sm(e, SM_C);
+  for (int p = threadIdx.x; p < n * J; p += blockDim.x) Cm[p] = Z[p];
+}
+
+// Ritz values; path 0: undo the diagonal scaling of C; then, for k > 1,
+// E = C with the X rows zeroed (start of the next search direction).
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_post(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   const Elem& e = E[active[blockIdx.x]];
   const int J = e.J;
   const int kb = single ? 1 : (has_p(e) ? 3 : 2);
   const int n = kb * J;
-  double* H = sm(e, SM_H);
-  double* M = sm(e, SM_M);
-  double* A = sm(e, SM_A);
-  double* Lm = sm(e, SM_L);
-  double* U = sm(e, SM_U);
+  const int path = e.fl[FL_RR_PATH];
   double* Cm = sm(e, SM_C);
-  double* Tm = sm(e, SM_T);
-  double* Z = sm(e, SM_Z);
   double* vec = sm(e, SM_V);
-  double* dm = vec + 6 * n;
-  double* w = vec + 7 * n;
-  if (e.fl[FL_RR_PATH] == 0) {
-    // C = D^-1 L^-T Y
-    gemm(t, 1, 0, n, J, n, 1.0, Tm, n, Z, n, 0.0, Cm, n);
-    for (int p = t.tid(); p < n * J; p += t.nt()) Cm[p] /= dm[p % n];
-    t.sync();
-    for (int j = t.tid(); j < J; j += t.nt()) e.theta[j] = w[j];
-  }
-  t.sync();
-  t.sync();
+  const double* dm = vec + 6 * n;
+  const double* w = vec + 7 * n;
+  if (path == 0)
+    for (int p = threadIdx.x; p < n * J; p += blockDim.x) Cm[p] /= dm[p % n];
+  if (path != 1)
+    for (int j = threadIdx.x; j < J; j += blockDim.x) e.theta[j] = w[j];
   if (kb == 1) {
-    if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 0;
+    if (threadIdx.x == 0) e.fl[FL_HASP_NEXT] = 0;
     return;
   }
-  // ---- next search direction ----
-  double* Ez = Z;                        // n x J
-  double* Dn = Cm + (long long)n * J;    // output block of SM_C
-  for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] = (p % n) < J ? 0.0 : Cm[p];
-  t.sync();
-  gemm(t, 0, 0, n, J, n, 1.0, M, n, Ez, n, 0.0, U, n);        // U = M E
-  gemm(t, 1, 0, J, J, n, 1.0, Cm, n, U, n, 0.0, A, J);        // A = C^T M E
-  gemm(t, 0, 0, n, J, J, -1.0, Cm, n, A, J, 1.0, Ez, n);      // E <- E - C A
-  gemm(t, 0, 0, n, J, n, 1.0, M, n, Ez, n, 0.0, U, n);        // U = M D
-  gemm(t, 1, 0, J, J, n, 1.0, Ez, n, U, n, 0.0, A, J);        // A = D^T M D
+  __syncthreads();
+  double* Ez = sm(e, SM_Z);
+  for (int p = threadIdx.x; p < n * J; p += blockDim.x) Ez[p] = (p % n) < J ? 0.0 : Cm[p];
+}
+
+// Next search direction, after dg_sgemm formed A = D^T M D (J x J) for
+// D = E - C (C^T M E): scaled Cholesky of A; D <- D Dg^-1 with L^-1 kept in
+// SM_L for the final product D L^-T.  If it breaks, P is dropped for one
+// iteration.
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_rr_dchol(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  const Elem& e = E[active[blockIdx.x]];
+  const int J = e.J;
+  const int n = (has_p(e) ? 3 : 2) * J;
+  double* A = sm(e, SM_A);
+  double* Lm = sm(e, SM_L);
+  double* Ez = sm(e, SM_Z);
+  double* Cm = sm(e, SM_C);
+  double* Dn = Cm + (long long)n * J;
+  double* dm = sm(e, SM_V) + 6 * n;
   for (int p = t.tid(); p < J * J; p += t.nt()) {
     int i = p % J, j = p / J;
     if (i > j) A[p] = A[j + (long long)J * i];
@@ -302,10 +356,8 @@ dg_rr_finish(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
     pok = chol_lower(t, A, J, J, CHOL_TOL);
   }
   if (pok) {
-    tri_inv_lower(t, A, J, Lm, J, J);                          // Lm = L^-1
+    tri_inv_lower(t, A, J, Lm, J, J);                                     // Lm = L^-1
     for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] /= dm[p / n];
-    t.sync();
-    gemm(t, 0, 1, n, J, J, 1.0, Ez, n, Lm, J, 0.0, Dn, n);     // D = E D^-1 L^-T
     if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 1;
   } else {
     for (int p = t.tid(); p < n * J; p += t.nt()) Dn[p] = 0.0;

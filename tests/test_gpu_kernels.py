@@ -129,3 +129,29 @@ def test_precondition_matches_oracle(dev):
     print("precondition rel err", rel)
     assert rel < 1e-12
     h.close()
+
+
+@pytest.mark.parametrize("ta,tb,dm,dn,dk", [(0, 0, 0, 0, 0), (0, 1, 0, 0, 0), (1, 0, 0, 1, 0),
+                                            (1, 0, 1, 1, 0), (0, 0, 0, 1, 1), (0, 1, 0, 1, 1),
+                                            (1, 1, 1, 0, 0)])
+@pytest.mark.parametrize("J,kb", [(37, 3), (64, 2), (10, 1), (128, 3)])
+def test_small_gemm_matches_numpy(dev, ta, tb, dm, dn, dk, J, kb):
+    from paper_1506_08147_amd import small_gemm_batched
+    n = kb * J
+    d = lambda c: n if c == 0 else J  # noqa: E731
+    M, N, K = d(dm), d(dn), d(dk)
+    rng = np.random.default_rng(M * 7 + N * 3 + K + ta + 2 * tb)
+    cnt = 3
+    Aop = rng.standard_normal((cnt, M, K))
+    Bop = rng.standard_normal((cnt, K, N))
+    C0 = rng.standard_normal((cnt, M, N))
+    A = np.transpose(Aop, (0, 2, 1)) if ta else Aop        # stored matrix (rows, cols)
+    B = np.transpose(Bop, (0, 2, 1)) if tb else Bop
+    # column-major per problem: tensor shape (cols, rows)
+    At = _t(np.transpose(A, (0, 2, 1)), dev)
+    Bt = _t(np.transpose(B, (0, 2, 1)), dev)
+    Ct = _t(np.transpose(C0, (0, 2, 1)), dev)
+    out = small_gemm_batched(ta, tb, J, kb, dm, dn, dk, At, Bt, Ct, alpha=0.5, beta=-1.25)
+    got = np.transpose(out.cpu().numpy(), (0, 2, 1))
+    ref = 0.5 * np.einsum("bik,bkj->bij", Aop, Bop) - 1.25 * C0
+    assert np.abs(got - ref).max() <= 1e-13 * np.sqrt(K) * 10
