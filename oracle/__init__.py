@@ -17,12 +17,16 @@ large scale density functional theory calculations", Sec. II.A):
   Teter-preconditioned LOBPCG (the method of Sec. II.B, "Generation of the
   ALB functions") -- ``dense``, ``teter``, ``lobpcg``;
 * restriction of the eigenvectors from Q_K to the element E_K followed by
-  orthonormalisation, done as an SVD truncation -- ``alb``.
+  orthonormalisation, done as an SVD truncation -- ``alb``;
+* a learned refinement of the Teter preconditioner (not in the paper): the
+  network, its training loss and gradient, Adam, the per-shell spectral sums
+  of residual/correction pairs and the Teter fallback -- ``learned``.
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against closed
 forms, textbook special cases, independent libraries or brute force.  The
-one result with no such pin is the LOBPCG iteration count, which depends on
-the path taken: **parity unpinned** (iteration counts are only compared
-between runs with identical settings).
+results with no such pin are the LOBPCG iteration count, which depends on
+the path taken, and what a trained network gains over Teter's factor:
+**parity unpinned** (iteration counts are only compared between runs with
+identical settings).
 """
-from . import hamiltonian, dense, teter, lobpcg, alb, solve  # noqa: F401
+from . import hamiltonian, dense, teter, lobpcg, alb, solve, learned  # noqa: F401

@@ -225,3 +225,29 @@ def uneven_batch(n_elem=200, seed=0, elements=None, edges=EDGES, j_range=(64, 25
                             with_x0=False))
     _fill_x0(out, 4, seed, elements)
     return out
+
+
+# ---------------------------------------------------------------- MLP inputs
+MLP_HIDDEN = 64
+MLP_NW = 3 * MLP_HIDDEN + MLP_HIDDEN + MLP_HIDDEN * MLP_HIDDEN + 3 * MLP_HIDDEN + 1   # 4481
+MLP_NTOT = MLP_NW + 6
+
+
+def mlp_init(seed=0, last_layer=0.0):
+    """Seeded initial parameters of the learned preconditioner's network, FP32,
+    in the order W1 [64][3], b1, W2 [64][64], b2, w3, b3, mu [3], sd [3]:
+    hidden weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases 0, output layer
+    U(-last_layer, last_layer) (0: the network starts as the identity factor),
+    mu = 0, sd = 1."""
+    h = MLP_HIDDEN
+    rng = np.random.default_rng([5, 0, seed, 2])
+    w = np.zeros(MLP_NTOT, dtype=np.float32)
+    o = 0
+    w[o:o + 3 * h] = rng.uniform(-1, 1, 3 * h) / np.sqrt(3.0); o += 3 * h
+    o += h
+    w[o:o + h * h] = rng.uniform(-1, 1, h * h) / np.sqrt(h); o += h * h
+    o += h
+    w[o:o + h] = rng.uniform(-1, 1, h) * last_layer; o += h
+    o += 1
+    w[o + 3:o + 6] = 1.0
+    return w
