@@ -58,6 +58,8 @@ extern "C" {
 #define DGDFT_PREC_MIXED       1   /* FP32 FFT/pointwise; reserved, see design    */
 
 #define DGDFT_PRECOND_TETER    0
+#define DGDFT_PRECOND_LEARNED  1   /* Teter factor times a learned per-shell gain *
+                                    * (network below), Teter fallback per band    */
 #define DGDFT_PRECOND_NONE     2   /* identity (for tests)                        */
 
 typedef struct dgdft_alb dgdft_alb;   /* opaque handle */
@@ -77,6 +79,9 @@ typedef struct dgdft_alb_opts {
     const int32_t* elem_lo;   /* [n_elem][3] restriction box, half-open; NULL =   */
     const int32_t* elem_hi;   /*   central floor(n/3) points per axis             */
     const int32_t* n_alb;     /* [n_elem] ALBs per element; NULL = J/2            */
+    const float* mlp_weights; /* device [DGDFT_MLP_NTOT]: network of the learned  *
+                               * preconditioner (read at every solve; may also be  *
+                               * set later with dgdft_alb_set_mlp)                 */
 } dgdft_alb_opts;
 
 /* Kleinman-Bylander projectors of the whole batch, CSR by projector
@@ -106,6 +111,8 @@ typedef struct dgdft_alb_stats {
     int32_t n_chol_fallback;  /* W orthonormalisations that fell back to SVQB      */
     int32_t n_rr_fallback;    /* Rayleigh-Ritz steps with a rank-deficient basis   */
     int32_t n_p_drop;         /* iterations that restarted without P               */
+    int32_t n_ql_fail;        /* small eigensolves whose QL iteration hit its cap  */
+    int32_t n_teter_fallback; /* bands switched to the Teter factor (learned mode)  */
     int32_t reserved;
 } dgdft_alb_stats;
 
@@ -236,6 +243,107 @@ int32_t dgdft_small_gemm_batched(int32_t ta, int32_t tb, int32_t count, int32_t 
                                  int32_t kb, int32_t dm, int32_t dn, int32_t dk,
                                  double alpha, const double* A, const double* B,
                                  double beta, double* C, void* stream);
+
+/* ---- learned preconditioner --------------------------------------------
+ * Not in the paper: a refinement of its Teter preconditioner (Sec. II.B).
+ * Band i of an element gets the factor
+ *   K_i(G) = K_Teter(t / T_i) * exp(f(u)),  f = 2 tanh(z(u) / 2),  t = |G|^2/2,
+ *   u = ((log max(t / T_i, 1e-3), theta_i, Vbar) - mu) / sd,
+ * with T_i as for Teter, theta_i = x_i^T H x_i and Vbar the mean of V.  z is a
+ * perceptron 3 -> 64 -> 64 -> 1 with SiLU activations, evaluated in FP32 with
+ * its trained weights rounded to bfloat16; the bound keeps K_i within a factor
+ * e^2 of Teter's.  K_i depends on G through |G|^2
+ * only, so it is tabulated per shell (distinct value of |G|^2 on the grid).
+ * A band whose residual has not fallen below 0.9 times its value three
+ * iterations earlier uses the Teter factor for the rest of the solve.
+ *
+ * Parameter vector, FP32, DGDFT_MLP_NTOT values: W1 [64][3] (row = hidden
+ * unit), b1 [64], W2 [64][64] (row = output unit), b2 [64], w3 [64], b3,
+ * mu [3], sd [3] (the last six are not trained). */
+#define DGDFT_MLP_HIDDEN  64
+#define DGDFT_MLP_NW      4481
+#define DGDFT_MLP_NTOT    4487
+
+/* Replace the network used by DGDFT_PRECOND_LEARNED (device pointer, read at
+ * every solve; the caller keeps it alive). */
+int32_t dgdft_alb_set_mlp(dgdft_alb* h, const float* weights);
+
+/* Shells of element `elem`: n_shell (host) and, if t_shell is non-NULL, the
+ * ascending values of |G|^2/2 (host [n_shell]).  Equal values up to 1e-12
+ * relative form one shell. */
+int32_t dgdft_alb_shells(const dgdft_alb* h, int32_t elem, int32_t* n_shell, double* t_shell);
+
+/* Training pairs.  A sample is one band of one element at one LOBPCG
+ * iteration; its rows are the element's shells.  With r the residual of the
+ * band and e = (I - X X^T) x~ its ideal correction (x~: the band's Ritz
+ * vector projected on the converged eigenvectors of its cluster, i.e. of
+ * eigenvalues within 1e-6 Ha), under the unnormalised DFT:
+ *   a[row] = sum_{G in shell} Re(conj(r^(G)) e^(G)),  b[row] = sum |r^(G)|^2,
+ *   s_feat[4 s + 3] = e2 = sum_G |e^(G)|^2.
+ * The training loss of a sample is 1 - (sum K a)^2 / ((sum K^2 b) e2) with K
+ * the factor above on each shell.  All arrays are device memory. */
+typedef struct dgdft_pairs {
+    int64_t n_samples;
+    int32_t n_elem;
+    const int64_t* shell_off;  /* [n_elem + 1] offsets into t_shell               */
+    const double*  t_shell;    /* |G|^2/2 per shell, per element                  */
+    const int32_t* s_elem;     /* [n_samples] element of the sample               */
+    const int64_t* s_row;      /* [n_samples] first row of the sample in a, b     */
+    const double*  s_feat;     /* [n_samples][4] theta, T, Vbar, e2               */
+    const double*  a;
+    const double*  b;
+} dgdft_pairs;
+
+/* Number of samples and rows dgdft_alb_log_pairs writes for max_log
+ * iterations: samples sum_e max_log J_e, rows sum_e max_log J_e n_shell_e. */
+int32_t dgdft_alb_log_capacity(const dgdft_alb* h, int32_t max_log, int64_t* n_samples,
+                               int64_t* n_rows);
+
+/* Generate training pairs with the solver itself: a first solve from X0
+ * gives the converged eigenvectors; a second solve from X0 records, at each
+ * of its first max_log iterations, every band's shell sums (before the
+ * preconditioner is applied).  Sample of element e, iteration k, band i:
+ * index sum_{e' < e} max_log J_e' + k J_e + i; its rows follow the same
+ * order (n_shell_e each).  Outputs (device, sized by
+ * dgdft_alb_log_capacity): s_elem, s_row, s_feat, a, b; n_logged (host
+ * [n_elem]) = iterations recorded per element (samples of later iterations
+ * are left with e2 = 0).  V, kb as in dgdft_alb_solve.  Requires J >= 2 and
+ * at most 4096 shells per element. */
+int32_t dgdft_alb_log_pairs(dgdft_alb* h, const double* V, const dgdft_kb* kb, const double* X0,
+                            int32_t max_log, int32_t* s_elem, int64_t* s_row, double* s_feat,
+                            double* a, double* b, int32_t* n_logged, void* stream);
+
+/* Training options (zero-initialise; 0 = default). */
+typedef struct dgdft_train_opts {
+    int32_t epochs;           /* default 10                                     */
+    int32_t batch;            /* samples per Adam step, default 256             */
+    double  lr;               /* default 1e-3                                   */
+    double  beta1, beta2, eps;/* defaults 0.9, 0.999, 1e-8                       */
+    uint64_t seed;            /* minibatch order                                */
+    int32_t set_norm;         /* 1: set mu, sd from the selected samples first  */
+} dgdft_train_opts;
+
+/* Train the network on the GPU (hand-written forward, backward and Adam
+ * kernels; FP32 master weights, bfloat16 evaluation, FP32 accumulation).
+ * index: host [n_index] samples to use (NULL = all); samples with e2 <= 0
+ * are skipped.  weights: device [DGDFT_MLP_NTOT], updated in place.
+ * loss_hist: host [epochs] mean sample loss of each epoch, or NULL. */
+int32_t dgdft_mlp_train(const dgdft_pairs* data, const int64_t* index, int64_t n_index,
+                        const dgdft_train_opts* opts, float* weights, double* loss_hist,
+                        void* stream);
+
+/* Mean loss (host) and its gradient with respect to the DGDFT_MLP_NW trained
+ * parameters (device [DGDFT_MLP_NW], FP64) over the selected samples, at the
+ * bfloat16-rounded weights (one forward + backward pass; exported for the
+ * gradient check). */
+int32_t dgdft_mlp_grad(const dgdft_pairs* data, const int64_t* index, int64_t n_index,
+                       const float* weights, double* loss, double* grad, void* stream);
+
+/* f (after the bound) for n raw input rows feat (device [n][3] = x, theta, Vbar with x = t/T;
+ * the logarithm and standardisation are applied inside) into f (device [n]).
+ * Exported for tests. */
+int32_t dgdft_mlp_eval(const double* feat, int64_t n, const float* weights, double* f,
+                       void* stream);
 
 /* Message of the last failure on h (NULL: of the last failed create). */
 const char* dgdft_alb_last_error(const dgdft_alb* h);

@@ -11,12 +11,14 @@ learned refinement of it and the data it is trained on:
   distinct values of |G|^2 on the FFT box ("shells").  Shell s has kinetic
   energy t_s; shells are ascending and equal values (up to 1e-12 relative)
   are one shell.
-* Model.  K_i(G) = K_Teter(t / T_i) * exp(f(u)), where f is a multilayer
-  perceptron 3 -> 64 -> 64 -> 1 with SiLU activations and
-  u = ((log max(x, XMIN), theta_i, Vbar) - mu) / sd: the Teter ratio x of the
-  shell, the Ritz value theta_i of the band and the mean local potential of the
-  element, standardised with constants mu, sd fixed before training.  With the
-  last layer zero, f = 0 and the preconditioner is exactly Teter's.  The
+* Model.  K_i(G) = K_Teter(t / T_i) * exp(f(u)), f = FMAX tanh(z(u) / FMAX),
+  where z is a multilayer perceptron 3 -> 64 -> 64 -> 1 with SiLU activations
+  and u = ((log max(x, XMIN), theta_i, Vbar) - mu) / sd: the Teter ratio x of
+  the shell, the Ritz value theta_i of the band and the mean local potential
+  of the element, standardised with constants mu, sd fixed before training.
+  The bound keeps the learned factor within exp(+-FMAX) of Teter's, so the
+  preconditioned residuals cannot collapse onto a few shells.  With the last
+  layer zero, f = 0 and the preconditioner is exactly Teter's.  The
   weights are kept in FP32 and rounded to bfloat16 (round to nearest, ties to
   even) for every evaluation; gradients are taken with respect to the rounded
   values and applied to the FP32 copy.
@@ -52,6 +54,7 @@ H = 64
 NW = 3 * H + H + H * H + H + H + 1          # 4481 trained parameters
 NTOT = NW + 6                                # + mu[3], sd[3]
 XMIN = 1e-3
+FMAX = 2.0
 CLUSTER_TOL = 1e-6
 STALL_FACTOR = 0.9
 STALL_LAG = 3
@@ -175,8 +178,9 @@ def forward(w, F, bf16=True):
     H1 = silu(Z1)
     Z2 = H1 @ W2.T + part(p, "b2")
     H2 = silu(Z2)
-    f = H2 @ part(p, "w3") + part(p, "b3")[0]
-    return f, (p, U, Z1, H1, Z2, H2)
+    z = H2 @ part(p, "w3") + part(p, "b3")[0]
+    f = FMAX * np.tanh(z / FMAX)
+    return f, (p, U, Z1, H1, Z2, H2, z)
 
 
 def gain_table(w, t_shell, T, theta, vbar, fallback=None, bf16=True):
@@ -203,7 +207,7 @@ def loss_and_grad(w, samples, bf16=True):
     n = len(samples)
     for smp in samples:
         F = features(smp["t"], smp["T"], smp["theta"], smp["vbar"])[0]
-        f, (p, U, Z1, H1, Z2, H2) = forward(w, F, bf16)
+        f, (p, U, Z1, H1, Z2, H2, z) = forward(w, F, bf16)
         x = np.asarray(smp["t"]) / smp["T"]
         K = teter_k(x) * np.exp(f)
         a, b, e2 = np.asarray(smp["a"]), np.asarray(smp["b"]), smp["e2"]
@@ -211,7 +215,7 @@ def loss_and_grad(w, samples, bf16=True):
         s2 = np.sum(K * K * b)
         total += 1.0 - s1 * s1 / (s2 * e2)
         dK = (-2.0 * s1 / (s2 * e2)) * a + (s1 * s1 / (s2 * s2 * e2)) * 2.0 * K * b
-        df = dK * K / n
+        df = dK * K / n * (1.0 - np.tanh(z / FMAX) ** 2)     # with respect to z
         W2 = part(p, "W2").reshape(H, H)
         w3 = part(p, "w3")
         g_w3 = H2.T @ df
@@ -238,11 +242,14 @@ def adam_step(w, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def normalisation(samples):
-    """mu, sd of the raw features over every (sample, shell) row."""
+    """mu, sd of the raw features over every (sample, shell) row (population
+    standard deviation; 1 where it is below 1e-6 of the root mean square)."""
     rows = np.concatenate([features(s["t"], s["T"], s["theta"], s["vbar"])[0] for s in samples])
     mu = rows.mean(axis=0)
     sd = rows.std(axis=0)
-    sd = np.where(sd > 0.0, sd, 1.0)
+    # an input that is constant over the data (up to rounding) is left unscaled
+    rms = np.sqrt(np.mean(rows * rows, axis=0))
+    sd = np.where(sd > 1e-6 * rms, sd, 1.0)
     return mu, sd
 
 

@@ -14,6 +14,9 @@ from .binding import (  # noqa: F401
     DGDFTError,
     gemm_batched,
     load_library,
+    mlp_eval,
+    mlp_grad,
+    mlp_train,
     small_gemm_batched,
     small_syev,
     LIB_PATH,

@@ -19,13 +19,17 @@ EXPORTS = (
     "dgdft_alb_solve", "dgdft_alb_apply_h", "dgdft_alb_precondition", "dgdft_small_syev",
     "dgdft_gemm_batched", "dgdft_alb_last_error", "dgdft_strerror", "dgdft_alb_profile",
     "dgdft_alb_kernel_stats", "dgdft_kernel_class_name", "dgdft_small_gemm_batched",
+    "dgdft_alb_set_mlp", "dgdft_alb_shells", "dgdft_alb_log_capacity", "dgdft_alb_log_pairs",
+    "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval",
 )
+MLP_NW = 4481
+MLP_NTOT = 4487
 KCLASS = ("dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
           "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm")
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM",
           -4: "EHIP", -5: "EBREAKDOWN"}
-PRECOND = {"teter": 0, "none": 2}
+PRECOND = {"teter": 0, "learned": 1, "none": 2}
 
 
 class LibraryMissing(ImportError):
@@ -42,7 +46,7 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("poll_every", C.c_int32),
                 ("elem_lo", C.POINTER(C.c_int32)), ("elem_hi", C.POINTER(C.c_int32)),
-                ("n_alb", C.POINTER(C.c_int32))]
+                ("n_alb", C.POINTER(C.c_int32)), ("mlp_weights", C.c_void_p)]
 
 
 class KB(C.Structure):
@@ -53,7 +57,20 @@ class KB(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("max_res", C.c_double),
                 ("n_chol_fallback", C.c_int32), ("n_rr_fallback", C.c_int32),
-                ("n_p_drop", C.c_int32), ("reserved", C.c_int32)]
+                ("n_p_drop", C.c_int32), ("n_ql_fail", C.c_int32),
+                ("n_teter_fallback", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Pairs(C.Structure):
+    _fields_ = [("n_samples", C.c_int64), ("n_elem", C.c_int32), ("shell_off", C.c_void_p),
+                ("t_shell", C.c_void_p), ("s_elem", C.c_void_p), ("s_row", C.c_void_p),
+                ("s_feat", C.c_void_p), ("a", C.c_void_p), ("b", C.c_void_p)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double),
+                ("seed", C.c_uint64), ("set_norm", C.c_int32)]
 
 
 _lib = None
@@ -100,6 +117,20 @@ def load_library():
     lib.dgdft_small_gemm_batched.restype = i32
     lib.dgdft_kernel_class_name.argtypes = [i32]
     lib.dgdft_kernel_class_name.restype = C.c_char_p
+    lib.dgdft_alb_set_mlp.argtypes = [vp, vp]
+    lib.dgdft_alb_set_mlp.restype = i32
+    lib.dgdft_alb_shells.argtypes = [vp, i32, P(C.c_int32), P(dbl)]
+    lib.dgdft_alb_shells.restype = i32
+    lib.dgdft_alb_log_capacity.argtypes = [vp, i32, P(i64), P(i64)]
+    lib.dgdft_alb_log_capacity.restype = i32
+    lib.dgdft_alb_log_pairs.argtypes = [vp, vp, P(KB), vp, i32, vp, vp, vp, vp, vp, P(C.c_int32), vp]
+    lib.dgdft_alb_log_pairs.restype = i32
+    lib.dgdft_mlp_train.argtypes = [P(Pairs), P(i64), i64, P(TrainOpts), vp, P(dbl), vp]
+    lib.dgdft_mlp_train.restype = i32
+    lib.dgdft_mlp_grad.argtypes = [P(Pairs), P(i64), i64, vp, P(dbl), vp, vp]
+    lib.dgdft_mlp_grad.restype = i32
+    lib.dgdft_mlp_eval.argtypes = [vp, i64, vp, vp, vp]
+    lib.dgdft_mlp_eval.restype = i32
     _lib = lib
     return lib
 
@@ -125,7 +156,7 @@ class ALB:
     """
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
-                 elem_hi=None, n_alb=None, precond="teter"):
+                 elem_hi=None, n_alb=None, precond="teter", mlp_weights=None):
         import torch  # noqa: F401  (device memory and streams)
         self.lib = load_library()
         self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
@@ -138,6 +169,9 @@ class ALB:
         o.tol = tol
         o.max_iter = max_iter
         o.poll_every = 1
+        if mlp_weights is not None:
+            self._mlp = mlp_weights
+            o.mlp_weights = mlp_weights.data_ptr()
         if elem_lo is not None:
             lo, plo = _i32(np.asarray(elem_lo).reshape(-1))
             hi, phi = _i32(np.asarray(elem_hi).reshape(-1))
@@ -233,9 +267,54 @@ class ALB:
         self._check(rc, allow=(0, 1))
         stats = [dict(iters=s.iters, converged=bool(s.converged), max_res=s.max_res,
                       n_chol_fallback=s.n_chol_fallback, n_rr_fallback=s.n_rr_fallback,
-                      n_p_drop=s.n_p_drop, n_ql_fail=s.reserved) for s in st]
+                      n_p_drop=s.n_p_drop, n_ql_fail=s.n_ql_fail,
+                      n_teter_fallback=s.n_teter_fallback) for s in st]
         return dict(status=rc, eigvals=vals, eigvecs=vecs, albs=albs, sigma=sig[:snalb],
                     stats=stats)
+
+    def set_mlp(self, weights):
+        """Network of the learned preconditioner (device FP32 tensor [MLP_NTOT])."""
+        self._mlp = weights
+        self._check(self.lib.dgdft_alb_set_mlp(self.h, _ptr(weights)))
+
+    def shells(self, e):
+        """Ascending |G|^2/2 shell values of element e (numpy)."""
+        n = C.c_int32()
+        self._check(self.lib.dgdft_alb_shells(self.h, e, C.byref(n), None))
+        t = np.zeros(n.value)
+        self._check(self.lib.dgdft_alb_shells(self.h, e, C.byref(n),
+                                              t.ctypes.data_as(C.POINTER(C.c_double))))
+        return t
+
+    def log_pairs(self, V, kbt, X0, max_log):
+        """Training pairs from two solves (see dgdft_alb_log_pairs): a dict of
+        device tensors in the dgdft_pairs layout plus n_logged (numpy)."""
+        import torch
+        dev = X0.device
+        ns, nr = C.c_int64(), C.c_int64()
+        self._check(self.lib.dgdft_alb_log_capacity(self.h, max_log, C.byref(ns), C.byref(nr)))
+        ns, nr = ns.value, nr.value
+        out = dict(s_elem=torch.empty(ns, dtype=torch.int32, device=dev),
+                   s_row=torch.empty(ns, dtype=torch.int64, device=dev),
+                   s_feat=torch.empty(4 * ns, dtype=torch.float64, device=dev),
+                   a=torch.empty(max(nr, 1), dtype=torch.float64, device=dev),
+                   b=torch.empty(max(nr, 1), dtype=torch.float64, device=dev))
+        nl = np.zeros(self.n_elem, dtype=np.int32)
+        k = self._kb_struct(kbt) if V is not None else None
+        rc = self.lib.dgdft_alb_log_pairs(self.h, _ptr(V), C.byref(k) if k else None, _ptr(X0),
+                                          max_log, _ptr(out["s_elem"]), _ptr(out["s_row"]),
+                                          _ptr(out["s_feat"]), _ptr(out["a"]), _ptr(out["b"]),
+                                          nl.ctypes.data_as(C.POINTER(C.c_int32)), _stream())
+        self._check(rc)
+        tsh = [self.shells(e) for e in range(self.n_elem)]
+        off = np.zeros(self.n_elem + 1, dtype=np.int64)
+        off[1:] = np.cumsum([t.shape[0] for t in tsh])
+        out["shell_off"] = torch.from_numpy(off).to(dev)
+        out["t_shell"] = torch.from_numpy(np.concatenate(tsh)).to(dev)
+        out["n_samples"] = ns
+        out["n_elem"] = self.n_elem
+        out["n_logged"] = nl
+        return out
 
     def split(self, out, e):
         """Per-element views (eigvals, eigvecs (Ng x J), albs (NE x n_alb), sigma)."""
@@ -339,3 +418,62 @@ def gemm_batched(trans, A, B, alpha=1.0, beta=0.0, Cin=None):
     if rc != 0:
         raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
     return Cout
+
+
+def _pairs_struct(d):
+    p = Pairs()
+    p.n_samples = int(d["n_samples"])
+    p.n_elem = int(d["n_elem"])
+    for f in ("shell_off", "t_shell", "s_elem", "s_row", "s_feat", "a", "b"):
+        setattr(p, f, d[f].data_ptr())
+    return p
+
+
+def _index(index):
+    if index is None:
+        return None, None, 0
+    idx = np.ascontiguousarray(index, dtype=np.int64)
+    return idx, idx.ctypes.data_as(C.POINTER(C.c_int64)), idx.shape[0]
+
+
+def mlp_train(pairs, weights, index=None, epochs=10, batch=256, lr=1e-3, seed=0, set_norm=True,
+              beta1=0.9, beta2=0.999, eps=1e-8):
+    """Train the learned preconditioner's network in place on the GPU
+    (dgdft_mlp_train); returns the mean loss of each epoch."""
+    lib = load_library()
+    p = _pairs_struct(pairs)
+    keep, ip, n = _index(index)
+    o = TrainOpts(epochs=epochs, batch=batch, lr=lr, beta1=beta1, beta2=beta2, eps=eps, seed=seed,
+                  set_norm=1 if set_norm else 0)
+    hist = np.zeros(epochs)
+    rc = lib.dgdft_mlp_train(C.byref(p), ip, n, C.byref(o), _ptr(weights),
+                             hist.ctypes.data_as(C.POINTER(C.c_double)), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return hist
+
+
+def mlp_grad(pairs, weights, index=None):
+    """(mean loss, gradient tensor [MLP_NW] FP64) at the given weights."""
+    import torch
+    lib = load_library()
+    p = _pairs_struct(pairs)
+    keep, ip, n = _index(index)
+    g = torch.empty(MLP_NW, dtype=torch.float64, device=weights.device)
+    loss = C.c_double()
+    rc = lib.dgdft_mlp_grad(C.byref(p), ip, n, _ptr(weights), C.byref(loss), _ptr(g), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return loss.value, g
+
+
+def mlp_eval(feat, weights):
+    """f for raw input rows feat (device [n, 3]: x = t/T, theta, Vbar)."""
+    import torch
+    lib = load_library()
+    feat = feat.contiguous()
+    f = torch.empty(feat.shape[0], dtype=torch.float64, device=feat.device)
+    rc = lib.dgdft_mlp_eval(_ptr(feat), feat.shape[0], _ptr(weights), _ptr(f), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return f

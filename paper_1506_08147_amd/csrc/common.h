@@ -55,6 +55,15 @@ struct Elem {
   long long small_stride;    // doubles per n x n matrix in `small`
   int* fl;                   // FL_COUNT status words, read back by the host
   long long off_ng, off_ngj, off_j, off_alb, off_nalb;   // offsets in batch arrays
+  // learned preconditioner and its pair log
+  int nsh;                   // |G|^2 shells of the grid
+  const int* shell_of;       // ng: shell of each grid frequency (flat, x fastest)
+  const double* t_shell;     // nsh: |G|^2/2 per shell, ascending
+  double* gain;              // J * nsh: exp(f) per band and shell
+  double* stall;             // 4 J: last three residuals and the Teter-fallback flag
+  double* vbar;              // 1: mean of V
+  double* thstar;            // J: converged eigenvalues (pair log)
+  long long log_s0, log_r0;  // first sample / row of the element in the pair log
 };
 
 // Status words written by the device (one group per element).  The host
@@ -69,8 +78,10 @@ enum Flag {
   FL_BREAKDOWN,       // unrecoverable rank deficiency
   FL_QL_FAIL,         // tridiagonal QL did not converge
   FL_NONFINITE,       // non-finite input seen
-  FL_RR_PATH,         // 0: Rayleigh-Ritz via Cholesky of M, 1: eigenvector reduction
-  FL_COUNT = 10
+  FL_RR_PATH,         // Rayleigh-Ritz reduction taken (0 Cholesky, 1 eigenvectors of M, 2 first order)
+  FL_LOGK,            // iterations written to the pair log
+  FL_STALLK,          // residual histories recorded for the Teter fallback
+  FL_COUNT = 12
 };
 
 // Virtual slots resolved per element through its buffer parity:

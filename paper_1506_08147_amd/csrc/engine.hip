@@ -11,11 +11,13 @@
 #include "fft.hip"
 #include "gemm.hip"
 #include "lobpcg.hip"
+#include "learned.hip"
 
 #include "../../include/dgdft_alb.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -63,6 +65,20 @@ struct dgdft_alb {
   double* proj_arena = nullptr;    // proj + projx
   size_t proj_cap = 0;
   int* d_flag = nullptr;           // scratch flag for input checks
+  // learned preconditioner: shells, gain tables, fallback state, Vbar, and
+  // the converged eigenvalues used by the pair log (one arena)
+  void* lrn_arena = nullptr;
+  double* stall_arena = nullptr;   // 4 * sumJ
+  double* thstar_arena = nullptr;  // sumJ
+  std::vector<std::vector<double>> tsh_host;
+  const float* mlp_w = nullptr;
+  // pair log (active during the second solve of dgdft_alb_log_pairs)
+  bool log_on = false;
+  int log_max = 0;
+  std::vector<int> log_k;
+  int* log_selem = nullptr;
+  long long* log_srow = nullptr;
+  double *log_feat = nullptr, *log_a = nullptr, *log_b = nullptr;
   // prefix ring
   int* ring_d = nullptr;
   int* ring_h = nullptr;           // pinned
@@ -231,7 +247,8 @@ struct dgdft_alb {
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
     hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
-                       P2.prefix, P2.na, col0, ncols_fixed, opts.precond == DGDFT_PRECOND_NONE ? 2 : 1);
+                       P2.prefix, P2.na, col0, ncols_fixed,
+                       opts.precond == DGDFT_PRECOND_NONE ? 2 : opts.precond == DGDFT_PRECOND_LEARNED ? 3 : 1);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, 32.0 * pts);
     hipLaunchKernelGGL(big ? dg_fft_xy_inv_l : dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0,
@@ -407,6 +424,40 @@ struct dgdft_alb {
     sgemm(act, single, 0, 1, SM_Z, 0, SM_L, 0, SM_C, 1, N, Jc, Jc, N, Jc, N, 1.0, 0.0, -1, 1);
   }
 
+  // Pair log: bands [i0, i0 + cnt) of every element in `act`.
+  void log_chunk(const std::vector<int>& act, int i0, int cnt) {
+    auto P0 = make_prefix(act, [&](int e) { return cnt * cdiv(eh[e].ng, 4096); });
+    hipLaunchKernelGGL(dg_interleave, dim3(P0.total), dim3(256), 0, stream, ed, P0.active, P0.prefix,
+                       P0.na, (int)S_W, (int)S_W2, (int)S_HW, i0, cnt);
+    const bool big = big_planes(act);
+    auto P1 = make_prefix(act, [&](int e) { return cnt * eh[e].n3; });
+    hipLaunchKernelGGL(big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0,
+                       stream, ed, P1.active, P1.prefix, P1.na, (int)S_HW, 0, 2 * cnt);
+    auto P2 = make_prefix(act, [&](int e) { return cnt * (eh[e].n2 / 2 + 1); });
+    hipLaunchKernelGGL(dg_fft_z_bin, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
+                       P2.prefix, P2.na, i0, log_max, log_a, log_b, log_feat);
+    HCHECK(hipGetLastError());
+  }
+
+  // Learned preconditioner: Teter-fallback bookkeeping (once per iteration)
+  // and the per-(band, shell) gain table from the network.
+  void stall_step(const std::vector<int>& act) {
+    auto P = make_prefix(act, [&](int) { return 1; });
+    pbeg(DGDFT_K_OTHER, 0, 0);
+    hipLaunchKernelGGL(dg_stall, dim3(P.na), dim3(256), 0, stream, ed, P.active, P.na);
+    pend();
+    HCHECK(hipGetLastError());
+  }
+
+  void gain_table(const std::vector<int>& act, int use_stall) {
+    auto P = make_prefix(act, [&](int e) { return cdiv(eh[e].J * eh[e].nsh, 256); });
+    pbeg(DGDFT_K_OTHER, 0, 0);
+    hipLaunchKernelGGL(dg_mlp_gain, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na,
+                       mlp_w, use_stall);
+    pend();
+    HCHECK(hipGetLastError());
+  }
+
   void per_elem(const std::vector<int>& act, int which, int arg, double* out = nullptr) {
     auto P = make_prefix(act, [&](int) { return 1; });
     if (P.na == 0) return;
@@ -511,6 +562,7 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   (void)hipFree(h->kb_arena);
   (void)hipFree(h->proj_arena);
   (void)hipFree(h->d_flag);
+  (void)hipFree(h->lrn_arena);
   (void)hipFree(h->ring_d);
   (void)hipHostFree(h->ring_h);
   (void)hipHostFree(h->h_resid);
@@ -522,6 +574,36 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   (void)hipSetDevice(cur);
   delete h;
+}
+
+// |G|^2/2 shells of an element's grid: shell index of every frequency (flat,
+// x fastest) and the ascending distinct values (equal up to 1e-12 relative).
+static void grid_shells(const Elem& E, std::vector<int>& shell_of, std::vector<double>& t_shell) {
+  const int n1 = E.n1, n2 = E.n2, n3 = E.n3;
+  auto g = [](int k, int n, double L) { return 2.0 * M_PI * (double)(k <= n / 2 ? k : k - n) / L; };
+  std::vector<double> t((size_t)E.ng);
+  for (int k = 0; k < n3; ++k) {
+    double g3 = g(k, n3, E.L[2]);
+    for (int j = 0; j < n2; ++j) {
+      double g2 = g(j, n2, E.L[1]);
+      for (int i = 0; i < n1; ++i) {
+        double g1 = g(i, n1, E.L[0]);
+        t[(size_t)i + (size_t)n1 * (j + (size_t)n2 * k)] = 0.5 * (g3 * g3 + g2 * g2 + g1 * g1);
+      }
+    }
+  }
+  std::vector<int> order((size_t)E.ng);
+  for (int q = 0; q < E.ng; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t[a] < t[b]; });
+  shell_of.assign((size_t)E.ng, 0);
+  t_shell.clear();
+  double prev = 0.0;
+  for (int q = 0; q < E.ng; ++q) {
+    double v = t[order[q]];
+    if (q == 0 || v - prev > 1e-12 * std::max(1.0, v)) t_shell.push_back(v);
+    shell_of[order[q]] = (int)t_shell.size() - 1;
+    prev = v;
+  }
 }
 
 int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box, int32_t n_elem,
@@ -537,6 +619,13 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
   if (h->opts.tol <= 0.0) h->opts.tol = 1e-8;
   if (h->opts.max_iter <= 0) h->opts.max_iter = 500;
   if (h->opts.poll_every <= 0) h->opts.poll_every = 1;
+  if (h->opts.precond != DGDFT_PRECOND_TETER && h->opts.precond != DGDFT_PRECOND_LEARNED &&
+      h->opts.precond != DGDFT_PRECOND_NONE) {
+    g_create_error = "unknown preconditioner";
+    delete h;
+    return DGDFT_EINVAL;
+  }
+  h->mlp_w = h->opts.mlp_weights;
   if (h->opts.precision != DGDFT_PREC_FP64) {
     g_create_error = "only DGDFT_PREC_FP64 is implemented";
     delete h;
@@ -636,6 +725,36 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       E.gpart = (double*)p;
     }
     HCHECK(hipMalloc(&h->vec_arena, sizeof(double) * 5 * h->sumJ));
+    // ---- shells, gain tables, fallback state, Vbar, converged eigenvalues
+    {
+      std::vector<std::vector<int>> sof(n_elem);
+      h->tsh_host.assign(n_elem, {});
+      size_t bytes = 0;
+      for (int e = 0; e < n_elem; ++e) {
+        grid_shells(h->eh[e], sof[e], h->tsh_host[e]);
+        Elem& E = h->eh[e];
+        E.nsh = (int)h->tsh_host[e].size();
+        bytes += align256(sizeof(int) * (size_t)E.ng) + align256(sizeof(double) * E.nsh) +
+                 align256(sizeof(double) * (size_t)E.J * E.nsh) + align256(sizeof(double));
+      }
+      bytes += align256(sizeof(double) * 4 * h->sumJ) + align256(sizeof(double) * h->sumJ);
+      HCHECK(hipMalloc(&h->lrn_arena, bytes));
+      char* p = (char*)h->lrn_arena;
+      h->stall_arena = (double*)p; p += align256(sizeof(double) * 4 * h->sumJ);
+      h->thstar_arena = (double*)p; p += align256(sizeof(double) * h->sumJ);
+      for (int e = 0; e < n_elem; ++e) {
+        Elem& E = h->eh[e];
+        HCHECK(hipMemcpy(p, sof[e].data(), sizeof(int) * (size_t)E.ng, hipMemcpyHostToDevice));
+        E.shell_of = (const int*)p; p += align256(sizeof(int) * (size_t)E.ng);
+        HCHECK(hipMemcpy(p, h->tsh_host[e].data(), sizeof(double) * E.nsh, hipMemcpyHostToDevice));
+        E.t_shell = (const double*)p; p += align256(sizeof(double) * E.nsh);
+        E.gain = (double*)p; p += align256(sizeof(double) * (size_t)E.J * E.nsh);
+        E.vbar = (double*)p; p += align256(sizeof(double));
+        E.stall = h->stall_arena + 4 * E.off_j;
+        E.thstar = h->thstar_arena + E.off_j;
+      }
+      HCHECK(hipMemset(h->stall_arena, 0, sizeof(double) * 4 * h->sumJ));
+    }
     HCHECK(hipMalloc(&h->fl_arena, sizeof(int) * (size_t)n_elem * FL_COUNT));
     HCHECK(hipMemset(h->fl_arena, 0, sizeof(int) * (size_t)n_elem * FL_COUNT));
     HCHECK(hipMalloc(&h->d_flag, sizeof(int)));
@@ -863,6 +982,14 @@ static Status set_potential_impl(dgdft_alb* h, const double* V, const dgdft_kb* 
     pbase += P;
   }
   h->upload_elems();
+  {
+    std::vector<int> all(n);
+    for (int e = 0; e < n; ++e) all[e] = e;
+    h->ring_reset();
+    auto P = h->make_prefix(all, [](int) { return 1; });
+    hipLaunchKernelGGL(dg_vmean, dim3(P.na), dim3(256), 0, h->stream, h->ed, P.active, P.na);
+    HCHECK(hipGetLastError());
+  }
   HCHECK(hipStreamSynchronize(s));
   h->potential_loaded = true;
   return fail(DGDFT_OK, "");
@@ -908,12 +1035,88 @@ static void rr_on_x(dgdft_alb* h, const std::vector<int>& act) {
   h->per_elem(act, 3, 0);   // advance: X <- X C etc. become current; hasP <- 0
 }
 
+// Pair log of one iteration (second solve of dgdft_alb_log_pairs): X* (the
+// converged eigenvectors) is bound to slot U0.  E = (I - X X^T) X* Gm into W2
+// with Gm = X*^T X kept on the clusters of the converged eigenvalues; then
+// (R_i, E_i) pairs are packed into HW, transformed, and binned per shell.
+static void log_step(dgdft_alb* h, const std::vector<int>& act_all) {
+  std::vector<int> act;
+  for (int e : act_all)
+    if (h->log_k[e] < h->log_max) act.push_back(e);
+  if (act.empty()) return;
+  GramArgs g{};
+  g.A = dgdft_alb::opnd({S_U0});
+  g.B[0] = dgdft_alb::opnd({VS_X});
+  g.njob = 1; g.out_mat[0] = SM_G; g.upper = 0;
+  h->gram(act, g);
+  {
+    auto P = h->make_prefix(act, [](int) { return 1; });
+    hipLaunchKernelGGL(dg_cluster_mask, dim3(P.na), dim3(256), 0, h->stream, h->ed, P.active, P.na,
+                       1e-6);
+    HCHECK(hipGetLastError());
+  }
+  UpdArgs u{};
+  u.A[0] = dgdft_alb::opnd({S_U0});
+  u.Y[0] = dgdft_alb::opnd({S_W2});
+  u.njob = 1; u.cmat = SM_G; u.ncol = -1; u.alpha = 1.0; u.beta = 0.0;
+  h->update(act, u);
+  GramArgs g2{};
+  g2.A = dgdft_alb::opnd({VS_X});
+  g2.B[0] = dgdft_alb::opnd({S_W2});
+  g2.njob = 1; g2.out_mat[0] = SM_T; g2.upper = 0;
+  h->gram(act, g2);
+  UpdArgs u2{};
+  u2.A[0] = dgdft_alb::opnd({VS_X});
+  u2.Y[0] = dgdft_alb::opnd({S_W2});
+  u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = -1.0; u2.beta = 1.0;
+  h->update(act, u2);
+  // pairs in chunks of `step` bands (J >= 2 for every element)
+  int step = 1 << 30, jmax = 0;
+  for (int e : act) { step = std::min(step, h->eh[e].J / 2); jmax = std::max(jmax, h->eh[e].J); }
+  for (int i0 = 0; i0 < jmax; i0 += step) {
+    // elements grouped by the pair count of this chunk (at most two values)
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<int> sub;
+      int cnt = 0;
+      for (int e : act) {
+        int J = h->eh[e].J;
+        if (i0 >= J) continue;
+        int c = std::min(step, J - i0);
+        if ((pass == 0) == (c == step)) { sub.push_back(e); cnt = c; }
+      }
+      if (sub.empty()) continue;
+      if (pass == 1) {   // all partial chunks of this i0 share J - i0 only if J agrees
+        std::vector<int> one;
+        for (int e : sub) {
+          one.assign(1, e);
+          int c = std::min(step, h->eh[e].J - i0);
+          h->log_chunk(one, i0, c);
+        }
+      } else {
+        h->log_chunk(sub, i0, cnt);
+      }
+    }
+  }
+  {
+    auto P = h->make_prefix(act, [](int) { return 1; });
+    hipLaunchKernelGGL(dg_log_feat, dim3(P.na), dim3(256), 0, h->stream, h->ed, P.active, P.na,
+                       h->log_max, h->log_selem, h->log_srow, h->log_feat);
+    HCHECK(hipGetLastError());
+  }
+  for (int e : act) h->log_k[e]++;
+}
+
 // One LOBPCG iteration for the active elements `act` on the current group's
 // stream: Teter preconditioning of the residual in W, projection against
 // [X P], orthonormalisation, H W, Rayleigh-Ritz on [X P W], update, advance.
 static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   h->launch_kbproj(act, VS_X, 0, -1, 1);
   h->per_elem(act, 2, 0);
+  if (h->log_on) log_step(h, act);
+  if (h->opts.precond == DGDFT_PRECOND_LEARNED) {
+    h->stall_step(act);
+    h->gain_table(act, 1);
+  }
   h->precondition(act, S_W, 0, -1);
   // W <- W - [X P]([X P]^T W)
   GramArgs g1{};
@@ -971,7 +1174,10 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   HCHECK(hipMemcpyAsync(&bad, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
   HCHECK(hipStreamSynchronize(s));
   if (bad) return fail(DGDFT_EINVAL, "X0 contains non-finite values");
+  if (h->opts.precond == DGDFT_PRECOND_LEARNED && !h->mlp_w)
+    return fail(DGDFT_EINVAL, "learned preconditioner without weights (dgdft_alb_set_mlp)");
   HCHECK(hipMemsetAsync(h->fl_arena, 0, sizeof(int) * (size_t)n * FL_COUNT, s));
+  HCHECK(hipMemsetAsync(h->stall_arena, 0, sizeof(double) * 4 * h->sumJ, s));
   memset(h->h_fl, 0, sizeof(int) * (size_t)n * FL_COUNT);
   std::vector<int> all = all_elems(n);
   // ---- initial block: X = X0 T with T from a scaled CholQR of X0
@@ -1005,47 +1211,58 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   std::vector<int> iters(n, 0);
   const double tol = h->opts.tol;
   const int max_iter = h->opts.max_iter;
-  // Split the elements into groups that iterate on their own streams; the
-  // second stream first waits for everything enqueued so far.
-  HCHECK(hipEventRecord(h->g_join, h->g_stream[0]));
-  HCHECK(hipStreamWaitEvent(h->g_stream[1], h->g_join, 0));
-  std::vector<int> act[dgdft_alb::NGROUP];
-  for (int e = 0; e < n; ++e) act[e % dgdft_alb::NGROUP].push_back(e);
-  for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
-    if (act[g].empty()) continue;
-    h->set_group(g);
-    h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);   // R -> W, norms
-  }
-  for (;;) {
-    bool any = false;
+  // Iterate until the running residuals reach tol, then check every element
+  // in FP64 from a fresh H X (with a Rayleigh-Ritz step on X); an element
+  // whose fresh residual is still above tol goes back to the iteration
+  // (without P) while it has iterations left.
+  std::vector<int> pending = all;
+  while (!pending.empty()) {
+    // Split the elements into groups that iterate on their own streams; the
+    // second stream first waits for everything enqueued so far.
+    HCHECK(hipEventRecord(h->g_join, h->g_stream[0]));
+    HCHECK(hipStreamWaitEvent(h->g_stream[1], h->g_join, 0));
+    std::vector<int> act[dgdft_alb::NGROUP];
+    for (size_t q = 0; q < pending.size(); ++q) act[q % dgdft_alb::NGROUP].push_back(pending[q]);
     for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
       if (act[g].empty()) continue;
       h->set_group(g);
-      h->poll();
-      std::vector<int> next;
-      for (int e : act[g])
-        if (!(h->max_res(e) <= tol || iters[e] >= max_iter)) next.push_back(e);
-      act[g].swap(next);
-      if (act[g].empty()) continue;
-      any = true;
-      iterate(h, act[g]);
-      for (int e : act[g]) iters[e]++;
-      h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);
+      h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);   // R -> W, norms
     }
-    if (!any) break;
+    for (;;) {
+      bool any = false;
+      for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+        if (act[g].empty()) continue;
+        h->set_group(g);
+        h->poll();
+        std::vector<int> next;
+        for (int e : act[g])
+          if (!(h->max_res(e) <= tol || iters[e] >= max_iter)) next.push_back(e);
+        act[g].swap(next);
+        if (act[g].empty()) continue;
+        any = true;
+        iterate(h, act[g]);
+        for (int e : act[g]) iters[e]++;
+        h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);
+      }
+      if (!any) break;
+    }
+    // join: group 0's stream waits for group 1
+    h->set_group(1);
+    HCHECK(hipEventRecord(h->g_join, h->g_stream[1]));
+    h->set_group(0);
+    HCHECK(hipStreamWaitEvent(h->g_stream[0], h->g_join, 0));
+    // ---- final FP64 check: fresh HX, RR on X, residuals
+    h->ring_reset();
+    h->op_apply(pending, VS_X, VS_HX, 0, -1);
+    // RR on X needs hasP = 0 for the operand layout; it reads only X/HX
+    rr_on_x(h, pending);
+    h->per_elem_cols(pending, 1, VS_X, VS_HX, S_W, nullptr, nullptr);
+    h->poll();
+    std::vector<int> again;
+    for (int e : pending)
+      if (!(h->max_res(e) <= tol) && iters[e] < max_iter) again.push_back(e);
+    pending.swap(again);
   }
-  // join: group 0's stream waits for group 1
-  h->set_group(1);
-  HCHECK(hipEventRecord(h->g_join, h->g_stream[1]));
-  h->set_group(0);
-  HCHECK(hipStreamWaitEvent(h->g_stream[0], h->g_join, 0));
-  // ---- final FP64 check on every element: fresh HX, RR on X, residuals
-  h->ring_reset();
-  h->op_apply(all, VS_X, VS_HX, 0, -1);
-  // RR on X needs hasP = 0 for the operand layout; it reads only X/HX
-  rr_on_x(h, all);
-  h->per_elem_cols(all, 1, VS_X, VS_HX, S_W, nullptr, nullptr);
-  h->poll();
   // ---- restriction + SVD truncation
   h->per_elem_cols(all, 4, VS_X, S_W, 0, nullptr, nullptr);
   GramArgs ga{};
@@ -1075,6 +1292,11 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   h->flush_prof();
   if (sig_tmp) (void)hipFree(sig_tmp);
   // ---- stats
+  std::vector<double> stall;
+  if (stats && h->opts.precond == DGDFT_PRECOND_LEARNED) {
+    stall.resize(4 * h->sumJ);
+    HCHECK(hipMemcpy(stall.data(), h->stall_arena, sizeof(double) * 4 * h->sumJ, hipMemcpyDeviceToHost));
+  }
   int any_nc = 0;
   for (int e = 0; e < n; ++e) {
     double mr = h->max_res(e);
@@ -1088,7 +1310,12 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
       stats[e].n_chol_fallback = f[FL_W_SVQB];
       stats[e].n_rr_fallback = f[FL_RR_FALLBACK];
       stats[e].n_p_drop = f[FL_P_DROP];
-      stats[e].reserved = f[FL_QL_FAIL];
+      stats[e].n_ql_fail = f[FL_QL_FAIL];
+      int nf = 0;
+      if (!stall.empty())
+        for (int j = 0; j < h->eh[e].J; ++j) nf += stall[4 * (h->eh[e].off_j + j) + 3] != 0.0;
+      stats[e].n_teter_fallback = nf;
+      stats[e].reserved = 0;
     }
   }
   return fail(any_nc ? DGDFT_NOT_CONVERGED : DGDFT_OK, any_nc ? "some element did not converge" : "");
@@ -1172,6 +1399,10 @@ int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R, cons
     }
     h->launch_kbproj(one, S_U0, 0, ncols, 1);
     h->per_elem(one, 2, 0);
+    if (h->opts.precond == DGDFT_PRECOND_LEARNED) {
+      if (!h->mlp_w) { h->err = "learned preconditioner without weights"; return DGDFT_EINVAL; }
+      h->gain_table(one, 0);
+    }
     h->precondition(one, S_U1, 0, ncols);
     HCHECK(hipStreamSynchronize(h->stream));
     return DGDFT_OK;
@@ -1389,6 +1620,293 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
     return DGDFT_OK;
   } catch (HipFail& f) {
     g_create_error = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Learned preconditioner: weights, shells, pair log, training.
+
+extern "C" {
+
+int32_t dgdft_alb_set_mlp(dgdft_alb* h, const float* weights) {
+  if (!h) return DGDFT_EINVAL;
+  h->mlp_w = weights;
+  return DGDFT_OK;
+}
+
+int32_t dgdft_alb_shells(const dgdft_alb* h, int32_t elem, int32_t* n_shell, double* t_shell) {
+  if (!h || elem < 0 || elem >= h->n) return DGDFT_EINVAL;
+  const auto& t = h->tsh_host[elem];
+  if (n_shell) *n_shell = (int32_t)t.size();
+  if (t_shell) memcpy(t_shell, t.data(), sizeof(double) * t.size());
+  return DGDFT_OK;
+}
+
+int32_t dgdft_alb_log_capacity(const dgdft_alb* h, int32_t max_log, int64_t* n_samples,
+                               int64_t* n_rows) {
+  if (!h || max_log < 1) return DGDFT_EINVAL;
+  long long ns = 0, nr = 0;
+  for (const Elem& E : h->eh) {
+    ns += (long long)max_log * E.J;
+    nr += (long long)max_log * E.J * E.nsh;
+  }
+  if (n_samples) *n_samples = ns;
+  if (n_rows) *n_rows = nr;
+  return DGDFT_OK;
+}
+
+int32_t dgdft_alb_log_pairs(dgdft_alb* h, const double* V, const dgdft_kb* kb, const double* X0,
+                            int32_t max_log, int32_t* s_elem, int64_t* s_row, double* s_feat,
+                            double* a, double* b, int32_t* n_logged, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!X0 || max_log < 1 || !s_elem || !s_row || !s_feat || !a || !b) {
+    h->err = "log_pairs: NULL output or max_log < 1";
+    return DGDFT_EINVAL;
+  }
+  for (const Elem& E : h->eh) {
+    if (E.J < 2) { h->err = "log_pairs: every element needs J >= 2"; return DGDFT_EUNSUPPORTED; }
+    if (E.nsh > BIN_MAXSH) { h->err = "log_pairs: more than 4096 shells"; return DGDFT_EUNSUPPORTED; }
+  }
+  bind_stream(h, stream);
+  const int n = h->n;
+  int64_t ns = 0, nr = 0;
+  dgdft_alb_log_capacity(h, max_log, &ns, &nr);
+  try {
+    if (V) {
+      Status st = set_potential_impl(h, V, kb, h->stream);
+      if (st.code != DGDFT_OK) { h->err = st.msg; return st.code; }
+    } else if (!h->potential_loaded) {
+      h->err = "no potential loaded";
+      return DGDFT_EINVAL;
+    }
+    TmpDev t;
+    double* eig = t.alloc<double>(h->sumJ);
+    double* xs = t.alloc<double>(h->sumNgJ);
+    // pass 1: converged eigenvectors and eigenvalues
+    Status st = solve_impl(h, X0, eig, nullptr, nullptr, nullptr, nullptr);
+    if (st.code < 0) { h->err = st.msg; return st.code; }
+    long long s0 = 0, r0 = 0;
+    for (int e = 0; e < n; ++e) {
+      Elem& E = h->eh[e];
+      int par = h->h_fl[(size_t)e * FL_COUNT + FL_PAR];
+      HCHECK(hipMemcpyAsync(xs + E.off_ngj, E.blk[S_X0 + par], sizeof(double) * (size_t)E.ng * E.J,
+                            hipMemcpyDeviceToDevice, h->stream));
+      E.blk[S_U0] = xs + E.off_ngj;
+      E.log_s0 = s0;
+      E.log_r0 = r0;
+      s0 += (long long)max_log * E.J;
+      r0 += (long long)max_log * E.J * E.nsh;
+    }
+    HCHECK(hipMemcpyAsync(h->thstar_arena, eig, sizeof(double) * h->sumJ, hipMemcpyDeviceToDevice,
+                          h->stream));
+    HCHECK(hipMemsetAsync(s_elem, 0xFF, sizeof(int32_t) * ns, h->stream));
+    HCHECK(hipMemsetAsync(s_row, 0, sizeof(int64_t) * ns, h->stream));
+    HCHECK(hipMemsetAsync(s_feat, 0, sizeof(double) * 4 * ns, h->stream));
+    HCHECK(hipMemsetAsync(a, 0, sizeof(double) * nr, h->stream));
+    HCHECK(hipMemsetAsync(b, 0, sizeof(double) * nr, h->stream));
+    h->upload_elems();
+    HCHECK(hipStreamSynchronize(h->stream));
+    // pass 2: the same solve, recording pairs
+    h->log_on = true;
+    h->log_max = max_log;
+    h->log_k.assign(n, 0);
+    h->log_selem = s_elem;
+    h->log_srow = (long long*)s_row;
+    h->log_feat = s_feat;
+    h->log_a = a;
+    h->log_b = b;
+    st = solve_impl(h, X0, eig, nullptr, nullptr, nullptr, nullptr);
+    h->log_on = false;
+    for (int e = 0; e < n; ++e) {
+      h->eh[e].blk[S_U0] = nullptr;
+      if (n_logged) n_logged[e] = h->h_fl[(size_t)e * FL_COUNT + FL_LOGK];
+    }
+    h->upload_elems();
+    HCHECK(hipStreamSynchronize(h->stream));
+    h->err = st.msg;
+    return st.code < 0 ? st.code : DGDFT_OK;
+  } catch (HipFail& f) {
+    h->log_on = false;
+    h->err = f.what;
+    return f.code == hipErrorOutOfMemory ? DGDFT_ENOMEM : DGDFT_EHIP;
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+PairsDev pairs_dev(const dgdft_pairs* d) {
+  PairsDev P;
+  P.shell_off = (const long long*)d->shell_off;
+  P.t_shell = d->t_shell;
+  P.s_elem = d->s_elem;
+  P.s_row = (const long long*)d->s_row;
+  P.s_feat = d->s_feat;
+  P.a = d->a;
+  P.b = d->b;
+  return P;
+}
+
+bool pairs_ok(const dgdft_pairs* d) {
+  return d && d->n_samples >= 0 && d->n_elem >= 1 && d->shell_off && d->t_shell && d->s_elem &&
+         d->s_row && d->s_feat && d->a && d->b;
+}
+
+// Selected samples with e2 > 0 (host list).
+std::vector<long long> select_samples(const dgdft_pairs* d, const int64_t* index, int64_t n_index,
+                                      hipStream_t s) {
+  std::vector<double> feat(4 * (size_t)d->n_samples);
+  if (d->n_samples)
+    HCHECK(hipMemcpyAsync(feat.data(), d->s_feat, sizeof(double) * feat.size(), hipMemcpyDeviceToHost, s));
+  HCHECK(hipStreamSynchronize(s));
+  std::vector<long long> out;
+  long long cnt = index ? n_index : d->n_samples;
+  for (long long k = 0; k < cnt; ++k) {
+    long long smp = index ? index[k] : k;
+    if (smp < 0 || smp >= d->n_samples) throw HipFail{hipErrorInvalidValue, "sample index out of range"};
+    if (feat[4 * smp + 3] > 0.0) out.push_back(smp);
+  }
+  return out;
+}
+
+constexpr int FB_MAXWG = 1024;
+
+}  // namespace
+
+extern "C" {
+
+int32_t dgdft_mlp_grad(const dgdft_pairs* data, const int64_t* index, int64_t n_index,
+                       const float* weights, double* loss, double* grad, void* stream) {
+  if (!pairs_ok(data) || !weights || !grad || (index && n_index < 0)) {
+    g_create_error = "mlp_grad: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    std::vector<long long> sel = select_samples(data, index, n_index, s);
+    if (sel.empty()) { g_create_error = "mlp_grad: no sample with e2 > 0"; return DGDFT_EINVAL; }
+    TmpDev t;
+    long long nsel = (long long)sel.size();
+    long long* d_idx = t.alloc<long long>(nsel);
+    HCHECK(hipMemcpyAsync(d_idx, sel.data(), sizeof(long long) * nsel, hipMemcpyHostToDevice, s));
+    int nwg = (int)std::min<long long>(nsel, FB_MAXWG);
+    float* gpart = t.alloc<float>((size_t)nwg * M_NW);
+    double* lpart = t.alloc<double>(nwg);
+    double* lacc = t.alloc<double>(1);
+    HCHECK(hipMemsetAsync(lacc, 0, sizeof(double), s));
+    hipLaunchKernelGGL(dg_mlp_fb, dim3(nwg), dim3(64), 0, s, pairs_dev(data), d_idx, 0LL, nsel, weights,
+                       1.0f / (float)nsel, gpart, lpart);
+    hipLaunchKernelGGL(dg_mlp_reduce, dim3(cdiv(M_NW, 256)), dim3(256), 0, s, gpart, nwg, 0, grad,
+                       nullptr, nullptr, nullptr, 0.0f, 0.0f, 0.0f, 0.0f, 1.0, 1.0);
+    hipLaunchKernelGGL(dg_sum_into, dim3(1), dim3(256), 0, s, lpart, nwg, lacc);
+    HCHECK(hipGetLastError());
+    double l = 0.0;
+    HCHECK(hipMemcpyAsync(&l, lacc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    if (loss) *loss = l / (double)nsel;
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    g_create_error = f.what;
+    return f.code == hipErrorInvalidValue ? DGDFT_EINVAL : DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_mlp_train(const dgdft_pairs* data, const int64_t* index, int64_t n_index,
+                        const dgdft_train_opts* opts, float* weights, double* loss_hist, void* stream) {
+  if (!pairs_ok(data) || !weights || (index && n_index < 0)) {
+    g_create_error = "mlp_train: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  dgdft_train_opts o{};
+  if (opts) o = *opts;
+  if (o.epochs <= 0) o.epochs = 10;
+  if (o.batch <= 0) o.batch = 256;
+  if (o.lr <= 0.0) o.lr = 1e-3;
+  if (o.beta1 <= 0.0) o.beta1 = 0.9;
+  if (o.beta2 <= 0.0) o.beta2 = 0.999;
+  if (o.eps <= 0.0) o.eps = 1e-8;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    std::vector<long long> sel = select_samples(data, index, n_index, s);
+    if (sel.empty()) { g_create_error = "mlp_train: no sample with e2 > 0"; return DGDFT_EINVAL; }
+    TmpDev t;
+    const long long nsel = (long long)sel.size();
+    long long* d_idx = t.alloc<long long>(nsel);
+    PairsDev P = pairs_dev(data);
+    if (o.set_norm) {
+      double* acc = t.alloc<double>(7);
+      HCHECK(hipMemcpyAsync(d_idx, sel.data(), sizeof(long long) * nsel, hipMemcpyHostToDevice, s));
+      HCHECK(hipMemsetAsync(acc, 0, sizeof(double) * 7, s));
+      hipLaunchKernelGGL(dg_mlp_norm_acc, dim3((unsigned)nsel), dim3(256), 0, s, P, d_idx, nsel, acc);
+      hipLaunchKernelGGL(dg_mlp_norm_fin, dim3(1), dim3(64), 0, s, acc, weights);
+      HCHECK(hipGetLastError());
+    }
+    const int maxwg = (int)std::min<long long>(std::min<long long>(o.batch, nsel), FB_MAXWG);
+    float* gpart = t.alloc<float>((size_t)maxwg * M_NW);
+    double* lpart = t.alloc<double>(maxwg);
+    float* m = t.alloc<float>(M_NW);
+    float* v = t.alloc<float>(M_NW);
+    double* lacc = t.alloc<double>(1);
+    HCHECK(hipMemsetAsync(m, 0, sizeof(float) * M_NW, s));
+    HCHECK(hipMemsetAsync(v, 0, sizeof(float) * M_NW, s));
+    // minibatch order: Fisher-Yates with splitmix64 from the seed
+    uint64_t st = o.seed ^ 0x9E3779B97F4A7C15ull;
+    auto next = [&]() {
+      uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      return z ^ (z >> 31);
+    };
+    std::vector<long long> perm = sel;
+    long long step = 0;
+    for (int ep = 0; ep < o.epochs; ++ep) {
+      for (long long i = nsel - 1; i > 0; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
+      HCHECK(hipMemcpyAsync(d_idx, perm.data(), sizeof(long long) * nsel, hipMemcpyHostToDevice, s));
+      HCHECK(hipMemsetAsync(lacc, 0, sizeof(double), s));
+      for (long long b0 = 0; b0 < nsel; b0 += o.batch) {
+        long long cnt = std::min<long long>(o.batch, nsel - b0);
+        int nwg = (int)std::min<long long>(cnt, maxwg);
+        ++step;
+        hipLaunchKernelGGL(dg_mlp_fb, dim3(nwg), dim3(64), 0, s, P, d_idx, b0, cnt, (const float*)weights,
+                           1.0f / (float)cnt, gpart, lpart);
+        double bc1 = 1.0 - std::pow(o.beta1, (double)step), bc2 = 1.0 - std::pow(o.beta2, (double)step);
+        hipLaunchKernelGGL(dg_mlp_reduce, dim3(cdiv(M_NW, 256)), dim3(256), 0, s, gpart, nwg, 1,
+                           (double*)nullptr, weights, m, v, (float)o.lr, (float)o.beta1, (float)o.beta2,
+                           (float)o.eps, bc1, bc2);
+        hipLaunchKernelGGL(dg_sum_into, dim3(1), dim3(256), 0, s, lpart, nwg, lacc);
+        HCHECK(hipGetLastError());
+      }
+      double l = 0.0;
+      HCHECK(hipMemcpyAsync(&l, lacc, sizeof(double), hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));   // the permutation buffer is rewritten next epoch
+      if (loss_hist) loss_hist[ep] = l / (double)nsel;
+    }
+    HCHECK(hipStreamSynchronize(s));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    g_create_error = f.what;
+    return f.code == hipErrorInvalidValue ? DGDFT_EINVAL : DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_mlp_eval(const double* feat, int64_t n, const float* weights, double* f, void* stream) {
+  if (!feat || !weights || !f || n < 1 || n > (1LL << 40)) {
+    g_create_error = "mlp_eval: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    hipLaunchKernelGGL(dg_mlp_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, feat, (long long)n,
+                       weights, f);
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(s));
+    return DGDFT_OK;
+  } catch (HipFail& f2) {
+    g_create_error = f2.what;
     return DGDFT_EHIP;
   }
 }

@@ -10,8 +10,9 @@
 // column through HBM (intermediates are one complex scratch per pair):
 //   fft_xy  : load an xy-plane of (a, b) into LDS, FFT along x then y, store
 //   fft_z   : load the z-pencils of row pair (m2, -m2), FFT along z, apply
-//             the G-space diagonal (kinetic |G|^2/2, or Teter with the mixing
-//             needed when a and b carry different K), inverse FFT along z
+//             the G-space diagonal (kinetic |G|^2/2, or Teter -- optionally
+//             times a learned per-shell gain -- with the mixing needed when
+//             a and b carry different K), inverse FFT along z
 //   fft_xyi : inverse FFT along y then x, scale 1/N, and the epilogue: for the
 //             operator HX = T x + V x + sum_p gamma_p beta_p (beta_p^T x)
 //             (V and the KB scatter fused), for the preconditioner the result
@@ -241,7 +242,9 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
       buf[p] = cscale(buf[p], 0.5 * (k1 * k1 + k2 * k2 + k3 * k3));
     }
     __syncthreads();
-  } else if (mode == 1) {
+  } else if (mode == 1 || mode == 3) {
+    // mode 3: Teter factor times the per-(band, shell) gain of the learned
+    // preconditioner
     const int nc = ncols < 0 ? e.J : ncols;
     int ca = col0 + 2 * q, cb = ca + 1;
     bool hasb = cb < col0 + nc;
@@ -258,6 +261,11 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
         double k1 = g1 * freq(x, n1), k2 = g2 * freq(row, n2), k3 = g3 * freq(z, n3);
         double t = 0.5 * (k1 * k1 + k2 * k2 + k3 * k3);
         double Ka = teter_k(t / Ta), Kb = teter_k(t / Tb);
+        if (mode == 3) {
+          int sh = e.shell_of[(long long)z * n1 * n2 + row * n1 + x];
+          Ka *= e.gain[(long long)ca * e.nsh + sh];
+          Kb = hasb ? Kb * e.gain[(long long)cb * e.nsh + sh] : Ka;
+        }
         // mirror point (-m1, -m2, -m3): the other row slot (or the same)
         int zm = (n3 - z) % n3, xm = (n1 - x) % n1;
         int sm = (nrows == 2) ? 1 - s : 0;

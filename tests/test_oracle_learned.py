@@ -159,11 +159,17 @@ def test_loss_zero_for_ideal_factor_and_scale_invariant():
     smp = [dict(t=t, a=a[0], b=b[0], e2=e2[0], theta=theta, T=T, vbar=vbar)]
     L, _ = learned.loss_and_grad(w, smp)
     assert abs(L) < 1e-12
-    # a constant factor on K (output bias) leaves the loss unchanged
-    smp2 = _samples(rng, grid, box, 2)
-    w2 = w.copy()
-    w2[learned._OFF["b3"][0]] += 0.75
-    assert abs(learned.loss_and_grad(w, smp2)[0] - learned.loss_and_grad(w2, smp2)[0]) < 1e-12
+    # a constant factor on K leaves the loss unchanged
+    smp2 = _samples(rng, grid, box, 2)[0]
+    Kr = rng.uniform(0.1, 2.0, t.shape[0])
+    l1 = learned.sample_loss(Kr, smp2["a"], smp2["b"], smp2["e2"])
+    l2 = learned.sample_loss(3.7 * Kr, smp2["a"], smp2["b"], smp2["e2"])
+    assert 0.0 <= l1 <= 1.0 and abs(l1 - l2) < 1e-12
+    # the network's factor stays within exp(+-FMAX) of Teter's
+    wbig = w.copy()
+    wbig[learned._OFF["b3"][0]] = 50.0
+    fb, _ = learned.forward(wbig, learned.features(t, T, theta, vbar)[0])
+    assert np.all(np.abs(fb) <= learned.FMAX)
 
 
 def test_adam_first_step_is_signed_lr():
