@@ -91,6 +91,7 @@ struct dgdft_alb {
   int g_ring_pos[NGROUP] = {};
   hipStream_t g_stream[NGROUP] = {};
   hipEvent_t g_join = nullptr;
+  hipEvent_t g_done[NGROUP] = {};
   int* d_active_all = nullptr;
   // host readback (pinned)
   double* h_resid = nullptr;
@@ -570,7 +571,10 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   for (auto& pool : h->ev_pool)
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   if (h->g_join) (void)hipEventDestroy(h->g_join);
-  if (h->g_stream[1]) (void)hipStreamDestroy(h->g_stream[1]);
+  for (int g = 1; g < dgdft_alb::NGROUP; ++g) {
+    if (h->g_done[g]) (void)hipEventDestroy(h->g_done[g]);
+    if (h->g_stream[g]) (void)hipStreamDestroy(h->g_stream[g]);
+  }
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   (void)hipSetDevice(cur);
   delete h;
@@ -787,7 +791,10 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     h->ring_stride = 2 * n_elem + 8;
     HCHECK(hipMalloc(&h->ring_d, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING * dgdft_alb::NGROUP));
     HCHECK(hipHostMalloc(&h->ring_h, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING * dgdft_alb::NGROUP));
-    HCHECK(hipStreamCreateWithFlags(&h->g_stream[1], hipStreamNonBlocking));
+    for (int g = 1; g < dgdft_alb::NGROUP; ++g) {
+      HCHECK(hipStreamCreateWithFlags(&h->g_stream[g], hipStreamNonBlocking));
+      HCHECK(hipEventCreateWithFlags(&h->g_done[g], hipEventDisableTiming));
+    }
     HCHECK(hipEventCreateWithFlags(&h->g_join, hipEventDisableTiming));
     HCHECK(hipHostMalloc(&h->h_resid, sizeof(double) * h->sumJ));
     HCHECK(hipHostMalloc(&h->h_fl, sizeof(int) * (size_t)n_elem * FL_COUNT));
@@ -1220,7 +1227,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
     // Split the elements into groups that iterate on their own streams; the
     // second stream first waits for everything enqueued so far.
     HCHECK(hipEventRecord(h->g_join, h->g_stream[0]));
-    HCHECK(hipStreamWaitEvent(h->g_stream[1], h->g_join, 0));
+    for (int g = 1; g < dgdft_alb::NGROUP; ++g) HCHECK(hipStreamWaitEvent(h->g_stream[g], h->g_join, 0));
     std::vector<int> act[dgdft_alb::NGROUP];
     for (size_t q = 0; q < pending.size(); ++q) act[q % dgdft_alb::NGROUP].push_back(pending[q]);
     for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
@@ -1246,11 +1253,12 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
       }
       if (!any) break;
     }
-    // join: group 0's stream waits for group 1
-    h->set_group(1);
-    HCHECK(hipEventRecord(h->g_join, h->g_stream[1]));
+    // join: group 0's stream waits for the others
+    for (int g = 1; g < dgdft_alb::NGROUP; ++g) {
+      HCHECK(hipEventRecord(h->g_done[g], h->g_stream[g]));
+      HCHECK(hipStreamWaitEvent(h->g_stream[0], h->g_done[g], 0));
+    }
     h->set_group(0);
-    HCHECK(hipStreamWaitEvent(h->g_stream[0], h->g_join, 0));
     // ---- final FP64 check: fresh HX, RR on X, residuals
     h->ring_reset();
     h->op_apply(pending, VS_X, VS_HX, 0, -1);

@@ -414,8 +414,18 @@ __host__ __device__ void gemm_fast(T& t, int ta, int tb, int m, int n, int k, do
 // scratch of n doubles each (LDS on the device).
 template <class T>
 __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
-                                              double* tau, double* v, double* p) {
+                                              double* tau, double* v, double* p,
+                                              double* scratch = nullptr, int scratch_size = 0) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  // Device path for n <= 64 * TRI_R with (waves + 1) * n doubles of LDS
+  // scratch: every trailing-block entry is read once per step for both
+  // halves of the symmetric product p = A2 v (column dot for the part on and
+  // below the diagonal, register axpy per wave for the part above, summed in
+  // a fixed order), and each lane keeps its rows of v and q in registers for
+  // the rank-2 update.
+  constexpr int TRI_R = 12;
+  bool fast = false;
+  if constexpr (T::is_device) fast = n <= 64 * TRI_R && scratch && (nw + 1) * n <= scratch_size;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     double part = 0.0;
@@ -434,6 +444,70 @@ __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, d
     for (int i = t.tid(); i < m; i += t.nt()) v[i] = (i == 0) ? v0 : IDX(A, lda, k + 1 + i, k);
     t.sync();
     if (t.tid() == 0) { IDX(A, lda, k + 1, k) = v0; e[k] = beta; tau[k] = tk; }
+    if constexpr (T::is_device) {
+      if (fast) {
+        double* A2 = &IDX(A, lda, k + 1, k + 1);
+        double* pc = scratch;          // column parts, one writer per entry
+        double* part = scratch + n;    // per-wave row parts
+        double vr[TRI_R], acc[TRI_R];
+#pragma unroll
+        for (int r = 0; r < TRI_R; ++r) {
+          int i = lane + 64 * r;
+          vr[r] = i < m ? v[i] : 0.0;
+          acc[r] = 0.0;
+        }
+        for (int j = wv; j < m; j += nw) {
+          const double vj = v[j];
+          const double* col = A2 + (long long)lda * j;
+          double s = 0.0;
+#pragma unroll
+          for (int r = 0; r < TRI_R; ++r) {
+            int i = lane + 64 * r;
+            if (i >= j && i < m) {
+              double a = col[i];
+              s += a * vr[r];
+              if (i > j) acc[r] += a * vj;
+            }
+          }
+          for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+          if (lane == 0) pc[j] = s;
+        }
+#pragma unroll
+        for (int r = 0; r < TRI_R; ++r) {
+          int i = lane + 64 * r;
+          if (i < m) part[(long long)wv * n + i] = acc[r];
+        }
+        t.sync();
+        for (int i = t.tid(); i < m; i += t.nt()) {
+          double s = pc[i];
+          for (int w = 0; w < nw; ++w) s += part[(long long)w * n + i];
+          p[i] = s;
+        }
+        t.sync();
+        double vp = 0.0;
+        for (int i = t.tid(); i < m; i += t.nt()) { p[i] *= tk; vp += v[i] * p[i]; }
+        double K = 0.5 * tk * t.sum(vp);
+        for (int i = t.tid(); i < m; i += t.nt()) p[i] -= K * v[i];   // p := q
+        t.sync();
+        double qr[TRI_R];
+#pragma unroll
+        for (int r = 0; r < TRI_R; ++r) {
+          int i = lane + 64 * r;
+          qr[r] = i < m ? p[i] : 0.0;
+        }
+        for (int j = wv; j < m; j += nw) {
+          const double vj = v[j], qj = p[j];
+          double* col = A2 + (long long)lda * j;
+#pragma unroll
+          for (int r = 0; r < TRI_R; ++r) {
+            int i = lane + 64 * r;
+            if (i >= j && i < m) col[i] -= vr[r] * qj + qr[r] * vj;
+          }
+        }
+        t.sync();
+        continue;
+      }
+    }
     // p = A2 v with A2 the trailing block, lower triangle stored:
     //   rows:    sum_{j <= i} A2[i][j] v[j]       (thread per row, coalesced)
     for (int i = t.tid(); i < m; i += t.nt()) {
@@ -749,7 +823,7 @@ __host__ __device__ void syev_lowest(T& t, double* A, int lda, int n, int k, dou
   double* d = work;
   double* e = work + n;
   double* tau = work + 2 * n;
-  tridiagonalize_lower(t, A, lda, n, d, e, tau, lds, lds + n);
+  tridiagonalize_lower(t, A, lda, n, d, e, tau, lds, lds + n, lds + 2 * n, lds_size - 2 * n);
   tridiag_lowest(t, d, e, n, k, w, Z, ldz, work + 3 * n, cl);
   backtransform(t, A, lda, tau, n, Z, ldz, k, lds, lds_size);
 }
