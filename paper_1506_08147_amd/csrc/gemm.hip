@@ -188,16 +188,23 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
 // Y (K x ncol) = alpha A (K x kA) C (kA x ncol) + beta Y.  Computed as the
 // transposed product so that lanes 0..15 of an accumulator own consecutive
 // rows of Y (coalesced stores).  Work item (job, row tile, column tile) with
-// 128 x 128 tiles; kA <= UPD_MAXK.
-constexpr int UPD_MAXK = 3 * 1024;
+// 128 x 128 tiles.  Column k of A is block k / J at column k % J of that
+// block (block base pointers resolved once per workgroup), so the LDS holds
+// only the two operand stages and the workgroup fits twice per compute unit.
+constexpr int UKS = 16;        // K stage of the update
+constexpr int UPD_NQ = UKS / 2;
+constexpr int UPD_NH = UKS / 16;
+#ifndef DG_UPD_WAVES_PER_EU
+#define DG_UPD_WAVES_PER_EU 2
+#endif
 
-extern "C" __global__ void __launch_bounds__(256)
+extern "C" __global__ void __launch_bounds__(256, DG_UPD_WAVES_PER_EU)
 dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
           int na, UpdArgs u) {
-  __shared__ double As[2][KS * LP];
-  __shared__ double Cs[2][KS * LP];
+  __shared__ double As[2][UKS * LP];
+  __shared__ double Cs[2][UKS * LP];
   __shared__ double* colY[TT];
-  __shared__ const double* colA[UPD_MAXK];
+  __shared__ const double* abase[6];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
   const Elem& e = E[active[ai]];
@@ -214,31 +221,52 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   const double* C = sm(e, u.cmat) + (long long)u.ccol0 * kA;
   const int row0 = tr * TT, col0 = tc * TT;
   const int tid = threadIdx.x;
-  for (int k = tid; k < kA; k += 256) colA[k] = opnd_col(A, e, k);
+  if (tid == 0) {
+    if (A.ncols >= 0) {
+      abase[0] = bp(e, A.slot[0]);
+    } else {
+      int q = 0;
+      for (int i = 0; i < A.nblk; ++i)
+        if (!(A.optP[i] && !has_p(e))) abase[q++] = bp(e, A.slot[i]);
+    }
+  }
   if (tid < TT) colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
   __syncthreads();
-  // A stage: row = tid % 128, k = tid / 128 + 2u (u < 8)
+  const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
+  const long long ld = e.ld;
+  // A stage: row = tid % 128, k = tid / 128 + 2q (q < UKS/2)
   const int ar = tid & 127, ak = tid >> 7;
-  // C stage: k = tid % 16, j = tid / 16 + 16u (u < 8)
+  // C stage: k = tid % 16 + 16h, j = tid / 16 + 16v (v < 8)
   const int ck = tid & 15, cj = tid >> 4;
   const bool rin = row0 + ar < K;
-  double ra[8], rc[8];
+  double ra[UPD_NQ], rc[8 * UPD_NH];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < UPD_NQ; ++q) {
       int k = k0 + ak + 2 * q;
-      ra[q] = (k < kA && rin) ? colA[k][row0 + ar] : 0.0;
-      int j = col0 + cj + 16 * q;
-      int kc = k0 + ck;
-      rc[q] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
+      double v = 0.0;
+      if (k < kA && rin) {
+        int bb = k / bcols;
+        v = abase[bb][(long long)(k - bb * bcols) * ld + row0 + ar];
+      }
+      ra[q] = v;
     }
+#pragma unroll
+    for (int h = 0; h < UPD_NH; ++h)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        int j = col0 + cj + 16 * v;
+        int kc = k0 + ck + 16 * h;
+        rc[8 * h + v] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
+      }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[buf][(ak + 2 * q) * LP + ar] = ra[q];
-      Cs[buf][ck * LP + cj + 16 * q] = rc[q];
-    }
+    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LP + ar] = ra[q];
+#pragma unroll
+    for (int h = 0; h < UPD_NH; ++h)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) Cs[buf][(ck + 16 * h) * LP + cj + 16 * v] = rc[8 * h + v];
   };
   const int lane = tid & 63, wv = tid >> 6;
   const int wj = wv & 1, wr = wv >> 1;
@@ -247,15 +275,15 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  const int nst = cdiv(kA, KS);
+  const int nst = cdiv(kA, UKS);
   load(0);
   store(0);
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    if (st + 1 < nst) load((st + 1) * KS);
+    if (st + 1 < nst) load((st + 1) * UKS);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < UKS / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
       double fc[4], fa[4];
 #pragma unroll

@@ -581,6 +581,159 @@ __host__ __device__ inline double start_value(unsigned long long c) {
   return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// Device form of tridiag_lowest for a workgroup with 3n doubles of LDS: the
+// tridiagonal lives in LDS; eigenvalues by multisection (G lanes of one wave
+// per eigenvalue evaluate Sturm counts at G interior points, so the interval
+// shrinks by G + 1 per round); eigenvectors by inverse iteration whose
+// factorisation of T - lambda I is fused with the forward substitution and
+// carries its recurrences in registers (only U and x go through memory, and
+// are read back with no dependence on the running recurrence).  Same
+// stopping rule, start vectors and cluster treatment as tridiag_lowest.
+template <class T>
+__device__ void tridiag_lowest_dev(T& t, const double* dg, const double* eg, int n, int k,
+                                   double* w, double* Y, int ldy, double* work, int* cl,
+                                   double* lds) {
+  double* d = lds;
+  double* e = lds + n;
+  double* e2 = lds + 2 * n;
+  for (int i = t.tid(); i < n; i += t.nt()) {
+    d[i] = dg[i];
+    double v = i < n - 1 ? eg[i] : 0.0;
+    e[i] = v;
+    e2[i] = v * v;
+  }
+  t.sync();
+  double gl = 1e300, gu = -1e300, emax2 = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    gl = fmin(gl, d[i] - r);
+    gu = fmax(gu, d[i] + r);
+    if (i < n - 1) emax2 = fmax(emax2, e2[i]);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = fmax(1e-290, 1e-290 * emax2);
+  gl -= 2.0 * eps * tnorm * n + pivmin;
+  gu += 2.0 * eps * tnorm * n + pivmin;
+  auto count = [&](double x) {
+    int c = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+    for (int i = 1; i < n; ++i) {
+      q = d[i] - x - e2[i - 1] / q;
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
+    return c;
+  };
+  int G = t.nt() / k;
+  G = G >= 8 ? 8 : (G >= 4 ? 4 : (G >= 2 ? 2 : 1));
+  if (G >= 2) {
+    const int tid = t.tid(), lane = tid & 63;
+    const int j = tid / G, sidx = tid - j * G;
+    const int base = lane - sidx;
+    const unsigned long long gmask = ((1ull << G) - 1ull) << base;
+    double lo = gl, hi = gu;
+    bool done = j >= k;
+    for (int it = 0; it < 200; ++it) {
+      if (!done && hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) done = true;
+      if (__all(done ? 1 : 0)) break;
+      const double pt = lo + (hi - lo) * (double)(sidx + 1) / (double)(G + 1);
+      const int c = done ? 0 : count(pt);
+      const unsigned long long m = __ballot((!done && c <= j) ? 1 : 0);
+      const int cnt = __popcll(m & gmask);
+      const double plo = __shfl(pt, base + (cnt > 0 ? cnt - 1 : 0), 64);
+      const double phi = __shfl(pt, base + (cnt < G ? cnt : G - 1), 64);
+      if (!done) {
+        double nlo = cnt > 0 ? plo : lo, nhi = cnt < G ? phi : hi;
+        if (nlo == lo && nhi == hi) done = true;
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+    if (j < k && sidx == 0) w[j] = 0.5 * (lo + hi);
+  } else {
+    for (int j = t.tid(); j < k; j += t.nt()) {
+      double lo = gl, hi = gu;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
+        if (count(mid) <= j) lo = mid; else hi = mid;
+      }
+      w[j] = 0.5 * (lo + hi);
+    }
+  }
+  t.sync();
+  for (int j = t.tid(); j < k; j += t.nt()) {
+#define WV(a, i) work[(a) * (long long)n * k + (long long)(i) * k + j]
+    // arrays: 0 dd, 1 du, 2 du2, 3 x
+    const double lam = w[j];
+    const double tiny = eps * tnorm + 1e-290;
+    for (int i = 0; i < n; ++i) WV(3, i) = start_value(((unsigned long long)j << 32) + i);
+    for (int it = 0; it < 3; ++it) {
+      // factor (partial pivoting) + forward substitution
+      double ddi = d[0] - lam, dui = n > 1 ? e[0] : 0.0, xi = WV(3, 0);
+      for (int i = 0; i < n - 1; ++i) {
+        const double b = e[i];
+        double ddn = d[i + 1] - lam;
+        double dun = i < n - 2 ? e[i + 1] : 0.0;
+        double xn = WV(3, i + 1);
+        if (fabs(ddi) >= fabs(b)) {
+          if (ddi == 0.0) ddi = tiny;
+          const double f = b / ddi;
+          WV(0, i) = ddi;
+          WV(1, i) = dui;
+          WV(2, i) = 0.0;
+          WV(3, i) = xi;
+          ddn -= f * dui;
+          xn -= f * xi;
+        } else {
+          const double f = ddi / b;
+          WV(0, i) = b;
+          WV(1, i) = ddn;
+          WV(2, i) = dun;
+          WV(3, i) = xn;
+          const double nddn = dui - f * ddn;
+          dun = -f * dun;
+          xn = xi - f * xn;
+          ddn = nddn;
+        }
+        ddi = ddn;
+        dui = dun;
+        xi = xn;
+      }
+      WV(0, n - 1) = ddi == 0.0 ? tiny : ddi;
+      WV(3, n - 1) = xi;
+      // backward substitution with U (two superdiagonals)
+      double x1 = 0.0, x2 = 0.0, smax = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        double v = WV(3, i);
+        if (i + 1 < n) v -= WV(1, i) * x1;
+        if (i + 2 < n) v -= WV(2, i) * x2;
+        double di = WV(0, i);
+        if (fabs(di) < tiny) di = di < 0 ? -tiny : tiny;
+        v /= di;
+        WV(3, i) = v;
+        smax = fmax(smax, fabs(v));
+        x2 = x1;
+        x1 = v;
+      }
+      double nr = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double v = WV(3, i) / smax;
+        WV(3, i) = v;
+        nr += v * v;
+      }
+      nr = 1.0 / sqrt(nr);
+      for (int i = 0; i < n; ++i) WV(3, i) *= nr;
+    }
+    for (int i = 0; i < n; ++i) IDX(Y, ldy, i, j) = WV(3, i);
+#undef WV
+  }
+  t.sync();
+}
+
 // Lowest k eigenpairs of the symmetric tridiagonal (d, e): eigenvalues by
 // bisection (one thread per eigenvalue), eigenvectors by inverse iteration
 // with partial-pivoting LU of T - lambda I (one thread per vector), then
@@ -588,7 +741,10 @@ __host__ __device__ inline double start_value(unsigned long long c) {
 // w[0..k) ascending, Y (n x k, ldy).  work: 6 n k doubles (interleaved).
 template <class T>
 __host__ __device__ void tridiag_lowest(T& t, const double* d, const double* e, int n, int k,
-                                        double* w, double* Y, int ldy, double* work, int* cl) {
+                                        double* w, double* Y, int ldy, double* work, int* cl,
+                                        double* lds = nullptr, int lds_size = 0) {
+  bool dev_path = false;
+  if constexpr (T::is_device) dev_path = lds && lds_size >= 3 * n;
   // Gershgorin interval and scale
   double gl = 1e300, gu = -1e300, emax2 = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -602,89 +758,93 @@ __host__ __device__ void tridiag_lowest(T& t, const double* d, const double* e, 
   const double pivmin = fmax(1e-290, 1e-290 * emax2);
   gl -= 2.0 * eps * tnorm * n + pivmin;
   gu += 2.0 * eps * tnorm * n + pivmin;
-  for (int j = t.tid(); j < k; j += t.nt()) {
-    double lo = gl, hi = gu;
-    for (int it = 0; it < 200; ++it) {
-      double mid = 0.5 * (lo + hi);
-      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
-      if (sturm_count(d, e, n, mid, pivmin) <= j) lo = mid; else hi = mid;
-    }
-    w[j] = 0.5 * (lo + hi);
-  }
-  t.sync();
-  // inverse iteration, work interleaved: element i of thread j at i*k + j
-  for (int j = t.tid(); j < k; j += t.nt()) {
-    double* dd = work;
-    double* du = work + (long long)n * k;
-    double* du2 = work + 2LL * n * k;
-    double* dl = work + 3LL * n * k;
-    double* x = work + 4LL * n * k;
-    double* piv = work + 5LL * n * k;   // 0: no swap, 1: swap
-#define W(a, i) a[(long long)(i) * k + j]
-    const double lam = w[j];
-    const double tiny = eps * tnorm + 1e-290;
-    // LU with partial pivoting of T - lam I (LAPACK gttrf layout)
-    for (int i = 0; i < n; ++i) {
-      W(dd, i) = d[i] - lam;
-      if (i < n - 1) { W(du, i) = e[i]; W(dl, i) = e[i]; }
-      if (i < n - 2) W(du2, i) = 0.0;
-    }
-    for (int i = 0; i < n - 1; ++i) {
-      double a = W(dd, i), b = W(dl, i);
-      if (fabs(a) >= fabs(b)) {
-        if (a == 0.0) { a = tiny; W(dd, i) = a; }
-        double f = b / a;
-        W(dl, i) = f;
-        W(dd, i + 1) -= f * W(du, i);
-        W(piv, i) = 0.0;
-      } else {
-        double f = a / b;
-        W(dd, i) = b;
-        W(dl, i) = f;
-        double tmp = W(du, i);
-        W(du, i) = W(dd, i + 1);
-        W(dd, i + 1) = tmp - f * W(dd, i + 1);
-        if (i < n - 2) {
-          W(du2, i) = W(du, i + 1);
-          W(du, i + 1) = -f * W(du, i + 1);
-        }
-        W(piv, i) = 1.0;
+  if (dev_path) {
+    if constexpr (T::is_device) tridiag_lowest_dev(t, d, e, n, k, w, Y, ldy, work, cl, lds);
+  } else {
+    for (int j = t.tid(); j < k; j += t.nt()) {
+      double lo = gl, hi = gu;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || mid == lo || mid == hi) break;
+        if (sturm_count(d, e, n, mid, pivmin) <= j) lo = mid; else hi = mid;
       }
+      w[j] = 0.5 * (lo + hi);
     }
-    if (W(dd, n - 1) == 0.0) W(dd, n - 1) = tiny;
-    for (int i = 0; i < n; ++i) W(x, i) = start_value(((unsigned long long)j << 32) + i);
-    for (int it = 0; it < 3; ++it) {
-      // forward: L with row interchanges
+    t.sync();
+    // inverse iteration, work interleaved: element i of thread j at i*k + j
+    for (int j = t.tid(); j < k; j += t.nt()) {
+      double* dd = work;
+      double* du = work + (long long)n * k;
+      double* du2 = work + 2LL * n * k;
+      double* dl = work + 3LL * n * k;
+      double* x = work + 4LL * n * k;
+      double* piv = work + 5LL * n * k;   // 0: no swap, 1: swap
+  #define W(a, i) a[(long long)(i) * k + j]
+      const double lam = w[j];
+      const double tiny = eps * tnorm + 1e-290;
+      // LU with partial pivoting of T - lam I (LAPACK gttrf layout)
+      for (int i = 0; i < n; ++i) {
+        W(dd, i) = d[i] - lam;
+        if (i < n - 1) { W(du, i) = e[i]; W(dl, i) = e[i]; }
+        if (i < n - 2) W(du2, i) = 0.0;
+      }
       for (int i = 0; i < n - 1; ++i) {
-        if (W(piv, i) == 0.0) {
-          W(x, i + 1) -= W(dl, i) * W(x, i);
+        double a = W(dd, i), b = W(dl, i);
+        if (fabs(a) >= fabs(b)) {
+          if (a == 0.0) { a = tiny; W(dd, i) = a; }
+          double f = b / a;
+          W(dl, i) = f;
+          W(dd, i + 1) -= f * W(du, i);
+          W(piv, i) = 0.0;
         } else {
-          double tmp = W(x, i);
-          W(x, i) = W(x, i + 1);
-          W(x, i + 1) = tmp - W(dl, i) * W(x, i);
+          double f = a / b;
+          W(dd, i) = b;
+          W(dl, i) = f;
+          double tmp = W(du, i);
+          W(du, i) = W(dd, i + 1);
+          W(dd, i + 1) = tmp - f * W(dd, i + 1);
+          if (i < n - 2) {
+            W(du2, i) = W(du, i + 1);
+            W(du, i + 1) = -f * W(du, i + 1);
+          }
+          W(piv, i) = 1.0;
         }
       }
-      // backward: U with two superdiagonals
-      double s = 0.0;
-      for (int i = n - 1; i >= 0; --i) {
-        double v = W(x, i);
-        if (i + 1 < n) v -= W(du, i) * W(x, i + 1);
-        if (i + 2 < n) v -= W(du2, i) * W(x, i + 2);
-        double di = W(dd, i);
-        if (fabs(di) < tiny) di = di < 0 ? -tiny : tiny;
-        v /= di;
-        W(x, i) = v;
-        s = fmax(s, fabs(v));
+      if (W(dd, n - 1) == 0.0) W(dd, n - 1) = tiny;
+      for (int i = 0; i < n; ++i) W(x, i) = start_value(((unsigned long long)j << 32) + i);
+      for (int it = 0; it < 3; ++it) {
+        // forward: L with row interchanges
+        for (int i = 0; i < n - 1; ++i) {
+          if (W(piv, i) == 0.0) {
+            W(x, i + 1) -= W(dl, i) * W(x, i);
+          } else {
+            double tmp = W(x, i);
+            W(x, i) = W(x, i + 1);
+            W(x, i + 1) = tmp - W(dl, i) * W(x, i);
+          }
+        }
+        // backward: U with two superdiagonals
+        double s = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+          double v = W(x, i);
+          if (i + 1 < n) v -= W(du, i) * W(x, i + 1);
+          if (i + 2 < n) v -= W(du2, i) * W(x, i + 2);
+          double di = W(dd, i);
+          if (fabs(di) < tiny) di = di < 0 ? -tiny : tiny;
+          v /= di;
+          W(x, i) = v;
+          s = fmax(s, fabs(v));
+        }
+        double nr = 0.0;
+        for (int i = 0; i < n; ++i) { W(x, i) /= s; nr += W(x, i) * W(x, i); }
+        nr = 1.0 / sqrt(nr);
+        for (int i = 0; i < n; ++i) W(x, i) *= nr;
       }
-      double nr = 0.0;
-      for (int i = 0; i < n; ++i) { W(x, i) /= s; nr += W(x, i) * W(x, i); }
-      nr = 1.0 / sqrt(nr);
-      for (int i = 0; i < n; ++i) W(x, i) *= nr;
+      for (int i = 0; i < n; ++i) IDX(Y, ldy, i, j) = W(x, i);
+  #undef W
     }
-    for (int i = 0; i < n; ++i) IDX(Y, ldy, i, j) = W(x, i);
-#undef W
+    t.sync();
   }
-  t.sync();
   // clusters: cl[j] = first index of the cluster containing j
   if (t.tid() == 0) {
     int c0 = 0;
@@ -824,7 +984,7 @@ __host__ __device__ void syev_lowest(T& t, double* A, int lda, int n, int k, dou
   double* e = work + n;
   double* tau = work + 2 * n;
   tridiagonalize_lower(t, A, lda, n, d, e, tau, lds, lds + n, lds + 2 * n, lds_size - 2 * n);
-  tridiag_lowest(t, d, e, n, k, w, Z, ldz, work + 3 * n, cl);
+  tridiag_lowest(t, d, e, n, k, w, Z, ldz, work + 3 * n, cl, lds, lds_size);
   backtransform(t, A, lda, tau, n, Z, ldz, k, lds, lds_size);
 }
 
