@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--graph", type=int, default=0,
+                    help="LOBPCG iterations per captured HIP graph launch (0: eager)")
+    ap.add_argument("--tune", type=int, default=0, help="1: autotune the Gram split-K at create")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -114,7 +117,7 @@ def main():
     X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
     h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=args.tol,
             max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-            n_alb=[e.n_alb for e in els])
+            n_alb=[e.n_alb for e in els], graph_iters=args.graph, tune=bool(args.tune))
     torch.cuda.synchronize()
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -158,7 +161,8 @@ def main():
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
                 data="synthetic", config=dict(desc, tol=args.tol, precision="fp64",
-                                              preconditioner="teter"),
+                                              preconditioner="teter", graph_iters=args.graph,
+                                              tuned=bool(args.tune)),
                 roofline=roof, kernels=kernels,
                 iterations=dict(mean=float(np.mean(iters)), min=int(min(iters)), max=int(max(iters))),
                 converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}")

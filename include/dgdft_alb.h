@@ -82,6 +82,16 @@ typedef struct dgdft_alb_opts {
     const float* mlp_weights; /* device [DGDFT_MLP_NTOT]: network of the learned  *
                                * preconditioner (read at every solve; may also be  *
                                * set later with dgdft_alb_set_mlp)                 */
+    int32_t graph_iters;      /* K > 0: each element group runs K LOBPCG          *
+                               * iterations per launch of a HIP graph captured     *
+                               * for its active set (re-captured when the set      *
+                               * changes); elements are checked between launches, *
+                               * so one that converges inside a launch runs the    *
+                               * rest of its K iterations.  0 = one launch per     *
+                               * kernel, checks every iteration (default)          */
+    int32_t tune;             /* 1: at create, time the split-K chunk count of    *
+                               * the N_g-long Gram products per element shape and  *
+                               * keep the fastest (see dgdft_alb_get_tuning)       */
 } dgdft_alb_opts;
 
 /* Kleinman-Bylander projectors of the whole batch, CSR by projector
@@ -113,7 +123,7 @@ typedef struct dgdft_alb_stats {
     int32_t n_p_drop;         /* iterations that restarted without P               */
     int32_t n_ql_fail;        /* small eigensolves whose QL iteration hit its cap  */
     int32_t n_teter_fallback; /* bands switched to the Teter factor (learned mode)  */
-    int32_t reserved;
+    int32_t graph_launches;   /* graph launches that advanced this element          */
 } dgdft_alb_stats;
 
 /* Create a handle for a batch of n_elem extended elements.
@@ -138,6 +148,10 @@ void dgdft_alb_destroy(dgdft_alb* h);
  */
 int32_t dgdft_alb_sizes(const dgdft_alb* h, int32_t elem, int64_t* ng, int64_t* ne,
                         int32_t* n_states, int32_t* n_alb, int64_t* offsets);
+
+/* Tuned parameters of element `elem` (host outputs, nullable): the split-K
+ * chunk count of its N_g-long Gram products (0 = the default rule). */
+int32_t dgdft_alb_get_tuning(const dgdft_alb* h, int32_t elem, int32_t* gram_split);
 
 /* Load the restricted potentials of all elements (V_eff^Q and V_nl^Q of
  * Sec. II.A).  V: device [sum N_g] (Ha); kb as above (n_proj may be NULL for

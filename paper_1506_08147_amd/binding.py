@@ -20,7 +20,7 @@ EXPORTS = (
     "dgdft_gemm_batched", "dgdft_alb_last_error", "dgdft_strerror", "dgdft_alb_profile",
     "dgdft_alb_kernel_stats", "dgdft_kernel_class_name", "dgdft_small_gemm_batched",
     "dgdft_alb_set_mlp", "dgdft_alb_shells", "dgdft_alb_log_capacity", "dgdft_alb_log_pairs",
-    "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval",
+    "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
@@ -46,7 +46,8 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("poll_every", C.c_int32),
                 ("elem_lo", C.POINTER(C.c_int32)), ("elem_hi", C.POINTER(C.c_int32)),
-                ("n_alb", C.POINTER(C.c_int32)), ("mlp_weights", C.c_void_p)]
+                ("n_alb", C.POINTER(C.c_int32)), ("mlp_weights", C.c_void_p),
+                ("graph_iters", C.c_int32), ("tune", C.c_int32)]
 
 
 class KB(C.Structure):
@@ -58,7 +59,7 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("max_res", C.c_double),
                 ("n_chol_fallback", C.c_int32), ("n_rr_fallback", C.c_int32),
                 ("n_p_drop", C.c_int32), ("n_ql_fail", C.c_int32),
-                ("n_teter_fallback", C.c_int32), ("reserved", C.c_int32)]
+                ("n_teter_fallback", C.c_int32), ("graph_launches", C.c_int32)]
 
 
 class Pairs(C.Structure):
@@ -131,6 +132,8 @@ def load_library():
     lib.dgdft_mlp_grad.restype = i32
     lib.dgdft_mlp_eval.argtypes = [vp, i64, vp, vp, vp]
     lib.dgdft_mlp_eval.restype = i32
+    lib.dgdft_alb_get_tuning.argtypes = [vp, i32, P(C.c_int32)]
+    lib.dgdft_alb_get_tuning.restype = i32
     _lib = lib
     return lib
 
@@ -156,7 +159,8 @@ class ALB:
     """
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
-                 elem_hi=None, n_alb=None, precond="teter", mlp_weights=None):
+                 elem_hi=None, n_alb=None, precond="teter", mlp_weights=None, graph_iters=0,
+                 tune=False):
         import torch  # noqa: F401  (device memory and streams)
         self.lib = load_library()
         self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
@@ -169,6 +173,8 @@ class ALB:
         o.tol = tol
         o.max_iter = max_iter
         o.poll_every = 1
+        o.graph_iters = int(graph_iters)
+        o.tune = 1 if tune else 0
         if mlp_weights is not None:
             self._mlp = mlp_weights
             o.mlp_weights = mlp_weights.data_ptr()
@@ -268,9 +274,16 @@ class ALB:
         stats = [dict(iters=s.iters, converged=bool(s.converged), max_res=s.max_res,
                       n_chol_fallback=s.n_chol_fallback, n_rr_fallback=s.n_rr_fallback,
                       n_p_drop=s.n_p_drop, n_ql_fail=s.n_ql_fail,
-                      n_teter_fallback=s.n_teter_fallback) for s in st]
+                      n_teter_fallback=s.n_teter_fallback,
+                      graph_launches=s.graph_launches) for s in st]
         return dict(status=rc, eigvals=vals, eigvecs=vecs, albs=albs, sigma=sig[:snalb],
                     stats=stats)
+
+    def get_tuning(self, e):
+        """Tuned split-K chunk count of element e's Gram products (0: default)."""
+        v = C.c_int32()
+        self._check(self.lib.dgdft_alb_get_tuning(self.h, e, C.byref(v)))
+        return v.value
 
     def set_mlp(self, weights):
         """Network of the learned preconditioner (device FP32 tensor [MLP_NTOT])."""

@@ -64,6 +64,7 @@ struct Elem {
   double* vbar;              // 1: mean of V
   double* thstar;            // J: converged eigenvalues (pair log)
   long long log_s0, log_r0;  // first sample / row of the element in the pair log
+  int gram_split;            // split-K chunks of N_g-long Gram products (0: default rule)
 };
 
 // Status words written by the device (one group per element).  The host
@@ -176,6 +177,16 @@ __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 __host__ __device__ inline int gram_nchunk(int K) {
   int c = cdiv(K, 4096);
   return c < 1 ? 1 : (c > GRAM_MAXCHUNK ? GRAM_MAXCHUNK : c);
+}
+// chunk count of an element's product over K rows: its tuned value for
+// N_g-long products (at most GRAM_MAXCHUNK), else the default rule
+__host__ __device__ inline int gram_nchunk_e(const Elem& e, int K) {
+  if (e.gram_split > 0 && K == e.ng) {
+    int c = e.gram_split > GRAM_MAXCHUNK ? GRAM_MAXCHUNK : e.gram_split;
+    int cmax = cdiv(K, 16);
+    return c > cmax ? cmax : c;
+  }
+  return gram_nchunk(K);
 }
 // chunk length, a multiple of 16
 __host__ __device__ inline int gram_chunklen(int K, int nchunk) { return cdiv(cdiv(K, nchunk), 16) * 16; }

@@ -92,6 +92,16 @@ struct dgdft_alb {
   hipStream_t g_stream[NGROUP] = {};
   hipEvent_t g_join = nullptr;
   hipEvent_t g_done[NGROUP] = {};
+  // HIP-graph mode: K iterations of a group captured once per active set.
+  // While capturing, prefix arrays go to a per-group table that is copied to
+  // the device once, before the graph's first launch.
+  bool capturing = false;
+  int cap_pos = 0;
+  size_t cap_slots = 0;
+  std::vector<int> cap_host[NGROUP];
+  int* cap_dev[NGROUP] = {};
+  hipGraphExec_t g_exec[NGROUP] = {};
+  std::vector<int> g_key[NGROUP];
   int* d_active_all = nullptr;
   // host readback (pinned)
   double* h_resid = nullptr;
@@ -129,13 +139,13 @@ struct dgdft_alb {
     return pool[ev_used[cur_g]++];
   }
   void pbeg(int kid, double flops, double bytes) {
-    if (!prof) return;
+    if (!prof || capturing) return;
     cur_kid = kid; cur_flops = flops; cur_bytes = bytes;
     cur_a = ev();
     HCHECK(hipEventRecord(cur_a, stream));
   }
   void pend() {
-    if (!prof) return;
+    if (!prof || capturing) return;
     hipEvent_t b = ev();
     HCHECK(hipEventRecord(b, stream));
     recs[cur_g].push_back(ProfRec{cur_kid, cur_a, b, cur_flops, cur_bytes});
@@ -174,6 +184,20 @@ struct dgdft_alb {
   // Upload `active` and per-element work counts; returns device pointers.
   template <class F>
   Prefix make_prefix(const std::vector<int>& act, F work) {
+    if (capturing) {
+      if ((size_t)cap_pos >= cap_slots) throw HipFail{hipErrorUnknown, "graph prefix table full"};
+      size_t off = (size_t)cap_pos * ring_stride;
+      ++cap_pos;
+      int* hp = cap_host[cur_g].data() + off;
+      int* dp = cap_dev[cur_g] + off;
+      int na = (int)act.size();
+      hp[n] = 0;
+      for (int i = 0; i < na; ++i) {
+        hp[i] = act[i];
+        hp[n + i + 1] = hp[n + i] + work(act[i]);
+      }
+      return Prefix{dp, dp + n, na, hp[n + na]};
+    }
     if (ring_pos >= PREFIX_RING) throw HipFail{hipErrorUnknown, "prefix ring exhausted"};
     size_t slot = (size_t)cur_g * PREFIX_RING + ring_pos;
     int* hp = ring_h + slot * ring_stride;
@@ -275,7 +299,7 @@ struct dgdft_alb {
     auto P = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
       for (int j = 0; j < g.njob; ++j) c += gram_tiles(m, cols_host(g.B[j], e), g.upper);
-      return c * gram_nchunk(K(e));
+      return c * gram_nchunk_e(eh[e], K(e));
     });
     if (P.total == 0) return;
     double fl = 0, by = 0;
@@ -571,6 +595,10 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   for (auto& pool : h->ev_pool)
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   if (h->g_join) (void)hipEventDestroy(h->g_join);
+  for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+    if (h->g_exec[g]) (void)hipGraphExecDestroy(h->g_exec[g]);
+    (void)hipFree(h->cap_dev[g]);
+  }
   for (int g = 1; g < dgdft_alb::NGROUP; ++g) {
     if (h->g_done[g]) (void)hipEventDestroy(h->g_done[g]);
     if (h->g_stream[g]) (void)hipStreamDestroy(h->g_stream[g]);
@@ -608,6 +636,58 @@ static void grid_shells(const Elem& E, std::vector<int>& shell_of, std::vector<d
     shell_of[order[q]] = (int)t_shell.size() - 1;
     prev = v;
   }
+}
+
+// Autotuner: for each element shape (N_g, J), time the Rayleigh-Ritz Gram
+// product (S^T [S, HS] upper triangles, S = three N_g x J blocks) with 1, 2,
+// 4 and 8 split-K chunks on a representative element and keep the fastest
+// for every element of that shape.  Contents of the blocks do not matter.
+static void tune_gram(dgdft_alb* h) {
+  std::vector<std::pair<long long, int>> shapes;
+  for (const Elem& E : h->eh) {
+    std::pair<long long, int> key{E.ng, E.J};
+    if (std::find(shapes.begin(), shapes.end(), key) == shapes.end()) shapes.push_back(key);
+  }
+  hipEvent_t a, b;
+  HCHECK(hipEventCreate(&a));
+  HCHECK(hipEventCreate(&b));
+  GramArgs g{};
+  g.A = dgdft_alb::opnd({S_W, S_W2, S_HW});
+  g.B[0] = g.A;
+  g.B[1] = dgdft_alb::opnd({S_X0, S_P0, S_HX0});
+  g.njob = 2; g.out_mat[0] = SM_M; g.out_mat[1] = SM_H; g.upper = 1;
+  const int cand[4] = {1, 2, 4, 8};
+  for (auto& sh : shapes) {
+    int e0 = -1;
+    for (int e = 0; e < h->n; ++e)
+      if (h->eh[e].ng == sh.first && h->eh[e].J == sh.second) { e0 = e; break; }
+    std::vector<int> one{e0};
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int c : cand) {
+      h->eh[e0].gram_split = c;
+      h->upload_elems();
+      float tot = 0.0f;
+      for (int rep = 0; rep < 3; ++rep) {
+        h->ring_reset();
+        HCHECK(hipEventRecord(a, h->stream));
+        h->gram(one, g);
+        HCHECK(hipEventRecord(b, h->stream));
+        HCHECK(hipEventSynchronize(b));
+        float ms = 0.0f;
+        HCHECK(hipEventElapsedTime(&ms, a, b));
+        if (rep > 0) tot += ms;   // first run warms up
+      }
+      if (tot < best_ms) { best_ms = tot; best = c; }
+    }
+    for (Elem& E : h->eh)
+      if (E.ng == sh.first && E.J == sh.second) E.gram_split = best;
+  }
+  h->upload_elems();
+  HCHECK(hipStreamSynchronize(h->stream));
+  h->ring_reset();
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
 }
 
 int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box, int32_t n_elem,
@@ -796,17 +876,31 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       HCHECK(hipEventCreateWithFlags(&h->g_done[g], hipEventDisableTiming));
     }
     HCHECK(hipEventCreateWithFlags(&h->g_join, hipEventDisableTiming));
+    if (h->opts.graph_iters > 0) {
+      h->cap_slots = (size_t)h->opts.graph_iters * 128;
+      for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+        h->cap_host[g].assign(h->cap_slots * h->ring_stride, 0);
+        HCHECK(hipMalloc(&h->cap_dev[g], sizeof(int) * h->cap_slots * h->ring_stride));
+      }
+    }
     HCHECK(hipHostMalloc(&h->h_resid, sizeof(double) * h->sumJ));
     HCHECK(hipHostMalloc(&h->h_fl, sizeof(int) * (size_t)n_elem * FL_COUNT));
     memset(h->h_fl, 0, sizeof(int) * (size_t)n_elem * FL_COUNT);
     h->upload_elems();
     HCHECK(hipStreamSynchronize(h->stream));
+    if (h->opts.tune) tune_gram(h);
   } catch (HipFail& f) {
     g_create_error = f.what;
     dgdft_alb_destroy(h);
     return f.code == hipErrorOutOfMemory ? DGDFT_ENOMEM : DGDFT_EHIP;
   }
   *out = h;
+  return DGDFT_OK;
+}
+
+int32_t dgdft_alb_get_tuning(const dgdft_alb* h, int32_t elem, int32_t* gram_split) {
+  if (!h || elem < 0 || elem >= h->n) return DGDFT_EINVAL;
+  if (gram_split) *gram_split = h->eh[elem].gram_split;
   return DGDFT_OK;
 }
 
@@ -1168,6 +1262,43 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   h->per_elem(act, 3, 0);
 }
 
+// Graph mode: K iterations (each followed by the residual step) of the
+// group's active set as one HIP graph, captured when the set differs from
+// the last captured one, then launched on the group's stream.
+static void run_graph(dgdft_alb* h, int g, const std::vector<int>& act, int K) {
+  if (!h->g_exec[g] || h->g_key[g] != act) {
+    if (h->g_exec[g]) {
+      HCHECK(hipStreamSynchronize(h->stream));
+      HCHECK(hipGraphExecDestroy(h->g_exec[g]));
+      h->g_exec[g] = nullptr;
+    }
+    h->capturing = true;
+    h->cap_pos = 0;
+    hipGraph_t graph = nullptr;
+    HCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int k = 0; k < K; ++k) {
+        iterate(h, act);
+        h->per_elem_cols(act, 0, VS_X, VS_HX, S_W, nullptr, nullptr);
+      }
+    } catch (...) {
+      (void)hipStreamEndCapture(h->stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      h->capturing = false;
+      throw;
+    }
+    h->capturing = false;
+    HCHECK(hipStreamEndCapture(h->stream, &graph));
+    hipError_t st = hipGraphInstantiate(&h->g_exec[g], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HCHECK(st);
+    HCHECK(hipMemcpy(h->cap_dev[g], h->cap_host[g].data(), sizeof(int) * (size_t)h->cap_pos * h->ring_stride,
+                     hipMemcpyHostToDevice));
+    h->g_key[g] = act;
+  }
+  HCHECK(hipGraphLaunch(h->g_exec[g], h->stream));
+}
+
 static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double* eigvecs, double* albs,
                          double* sigma, dgdft_alb_stats* stats) {
   const int n = h->n;
@@ -1215,7 +1346,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   h->op_apply(all, VS_X, VS_HX, 0, -1);
   rr_on_x(h, all);
 
-  std::vector<int> iters(n, 0);
+  std::vector<int> iters(n, 0), glaunch(n, 0);
   const double tol = h->opts.tol;
   const int max_iter = h->opts.max_iter;
   // Iterate until the running residuals reach tol, then check every element
@@ -1247,9 +1378,19 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
         act[g].swap(next);
         if (act[g].empty()) continue;
         any = true;
-        iterate(h, act[g]);
-        for (int e : act[g]) iters[e]++;
-        h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);
+        // graph mode once every element of the group carries P and has K
+        // iterations left (the first iteration and the pair log run eagerly)
+        const int K = h->opts.graph_iters;
+        bool graph = K > 0 && !h->log_on;
+        for (int e : act[g]) graph = graph && h->hasP_host(e) && iters[e] + K <= max_iter;
+        if (graph) {
+          run_graph(h, g, act[g], K);
+          for (int e : act[g]) { iters[e] += K; glaunch[e]++; }
+        } else {
+          iterate(h, act[g]);
+          for (int e : act[g]) iters[e]++;
+          h->per_elem_cols(act[g], 0, VS_X, VS_HX, S_W, nullptr, nullptr);
+        }
       }
       if (!any) break;
     }
@@ -1299,6 +1440,13 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   HCHECK(hipStreamSynchronize(s));
   h->flush_prof();
   if (sig_tmp) (void)hipFree(sig_tmp);
+  for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+    if (h->g_exec[g]) {
+      HCHECK(hipGraphExecDestroy(h->g_exec[g]));
+      h->g_exec[g] = nullptr;
+      h->g_key[g].clear();
+    }
+  }
   // ---- stats
   std::vector<double> stall;
   if (stats && h->opts.precond == DGDFT_PRECOND_LEARNED) {
@@ -1323,7 +1471,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
       if (!stall.empty())
         for (int j = 0; j < h->eh[e].J; ++j) nf += stall[4 * (h->eh[e].off_j + j) + 3] != 0.0;
       stats[e].n_teter_fallback = nf;
-      stats[e].reserved = 0;
+      stats[e].graph_launches = glaunch[e];
     }
   }
   return fail(any_nc ? DGDFT_NOT_CONVERGED : DGDFT_OK, any_nc ? "some element did not converge" : "");

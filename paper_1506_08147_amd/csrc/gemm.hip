@@ -68,7 +68,7 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   int w = blk - prefix[ai];
   const int K = rowsK(e, g.use_ne);
   const int m = opnd_cols(g.A, e);
-  const int nch = gram_nchunk(K), clen = gram_chunklen(K, nch);
+  const int nch = gram_nchunk_e(e, K), clen = gram_chunklen(K, nch);
   const int n0 = opnd_cols(g.B[0], e);
   int job = 0, n = n0;
   int ntile = gram_tiles(m, n, g.upper);
@@ -78,6 +78,9 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
     n = opnd_cols(g.B[1], e);
     ntile = gram_tiles(m, n, g.upper);
   }
+  // a grid sized for more blocks than the element has now (P dropped since
+  // the launch was planned, e.g. inside a captured graph) leaves spare items
+  if (job >= g.njob || ntile == 0 || w >= ntile * nch) return;
   const Opnd& B = g.B[job];
   int chunk = w / ntile, tile = w - chunk * ntile;
   int ti, tj;
@@ -171,11 +174,12 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
   int w = blk - prefix[ai];
   const int K = rowsK(e, g.use_ne);
   const int m = opnd_cols(g.A, e);
-  const int nch = gram_nchunk(K);
+  const int nch = gram_nchunk_e(e, K);
   const int n0 = opnd_cols(g.B[0], e);
   int job = 0, n = n0;
   int nb = cdiv(m * n, 256);
   if (w >= nb) { job = 1; w -= nb; n = opnd_cols(g.B[1], e); }
+  if (job >= g.njob) return;
   int idx = w * 256 + threadIdx.x;
   if (idx >= m * n) return;
   const double* part = e.gpart + (job ? (long long)nch * m * n0 : 0LL);
@@ -213,7 +217,9 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   const int kA = opnd_cols(u.A[0], e);
   const int ncol = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? e.nalb : opnd_cols(u.Y[0], e));
   const int ntr = cdiv(K, TT), ntc = cdiv(ncol, TT);
+  if (ntr * ntc == 0) return;
   int job = w / (ntr * ntc);
+  if (job >= u.njob) return;   // spare items of a grid planned for more columns
   w -= job * ntr * ntc;
   int tr = w / ntc, tc = w - tr * ntc;
   const Opnd& A = u.A[job];
