@@ -251,3 +251,23 @@ def mlp_init(seed=0, last_layer=0.0):
     o += 1
     w[o + 3:o + 6] = 1.0
     return w
+
+
+# ---------------------------------------------------------------- SCF-like updates
+def perturbed_potential(el, step, amp=0.02, modes=6):
+    """V of element `el` plus a smooth seeded perturbation standing in for the
+    change of the effective potential between two SCF steps: `modes` random
+    low-frequency cosines (|m_d| <= 2), total amplitude `amp` Ha."""
+    rng = np.random.default_rng([6, 0, step, int(el.grid[0] * 10000 + el.grid[1] * 100 + el.grid[2])])
+    n1, n2, n3 = el.grid
+    x = np.arange(n1) / n1
+    y = np.arange(n2) / n2
+    z = np.arange(n3) / n3
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    dV = np.zeros((n3, n2, n1))
+    for _ in range(modes):
+        m = rng.integers(-2, 3, size=3)
+        ph = rng.uniform(0, 2 * np.pi)
+        dV += np.cos(2 * np.pi * (m[0] * X + m[1] * Y + m[2] * Z) + ph)
+    dV *= amp / modes
+    return el.V + dV.ravel()
