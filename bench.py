@@ -136,6 +136,7 @@ def main():
     ap.add_argument("--graph", type=int, default=0,
                     help="LOBPCG iterations per captured HIP graph launch (0: eager)")
     ap.add_argument("--tune", type=int, default=0, help="1: autotune the Gram split-K at create")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--warm", type=int, default=0,
                     help="S > 0: warm-start mode instead: after one converged solve, S timed "
                          "SCF-like steps (perturbed V, 3 LOBPCG iterations from the previous "
@@ -162,7 +163,8 @@ def main():
     X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
     h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=args.tol,
             max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-            n_alb=[e.n_alb for e in els], graph_iters=args.graph, tune=bool(args.tune))
+            n_alb=[e.n_alb for e in els], graph_iters=args.graph, tune=bool(args.tune),
+            precision=args.precision)
     torch.cuda.synchronize()
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -207,8 +209,9 @@ def main():
                for k, v in ks.items() if v["launches"]}
     line = dict(metric=METRIC, value=round(n_conv / elapsed, 4), unit="elements/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
-                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
-                data="synthetic", config=dict(desc, tol=args.tol, precision="fp64",
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64" if args.precision == "fp64" else "f64+f32",
+                data="synthetic", config=dict(desc, tol=args.tol, precision=args.precision,
                                               preconditioner="teter", graph_iters=args.graph,
                                               tuned=bool(args.tune)),
                 roofline=roof, kernels=kernels,

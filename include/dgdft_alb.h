@@ -55,7 +55,9 @@ extern "C" {
 #define DGDFT_EBREAKDOWN      -5   /* initial block rank deficient (CholQR)       */
 
 #define DGDFT_PREC_FP64        0
-#define DGDFT_PREC_MIXED       1   /* FP32 FFT/pointwise; reserved, see design    */
+#define DGDFT_PREC_MIXED       1   /* FP32 transforms for H W and the             *
+                                    * preconditioner; Grams, Rayleigh-Ritz, X/HX   *
+                                    * updates, final check and ALBs stay FP64      */
 
 #define DGDFT_PRECOND_TETER    0
 #define DGDFT_PRECOND_LEARNED  1   /* Teter factor times a learned per-shell gain *
@@ -182,7 +184,9 @@ int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb,
  * unit-basis columns: HX = (F^-1 diag(|G|^2/2) F + diag(V) +
  * sum_p gamma_p beta_p beta_p^T) X with beta_p = sqrt(dV) b_p
  * (Eq. localproblem with the KB term of Eq. DGvar; the operation-1 of the
- * LOBPCG list in Sec. II.B).  X, HX: device [N_g*ncols]; 1 <= ncols <= J. */
+ * LOBPCG list in Sec. II.B).  X, HX: device [N_g*ncols]; 1 <= ncols <= J.
+ * A handle created with DGDFT_PREC_MIXED applies the kinetic term with FP32
+ * transforms, as inside its iteration (V and KB terms in FP64). */
 int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* HX,
                           int32_t ncols, void* stream);
 
@@ -190,7 +194,8 @@ int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* H
  * al.): W_i = F^-1 K(|G|^2/2 / T_i) F R_i with T_i = the kinetic energy of the
  * unit vector X_i, floored at (2 pi / L_max)^2 / 2, and
  * K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4).
- * R, X, W: device [N_g*ncols]; W may equal R. */
+ * R, X, W: device [N_g*ncols]; W may equal R.  FP32 transforms for a
+ * DGDFT_PREC_MIXED handle (T_i in FP64). */
 int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R,
                                const double* X, double* W, int32_t ncols, void* stream);
 

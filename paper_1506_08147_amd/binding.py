@@ -160,7 +160,7 @@ class ALB:
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
                  elem_hi=None, n_alb=None, precond="teter", mlp_weights=None, graph_iters=0,
-                 tune=False):
+                 tune=False, precision="fp64"):
         import torch  # noqa: F401  (device memory and streams)
         self.lib = load_library()
         self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
@@ -168,7 +168,7 @@ class ALB:
         boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 3)
         self._keep = []
         o = Opts()
-        o.precision = 0
+        o.precision = {"fp64": 0, "mixed": 1}[precision]
         o.precond = PRECOND[precond]
         o.tol = tol
         o.max_iter = max_iter

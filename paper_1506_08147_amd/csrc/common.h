@@ -34,6 +34,7 @@ struct Elem {
   double* V;                 // ng
   double2* zscr;             // FFT scratch: ceil(J/2) * ng complex
   const double2* tw[3];      // exp(-2 pi i t / n_d), t < n_d
+  const float2* tw32[3];     // the same in FP32 (mixed-precision transforms)
   double* theta;             // J   Ritz values
   double* resid;             // J   residual norms
   double* xhx;               // J   x_i . (HX)_i

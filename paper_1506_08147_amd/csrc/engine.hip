@@ -60,6 +60,7 @@ struct dgdft_alb {
   double* vec_arena = nullptr;     // theta, resid, xhx, vx, tkin (5 * sumJ)
   int* fl_arena = nullptr;         // n * FL_COUNT
   double2* tw_arena = nullptr;
+  float2* tw32_arena = nullptr;
   void* kb_arena = nullptr;        // KB layout of the loaded potential
   size_t kb_cap = 0;
   double* proj_arena = nullptr;    // proj + projx
@@ -224,7 +225,9 @@ struct dgdft_alb {
     return false;
   }
 
-  void op_apply(const std::vector<int>& act, int in_slot, int out_slot, int col0, int ncols_fixed) {
+  // fp32: the transforms run in FP32 (the V and KB terms stay FP64)
+  void op_apply(const std::vector<int>& act, int in_slot, int out_slot, int col0, int ncols_fixed,
+                bool fp32 = false) {
     // ncols_fixed < 0: all J columns
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
     launch_kbproj(act, in_slot, col0, ncols_fixed, 0);
@@ -232,18 +235,20 @@ struct dgdft_alb {
     double pts = 0;   // grid points x column pairs
     for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
     const bool big = big_planes(act);
-    pbeg(DGDFT_K_FFT_XY_FWD, 0, 32.0 * pts);
-    hipLaunchKernelGGL(big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0,
-                       stream, ed, P1.active, P1.prefix, P1.na, in_slot, col0, ncols_fixed);
+    pbeg(DGDFT_K_FFT_XY_FWD, 0, (fp32 ? 24.0 : 32.0) * pts);
+    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd32) : (big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd),
+                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, in_slot,
+                       col0, ncols_fixed);
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
-    pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
-    hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
-                       P2.prefix, P2.na, col0, ncols_fixed, 0);
+    pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
+    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed,
+                       P2.active, P2.prefix, P2.na, col0, ncols_fixed, 0);
     pend();
-    pbeg(DGDFT_K_FFT_XY_INV, 0, 56.0 * pts);
-    hipLaunchKernelGGL(big ? dg_fft_xy_inv_l : dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0,
-                       stream, ed, P1.active, P1.prefix, P1.na, in_slot, out_slot, col0, ncols_fixed, 0);
+    pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 48.0 : 56.0) * pts);
+    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_inv32_l : dg_fft_xy_inv32) : (big ? dg_fft_xy_inv_l : dg_fft_xy_inv),
+                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, in_slot,
+                       out_slot, col0, ncols_fixed, 0);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -259,25 +264,27 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
   }
 
-  void precondition(const std::vector<int>& act, int slot, int col0, int ncols_fixed) {
+  void precondition(const std::vector<int>& act, int slot, int col0, int ncols_fixed, bool fp32 = false) {
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
     auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
     double pts = 0;
     for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
     const bool big = big_planes(act);
-    pbeg(DGDFT_K_FFT_XY_FWD, 0, 32.0 * pts);
-    hipLaunchKernelGGL(big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd, dim3(P1.total), dim3(FFT_THREADS), 0,
-                       stream, ed, P1.active, P1.prefix, P1.na, slot, col0, ncols_fixed);
+    pbeg(DGDFT_K_FFT_XY_FWD, 0, (fp32 ? 24.0 : 32.0) * pts);
+    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd32) : (big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd),
+                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, slot,
+                       col0, ncols_fixed);
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
-    pbeg(DGDFT_K_FFT_Z, 0, 32.0 * pts);
-    hipLaunchKernelGGL(dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed, P2.active,
-                       P2.prefix, P2.na, col0, ncols_fixed,
+    pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
+    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed,
+                       P2.active, P2.prefix, P2.na, col0, ncols_fixed,
                        opts.precond == DGDFT_PRECOND_NONE ? 2 : opts.precond == DGDFT_PRECOND_LEARNED ? 3 : 1);
     pend();
-    pbeg(DGDFT_K_FFT_XY_INV, 0, 32.0 * pts);
-    hipLaunchKernelGGL(big ? dg_fft_xy_inv_l : dg_fft_xy_inv, dim3(P1.total), dim3(FFT_THREADS), 0,
-                       stream, ed, P1.active, P1.prefix, P1.na, slot, slot, col0, ncols_fixed, 1);
+    pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 24.0 : 32.0) * pts);
+    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_inv32_l : dg_fft_xy_inv32) : (big ? dg_fft_xy_inv_l : dg_fft_xy_inv),
+                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, slot,
+                       slot, col0, ncols_fixed, 1);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -584,6 +591,7 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   (void)hipFree(h->vec_arena);
   (void)hipFree(h->fl_arena);
   (void)hipFree(h->tw_arena);
+  (void)hipFree(h->tw32_arena);
   (void)hipFree(h->kb_arena);
   (void)hipFree(h->proj_arena);
   (void)hipFree(h->d_flag);
@@ -710,8 +718,8 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     return DGDFT_EINVAL;
   }
   h->mlp_w = h->opts.mlp_weights;
-  if (h->opts.precision != DGDFT_PREC_FP64) {
-    g_create_error = "only DGDFT_PREC_FP64 is implemented";
+  if (h->opts.precision != DGDFT_PREC_FP64 && h->opts.precision != DGDFT_PREC_MIXED) {
+    g_create_error = "unknown precision";
     delete h;
     return DGDFT_EUNSUPPORTED;
   }
@@ -846,7 +854,9 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     long long ntw = 0;
     for (auto& E : h->eh) ntw += E.n1 + E.n2 + E.n3;
     HCHECK(hipMalloc(&h->tw_arena, sizeof(double2) * ntw));
+    HCHECK(hipMalloc(&h->tw32_arena, sizeof(float2) * ntw));
     std::vector<double2> tw(ntw);
+    std::vector<float2> tw32(ntw);
     long long o = 0;
     for (int e = 0; e < n_elem; ++e) {
       Elem& E = h->eh[e];
@@ -855,8 +865,10 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
         for (int t = 0; t < nd3[d]; ++t) {
           double a = 2.0 * M_PI * (double)t / (double)nd3[d];
           tw[o + t] = make_double2(std::cos(a), -std::sin(a));
+          tw32[o + t] = make_float2((float)std::cos(a), (float)-std::sin(a));
         }
         E.tw[d] = h->tw_arena + o;
+        E.tw32[d] = h->tw32_arena + o;
         o += nd3[d];
       }
       E.theta = h->vec_arena + E.off_j;
@@ -867,6 +879,7 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       E.fl = h->fl_arena + (size_t)e * FL_COUNT;
     }
     HCHECK(hipMemcpy(h->tw_arena, tw.data(), sizeof(double2) * ntw, hipMemcpyHostToDevice));
+    HCHECK(hipMemcpy(h->tw32_arena, tw32.data(), sizeof(float2) * ntw, hipMemcpyHostToDevice));
     HCHECK(hipMalloc(&h->ed, sizeof(Elem) * n_elem));
     h->ring_stride = 2 * n_elem + 8;
     HCHECK(hipMalloc(&h->ring_d, sizeof(int) * (size_t)h->ring_stride * PREFIX_RING * dgdft_alb::NGROUP));
@@ -1214,11 +1227,12 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   h->launch_kbproj(act, VS_X, 0, -1, 1);
   h->per_elem(act, 2, 0);
   if (h->log_on) log_step(h, act);
+  const bool mixed = h->opts.precision == DGDFT_PREC_MIXED;
   if (h->opts.precond == DGDFT_PRECOND_LEARNED) {
     h->stall_step(act);
     h->gain_table(act, 1);
   }
-  h->precondition(act, S_W, 0, -1);
+  h->precondition(act, S_W, 0, -1, mixed);
   // W <- W - [X P]([X P]^T W)
   GramArgs g1{};
   g1.A = dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
@@ -1242,8 +1256,9 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   u2.Y[0] = dgdft_alb::opnd({S_W2});
   u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = 1.0; u2.beta = 0.0;
   h->update(act, u2);
-  // HW
-  h->op_apply(act, S_W2, S_HW, 0, -1);
+  // HW (FP32 transforms in the mixed form: errors enter H X and H P only
+  // through the correction coefficients, and the final check is FP64)
+  h->op_apply(act, S_W2, S_HW, 0, -1, mixed);
   // Rayleigh-Ritz on S = [X P W2]
   GramArgs g3{};
   g3.A = dgdft_alb::opnd({VS_X, VS_P, S_W2}, {0, 1, 0});
@@ -1354,6 +1369,11 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   // whose fresh residual is still above tol goes back to the iteration
   // (without P) while it has iterations left.
   std::vector<int> pending = all;
+  // Mixed form: iterate first to max(tol, MIXED_REFRESH), refresh H X in FP64
+  // (the check below), then iterate to tol: what the FP32 transforms left in
+  // H X is then scaled by corrections of the size of the residual.
+  constexpr double MIXED_REFRESH = 1e-4;
+  double target = (h->opts.precision == DGDFT_PREC_MIXED && tol < MIXED_REFRESH) ? MIXED_REFRESH : tol;
   while (!pending.empty()) {
     // Split the elements into groups that iterate on their own streams; the
     // second stream first waits for everything enqueued so far.
@@ -1374,7 +1394,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
         h->poll();
         std::vector<int> next;
         for (int e : act[g])
-          if (!(h->max_res(e) <= tol || iters[e] >= max_iter)) next.push_back(e);
+          if (!(h->max_res(e) <= target || iters[e] >= max_iter)) next.push_back(e);
         act[g].swap(next);
         if (act[g].empty()) continue;
         any = true;
@@ -1411,6 +1431,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
     for (int e : pending)
       if (!(h->max_res(e) <= tol) && iters[e] < max_iter) again.push_back(e);
     pending.swap(again);
+    target = tol;
   }
   // ---- restriction + SVD truncation
   h->per_elem_cols(all, 4, VS_X, S_W, 0, nullptr, nullptr);
@@ -1522,7 +1543,7 @@ int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* H
     h->ring_reset();
     bind_user(h, elem, X, HX, nullptr);
     std::vector<int> one{elem};
-    h->op_apply(one, S_U0, S_U1, 0, ncols);
+    h->op_apply(one, S_U0, S_U1, 0, ncols, h->opts.precision == DGDFT_PREC_MIXED);
     HCHECK(hipStreamSynchronize(h->stream));
     return DGDFT_OK;
   } catch (HipFail& f) {
@@ -1559,7 +1580,7 @@ int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R, cons
       if (!h->mlp_w) { h->err = "learned preconditioner without weights"; return DGDFT_EINVAL; }
       h->gain_table(one, 0);
     }
-    h->precondition(one, S_U1, 0, ncols);
+    h->precondition(one, S_U1, 0, ncols, h->opts.precision == DGDFT_PREC_MIXED);
     HCHECK(hipStreamSynchronize(h->stream));
     return DGDFT_OK;
   } catch (HipFail& f) {

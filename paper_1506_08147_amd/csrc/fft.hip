@@ -45,62 +45,102 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_dou
 // i*sign*z
 __device__ __forceinline__ double2 cisgn(double2 z, double sgn) { return make_double2(-sgn * z.y, sgn * z.x); }
 
-template <int R> __device__ __forceinline__ void dft(double2* v, double sgn);
-
-template <> __device__ __forceinline__ void dft<2>(double2* v, double) {
-  double2 a = v[0], b = v[1];
-  v[0] = cadd(a, b);
-  v[1] = csub(a, b);
+// FP32 forms (mixed-precision transforms)
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, double s) {
+  const float f = (float)s;
+  return make_float2(a.x * f, a.y * f);
+}
+__device__ __forceinline__ float2 cisgn(float2 z, double sgn) {
+  const float f = (float)sgn;
+  return make_float2(-f * z.y, f * z.x);
+}
+template <class C> __device__ __forceinline__ C cmake(double x, double y);
+template <> __device__ __forceinline__ double2 cmake<double2>(double x, double y) { return make_double2(x, y); }
+template <> __device__ __forceinline__ float2 cmake<float2>(double x, double y) {
+  return make_float2((float)x, (float)y);
+}
+// twiddle table of axis d in the transform's precision
+template <class C> __device__ __forceinline__ const C* twiddles(const Elem& e, int d);
+template <> __device__ __forceinline__ const double2* twiddles<double2>(const Elem& e, int d) { return e.tw[d]; }
+template <> __device__ __forceinline__ const float2* twiddles<float2>(const Elem& e, int d) { return e.tw32[d]; }
+// FFT scratch of a pair (FP32 pairs use the first half of each FP64 pair slot)
+template <class C> __device__ __forceinline__ C* zpair(const Elem& e, int q);
+template <> __device__ __forceinline__ double2* zpair<double2>(const Elem& e, int q) {
+  return e.zscr + (long long)q * e.ng;
+}
+template <> __device__ __forceinline__ float2* zpair<float2>(const Elem& e, int q) {
+  return (float2*)(e.zscr + (long long)q * e.ng);
 }
 
-template <> __device__ __forceinline__ void dft<3>(double2* v, double sgn) {
-  const double h = 0.86602540378443864676;   // sin(2 pi / 3)
-  double2 s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
-  double2 m = csub(v[0], cscale(s, 0.5));
-  double2 r = cisgn(cscale(d, h), sgn);
-  v[0] = cadd(v[0], s);
-  v[1] = cadd(m, r);
-  v[2] = csub(m, r);
-}
+template <int R> struct Dft;
 
-template <> __device__ __forceinline__ void dft<4>(double2* v, double sgn) {
-  double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-  double2 s13 = cadd(v[1], v[3]), d13 = cisgn(csub(v[1], v[3]), sgn);
-  v[0] = cadd(s02, s13);
-  v[2] = csub(s02, s13);
-  v[1] = cadd(d02, d13);
-  v[3] = csub(d02, d13);
-}
+template <> struct Dft<2> {
+  template <class C> static __device__ __forceinline__ void run(C* v, double) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
 
-template <> __device__ __forceinline__ void dft<5>(double2* v, double sgn) {
-  const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-  const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
-  double2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-  double2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-  double2 a = v[0];
-  double2 m1 = cadd(a, cadd(cscale(t1, c1), cscale(t2, c2)));
-  double2 m2 = cadd(a, cadd(cscale(t1, c2), cscale(t2, c1)));
-  double2 r1 = cisgn(cadd(cscale(t3, s1), cscale(t4, s2)), sgn);
-  double2 r2 = cisgn(csub(cscale(t3, s2), cscale(t4, s1)), sgn);
-  v[0] = cadd(a, cadd(t1, t2));
-  v[1] = cadd(m1, r1);
-  v[4] = csub(m1, r1);
-  v[2] = cadd(m2, r2);
-  v[3] = csub(m2, r2);
-}
+template <> struct Dft<3> {
+  template <class C> static __device__ __forceinline__ void run(C* v, double sgn) {
+    const double h = 0.86602540378443864676;   // sin(2 pi / 3)
+    C s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    C m = csub(v[0], cscale(s, 0.5));
+    C r = cisgn(cscale(d, h), sgn);
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+  }
+};
+
+template <> struct Dft<4> {
+  template <class C> static __device__ __forceinline__ void run(C* v, double sgn) {
+    C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    C s13 = cadd(v[1], v[3]), d13 = cisgn(csub(v[1], v[3]), sgn);
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+template <> struct Dft<5> {
+  template <class C> static __device__ __forceinline__ void run(C* v, double sgn) {
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
+    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+    C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    C a = v[0];
+    C m1 = cadd(a, cadd(cscale(t1, c1), cscale(t2, c2)));
+    C m2 = cadd(a, cadd(cscale(t1, c2), cscale(t2, c1)));
+    C r1 = cisgn(cadd(cscale(t3, s1), cscale(t4, s2)), sgn);
+    C r2 = cisgn(csub(cscale(t3, s2), cscale(t4, s1)), sgn);
+    v[0] = cadd(a, cadd(t1, t2));
+    v[1] = cadd(m1, r1);
+    v[4] = csub(m1, r1);
+    v[2] = cadd(m2, r2);
+    v[3] = csub(m2, r2);
+  }
+};
 
 // One Stockham stage of radix R on `nlines` lines of length n stored in LDS
 // at buf[line*lstride + m*estride].  Ns = product of the radices done so far.
 // MAXPTS bounds the points of the tile, so the register staging is sized at
 // compile time.
-template <int R, int MAXPTS>
-__device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstride, int estride,
-                                      int Ns, const double2* __restrict__ tw, double sgn) {
+template <int R, int MAXPTS, class C>
+__device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, int estride,
+                                      int Ns, const C* __restrict__ tw, double sgn) {
   constexpr int MAXK = (MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
   const unsigned nb = n / R;
   const unsigned total = nb * nlines;
   const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
-  double2 v[MAXK][R];
+  C v[MAXK][R];
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
     unsigned b = threadIdx.x + q * FFT_THREADS;
@@ -122,11 +162,11 @@ __device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstri
       int k = j - jq * Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        double2 w = tw[k * r * step];
+        C w = tw[k * r * step];
         if (sgn > 0) w.y = -w.y;
         v[q][r] = cmul(v[q][r], w);
       }
-      dft<R>(v[q], sgn);
+      Dft<R>::run(v[q], sgn);
       int o = jq * Ns * R + k;
       int base = line * lstride;
 #pragma unroll
@@ -136,18 +176,18 @@ __device__ __forceinline__ void stage(double2* buf, int n, int nlines, int lstri
   __syncthreads();
 }
 
-template <int MAXPTS>
-__device__ __forceinline__ void fft_lines(double2* buf, int n, int nlines, int lstride, int estride,
-                                          const int* rad, int nrad, const double2* __restrict__ tw,
+template <int MAXPTS, class C>
+__device__ __forceinline__ void fft_lines(C* buf, int n, int nlines, int lstride, int estride,
+                                          const int* rad, int nrad, const C* __restrict__ tw,
                                           double sgn) {
   int Ns = 1;
   for (int s = 0; s < nrad; ++s) {
     int R = rad[s];
     switch (R) {
-      case 4: stage<4, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      case 2: stage<2, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      case 3: stage<3, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      default: stage<5, MAXPTS>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 4: stage<4, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 2: stage<2, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 3: stage<3, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      default: stage<5, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
     }
     Ns *= R;
   }
@@ -164,8 +204,8 @@ __device__ __forceinline__ double teter_k(double x) {
 // Pass 1: xy-plane forward transform.  Work item (pair q, plane z).
 // Columns col0 + 2q and col0 + 2q + 1 (if < col0 + ncols) of block `slot`;
 // ncols < 0 means all J columns of the element (here and below).
-template <int MAXPTS>
-__device__ __forceinline__ void fft_xy_fwd_body(double2* buf, Elem* __restrict__ E,
+template <int MAXPTS, class C>
+__device__ __forceinline__ void fft_xy_fwd_body(C* buf, Elem* __restrict__ E,
                                                 const int* __restrict__ active,
                                                 const int* __restrict__ prefix, int na, int slot,
                                                 int col0, int ncols) {
@@ -181,11 +221,11 @@ __device__ __forceinline__ void fft_xy_fwd_body(double2* buf, Elem* __restrict__
   const double* A = bp(e, slot) + (long long)ca * e.ld + (long long)z * np;
   const double* B = bp(e, slot) + (long long)cb * e.ld + (long long)z * np;
   for (int p = threadIdx.x; p < np; p += FFT_THREADS)
-    buf[p] = make_double2(A[p], hasb ? B[p] : 0.0);
+    buf[p] = cmake<C>(A[p], hasb ? B[p] : 0.0);
   __syncthreads();
-  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], -1.0);
-  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], -1.0);
-  double2* Z = e.zscr + (long long)q * e.ng + (long long)z * np;
+  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), -1.0);
+  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), -1.0);
+  C* Z = zpair<C>(e, q) + (long long)z * np;
   for (int p = threadIdx.x; p < np; p += FFT_THREADS) Z[p] = buf[p];
 }
 
@@ -197,19 +237,33 @@ dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* _
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_fwd32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int slot, int col0, int ncols) {
+  __shared__ float2 buf[FFT_XY_SMALL];
+  fft_xy_fwd_body<FFT_XY_SMALL>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
 dg_fft_xy_fwd_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int slot, int col0, int ncols) {
   __shared__ double2 buf[FFT_MAXPTS];
   fft_xy_fwd_body<FFT_MAXPTS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_fwd32_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                  int na, int slot, int col0, int ncols) {
+  __shared__ float2 buf[FFT_MAXPTS];
+  fft_xy_fwd_body<FFT_MAXPTS>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
 // Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
 // (pair q, row pair m2 in [0, n2/2]).  mode 0: kinetic |G|^2/2.  mode 1:
 // Teter with band kinetic energies tkin[col].  mode 2: identity.
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
-dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-         int na, int col0, int ncols, int mode) {
-  __shared__ double2 buf[FFT_MAXPTS];
+template <class C>
+__device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const int* __restrict__ active,
+                                           const int* __restrict__ prefix, int na, int col0, int ncols,
+                                           int mode) {
   int b = blockIdx.x;
   int ai = find_elem(prefix, na, b);
   const Elem& e = E[active[ai]];
@@ -221,7 +275,7 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
   int nrows = (ra == rb) ? 1 : 2;
   int width = nrows * n1;            // lines per z-slice, contiguous in LDS
   int npts = width * n3;
-  double2* Z = e.zscr + (long long)q * e.ng;
+  C* Z = zpair<C>(e, q);
   // LDS layout: buf[z*width + slot*n1 + x]
   for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
     int z = p / width, r = p - z * width;
@@ -230,7 +284,7 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
     buf[p] = Z[(long long)z * n1 * n2 + row * n1 + x];
   }
   __syncthreads();
-  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], -1.0);
+  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), -1.0);
 
   const double g1 = 2.0 * M_PI / e.L[0], g2 = 2.0 * M_PI / e.L[1], g3 = 2.0 * M_PI / e.L[2];
   if (mode == 0) {
@@ -250,7 +304,7 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
     bool hasb = cb < col0 + nc;
     double Ta = e.tkin[ca], Tb = hasb ? e.tkin[cb] : Ta;
     constexpr int PPT = FFT_MAXPTS / FFT_THREADS;
-    double2 nv[PPT];
+    C nv[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
       int p = threadIdx.x + u * FFT_THREADS;
@@ -269,9 +323,9 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
         // mirror point (-m1, -m2, -m3): the other row slot (or the same)
         int zm = (n3 - z) % n3, xm = (n1 - x) % n1;
         int sm = (nrows == 2) ? 1 - s : 0;
-        double2 zp = buf[p], zmr = buf[zm * width + sm * n1 + xm];
+        C zp = buf[p], zmr = buf[zm * width + sm * n1 + xm];
         double hs = 0.5 * (Ka + Kb), hd = 0.5 * (Ka - Kb);
-        nv[u] = make_double2(hs * zp.x + hd * zmr.x, hs * zp.y - hd * zmr.y);
+        nv[u] = cmake<C>(hs * zp.x + hd * zmr.x, hs * zp.y - hd * zmr.y);
       }
     }
     __syncthreads();
@@ -282,7 +336,7 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
     }
     __syncthreads();
   }
-  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], e.tw[2], 1.0);
+  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), 1.0);
   for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
     int z = p / width, r = p - z * width;
     int s = r / n1, x = r - s * n1;
@@ -291,12 +345,26 @@ dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
   }
 }
 
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+         int na, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_MAXPTS];
+  fft_z_body(buf, E, active, prefix, na, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_z32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+           int na, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_MAXPTS];
+  fft_z_body(buf, E, active, prefix, na, col0, ncols, mode);
+}
+
 // Pass 3: inverse xy transform and epilogue.  Work item (pair q, plane z).
 // mode 0 (operator): out = T x + V x + KB, reading x from block `in_slot`
 //   and the projections beta^T x from e.proj (n_proj x ncols).
 // mode 1 (plain): out = result (preconditioner; out may equal in).
-template <int MAXPTS>
-__device__ __forceinline__ void fft_xy_inv_body(double2* buf, Elem* __restrict__ E,
+template <int MAXPTS, class C>
+__device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
                                                 const int* __restrict__ active,
                                                 const int* __restrict__ prefix, int na, int in_slot,
                                                 int out_slot, int col0, int ncols, int mode) {
@@ -306,11 +374,11 @@ __device__ __forceinline__ void fft_xy_inv_body(double2* buf, Elem* __restrict__
   int w = b - prefix[ai];
   int q = w / e.n3, z = w - q * e.n3;
   int n1 = e.n1, n2 = e.n2, np = n1 * n2;
-  const double2* Z = e.zscr + (long long)q * e.ng + (long long)z * np;
+  const C* Z = zpair<C>(e, q) + (long long)z * np;
   for (int p = threadIdx.x; p < np; p += FFT_THREADS) buf[p] = Z[p];
   __syncthreads();
-  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], e.tw[1], 1.0);
-  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], e.tw[0], 1.0);
+  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), 1.0);
+  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), 1.0);
   const double sc = 1.0 / (double)e.ng;
   const int nc = ncols < 0 ? e.J : ncols;
   int ca = col0 + 2 * q, cb = ca + 1;
@@ -326,7 +394,7 @@ __device__ __forceinline__ void fft_xy_inv_body(double2* buf, Elem* __restrict__
     const double* pa = e.proj + (long long)(ca - col0) * e.n_proj;
     const double* pb = e.proj + (long long)(cb - col0) * e.n_proj;
     for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
-      double2 r = buf[p];
+      const C r = buf[p];
       double v = V[p];
       double ya = sc * r.x + v * IA[p];
       double yb = hasb ? sc * r.y + v * IB[p] : 0.0;
@@ -344,7 +412,7 @@ __device__ __forceinline__ void fft_xy_inv_body(double2* buf, Elem* __restrict__
     }
   } else {
     for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
-      double2 r = buf[p];
+      const C r = buf[p];
       OA[p] = sc * r.x;
       if (hasb) OB[p] = sc * r.y;
     }
@@ -359,9 +427,23 @@ dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* _
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_inv32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_XY_SMALL];
+  fft_xy_inv_body<FFT_XY_SMALL>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
 dg_fft_xy_inv_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_MAXPTS];
+  fft_xy_inv_body<FFT_MAXPTS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+dg_fft_xy_inv32_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                  int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_MAXPTS];
   fft_xy_inv_body<FFT_MAXPTS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 

@@ -1,0 +1,93 @@
+"""Mixed-precision form (FP32 transforms for H W and the preconditioner,
+FP64 elsewhere and in the final check) against the FP64 oracle, through the
+C ABI: eigenvalue error and largest principal angle per element."""
+import numpy as np
+import pytest
+
+import synth
+from oracle.solve import solve_element
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def _solve(els, dev, tol, **kw):
+    import torch
+    from paper_1506_08147_amd import ALB
+    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=tol,
+            elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+            n_alb=[e.n_alb for e in els], **kw)
+    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
+    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
+    out = h.solve(V, ALB.kb_batch([e.kb for e in els], dev), X0)
+    res = [{k: v.cpu().numpy() for k, v in h.split(out, i).items()} for i in range(len(els))]
+    st = out["stats"]
+    h.close()
+    return res, st, out["status"]
+
+
+def test_fp32_transforms_match_oracle(dev):
+    """Operator and preconditioner of a mixed handle (FP32 transforms) vs the
+    FP64 oracle: relative error at FP32 rounding of the kinetic part."""
+    import torch
+    from paper_1506_08147_amd import ALB
+    from oracle import teter
+    from oracle.hamiltonian import Operator
+    el = synth.single_element(seed=9, grid=(24, 20, 18), n_states=6, n_atoms=3)
+    rng = np.random.default_rng(0)
+    X = np.linalg.qr(rng.standard_normal((el.ng, 6)))[0]
+    R = rng.standard_normal((el.ng, 6))
+    Xt = torch.from_numpy(np.ascontiguousarray(X.T)).to(dev)
+    Rt = torch.from_numpy(np.ascontiguousarray(R.T)).to(dev)
+    V = torch.from_numpy(el.V).to(dev)
+    kbt = ALB.kb_batch([el.kb], dev)
+    op = Operator(el.grid, el.box, el.V, el.kb)
+    HXo = op.apply(X)
+    Wo = teter.precondition(R, X, el.grid, el.box)
+    errs = {}
+    for prec in ("fp64", "mixed"):
+        h = ALB([el.grid], [el.box], [6], precision=prec)
+        h.set_potential(V, kbt)
+        HX = h.apply_h(0, Xt).cpu().numpy().T
+        W = h.precondition(0, Rt, Xt).cpu().numpy().T
+        h.close()
+        errs[prec] = (np.abs(HX - HXo).max() / np.abs(HXo).max(), np.abs(W - Wo).max() / np.abs(Wo).max())
+    print("rel err fp64", errs["fp64"], "mixed", errs["mixed"])
+    assert max(errs["fp64"]) < 1e-13
+    assert max(errs["mixed"]) < 2e-6 and min(errs["mixed"]) > 1e-10   # really FP32
+
+
+@pytest.mark.parametrize("seed", [1000, 1001, 1002])
+def test_mixed_solve_vs_fp64_oracle(dev, seed):
+    el = synth.single_element(seed=seed)
+    (r,), (st,), status = _solve([el], dev, 1e-6, precision="mixed")
+    ref = solve_element(el, tol=1e-8)
+    err = np.abs(r["eigvals"] - ref["eigvals"]).max()
+    Xg = r["eigvecs"] * np.sqrt(el.dv)
+    Xo = ref["eigvecs"] * np.sqrt(el.dv)
+    # largest principal angle between the spans of the lowest 27 (a gap of
+    # the 32-state spectrum is required for a well-defined subspace)
+    k = 27
+    s = np.linalg.svd(Xg[:, :k].T @ Xo[:, :k], compute_uv=False)
+    sin_t = float(np.sqrt(max(0.0, 1.0 - s.min() ** 2)))
+    print(f"seed {seed}: iters {st['iters']} max|dlambda| {err:.2e} sin(angle) {sin_t:.2e} "
+          f"res {st['max_res']:.2e}")
+    assert status == 0 and st["converged"] and st["max_res"] <= 1e-6
+    assert err < 1e-6
+    assert sin_t < 1e-4
+
+
+def test_mixed_batch_matches_fp64_batch(dev):
+    els = synth.uneven_batch(4)
+    rf, sf, _ = _solve(els, dev, 1e-6)
+    rm, sm, stm = _solve(els, dev, 1e-6, precision="mixed")
+    print("iters fp64", [s["iters"] for s in sf], "mixed", [s["iters"] for s in sm])
+    assert stm == 0
+    for a, b in zip(rf, rm):
+        assert np.abs(a["eigvals"] - b["eigvals"]).max() < 1e-6
