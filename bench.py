@@ -123,6 +123,62 @@ def warm_mode(args, h, els, desc, V, kbt, out):
     print(json.dumps(line), flush=True)
 
 
+def time_form(args, els, V, kbt, X0, precision, precond, w):
+    """Converged elements/s of one form on the same resident inputs (1 warm-up
+    solve, args.steps timed)."""
+    import numpy as np
+    import torch
+    from paper_1506_08147_amd import ALB
+    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=args.tol,
+            max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+            n_alb=[e.n_alb for e in els], precision=precision, precond=precond, mlp_weights=w)
+    out = h.solve(V, kbt, X0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_conv = 0
+    for s in range(args.steps):
+        out = h.solve(V, kbt, X0)
+        n_conv += sum(1 for st in out["stats"] if st["converged"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = out["stats"]
+    h.close()
+    log(f"form {precision}/{precond}: {n_conv / el:.3f} elements/s")
+    return dict(value=round(n_conv / el, 4), ms_per_step=round(1e3 * el / args.steps, 2),
+                precision=precision, preconditioner=precond,
+                iterations_mean=float(np.mean([s["iters"] for s in st])),
+                converged=f"{sum(1 for s in st if s['converged'])}/{len(st)}",
+                teter_fallback_bands=int(sum(s["n_teter_fallback"] for s in st)))
+
+
+def train_network(dev):
+    """Network of the learned preconditioner: pairs logged by the solver on
+    one-element workloads (seeds 100-115, 24^3, 32 states, residual 1e-8,
+    first 40 iterations), 30 epochs of Adam on the GPU."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1506_08147_amd import ALB, mlp_train
+    t = time.perf_counter()
+    els = [synth.single_element(seed=s) for s in range(100, 116)]
+    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=1e-8,
+            elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+            n_alb=[e.n_alb for e in els])
+    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
+    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
+    P = h.log_pairs(V, ALB.kb_batch([e.kb for e in els], dev), X0, 40)
+    h.close()
+    idx = []
+    for e, nl in enumerate(P["n_logged"]):
+        idx += [e * 40 * 32 + k for k in range(nl * 32)]
+    w = torch.from_numpy(synth.mlp_init(seed=0, last_layer=0.0)).to(dev)
+    hist = mlp_train(P, w, index=np.asarray(idx), epochs=30, batch=256, lr=2e-3, seed=1)
+    el = time.perf_counter() - t
+    log(f"network trained in {el:.1f} s: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    return w, dict(samples=len(idx), epochs=30, loss_first=round(float(hist[0]), 5),
+                   loss_last=round(float(hist[-1]), 5), seconds=round(el, 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +193,13 @@ def main():
                     help="LOBPCG iterations per captured HIP graph launch (0: eager)")
     ap.add_argument("--tune", type=int, default=0, help="1: autotune the Gram split-K at create")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="1: one 1 GiB device copy before the timed region, whose hardware "
+                         "counters calibrate FETCH_SIZE / WRITE_SIZE in profiler runs")
+    ap.add_argument("--forms", type=int, default=1,
+                    help="1: also time the mixed and the mixed + learned-preconditioner forms "
+                         "(network trained first on solver-logged pairs of one-element "
+                         "workloads) and report them under 'forms'")
     ap.add_argument("--warm", type=int, default=0,
                     help="S > 0: warm-start mode instead: after one converged solve, S timed "
                          "SCF-like steps (perturbed V, 3 LOBPCG iterations from the previous "
@@ -165,6 +228,12 @@ def main():
             max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
             n_alb=[e.n_alb for e in els], graph_iters=args.graph, tune=bool(args.tune),
             precision=args.precision)
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     torch.cuda.synchronize()
     for w in range(args.warmup):
         t = time.perf_counter()
@@ -189,7 +258,9 @@ def main():
     ms_step = 1e3 * elapsed / args.steps
 
     # roofline of the dominant kernel class (largest time in the timed region)
-    dom = max((k for k in ks if k not in ("other",)), key=lambda k: ks[k]["ms"])
+    # (the small-dense Rayleigh-Ritz kernels are latency-bound, not roofline
+    # kernels: only classes with algorithmic flops or bytes compete)
+    dom = max((k for k in ks if ks[k]["flops"] > 0 or ks[k]["bytes"] > 0), key=lambda k: ks[k]["ms"])
     d = ks[dom]
     per_launch_ms = d["ms"] / max(d["launches"], 1)
     if d["flops"] > 0:
@@ -207,6 +278,17 @@ def main():
                        tflops=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] else 0,
                        gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else 0)
                for k, v in ks.items() if v["launches"]}
+    h.close()
+    forms = None
+    if args.forms and args.warm == 0:
+        forms = dict(fp64_plain=dict(value=round(n_conv / elapsed, 4), ms_per_step=round(ms_step, 2),
+                                     iterations_mean=float(np.mean(iters))))
+        forms["mixed"] = time_form(args, els, V, kbt, X0, "mixed", "teter", None)
+        w, training = train_network(dev)
+        forms["mixed_learned"] = time_form(args, els, V, kbt, X0, "mixed", "learned", w)
+        forms["mixed_learned"]["training"] = training
+        forms["ratio_mixed_learned_over_fp64"] = round(
+            forms["mixed_learned"]["value"] / forms["fp64_plain"]["value"], 3)
     line = dict(metric=METRIC, value=round(n_conv / elapsed, 4), unit="elements/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
                 higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -217,7 +299,8 @@ def main():
                 roofline=roof, kernels=kernels,
                 iterations=dict(mean=float(np.mean(iters)), min=int(min(iters)), max=int(max(iters))),
                 converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}")
-    h.close()
+    if forms is not None:
+        line["forms"] = forms
     if args.cpu_baseline:
         log("timing the oracle sample on the host")
         line["cpu_baseline"] = cpu_baseline(els[0], stats[0]["iters"], args.cpu_iters)
