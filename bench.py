@@ -26,6 +26,11 @@ sys.path.insert(0, ROOT)
 METRIC = "converged element eigensolves/s at residual 1e-6: plain FP64 vs mixed+learned"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of this
+# command, calibrated on a 1 GiB copy (profiles/slab64_fp64_hbm_traffic.md):
+# (kernel, workload, elements) -> bytes.  Valid for the kernel build that was
+# measured; set to None when the kernel changes.
+MEASURED_TRAFFIC = {("dg_update", "slab_36x36x60_J128", 64): 14.917e9}
 
 
 def log(*a):
@@ -271,6 +276,7 @@ def main():
         ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
+    roof["traffic"] = MEASURED_TRAFFIC.get((dom, desc["workload"], desc.get("elements")))
     roof.update(kernel=dom, launches=d["launches"], avg_launch_ms=round(per_launch_ms, 4),
                 algorithmic_flops_per_launch=d["flops"] / max(d["launches"], 1),
                 algorithmic_bytes_per_launch=d["bytes"] / max(d["launches"], 1))
