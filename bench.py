@@ -304,7 +304,9 @@ def main():
                                               tuned=bool(args.tune)),
                 roofline=roof, kernels=kernels,
                 iterations=dict(mean=float(np.mean(iters)), min=int(min(iters)), max=int(max(iters))),
-                converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}")
+                converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}",
+                rr_reductions=dict(cholesky=int(sum(st["n_rr_cholesky"] for st in stats)),
+                                   series=int(sum(st["n_rr_series"] for st in stats))))
     if forms is not None:
         line["forms"] = forms
     if args.cpu_baseline:

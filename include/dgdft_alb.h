@@ -126,6 +126,9 @@ typedef struct dgdft_alb_stats {
     int32_t n_ql_fail;        /* small eigensolves whose QL iteration hit its cap  */
     int32_t n_teter_fallback; /* bands switched to the Teter factor (learned mode)  */
     int32_t graph_launches;   /* graph launches that advanced this element          */
+    int32_t n_rr_cholesky;    /* Rayleigh-Ritz steps reduced by a Cholesky of S^T S */
+    int32_t n_rr_series;      /* ... by the series for (S^T S)^-1/2 (basis nearly   *
+                               * orthonormal, ||S^T S - I||_F <= 1e-4)              */
 } dgdft_alb_stats;
 
 /* Create a handle for a batch of n_elem extended elements.

@@ -59,7 +59,8 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("max_res", C.c_double),
                 ("n_chol_fallback", C.c_int32), ("n_rr_fallback", C.c_int32),
                 ("n_p_drop", C.c_int32), ("n_ql_fail", C.c_int32),
-                ("n_teter_fallback", C.c_int32), ("graph_launches", C.c_int32)]
+                ("n_teter_fallback", C.c_int32), ("graph_launches", C.c_int32),
+                ("n_rr_cholesky", C.c_int32), ("n_rr_series", C.c_int32)]
 
 
 class Pairs(C.Structure):
@@ -275,7 +276,8 @@ class ALB:
                       n_chol_fallback=s.n_chol_fallback, n_rr_fallback=s.n_rr_fallback,
                       n_p_drop=s.n_p_drop, n_ql_fail=s.n_ql_fail,
                       n_teter_fallback=s.n_teter_fallback,
-                      graph_launches=s.graph_launches) for s in st]
+                      graph_launches=s.graph_launches, n_rr_cholesky=s.n_rr_cholesky,
+                      n_rr_series=s.n_rr_series) for s in st]
         return dict(status=rc, eigvals=vals, eigvecs=vecs, albs=albs, sigma=sig[:snalb],
                     stats=stats)
 

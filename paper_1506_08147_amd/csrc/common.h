@@ -83,7 +83,9 @@ enum Flag {
   FL_RR_PATH,         // Rayleigh-Ritz reduction taken (0 Cholesky, 1 eigenvectors of M, 2 first order)
   FL_LOGK,            // iterations written to the pair log
   FL_STALLK,          // residual histories recorded for the Teter fallback
-  FL_COUNT = 12
+  FL_RR_NCHOL,        // Rayleigh-Ritz steps reduced through a Cholesky factor of M
+  FL_RR_NSERIES,      // Rayleigh-Ritz steps reduced through the series for M^-1/2
+  FL_COUNT = 14
 };
 
 // Virtual slots resolved per element through its buffer parity:

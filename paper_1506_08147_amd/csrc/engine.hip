@@ -428,17 +428,27 @@ struct dgdft_alb {
   void rr_step(const std::vector<int>& act, int single) {
     const int N = 0, Jc = 1;
     rr_one(act, dg_rr_reduce, SMALL_THREADS, single);
-    // path 0: A = L^-1 A L^-T
-    sgemm(act, single, 0, 0, SM_T, 0, SM_A, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
-    sgemm(act, single, 0, 1, SM_U, 0, SM_T, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
+    // path 0: A = L^-1 A L^-T with SM_T = L^-T
+    sgemm(act, single, 1, 0, SM_T, 0, SM_A, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
+    sgemm(act, single, 0, 0, SM_U, 0, SM_T, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
     if (!single) {
       // path 2: A = Hh - sym(E Hh)
       sgemm(act, single, 0, 1, SM_L, 0, SM_H, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 2);
       rr_one(act, dg_rr_form, 256, single);
     }
+    if (!single) {
+      // path 3: E^2, E^3, T = series, A = T Hh T
+      sgemm(act, single, 0, 0, SM_L, 0, SM_L, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
+      sgemm(act, single, 0, 0, SM_L, 0, SM_U, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
+      rr_one(act, dg_rr_series, 256, single);
+      sgemm(act, single, 0, 0, SM_H, 0, SM_T, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
+      sgemm(act, single, 0, 0, SM_T, 0, SM_U, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
+    }
     rr_one(act, dg_rr_eig, SMALL_THREADS, single);
     // path 0: C = L^-T Y
-    sgemm(act, single, 1, 0, SM_T, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, 1.0, 0.0, 0);
+    sgemm(act, single, 0, 0, SM_T, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, 1.0, 0.0, 0);
+    // path 3: C = T Y
+    if (!single) sgemm(act, single, 0, 0, SM_T, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, 1.0, 0.0, 3);
     if (!single) {
       // path 2: C = Y - E Y / 2
       rr_one(act, dg_rr_cinit, 256, single);
@@ -453,7 +463,8 @@ struct dgdft_alb {
     sgemm(act, single, 0, 0, SM_M, 0, SM_Z, 0, SM_U, 0, N, Jc, N, N, N, N, 1.0, 0.0, -1);
     sgemm(act, single, 1, 0, SM_Z, 0, SM_U, 0, SM_A, 0, Jc, Jc, N, N, N, Jc, 1.0, 0.0, -1);
     rr_one(act, dg_rr_dchol, SMALL_THREADS, single);
-    sgemm(act, single, 0, 1, SM_Z, 0, SM_L, 0, SM_C, 1, N, Jc, Jc, N, Jc, N, 1.0, 0.0, -1, 1);
+    // D <- D L^-T with SM_L = L^-T
+    sgemm(act, single, 0, 0, SM_Z, 0, SM_L, 0, SM_C, 1, N, Jc, Jc, N, Jc, N, 1.0, 0.0, -1, 1);
   }
 
   // Pair log: bands [i0, i0 + cnt) of every element in `act`.
@@ -1488,6 +1499,8 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
       stats[e].n_rr_fallback = f[FL_RR_FALLBACK];
       stats[e].n_p_drop = f[FL_P_DROP];
       stats[e].n_ql_fail = f[FL_QL_FAIL];
+      stats[e].n_rr_cholesky = f[FL_RR_NCHOL];
+      stats[e].n_rr_series = f[FL_RR_NSERIES];
       int nf = 0;
       if (!stall.empty())
         for (int j = 0; j < h->eh[e].J; ++j) nf += stall[4 * (h->eh[e].off_j + j) + 3] != 0.0;

@@ -99,11 +99,11 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
   t.sync();
   int ok = chol_lower(t, Ls, n, n, CHOL_TOL);
   if (ok) {
-    double* Li = sm(e, SM_A);
-    tri_inv_lower(t, Ls, n, Li, n, n);
+    double* Lt = sm(e, SM_A);
+    tri_inv_lower_t(t, Ls, n, Lt, n, n);   // Lt = L^-T
     for (int p = t.tid(); p < n * n; p += t.nt()) {
-      int i = p % n, j = p / n;
-      Tm[p] = Li[j + (long long)n * i] / dm[i];
+      int i = p % n;
+      Tm[p] = Lt[p] / dm[i];
     }
     t.sync();
     return;
@@ -143,15 +143,19 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
 // n^2 J and n J^2 run on dg_sgemm over many workgroups.  Reduction paths
 // (fl[FL_RR_PATH]):
 //   2  the blocks of S are orthonormalised as they are built, so M = I + E;
-//      when max|E| <= 1e-8 (and not the step on X alone) the problem is
+//      when ||E||_F <= 1e-8 (and not the step on X alone) the problem is
 //      reduced to first order, T = I - E/2 with T^T M T = I + O(E^2):
 //      A = Hh - sym(E Hh), C = Y - E Y / 2;
+//   3  when 1e-8 < ||E||_F <= 1e-4: T = M^-1/2 by its binomial series to
+//      third order, T = I - E/2 + 3E^2/8 - 5E^3/16 (T^T M T = I + O(E^4),
+//      <= 1e-16), A = T Hh T, C = T Y, all products on dg_sgemm;
 //   0  exact reduction with a Cholesky factor of the scaled M:
-//      A = L^-1 D^-1 Hh D^-1 L^-T, C = D^-1 L^-T Y;
+//      A = L^-1 D^-1 Hh D^-1 L^-T, C = D^-1 L^-T Y (L^-T kept in SM_T);
 //   1  M not numerically SPD: reduction to the eigenvectors of the scaled M
 //      above CHOL_TOL times the largest, finished inside dg_rr_reduce.
 // (Y, theta): lowest J eigenpairs of A from dg_rr_eig.
 constexpr double NEAR_ORTHO = 1e-8;
+constexpr double SERIES_ORTHO = 1e-4;
 
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
@@ -175,22 +179,27 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   sym_from_upper(t, H, n, n);
   sym_from_upper(t, M, n, n);
   if (!single) {
-    double em = 0.0;
+    double ef = 0.0;
     for (int p = t.tid(); p < n * n; p += t.nt()) {
       int i = p % n, j = p / n;
-      em = fmax(em, fabs(M[p] - (i == j ? 1.0 : 0.0)));
+      double v = M[p] - (i == j ? 1.0 : 0.0);
+      ef += v * v;
     }
-    em = t.maxv(em);
-    if (em <= NEAR_ORTHO) {
+    ef = sqrt(t.sum(ef));   // ||E||_F >= ||E||_2
+    if (ef <= SERIES_ORTHO) {
       for (int p = t.tid(); p < n * n; p += t.nt()) {
         int i = p % n, j = p / n;
         Lm[p] = M[p] - (i == j ? 1.0 : 0.0);      // E
       }
-      if (t.tid() == 0) e.fl[FL_RR_PATH] = 2;
+      if (t.tid() == 0) {
+        e.fl[FL_RR_PATH] = ef <= NEAR_ORTHO ? 2 : 3;
+        e.fl[FL_RR_NSERIES] += 1;
+      }
       t.sync();
       return;
     }
   }
+  if (t.tid() == 0 && !single) e.fl[FL_RR_NCHOL] += 1;
   for (int i = t.tid(); i < n; i += t.nt()) {
     double d = sqrt(fmax(M[i + (long long)n * i], 0.0));
     dm[i] = d > 0.0 ? d : 1.0;
@@ -205,7 +214,7 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   int ok = chol_lower(t, Lm, n, n, CHOL_TOL);
   int nk = n;
   if (ok) {
-    tri_inv_lower(t, Lm, n, Tm, n, n);   // Tm = L^-1; products follow on dg_sgemm
+    tri_inv_lower_t(t, Lm, n, Tm, n, n);   // Tm = L^-T; products follow on dg_sgemm
     if (t.tid() == 0) e.fl[FL_RR_PATH] = 0;
     t.sync();
     return;
@@ -282,6 +291,24 @@ dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int sing
   syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, 8192);
 }
 
+// Path 3: T = I - E/2 + 3 E^2/8 - 5 E^3/16 from E (SM_L), E^2 (SM_U) and
+// E^3 (SM_A), into SM_T.
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_series(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  const Elem& e = E[active[blockIdx.x]];
+  if (e.fl[FL_RR_PATH] != 3) return;
+  const int J = e.J;
+  const int n = (single ? 1 : (has_p(e) ? 3 : 2)) * J;
+  const double* Em = sm(e, SM_L);
+  const double* E2 = sm(e, SM_U);
+  const double* E3 = sm(e, SM_A);
+  double* Tm = sm(e, SM_T);
+  for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+    int i = p % n, j = p / n;
+    Tm[p] = (i == j ? 1.0 : 0.0) - 0.5 * Em[p] + 0.375 * E2[p] - 0.3125 * E3[p];
+  }
+}
+
 // Path 2: C = Y (the E Y / 2 correction follows on dg_sgemm).
 extern "C" __global__ void __launch_bounds__(256)
 dg_rr_cinit(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
@@ -321,7 +348,7 @@ dg_rr_post(Elem* __restrict__ E, const int* __restrict__ active, int na, int sin
 }
 
 // Next search direction, after dg_sgemm formed A = D^T M D (J x J) for
-// D = E - C (C^T M E): scaled Cholesky of A; D <- D Dg^-1 with L^-1 kept in
+// D = E - C (C^T M E): scaled Cholesky of A; D <- D Dg^-1 with L^-T kept in
 // SM_L for the final product D L^-T.  If it breaks, P is dropped for one
 // iteration.
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
@@ -356,7 +383,7 @@ dg_rr_dchol(Elem* __restrict__ E, const int* __restrict__ active, int na, int si
     pok = chol_lower(t, A, J, J, CHOL_TOL);
   }
   if (pok) {
-    tri_inv_lower(t, A, J, Lm, J, J);                                     // Lm = L^-1
+    tri_inv_lower_t(t, A, J, Lm, J, J);                                   // Lm = L^-T
     for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] /= dm[p / n];
     if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 1;
   } else {

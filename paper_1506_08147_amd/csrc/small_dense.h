@@ -161,6 +161,28 @@ __host__ __device__ void tri_inv_lower(T& t, const double* L, int ldl, double* X
   t.sync();
 }
 
+// Y = L^-T for lower-triangular L (so column j of L^-1 is row j of Y): the
+// rows of L^-1 are formed in order k = 0..n-1, X[k][j] = (delta_kj -
+// sum_{l<k} L[k][l] X[l][j]) / L[k][k], with thread j owning column j of
+// L^-1 stored as row j of Y.  All threads read the same L[k][l] at the same
+// time and neighbouring threads neighbouring entries of Y.
+template <class T>
+__host__ __device__ void tri_inv_lower_t(T& t, const double* L, int ldl, double* Y, int ldy, int n) {
+  for (int j = t.tid(); j < n; j += t.nt()) {
+    for (int k = 0; k < n; ++k) {
+      double s = (k == j) ? 1.0 : 0.0;
+      if (k >= j) {
+        // from l = 0 (Y[j][l] = 0 for l < j) so that the lanes of a wave
+        // read one L[k][l] together
+        for (int l = 0; l < k; ++l) s -= IDX(L, ldl, k, l) * IDX(Y, ldy, j, l);
+        s /= IDX(L, ldl, k, k);
+      }
+      IDX(Y, ldy, j, k) = s;
+    }
+  }
+  t.sync();
+}
+
 // Householder tridiagonalisation of the full symmetric n x n matrix A.
 // Output: d[0..n), e[0..n-1) (e[k] couples k and k+1), tau[0..n-2); the
 // reflector of step k is v = (A[k+1,k], A[k+2,k], ..., A[n-1,k]) with
