@@ -284,6 +284,22 @@ def main():
                        tflops=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] else 0,
                        gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else 0)
                for k, v in ks.items() if v["launches"]}
+    # element-local DG quantities from the ALBs of the last step
+    nal = [e.n_alb for e in els]
+    Pd = torch.cat([torch.eye(n, dtype=torch.float64).reshape(-1) * 2.0 for n in nal]).to(dev)
+    h.density(out["albs"], Pd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rho = h.density(out["albs"], Pd)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    h.nonlocal_block(out["albs"])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    dgb = dict(density_ms=round(1e3 * (t2 - t1), 3), nonlocal_block_ms=round(1e3 * (t3 - t2), 3),
+               electrons_check=round(float(sum(
+                   e.dv * float(r.sum()) for e, r in zip(els, torch.split(rho, [x["ne"] for x in h.sizes])))
+                   / (2.0 * sum(nal)), 12)))
     h.close()
     forms = None
     if args.forms and args.warm == 0:
@@ -307,6 +323,7 @@ def main():
                 converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}",
                 rr_reductions=dict(cholesky=int(sum(st["n_rr_cholesky"] for st in stats)),
                                    series=int(sum(st["n_rr_series"] for st in stats))))
+    line["dg_blocks"] = dgb
     if forms is not None:
         line["forms"] = forms
     if args.cpu_baseline:

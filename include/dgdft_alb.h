@@ -367,6 +367,28 @@ int32_t dgdft_mlp_grad(const dgdft_pairs* data, const int64_t* index, int64_t n_
 int32_t dgdft_mlp_eval(const double* feat, int64_t n, const float* weights, double* f,
                        void* stream);
 
+/* ---- element-local DG quantities from the ALBs -------------------------
+ * albs: device [sum N_E n_alb], the layout dgdft_alb_solve writes (per
+ * element N_E x n_alb column-major, rows in element-box order x fastest,
+ * dV sum phi^2 = 1). */
+
+/* Electron density on every element box from the diagonal blocks of the
+ * density matrix (Sec. II.A, Eq. newdensity: the ALBs of different elements
+ * do not overlap, so only P_{K;K} enters):
+ *   rho_K(x) = sum_{j,j'} phi_{K,j}(x) P_{K,j;K,j'} phi_{K,j'}(x).
+ * P: device [sum n_alb^2], per element n_alb x n_alb column-major.
+ * rho: device [sum N_E]. */
+int32_t dgdft_alb_density(dgdft_alb* h, const double* albs, const double* P, double* rho,
+                          void* stream);
+
+/* Kleinman-Bylander term of the DG Hamiltonian for one element and itself
+ * (Sec. II.A, Eq. DGHamiltonian, second bracket with K = K'):
+ *   H_K[j][j'] = sum_p gamma_p <phi_{K,j}, b_p> <b_p, phi_{K,j'}>,
+ * inner products = dV sums over the element box on the element's uniform
+ * grid, projectors of the loaded potential.  Coupling to neighbouring
+ * elements is not formed.  out: device [sum n_alb^2], column-major. */
+int32_t dgdft_alb_nonlocal_block(dgdft_alb* h, const double* albs, double* out, void* stream);
+
 /* Message of the last failure on h (NULL: of the last failed create). */
 const char* dgdft_alb_last_error(const dgdft_alb* h);
 

@@ -20,7 +20,10 @@ large scale density functional theory calculations", Sec. II.A):
   orthonormalisation, done as an SVD truncation -- ``alb``;
 * a learned refinement of the Teter preconditioner (not in the paper): the
   network, its training loss and gradient, Adam, the per-shell spectral sums
-  of residual/correction pairs and the Teter fallback -- ``learned``.
+  of residual/correction pairs and the Teter fallback -- ``learned``;
+* element-local DG quantities from the ALBs: the density from diagonal
+  density-matrix blocks (Eq. newdensity) and the Kleinman-Bylander block of
+  Eq. DGHamiltonian -- ``dgblocks``.
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against closed
 forms, textbook special cases, independent libraries or brute force.  The
@@ -29,4 +32,4 @@ the path taken, and what a trained network gains over Teter's factor:
 **parity unpinned** (iteration counts are only compared between runs with
 identical settings).
 """
-from . import hamiltonian, dense, teter, lobpcg, alb, solve, learned  # noqa: F401
+from . import hamiltonian, dense, teter, lobpcg, alb, solve, learned, dgblocks  # noqa: F401

@@ -21,6 +21,7 @@ EXPORTS = (
     "dgdft_alb_kernel_stats", "dgdft_kernel_class_name", "dgdft_small_gemm_batched",
     "dgdft_alb_set_mlp", "dgdft_alb_shells", "dgdft_alb_log_capacity", "dgdft_alb_log_pairs",
     "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
+    "dgdft_alb_density", "dgdft_alb_nonlocal_block",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
@@ -135,6 +136,10 @@ def load_library():
     lib.dgdft_mlp_eval.restype = i32
     lib.dgdft_alb_get_tuning.argtypes = [vp, i32, P(C.c_int32)]
     lib.dgdft_alb_get_tuning.restype = i32
+    lib.dgdft_alb_density.argtypes = [vp, vp, vp, vp, vp]
+    lib.dgdft_alb_density.restype = i32
+    lib.dgdft_alb_nonlocal_block.argtypes = [vp, vp, vp, vp]
+    lib.dgdft_alb_nonlocal_block.restype = i32
     _lib = lib
     return lib
 
@@ -280,6 +285,22 @@ class ALB:
                       n_rr_series=s.n_rr_series) for s in st]
         return dict(status=rc, eigvals=vals, eigvecs=vecs, albs=albs, sigma=sig[:snalb],
                     stats=stats)
+
+    def density(self, albs, P):
+        """rho on every element box (device [sum N_E]) from ALBs and the
+        diagonal density-matrix blocks P (device [sum n_alb^2])."""
+        import torch
+        rho = torch.empty(sum(x["ne"] for x in self.sizes), dtype=torch.float64, device=albs.device)
+        self._check(self.lib.dgdft_alb_density(self.h, _ptr(albs), _ptr(P), _ptr(rho), _stream()))
+        return rho
+
+    def nonlocal_block(self, albs):
+        """KB term of the DG Hamiltonian per element (device [sum n_alb^2])."""
+        import torch
+        out = torch.empty(sum(x["n_alb"] ** 2 for x in self.sizes), dtype=torch.float64,
+                          device=albs.device)
+        self._check(self.lib.dgdft_alb_nonlocal_block(self.h, _ptr(albs), _ptr(out), _stream()))
+        return out
 
     def get_tuning(self, e):
         """Tuned split-K chunk count of element e's Gram products (0: default)."""

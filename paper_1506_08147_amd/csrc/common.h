@@ -66,6 +66,7 @@ struct Elem {
   double* thstar;            // J: converged eigenvalues (pair log)
   long long log_s0, log_r0;  // first sample / row of the element in the pair log
   int gram_split;            // split-K chunks of N_g-long Gram products (0: default rule)
+  long long off_ne, off_nl;  // offsets of the element in batch arrays of N_E and n_alb^2
 };
 
 // Status words written by the device (one group per element).  The host

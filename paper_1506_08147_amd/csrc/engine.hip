@@ -12,6 +12,7 @@
 #include "gemm.hip"
 #include "lobpcg.hip"
 #include "learned.hip"
+#include "dg_blocks.hip"
 
 #include "../../include/dgdft_alb.h"
 
@@ -737,7 +738,7 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
   h->n = n_elem;
   h->eh.assign(n_elem, Elem{});
   // ---- validate shapes, fill host descriptors
-  long long offng = 0, offngj = 0, offj = 0, offalb = 0, offnalb = 0;
+  long long offng = 0, offngj = 0, offj = 0, offalb = 0, offnalb = 0, offne = 0, offnl = 0;
   for (int e = 0; e < n_elem; ++e) {
     Elem& E = h->eh[e];
     E.n1 = grid[3 * e]; E.n2 = grid[3 * e + 1]; E.n3 = grid[3 * e + 2];
@@ -793,8 +794,10 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     double lmax = std::max(E.L[0], std::max(E.L[1], E.L[2]));
     E.tfloor = 0.5 * (2.0 * M_PI / lmax) * (2.0 * M_PI / lmax);
     E.off_ng = offng; E.off_ngj = offngj; E.off_j = offj; E.off_alb = offalb; E.off_nalb = offnalb;
+    E.off_ne = offne; E.off_nl = offnl;
     offng += E.ng; offngj += (long long)E.ng * E.J; offj += E.J;
     offalb += (long long)E.ne * E.nalb; offnalb += E.nalb;
+    offne += E.ne; offnl += (long long)E.nalb * E.nalb;
   }
   h->sumNg = offng; h->sumNgJ = offngj; h->sumJ = offj; h->sumAlb = offalb; h->sumNalb = offnalb;
   try {
@@ -2097,6 +2100,57 @@ int32_t dgdft_mlp_eval(const double* feat, int64_t n, const float* weights, doub
     return DGDFT_OK;
   } catch (HipFail& f2) {
     g_create_error = f2.what;
+    return DGDFT_EHIP;
+  }
+}
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------------------------
+// Element-local DG quantities from the ALBs.
+
+extern "C" {
+
+int32_t dgdft_alb_density(dgdft_alb* h, const double* albs, const double* P, double* rho, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!albs || !P || !rho) { h->err = "density: NULL pointer"; return DGDFT_EINVAL; }
+  bind_stream(h, stream);
+  try {
+    h->ring_reset();
+    std::vector<int> all = all_elems(h->n);
+    auto Pf = h->make_prefix(all, [&](int e) { return cdiv(h->eh[e].ne, 256); });
+    hipLaunchKernelGGL(dg_density, dim3(Pf.total), dim3(256), 0, h->stream, h->ed, Pf.active, Pf.prefix,
+                       Pf.na, albs, P, rho);
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(h->stream));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_alb_nonlocal_block(dgdft_alb* h, const double* albs, double* out, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!albs || !out) { h->err = "nonlocal_block: NULL pointer"; return DGDFT_EINVAL; }
+  if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
+  bind_stream(h, stream);
+  try {
+    h->ring_reset();
+    std::vector<int> all = all_elems(h->n);
+    auto P1 = h->make_prefix(all, [&](int e) { return h->eh[e].J; });
+    hipLaunchKernelGGL(dg_scatter_box, dim3(P1.total), dim3(256), 0, h->stream, h->ed, P1.active,
+                       P1.prefix, P1.na, albs, (int)S_W);
+    HCHECK(hipGetLastError());
+    h->launch_kbproj(all, S_W, 0, -1, 0);
+    auto P2 = h->make_prefix(all, [](int) { return 1; });
+    hipLaunchKernelGGL(dg_nl_block, dim3(P2.na), dim3(256), 0, h->stream, h->ed, P2.active, P2.na, out);
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(h->stream));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
     return DGDFT_EHIP;
   }
 }
