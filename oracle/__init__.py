@@ -22,8 +22,10 @@ large scale density functional theory calculations", Sec. II.A):
   network, its training loss and gradient, Adam, the per-shell spectral sums
   of residual/correction pairs and the Teter fallback -- ``learned``;
 * element-local DG quantities from the ALBs: the density from diagonal
-  density-matrix blocks (Eq. newdensity) and the Kleinman-Bylander block of
-  Eq. DGHamiltonian -- ``dgblocks``.
+  density-matrix blocks (Eq. newdensity), the Kleinman-Bylander block of
+  Eq. DGHamiltonian and its volume terms (kinetic and V_eff) by Gauss-Lobatto
+  quadrature with differentiation matrices (Sec. III, construction of the DG
+  Hamiltonian) -- ``dgblocks``.
 
 Pins: every function is checked in ``tests/test_oracle_*.py`` against closed
 forms, textbook special cases, independent libraries or brute force.  The
