@@ -296,10 +296,30 @@ def main():
     h.nonlocal_block(out["albs"])
     torch.cuda.synchronize()
     t3 = time.perf_counter()
+    # volume terms of the diagonal DG block on the LGL grid (twice the uniform
+    # points per axis): once untimed, once timed, once with per-launch events
+    h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    vol = h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    h.profile(True)
+    h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
+    bg = h.kernel_stats()["dg_bgemm"]
+    h.profile(False)
+    bg_tf = bg["flops"] / (bg["ms"] * 1e-3) / 1e12 if bg["ms"] else 0.0
+    sym = max(float((v.reshape(n, n) - v.reshape(n, n).T).abs().max())
+              for v, n in zip(torch.split(vol, [n * n for n in nal]), nal))
     dgb = dict(density_ms=round(1e3 * (t2 - t1), 3), nonlocal_block_ms=round(1e3 * (t3 - t2), 3),
                electrons_check=round(float(sum(
                    e.dv * float(r.sum()) for e, r in zip(els, torch.split(rho, [x["ne"] for x in h.sizes])))
-                   / (2.0 * sum(nal)), 12)))
+                   / (2.0 * sum(nal)), 12)),
+               volume_ms=round(1e3 * (t5 - t4), 3),
+               volume_bgemm=dict(launches=bg["launches"], ms=round(bg["ms"], 3),
+                                 gflop=round(bg["flops"] / 1e9, 2), tflops=round(bg_tf, 2),
+                                 frac_fp64_peak=round(bg_tf / PEAK_FP64_TFLOPS, 4)),
+               volume_asymmetry=sym)
     h.close()
     forms = None
     if args.forms and args.warm == 0:

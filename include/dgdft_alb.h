@@ -229,7 +229,9 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m,
  * polls.  Algorithmic work per launch: Gram products count 2 K m n flops
  * (K m (m+1) for the symmetric, upper-triangle products) and 8 K (m + n)
  * bytes; update products 2 K kA n flops and 8 K (kA + n) bytes (+8 K n when
- * accumulating); FFT passes count the HBM bytes of their input and output. */
+ * accumulating); FFT passes count the HBM bytes of their input and output;
+ * the strided-batched products of dgdft_alb_dg_volume count 2 M N K per
+ * problem and the bytes of their operands (a shared operand once) and result. */
 #define DGDFT_K_GRAM         0
 #define DGDFT_K_GRAM_REDUCE  1
 #define DGDFT_K_UPDATE       2
@@ -242,7 +244,8 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m,
 #define DGDFT_K_CHOLQR       9
 #define DGDFT_K_OTHER       10
 #define DGDFT_K_SGEMM       11
-#define DGDFT_KCLASS_COUNT  12
+#define DGDFT_K_BGEMM       12
+#define DGDFT_KCLASS_COUNT  13
 
 /* Enable (1) or disable (0) timing and reset the counters. */
 int32_t dgdft_alb_profile(dgdft_alb* h, int32_t enable);
@@ -388,6 +391,27 @@ int32_t dgdft_alb_density(dgdft_alb* h, const double* albs, const double* P, dou
  * grid, projectors of the loaded potential.  Coupling to neighbouring
  * elements is not formed.  out: device [sum n_alb^2], column-major. */
 int32_t dgdft_alb_nonlocal_block(dgdft_alb* h, const double* albs, double* out, void* stream);
+
+/* Volume terms of the diagonal DG block of every element (Sec. II.A,
+ * Eq. DGHamiltonian, first bracket; Sec. III, construction of the DG
+ * Hamiltonian):
+ *   A_K[j][j'] = 1/2 <grad phi_{K,j}, grad phi_{K,j'}>_E + <phi_{K,j}, V phi_{K,j'}>_E
+ * as Gauss quadratures on the element's Legendre-Gauss-Lobatto grid with
+ * lgl_ratio * (hi_d - lo_d) points along axis d (the paper uses twice the
+ * uniform grid, lgl_ratio = 2) and gradients by LGL differentiation matrices.
+ * E_K along axis d is [lo_d h_d, hi_d h_d], grid point i at i h_d.  The ALBs
+ * are sampled on the LGL grid as phi = psi T: psi, the eigenvectors of the
+ * extended element, evaluated by trigonometric interpolation on its periodic
+ * box (an even-n Nyquist mode as a cosine), and T = dV psi_E^T phi sigma^-2
+ * the map from the restricted eigenvectors to the ALBs (zero column where
+ * sigma = 0).  V: the potential loaded last, interpolated likewise.
+ * eigvecs, albs, sigma: device, as dgdft_alb_solve writes them (eigvecs per
+ * element N_g x J column-major with dV sum psi^2 = 1).  out: device
+ * [sum n_alb^2], per element n_alb x n_alb column-major.  lgl_ratio in 1..8
+ * with at most 1024 points per axis, else DGDFT_EINVAL.  The library holds a
+ * workspace for the largest element between calls (released by destroy). */
+int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* albs,
+                            const double* sigma, int32_t lgl_ratio, double* out, void* stream);
 
 /* Message of the last failure on h (NULL: of the last failed create). */
 const char* dgdft_alb_last_error(const dgdft_alb* h);

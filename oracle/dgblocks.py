@@ -52,7 +52,8 @@ def nonlocal_block(albs, kb, grid, lo, hi, dv):
 #   polynomials of the periodic box, so they are evaluated at the LGL points
 #   by Fourier interpolation (the even-n Nyquist mode as a cosine) and the
 #   ALBs follow as phi = psi_E T with the same T that maps the restricted
-#   eigenvectors to the ALBs on the uniform grid: T = dV psi_E^T phi sigma^-2.
+#   eigenvectors to the ALBs on the uniform grid: T = dV psi_E^T phi sigma^-2
+#   (a zero column where sigma = 0).
 # * V_eff at the LGL points: Fourier interpolation of V on Q_K.
 # * E_K along axis d is [lo_d h_d, hi_d h_d] with grid point i at i h_d.
 # ---------------------------------------------------------------------------
@@ -127,7 +128,9 @@ def volume_block(psi, albs, sigma, V, grid, box, lo, hi, ratio=2):
     V: Ng -> n_alb x n_alb volume terms of the diagonal DG block."""
     dv = float(np.prod(box)) / float(np.prod(grid))
     rows = box_rows(grid, lo, hi)
-    T = dv * (psi[rows].T @ albs) / sigma[None, :] ** 2     # psi_E T = albs
+    inv = np.zeros_like(sigma)                # a zero singular value gives a zero column
+    inv[sigma > 0] = 1.0 / sigma[sigma > 0] ** 2
+    T = dv * (psi[rows].T @ albs) * inv[None, :]            # psi_E T = albs
     ax = lgl_grid(grid, box, lo, hi, ratio)
     pts = [a[0] for a in ax]
     Phi = np.einsum("zyxj,jk->zyxk", fourier_eval(psi, grid, box, pts), T)

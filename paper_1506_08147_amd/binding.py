@@ -21,12 +21,12 @@ EXPORTS = (
     "dgdft_alb_kernel_stats", "dgdft_kernel_class_name", "dgdft_small_gemm_batched",
     "dgdft_alb_set_mlp", "dgdft_alb_shells", "dgdft_alb_log_capacity", "dgdft_alb_log_pairs",
     "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
-    "dgdft_alb_density", "dgdft_alb_nonlocal_block",
+    "dgdft_alb_density", "dgdft_alb_nonlocal_block", "dgdft_alb_dg_volume",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
 KCLASS = ("dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
-          "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm")
+          "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm", "dg_bgemm")
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM",
           -4: "EHIP", -5: "EBREAKDOWN"}
@@ -140,6 +140,8 @@ def load_library():
     lib.dgdft_alb_density.restype = i32
     lib.dgdft_alb_nonlocal_block.argtypes = [vp, vp, vp, vp]
     lib.dgdft_alb_nonlocal_block.restype = i32
+    lib.dgdft_alb_dg_volume.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+    lib.dgdft_alb_dg_volume.restype = i32
     _lib = lib
     return lib
 
@@ -300,6 +302,16 @@ class ALB:
         out = torch.empty(sum(x["n_alb"] ** 2 for x in self.sizes), dtype=torch.float64,
                           device=albs.device)
         self._check(self.lib.dgdft_alb_nonlocal_block(self.h, _ptr(albs), _ptr(out), _stream()))
+        return out
+
+    def dg_volume(self, eigvecs, albs, sigma, lgl_ratio=2):
+        """Volume terms (kinetic + V) of the diagonal DG block per element on
+        its LGL grid (device [sum n_alb^2]); inputs as solve() returns them."""
+        import torch
+        out = torch.empty(sum(x["n_alb"] ** 2 for x in self.sizes), dtype=torch.float64,
+                          device=albs.device)
+        self._check(self.lib.dgdft_alb_dg_volume(self.h, _ptr(eigvecs), _ptr(albs), _ptr(sigma),
+                                                 int(lgl_ratio), _ptr(out), _stream()))
         return out
 
     def get_tuning(self, e):

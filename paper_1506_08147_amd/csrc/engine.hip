@@ -105,6 +105,9 @@ struct dgdft_alb {
   hipGraphExec_t g_exec[NGROUP] = {};
   std::vector<int> g_key[NGROUP];
   int* d_active_all = nullptr;
+  // workspace of dgdft_alb_dg_volume, grown on demand
+  double* vol_ws = nullptr;
+  size_t vol_cap = 0;
   // host readback (pinned)
   double* h_resid = nullptr;
   int* h_fl = nullptr;
@@ -415,6 +418,37 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
   }
 
+  // Strided-batched product (dg_bgemm) with split-K over at most BG_KSPLIT
+  // chunks when the output tiles alone cannot fill the chip; `part` holds
+  // BG_KSPLIT * batch * M * N doubles.
+  static constexpr int BG_KSPLIT = 128;
+  void bgemm(BgArgs a, double* part) {
+    if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
+    const long long tiles = (long long)cdiv(a.M, 64) * cdiv(a.N, 64) * a.batch;
+    a.ksplit = 1;
+    a.kchunk = a.K > 0 ? a.K : 16;
+    if (part && tiles < 512 && a.K > 256) {
+      int want = (int)std::min<long long>(BG_KSPLIT, cdiv(1024, (int)tiles));
+      want = std::min(want, cdiv(a.K, 64));
+      if (want > 1) {
+        a.kchunk = cdiv(cdiv(a.K, want), 16) * 16;
+        a.ksplit = cdiv(a.K, a.kchunk);
+      }
+    }
+    a.part = part;
+    double fl = 2.0 * a.M * a.N * (double)std::max(a.K, 0) * a.batch;
+    double by = 8.0 * ((double)a.M * a.K * (a.sa ? a.batch : 1) + (double)a.K * a.N * (a.sb ? a.batch : 1) +
+                       (double)a.M * a.N * a.batch * (a.beta != 0.0 ? 2 : 1));
+    pbeg(DGDFT_K_BGEMM, fl, by);
+    hipLaunchKernelGGL(dg_bgemm, dim3((unsigned)(tiles * a.ksplit)), dim3(256), 0, stream, a);
+    if (a.ksplit > 1) {
+      long long n = (long long)a.M * a.N * a.batch;
+      hipLaunchKernelGGL(dg_bgemm_reduce, dim3((unsigned)cdiv((int)n, 256)), dim3(256), 0, stream, a);
+    }
+    pend();
+    HCHECK(hipGetLastError());
+  }
+
   void rr_one(const std::vector<int>& act, void (*k)(Elem*, const int*, int, int), int threads,
               int single) {
     auto P = make_prefix(act, [&](int) { return 1; });
@@ -608,6 +642,7 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   (void)hipFree(h->proj_arena);
   (void)hipFree(h->d_flag);
   (void)hipFree(h->lrn_arena);
+  (void)hipFree(h->vol_ws);
   (void)hipFree(h->ring_d);
   (void)hipHostFree(h->ring_h);
   (void)hipHostFree(h->h_resid);
@@ -1632,7 +1667,7 @@ int32_t dgdft_alb_kernel_stats(const dgdft_alb* h, int32_t kclass, int64_t* laun
 const char* dgdft_kernel_class_name(int32_t kclass) {
   static const char* names[DGDFT_KCLASS_COUNT] = {
       "dg_gram", "dg_gram_reduce", "dg_update", "dg_fft_xy_fwd", "dg_fft_z", "dg_fft_xy_inv",
-      "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm"};
+      "dg_kb_project", "dg_resid", "dg_rr_*", "dg_cholqr", "other", "dg_sgemm", "dg_bgemm"};
   return (kclass >= 0 && kclass < DGDFT_KCLASS_COUNT) ? names[kclass] : "";
 }
 
@@ -2124,6 +2159,139 @@ int32_t dgdft_alb_density(dgdft_alb* h, const double* albs, const double* P, dou
                        Pf.na, albs, P, rho);
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(h->stream));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* albs,
+                            const double* sigma, int32_t lgl_ratio, double* out, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!eigvecs || !albs || !sigma || !out) { h->err = "dg_volume: NULL pointer"; return DGDFT_EINVAL; }
+  if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
+  if (lgl_ratio < 1 || lgl_ratio > 8) { h->err = "dg_volume: lgl_ratio outside 1..8"; return DGDFT_EINVAL; }
+  auto al = [](size_t n) { return (n + 31) / 32 * 32; };
+  // workspace (doubles) for the largest element
+  size_t need = 0;
+  for (int e = 0; e < h->n; ++e) {
+    const Elem& E = h->eh[e];
+    size_t m[3], n[3] = {(size_t)E.n1, (size_t)E.n2, (size_t)E.n3}, J = E.J, na = E.nalb;
+    for (int d = 0; d < 3; ++d) {
+      m[d] = (size_t)lgl_ratio * (E.hi[d] - E.lo[d]);
+      if (m[d] < 2 || m[d] > (size_t)LGL_MAX) {
+        h->err = "dg_volume: LGL points per axis outside 2..1024";
+        return DGDFT_EINVAL;
+      }
+    }
+    size_t ME = m[0] * m[1] * m[2];
+    size_t bufA = std::max({(size_t)E.ne * J, m[0] * n[1] * n[2] * J, ME * J});
+    size_t bufB = std::max(m[0] * m[1] * n[2] * J, ME * na);
+    size_t tab = 0;
+    for (int d = 0; d < 3; ++d) tab += al(m[d]) + al(m[d] * m[d]) + al(m[d] * n[d]);
+    size_t tot = al(bufA) + al(bufB) + al(m[0] * n[1] * n[2]) + al(m[0] * m[1] * n[2]) + 3 * al(ME) +
+                 tab + al(J * na) + al((size_t)dgdft_alb::BG_KSPLIT * J * na);
+    need = std::max(need, tot);
+  }
+  bind_stream(h, stream);
+  try {
+    h->ring_reset();
+    if (need > h->vol_cap) {
+      HCHECK(hipStreamSynchronize(h->stream));
+      (void)hipFree(h->vol_ws);
+      h->vol_ws = nullptr;
+      h->vol_cap = 0;
+      if (hipMalloc(&h->vol_ws, need * sizeof(double)) != hipSuccess) {
+        h->vol_ws = nullptr;
+        h->err = "dg_volume: out of device memory";
+        return DGDFT_ENOMEM;
+      }
+      h->vol_cap = need;
+    }
+    for (int e = 0; e < h->n; ++e) {
+      const Elem& E = h->eh[e];
+      const int J = E.J, na = E.nalb, n1 = E.n1, n2 = E.n2, n3 = E.n3;
+      int m[3];
+      for (int d = 0; d < 3; ++d) m[d] = lgl_ratio * (E.hi[d] - E.lo[d]);
+      const int m1 = m[0], m2 = m[1], m3 = m[2], ME = m1 * m2 * m3;
+      const int nn[3] = {n1, n2, n3};
+      double* p = h->vol_ws;
+      auto take = [&](size_t n) { double* q = p; p += al(n); return q; };
+      double* bufA = take(std::max({(size_t)E.ne * J, (size_t)m1 * n2 * n3 * J, (size_t)ME * J}));
+      double* bufB = take(std::max((size_t)m1 * m2 * n3 * J, (size_t)ME * na));
+      double* vX = take((size_t)m1 * n2 * n3);
+      double* vY = take((size_t)m1 * m2 * n3);
+      double* vL = take(ME);
+      double* wq = take(ME);
+      double* vw = take(ME);
+      LglTab t{};
+      for (int d = 0; d < 3; ++d) {
+        t.m[d] = m[d];
+        t.w[d] = take(m[d]);
+        t.D[d] = take((size_t)m[d] * m[d]);
+        t.I[d] = take((size_t)m[d] * nn[d]);
+      }
+      double* Tu = take((size_t)J * na);
+      double* part = take((size_t)dgdft_alb::BG_KSPLIT * J * na);
+      const size_t part_cap = (size_t)dgdft_alb::BG_KSPLIT * J * na;
+      auto gemm = [&](int ta, int tb, int M, int N, int K, const double* A, int lda, long long sa,
+                      const double* B, int ldb, long long sb, double* Cm, int ldc, long long sc,
+                      int batch, double alpha, double beta, const double* ks, const double* cs,
+                      int cs_pow) {
+        BgArgs a{};
+        a.A = A; a.B = B; a.C = Cm; a.ks = ks; a.cs = cs; a.cs_pow = cs_pow;
+        a.sa = sa; a.sb = sb; a.sc = sc;
+        a.M = M; a.N = N; a.K = K; a.lda = lda; a.ldb = ldb; a.ldc = ldc; a.batch = batch;
+        a.ta = ta; a.tb = tb; a.alpha = alpha; a.beta = beta;
+        bool fits = (size_t)dgdft_alb::BG_KSPLIT * M * N * batch <= part_cap;
+        h->bgemm(a, fits ? part : nullptr);
+      };
+      const double* psi = eigvecs + E.off_ngj;
+      const double* phi = albs + E.off_alb;
+      double* oe = out + E.off_nl;
+      hipLaunchKernelGGL(dg_lgl_tables, dim3(3), dim3(256), 0, h->stream, (const Elem*)h->ed, e, t);
+      HCHECK(hipGetLastError());
+      // T = dV psi_E^T phi sigma^-2  (J x n_alb)
+      hipLaunchKernelGGL(dg_box_cols, dim3(cdiv(E.ne, 256), J), dim3(256), 0, h->stream,
+                         (const Elem*)h->ed, e, psi, bufA);
+      HCHECK(hipGetLastError());
+      gemm(1, 0, J, na, E.ne, bufA, E.ne, 0, phi, E.ne, 0, Tu, J, 0, 1, E.dv, 0.0, nullptr,
+           sigma + E.off_nalb, -2);
+      // psi at the LGL points, one axis at a time: x (m1 x n2 n3 J), y, z
+      gemm(0, 0, m1, n2 * n3 * J, n1, t.I[0], m1, 0, psi, n1, 0, bufA, m1, 0, 1, 1.0, 0.0,
+           nullptr, nullptr, 0);
+      gemm(0, 1, m1, m2, n2, bufA, m1, (long long)m1 * n2, t.I[1], m2, 0, bufB, m1,
+           (long long)m1 * m2, n3 * J, 1.0, 0.0, nullptr, nullptr, 0);
+      gemm(0, 1, m1 * m2, m3, n3, bufB, m1 * m2, (long long)m1 * m2 * n3, t.I[2], m3, 0, bufA,
+           m1 * m2, ME, J, 1.0, 0.0, nullptr, nullptr, 0);
+      // Phi = Psi_LGL T  (ME x n_alb) into bufB
+      gemm(0, 0, ME, na, J, bufA, ME, 0, Tu, J, 0, bufB, ME, 0, 1, 1.0, 0.0, nullptr, nullptr, 0);
+      // V at the LGL points
+      gemm(0, 0, m1, n2 * n3, n1, t.I[0], m1, 0, E.V, n1, 0, vX, m1, 0, 1, 1.0, 0.0, nullptr,
+           nullptr, 0);
+      gemm(0, 1, m1, m2, n2, vX, m1, (long long)m1 * n2, t.I[1], m2, 0, vY, m1, (long long)m1 * m2,
+           n3, 1.0, 0.0, nullptr, nullptr, 0);
+      gemm(0, 1, m1 * m2, m3, n3, vY, m1 * m2, 0, t.I[2], m3, 0, vL, m1 * m2, 0, 1, 1.0, 0.0,
+           nullptr, nullptr, 0);
+      hipLaunchKernelGGL(dg_lgl_weights, dim3(cdiv(ME, 256)), dim3(256), 0, h->stream, t,
+                         (const double*)vL, wq, vw);
+      HCHECK(hipGetLastError());
+      // <phi, V phi> = Phi^T diag(w V) Phi
+      gemm(1, 0, na, na, ME, bufB, ME, 0, bufB, ME, 0, oe, na, 0, 1, 1.0, 0.0, vw, nullptr, 0);
+      // 1/2 <d phi, d phi> per axis, the derivative into bufA
+      gemm(0, 0, m1, m2 * m3 * na, m1, t.D[0], m1, 0, bufB, m1, 0, bufA, m1, 0, 1, 1.0, 0.0,
+           nullptr, nullptr, 0);
+      gemm(1, 0, na, na, ME, bufA, ME, 0, bufA, ME, 0, oe, na, 0, 1, 0.5, 1.0, wq, nullptr, 0);
+      gemm(0, 1, m1, m2, m2, bufB, m1, (long long)m1 * m2, t.D[1], m2, 0, bufA, m1,
+           (long long)m1 * m2, m3 * na, 1.0, 0.0, nullptr, nullptr, 0);
+      gemm(1, 0, na, na, ME, bufA, ME, 0, bufA, ME, 0, oe, na, 0, 1, 0.5, 1.0, wq, nullptr, 0);
+      gemm(0, 1, m1 * m2, m3, m3, bufB, m1 * m2, ME, t.D[2], m3, 0, bufA, m1 * m2, ME, na, 1.0,
+           0.0, nullptr, nullptr, 0);
+      gemm(1, 0, na, na, ME, bufA, ME, 0, bufA, ME, 0, oe, na, 0, 1, 0.5, 1.0, wq, nullptr, 0);
+    }
+    HCHECK(hipStreamSynchronize(h->stream));
+    if (h->prof) h->flush_prof();
     return DGDFT_OK;
   } catch (HipFail& f) {
     h->err = f.what;

@@ -421,4 +421,125 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
       }
 }
 
+// General strided-batched product for the element-local DG blocks:
+//   C_b = alpha * op(A_b) diag(ks) op(B_b) diag(s) + beta C_b
+// for b < batch, with A_b = A + b*sa (likewise B, C; stride 0 shares an
+// operand), column-major, op = transpose when ta/tb = 1.  ks (nullable)
+// weights the inner index (a diagonal quadrature weight between the two
+// factors); s_j = cs[j] (cs_pow 1) or 1/cs[j]^2 (cs_pow -2, zero where
+// cs[j] == 0), or 1 when cs is null.  With ksplit > 1 each
+// workgroup reduces one kchunk of the inner index into `part` and
+// dg_bgemm_reduce sums the chunks in a fixed order.
+struct BgArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  const double* ks;
+  const double* cs;
+  double* part;                  // ksplit * batch * M * N partial products
+  long long sa, sb, sc;
+  int M, N, K, lda, ldb, ldc, batch, ta, tb, ksplit, kchunk, cs_pow;
+  double alpha, beta;
+};
+
+__device__ __forceinline__ double bg_colscale(const BgArgs& a, int j) {
+  if (!a.cs) return 1.0;
+  double c = a.cs[j];
+  if (a.cs_pow == 1) return c;
+  return c != 0.0 ? 1.0 / (c * c) : 0.0;
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+dg_bgemm(BgArgs a) {
+  __shared__ double As[16 * 65];
+  __shared__ double Bs[16 * 65];
+  const int ntm = cdiv(a.M, 64), ntn = cdiv(a.N, 64);
+  const long long blk = blockIdx.x;
+  const int t = (int)(blk % (ntm * ntn));
+  const long long rest = blk / (ntm * ntn);
+  const int bi = (int)(rest % a.batch), kc = (int)(rest / a.batch);
+  const int i0 = (t % ntm) * 64, j0 = (t / ntm) * 64;
+  const double* A = a.A + a.sa * bi;
+  const double* B = a.B + a.sb * bi;
+  const int kbeg = kc * a.kchunk, kend = min(a.K, kbeg + a.kchunk);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = wv & 1, wj = wv >> 1;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int el = tid + 256 * q;          // 0..1023 over a 64 x 16 tile
+      int f = el & 63, s16 = el >> 6;
+      int g = el & 15, s64 = el >> 4;
+      int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
+      double av = 0.0;
+      if (i0 + ii < a.M && k0 + kk < kend) {
+        av = a.ta ? A[(k0 + kk) + (long long)a.lda * (i0 + ii)] : A[(i0 + ii) + (long long)a.lda * (k0 + kk)];
+        if (a.ks) av *= a.ks[k0 + kk];
+      }
+      As[kk * 65 + ii] = av;
+      int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
+      double bv = 0.0;
+      if (j0 + jj < a.N && k0 + kb < kend)
+        bv = a.tb ? B[(j0 + jj) + (long long)a.ldb * (k0 + kb)] : B[(k0 + kb) + (long long)a.ldb * (j0 + jj)];
+      Bs[kb * 65 + jj] = bv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      int kk = ks * 4 + (lane >> 4);
+      double a0 = As[kk * 65 + wi * 32 + (lane & 15)];
+      double a1 = As[kk * 65 + wi * 32 + 16 + (lane & 15)];
+      double b0 = Bs[kk * 65 + wj * 32 + (lane & 15)];
+      double b1 = Bs[kk * 65 + wj * 32 + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* C = a.C + a.sc * bi;
+  double* P = a.part + ((long long)kc * a.batch + bi) * a.M * a.N;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = i0 + wi * 32 + x * 16 + 4 * r + (lane >> 4);
+        int j = j0 + wj * 32 + y * 16 + (lane & 15);
+        if (i < a.M && j < a.N) {
+          if (a.ksplit > 1) {
+            P[i + (long long)a.M * j] = acc[x][y][r];
+          } else {
+            double* c = C + i + (long long)a.ldc * j;
+            double v = a.alpha * bg_colscale(a, j) * acc[x][y][r];
+            *c = a.beta != 0.0 ? v + a.beta * *c : v;
+          }
+        }
+      }
+}
+
+// C_b = alpha * cs-scaled sum over chunks of the partials + beta C_b; one
+// thread per output entry.
+extern "C" __global__ void __launch_bounds__(256)
+dg_bgemm_reduce(BgArgs a) {
+  const long long mn = (long long)a.M * a.N;
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (p >= mn * a.batch) return;
+  const int bi = (int)(p / mn);
+  const long long ij = p - (long long)bi * mn;
+  const int i = (int)(ij % a.M), j = (int)(ij / a.M);
+  double s = 0.0;
+  for (int kc = 0; kc < a.ksplit; ++kc) s += a.part[((long long)kc * a.batch + bi) * mn + ij];
+  double* c = a.C + a.sc * bi + i + (long long)a.ldc * j;
+  double v = a.alpha * bg_colscale(a, j) * s;
+  *c = a.beta != 0.0 ? v + a.beta * *c : v;
+}
+
 }  // namespace dg

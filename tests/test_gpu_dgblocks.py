@@ -1,38 +1,67 @@
 """Element-local DG quantities on the GPU against the oracle (through the C
-ABI): density from diagonal density-matrix blocks and the nonlocal block."""
+ABI): density from diagonal density-matrix blocks, the nonlocal block and the
+volume terms of the diagonal block on the LGL grid.
+
+Inputs of both sides come from the oracle (its LOBPCG solve and restriction)
+or from the seeded generators, never from the GPU path."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import dgblocks
+from oracle.alb import restrict_svd
+from oracle.solve import solve_element
 
 pytestmark = pytest.mark.gpu
 
+# volume terms: FP64 on both sides, different algorithms for every factor
+# (Dirichlet-kernel sums vs FFT coefficients, Newton vs Golub-Welsch nodes,
+# closed-form vs barycentric differentiation); rounding of O(10^2) terms per
+# entry of each factor
+VOL_RTOL = 1e-10
 
-def test_density_and_nonlocal_block_match_oracle():
+
+def _handle(els, dev):
     import torch
     from paper_1506_08147_amd import ALB
-    dev = torch.device("cuda:0")
-    els = [synth.single_element(seed=s, grid=g, n_states=J, n_atoms=4)
-           for s, g, J in [(31, (16, 16, 16), 10), (32, (18, 16, 20), 12)]]
     h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=1e-8,
             elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
             n_alb=[e.n_alb for e in els])
     V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
-    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
-    out = h.solve(V, ALB.kb_batch([e.kb for e in els], dev), X0)
-    assert out["status"] == 0
+    h.set_potential(V, ALB.kb_batch([e.kb for e in els], dev))
+    return h
+
+
+def _cat(mats, dev):
+    import torch
+    return torch.cat([torch.from_numpy(np.asfortranarray(M).ravel(order="F")) for M in mats]).to(dev)
+
+
+@pytest.fixture(scope="module")
+def small():
+    els = [synth.single_element(seed=s, grid=g, n_states=J, n_atoms=4)
+           for s, g, J in [(31, (16, 16, 16), 10), (32, (18, 16, 20), 12)]]
+    refs = [solve_element(e, tol=1e-8) for e in els]
+    assert all(r["converged"] for r in refs)
+    return els, refs
+
+
+def test_density_and_nonlocal_block_match_oracle(small):
+    import torch
+    els, refs = small
+    dev = torch.device("cuda:0")
+    h = _handle(els, dev)
+    albs = _cat([r["albs"] for r in refs], dev)
     rng = np.random.default_rng(0)
     Ps = []
     for e in els:
         A = rng.standard_normal((e.n_alb, e.n_alb))
         Ps.append(A @ A.T / e.n_alb)
-    Pt = torch.cat([torch.from_numpy(np.asfortranarray(P).ravel(order="F")) for P in Ps]).to(dev)
-    rho = h.density(out["albs"], Pt).cpu().numpy()
-    Hnl = h.nonlocal_block(out["albs"]).cpu().numpy()
+    rho = h.density(albs, _cat(Ps, dev)).cpu().numpy()
+    Hnl = h.nonlocal_block(albs).cpu().numpy()
     oa = on = 0
     for i, e in enumerate(els):
-        phi = h.split(out, i)["albs"].cpu().numpy()
+        phi = refs[i]["albs"]
         ne, n = phi.shape
         ref = dgblocks.density(phi, Ps[i])
         assert np.abs(rho[oa:oa + ne] - ref).max() < 1e-12 * np.abs(ref).max()
@@ -43,4 +72,71 @@ def test_density_and_nonlocal_block_match_oracle():
         assert np.abs(Hg - Hr).max() < 1e-12 * max(np.abs(Hr).max(), 1e-300)
         oa += ne
         on += n * n
+    h.close()
+
+
+def _volume_check(h, els, psis, albs, sigmas, dev, ratio=2):
+    import torch
+    out = h.dg_volume(_cat(psis, dev), _cat(albs, dev),
+                      torch.from_numpy(np.concatenate(sigmas)).to(dev), ratio).cpu().numpy()
+    on = 0
+    for i, e in enumerate(els):
+        n = e.n_alb
+        Ag = out[on:on + n * n].reshape(n, n, order="F")
+        Ar = dgblocks.volume_block(psis[i], albs[i], sigmas[i], e.V, e.grid, e.box,
+                                   e.elem_lo, e.elem_hi, ratio)
+        err = np.abs(Ag - Ar).max()
+        assert err < VOL_RTOL * np.abs(Ar).max(), (i, ratio, err)
+        on += n * n
+
+
+def test_volume_block_matches_oracle(small):
+    import torch
+    els, refs = small
+    dev = torch.device("cuda:0")
+    h = _handle(els, dev)
+    for ratio in (2, 1, 3):
+        _volume_check(h, els, [r["eigvecs"] for r in refs], [r["albs"] for r in refs],
+                      [r["sigma"] for r in refs], dev, ratio)
+    h.close()
+
+
+def test_volume_block_truncated_and_degenerate():
+    """A zero singular value (a column of psi vanishing on the element, all
+    J columns kept): T gets a zero column on both sides.  Odd grid edge."""
+    import torch
+    dev = torch.device("cuda:0")
+    e = synth.single_element(seed=33, grid=(15, 16, 12), n_states=6, n_atoms=2)
+    rng = np.random.default_rng(7)
+    psi = rng.standard_normal((e.ng, e.n_states))
+    from oracle.alb import box_rows
+    psi[box_rows(e.grid, e.elem_lo, e.elem_hi), 0] = 0.0
+    import dataclasses
+    e = dataclasses.replace(e, n_alb=e.n_states)          # keep the zero singular value
+    albs, sigma = restrict_svd(np.sqrt(e.dv) * psi, e.grid, e.elem_lo, e.elem_hi, e.dv, e.n_alb)
+    assert sigma.min() < 1e-12 * sigma.max()
+    sigma[-1] = 0.0
+    albs[:, -1] = 0.0
+    h = _handle([e], dev)
+    _volume_check(h, [e], [psi], [albs], [sigma], dev)
+    h.close()
+
+
+def test_volume_block_full_size_slab_elements():
+    """Two elements of the 64-element slab workload (36x36x60 extended grid,
+    12x12x60 element, J = 128, 64 ALBs, 24x24x120 LGL points), the kernels
+    and launch shapes of the benchmark; seeded random eigenvector stand-ins
+    with the oracle's restriction."""
+    import torch
+    dev = torch.device("cuda:0")
+    els = synth.slab_batch(n_elem=2)
+    psis, albs, sigmas = [], [], []
+    for e in els:
+        X = e.X0 / np.linalg.norm(e.X0, axis=0)
+        a, s = restrict_svd(X, e.grid, e.elem_lo, e.elem_hi, e.dv, e.n_alb)
+        psis.append(X / np.sqrt(e.dv))
+        albs.append(a)
+        sigmas.append(s)
+    h = _handle(els, dev)
+    _volume_check(h, els, psis, albs, sigmas, dev)
     h.close()
