@@ -175,13 +175,17 @@ dg_lgl_tables(const Elem* __restrict__ E, int ei, LglTab t) {
 }
 
 // dst[r + N_E c] = src[flat(r) + N_g c] for the rows r of the element box
-// (x fastest), c < ncols.  Grid (row chunks of 256, ncols).
+// (x fastest), c < J, for blockIdx.z elements of the geometry of element ei
+// whose columns follow one another (src stride N_g J, dst stride N_E J).
+// Grid (row chunks of 256, J, elements).
 extern "C" __global__ void __launch_bounds__(256)
 dg_box_cols(const Elem* __restrict__ E, int ei, const double* __restrict__ src, double* __restrict__ dst) {
   const Elem& e = E[ei];
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= e.ne) return;
   const int c = blockIdx.y;
+  src += (long long)blockIdx.z * e.ng * e.J;
+  dst += (long long)blockIdx.z * e.ne * e.J;
   int b1 = e.hi[0] - e.lo[0], b2 = e.hi[1] - e.lo[1];
   int i = r % b1, q = r / b1;
   int jj = q % b2, kk = q / b2;
@@ -190,18 +194,20 @@ dg_box_cols(const Elem* __restrict__ E, int ei, const double* __restrict__ src, 
 }
 
 // w[q] = w1[i] w2[j] w3[k] and vw[q] = w[q] vL[q] for LGL point q = (i, j, k),
-// i fastest.
+// i fastest; blockIdx.y selects the element (vL, vw stride = LGL points).
 extern "C" __global__ void __launch_bounds__(256)
 dg_lgl_weights(LglTab t, const double* __restrict__ vL, double* __restrict__ w, double* __restrict__ vw) {
   const int m1 = t.m[0], m2 = t.m[1];
   const long long M = (long long)m1 * m2 * t.m[2];
   const long long q = (long long)blockIdx.x * 256 + threadIdx.x;
   if (q >= M) return;
+  vL += M * blockIdx.y;
+  vw += M * blockIdx.y;
   int i = (int)(q % m1);
   long long r = q / m1;
   int j = (int)(r % m2), k = (int)(r / m2);
   double v = t.w[0][i] * t.w[1][j] * t.w[2][k];
-  w[q] = v;
+  if (blockIdx.y == 0) w[q] = v;
   vw[q] = v * vL[q];
 }
 

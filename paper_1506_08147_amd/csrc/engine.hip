@@ -246,7 +246,7 @@ struct dgdft_alb {
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed,
+    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_Z_THREADS), 0, stream, ed,
                        P2.active, P2.prefix, P2.na, col0, ncols_fixed, 0);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 48.0 : 56.0) * pts);
@@ -281,7 +281,7 @@ struct dgdft_alb {
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_THREADS), 0, stream, ed,
+    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_Z_THREADS), 0, stream, ed,
                        P2.active, P2.prefix, P2.na, col0, ncols_fixed,
                        opts.precond == DGDFT_PRECOND_NONE ? 2 : opts.precond == DGDFT_PRECOND_LEARNED ? 3 : 1);
     pend();
@@ -2173,26 +2173,76 @@ int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* a
   if (!h->potential_loaded) { h->err = "no potential loaded"; return DGDFT_EINVAL; }
   if (lgl_ratio < 1 || lgl_ratio > 8) { h->err = "dg_volume: lgl_ratio outside 1..8"; return DGDFT_EINVAL; }
   auto al = [](size_t n) { return (n + 31) / 32 * 32; };
-  // workspace (doubles) for the largest element
-  size_t need = 0;
+  // Per-element sizes (doubles).  Runs of consecutive elements with the same
+  // geometry are processed together, each product batched over the run;
+  // a run holds at most VOL_RUN_BYTES of per-element workspace.
+  constexpr size_t VOL_RUN_BYTES = size_t(2) << 30;
+  struct Sz { int m[3]; size_t ME, a, b; };
+  std::vector<Sz> sz(h->n);
   for (int e = 0; e < h->n; ++e) {
     const Elem& E = h->eh[e];
-    size_t m[3], n[3] = {(size_t)E.n1, (size_t)E.n2, (size_t)E.n3}, J = E.J, na = E.nalb;
+    Sz& z = sz[e];
     for (int d = 0; d < 3; ++d) {
-      m[d] = (size_t)lgl_ratio * (E.hi[d] - E.lo[d]);
-      if (m[d] < 2 || m[d] > (size_t)LGL_MAX) {
+      z.m[d] = lgl_ratio * (E.hi[d] - E.lo[d]);
+      if (z.m[d] < 2 || z.m[d] > LGL_MAX) {
         h->err = "dg_volume: LGL points per axis outside 2..1024";
         return DGDFT_EINVAL;
       }
     }
-    size_t ME = m[0] * m[1] * m[2];
-    size_t bufA = std::max({(size_t)E.ne * J, m[0] * n[1] * n[2] * J, ME * J});
-    size_t bufB = std::max(m[0] * m[1] * n[2] * J, ME * na);
-    size_t tab = 0;
-    for (int d = 0; d < 3; ++d) tab += al(m[d]) + al(m[d] * m[d]) + al(m[d] * n[d]);
-    size_t tot = al(bufA) + al(bufB) + al(m[0] * n[1] * n[2]) + al(m[0] * m[1] * n[2]) + 3 * al(ME) +
-                 tab + al(J * na) + al((size_t)dgdft_alb::BG_KSPLIT * J * na);
-    need = std::max(need, tot);
+    const size_t J = E.J, na = E.nalb, m1 = z.m[0], m2 = z.m[1];
+    z.ME = m1 * m2 * z.m[2];
+    z.a = std::max({(size_t)E.ne * J, m1 * E.n2 * E.n3 * J, z.ME * J});
+    z.b = std::max(m1 * m2 * E.n3 * J, z.ME * na);
+  }
+  auto same = [&](int a, int b) {
+    const Elem &x = h->eh[a], &y = h->eh[b];
+    if (x.n1 != y.n1 || x.n2 != y.n2 || x.n3 != y.n3 || x.J != y.J || x.nalb != y.nalb) return false;
+    for (int d = 0; d < 3; ++d)
+      if (x.lo[d] != y.lo[d] || x.hi[d] != y.hi[d] || x.L[d] != y.L[d]) return false;
+    return true;
+  };
+  // workspace of one run, carved in this order (also the allocation size)
+  struct Parts {
+    double *bufA, *bufB, *vX, *vY, *vL, *wq, *vw, *Tu, *part;
+    LglTab t;
+    size_t part_cap;
+  };
+  auto carve = [&](int e0, int G, double* base, Parts& P) {
+    const Elem& E = h->eh[e0];
+    const Sz& z = sz[e0];
+    const int nn[3] = {E.n1, E.n2, E.n3};
+    size_t off = 0;
+    auto take = [&](size_t n) { double* q = base ? base + off : nullptr; off += al(n); return q; };
+    P.bufA = take(G * z.a);
+    P.bufB = take(G * z.b);
+    P.vX = take((size_t)z.m[0] * E.n2 * E.n3);
+    P.vY = take((size_t)z.m[0] * z.m[1] * E.n3);
+    P.vL = take(G * z.ME);
+    P.wq = take(z.ME);
+    P.vw = take(G * z.ME);
+    P.t = LglTab{};
+    for (int d = 0; d < 3; ++d) {
+      P.t.m[d] = z.m[d];
+      P.t.w[d] = take(z.m[d]);
+      P.t.D[d] = take((size_t)z.m[d] * z.m[d]);
+      P.t.I[d] = take((size_t)z.m[d] * nn[d]);
+    }
+    P.Tu = take((size_t)G * E.J * E.nalb);
+    P.part_cap = (size_t)dgdft_alb::BG_KSPLIT * G * E.J * E.nalb;
+    P.part = take(P.part_cap);
+    return off;
+  };
+  std::vector<std::pair<int, int>> runs;   // (first element, count)
+  size_t need = 0;
+  for (int e = 0; e < h->n;) {
+    Parts P;
+    size_t per = carve(e, 1, nullptr, P) * sizeof(double);
+    int gmax = (int)std::max<size_t>(1, VOL_RUN_BYTES / per);
+    int g = 1;
+    while (e + g < h->n && g < gmax && same(e, e + g)) ++g;
+    runs.push_back({e, g});
+    need = std::max(need, carve(e, g, nullptr, P));
+    e += g;
   }
   bind_stream(h, stream);
   try {
@@ -2209,39 +2259,25 @@ int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* a
       }
       h->vol_cap = need;
     }
-    for (int e = 0; e < h->n; ++e) {
-      const Elem& E = h->eh[e];
+    for (auto [e0, G] : runs) {
+      const Elem& E = h->eh[e0];
+      const Sz& z = sz[e0];
       const int J = E.J, na = E.nalb, n1 = E.n1, n2 = E.n2, n3 = E.n3;
-      int m[3];
-      for (int d = 0; d < 3; ++d) m[d] = lgl_ratio * (E.hi[d] - E.lo[d]);
-      const int m1 = m[0], m2 = m[1], m3 = m[2], ME = m1 * m2 * m3;
-      const int nn[3] = {n1, n2, n3};
-      double* p = h->vol_ws;
-      auto take = [&](size_t n) { double* q = p; p += al(n); return q; };
-      double* bufA = take(std::max({(size_t)E.ne * J, (size_t)m1 * n2 * n3 * J, (size_t)ME * J}));
-      double* bufB = take(std::max((size_t)m1 * m2 * n3 * J, (size_t)ME * na));
-      double* vX = take((size_t)m1 * n2 * n3);
-      double* vY = take((size_t)m1 * m2 * n3);
-      double* vL = take(ME);
-      double* wq = take(ME);
-      double* vw = take(ME);
-      LglTab t{};
-      for (int d = 0; d < 3; ++d) {
-        t.m[d] = m[d];
-        t.w[d] = take(m[d]);
-        t.D[d] = take((size_t)m[d] * m[d]);
-        t.I[d] = take((size_t)m[d] * nn[d]);
-      }
-      double* Tu = take((size_t)J * na);
-      double* part = take((size_t)dgdft_alb::BG_KSPLIT * J * na);
-      const size_t part_cap = (size_t)dgdft_alb::BG_KSPLIT * J * na;
+      const int m1 = z.m[0], m2 = z.m[1], m3 = z.m[2], ME = (int)z.ME;
+      const long long ngJ = (long long)E.ng * J, m12 = (long long)m1 * m2;
+      Parts P;
+      carve(e0, G, h->vol_ws, P);
+      double *bufA = P.bufA, *bufB = P.bufB, *vX = P.vX, *vY = P.vY, *vL = P.vL, *wq = P.wq,
+             *vw = P.vw, *Tu = P.Tu, *part = P.part;
+      const LglTab t = P.t;
+      const size_t part_cap = P.part_cap;
       auto gemm = [&](int ta, int tb, int M, int N, int K, const double* A, int lda, long long sa,
                       const double* B, int ldb, long long sb, double* Cm, int ldc, long long sc,
-                      int batch, double alpha, double beta, const double* ks, const double* cs,
-                      int cs_pow) {
+                      int batch, double alpha, double beta, const double* ks, long long sks,
+                      const double* cs, long long scs, int cs_pow) {
         BgArgs a{};
         a.A = A; a.B = B; a.C = Cm; a.ks = ks; a.cs = cs; a.cs_pow = cs_pow;
-        a.sa = sa; a.sb = sb; a.sc = sc;
+        a.sa = sa; a.sb = sb; a.sc = sc; a.sks = sks; a.scs = scs;
         a.M = M; a.N = N; a.K = K; a.lda = lda; a.ldb = ldb; a.ldc = ldc; a.batch = batch;
         a.ta = ta; a.tb = tb; a.alpha = alpha; a.beta = beta;
         bool fits = (size_t)dgdft_alb::BG_KSPLIT * M * N * batch <= part_cap;
@@ -2250,45 +2286,54 @@ int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* a
       const double* psi = eigvecs + E.off_ngj;
       const double* phi = albs + E.off_alb;
       double* oe = out + E.off_nl;
-      hipLaunchKernelGGL(dg_lgl_tables, dim3(3), dim3(256), 0, h->stream, (const Elem*)h->ed, e, t);
+      const long long ne = E.ne;
+      hipLaunchKernelGGL(dg_lgl_tables, dim3(3), dim3(256), 0, h->stream, (const Elem*)h->ed, e0, t);
       HCHECK(hipGetLastError());
-      // T = dV psi_E^T phi sigma^-2  (J x n_alb)
-      hipLaunchKernelGGL(dg_box_cols, dim3(cdiv(E.ne, 256), J), dim3(256), 0, h->stream,
-                         (const Elem*)h->ed, e, psi, bufA);
+      // T = dV psi_E^T phi sigma^-2  (J x n_alb per element)
+      hipLaunchKernelGGL(dg_box_cols, dim3(cdiv(E.ne, 256), J, G), dim3(256), 0, h->stream,
+                         (const Elem*)h->ed, e0, psi, bufA);
       HCHECK(hipGetLastError());
-      gemm(1, 0, J, na, E.ne, bufA, E.ne, 0, phi, E.ne, 0, Tu, J, 0, 1, E.dv, 0.0, nullptr,
-           sigma + E.off_nalb, -2);
-      // psi at the LGL points, one axis at a time: x (m1 x n2 n3 J), y, z
-      gemm(0, 0, m1, n2 * n3 * J, n1, t.I[0], m1, 0, psi, n1, 0, bufA, m1, 0, 1, 1.0, 0.0,
-           nullptr, nullptr, 0);
-      gemm(0, 1, m1, m2, n2, bufA, m1, (long long)m1 * n2, t.I[1], m2, 0, bufB, m1,
-           (long long)m1 * m2, n3 * J, 1.0, 0.0, nullptr, nullptr, 0);
-      gemm(0, 1, m1 * m2, m3, n3, bufB, m1 * m2, (long long)m1 * m2 * n3, t.I[2], m3, 0, bufA,
-           m1 * m2, ME, J, 1.0, 0.0, nullptr, nullptr, 0);
-      // Phi = Psi_LGL T  (ME x n_alb) into bufB
-      gemm(0, 0, ME, na, J, bufA, ME, 0, Tu, J, 0, bufB, ME, 0, 1, 1.0, 0.0, nullptr, nullptr, 0);
-      // V at the LGL points
-      gemm(0, 0, m1, n2 * n3, n1, t.I[0], m1, 0, E.V, n1, 0, vX, m1, 0, 1, 1.0, 0.0, nullptr,
-           nullptr, 0);
-      gemm(0, 1, m1, m2, n2, vX, m1, (long long)m1 * n2, t.I[1], m2, 0, vY, m1, (long long)m1 * m2,
-           n3, 1.0, 0.0, nullptr, nullptr, 0);
-      gemm(0, 1, m1 * m2, m3, n3, vY, m1 * m2, 0, t.I[2], m3, 0, vL, m1 * m2, 0, 1, 1.0, 0.0,
-           nullptr, nullptr, 0);
-      hipLaunchKernelGGL(dg_lgl_weights, dim3(cdiv(ME, 256)), dim3(256), 0, h->stream, t,
+      gemm(1, 0, J, na, E.ne, bufA, E.ne, ne * J, phi, E.ne, ne * na, Tu, J, (long long)J * na, G,
+           E.dv, 0.0, nullptr, 0, sigma + E.off_nalb, na, -2);
+      // psi at the LGL points, one axis at a time: x, y, z
+      gemm(0, 0, m1, n2 * n3 * J, n1, t.I[0], m1, 0, psi, n1, ngJ, bufA, m1,
+           (long long)m1 * n2 * n3 * J, G, 1.0, 0.0, nullptr, 0, nullptr, 0, 0);
+      gemm(0, 1, m1, m2, n2, bufA, m1, (long long)m1 * n2, t.I[1], m2, 0, bufB, m1, m12,
+           n3 * J * G, 1.0, 0.0, nullptr, 0, nullptr, 0, 0);
+      gemm(0, 1, m1 * m2, m3, n3, bufB, m1 * m2, m12 * n3, t.I[2], m3, 0, bufA, m1 * m2, ME,
+           J * G, 1.0, 0.0, nullptr, 0, nullptr, 0, 0);
+      // Phi = Psi_LGL T  (ME x n_alb per element) into bufB
+      gemm(0, 0, ME, na, J, bufA, ME, (long long)ME * J, Tu, J, (long long)J * na, bufB, ME,
+           (long long)ME * na, G, 1.0, 0.0, nullptr, 0, nullptr, 0, 0);
+      // V at the LGL points, per element
+      for (int g = 0; g < G; ++g) {
+        gemm(0, 0, m1, n2 * n3, n1, t.I[0], m1, 0, h->eh[e0 + g].V, n1, 0, vX, m1, 0, 1, 1.0, 0.0,
+             nullptr, 0, nullptr, 0, 0);
+        gemm(0, 1, m1, m2, n2, vX, m1, (long long)m1 * n2, t.I[1], m2, 0, vY, m1, m12, n3, 1.0,
+             0.0, nullptr, 0, nullptr, 0, 0);
+        gemm(0, 1, m1 * m2, m3, n3, vY, m1 * m2, 0, t.I[2], m3, 0, vL + (long long)g * ME, m1 * m2,
+             0, 1, 1.0, 0.0, nullptr, 0, nullptr, 0, 0);
+      }
+      hipLaunchKernelGGL(dg_lgl_weights, dim3(cdiv(ME, 256), G), dim3(256), 0, h->stream, t,
                          (const double*)vL, wq, vw);
       HCHECK(hipGetLastError());
+      const long long MEna = (long long)ME * na, nana = (long long)na * na;
       // <phi, V phi> = Phi^T diag(w V) Phi
-      gemm(1, 0, na, na, ME, bufB, ME, 0, bufB, ME, 0, oe, na, 0, 1, 1.0, 0.0, vw, nullptr, 0);
+      gemm(1, 0, na, na, ME, bufB, ME, MEna, bufB, ME, MEna, oe, na, nana, G, 1.0, 0.0, vw, ME,
+           nullptr, 0, 0);
       // 1/2 <d phi, d phi> per axis, the derivative into bufA
-      gemm(0, 0, m1, m2 * m3 * na, m1, t.D[0], m1, 0, bufB, m1, 0, bufA, m1, 0, 1, 1.0, 0.0,
-           nullptr, nullptr, 0);
-      gemm(1, 0, na, na, ME, bufA, ME, 0, bufA, ME, 0, oe, na, 0, 1, 0.5, 1.0, wq, nullptr, 0);
-      gemm(0, 1, m1, m2, m2, bufB, m1, (long long)m1 * m2, t.D[1], m2, 0, bufA, m1,
-           (long long)m1 * m2, m3 * na, 1.0, 0.0, nullptr, nullptr, 0);
-      gemm(1, 0, na, na, ME, bufA, ME, 0, bufA, ME, 0, oe, na, 0, 1, 0.5, 1.0, wq, nullptr, 0);
-      gemm(0, 1, m1 * m2, m3, m3, bufB, m1 * m2, ME, t.D[2], m3, 0, bufA, m1 * m2, ME, na, 1.0,
-           0.0, nullptr, nullptr, 0);
-      gemm(1, 0, na, na, ME, bufA, ME, 0, bufA, ME, 0, oe, na, 0, 1, 0.5, 1.0, wq, nullptr, 0);
+      gemm(0, 0, m1, m2 * m3 * na, m1, t.D[0], m1, 0, bufB, m1, MEna, bufA, m1, MEna, G, 1.0, 0.0,
+           nullptr, 0, nullptr, 0, 0);
+      gemm(1, 0, na, na, ME, bufA, ME, MEna, bufA, ME, MEna, oe, na, nana, G, 0.5, 1.0, wq, 0,
+           nullptr, 0, 0);
+      gemm(0, 1, m1, m2, m2, bufB, m1, m12, t.D[1], m2, 0, bufA, m1, m12, m3 * na * G, 1.0, 0.0,
+           nullptr, 0, nullptr, 0, 0);
+      gemm(1, 0, na, na, ME, bufA, ME, MEna, bufA, ME, MEna, oe, na, nana, G, 0.5, 1.0, wq, 0,
+           nullptr, 0, 0);
+      gemm(0, 1, m1 * m2, m3, m3, bufB, m1 * m2, ME, t.D[2], m3, 0, bufA, m1 * m2, ME, na * G, 1.0,
+           0.0, nullptr, 0, nullptr, 0, 0);
+      gemm(1, 0, na, na, ME, bufA, ME, MEna, bufA, ME, MEna, oe, na, nana, G, 0.5, 1.0, wq, 0,
+           nullptr, 0, 0);
     }
     HCHECK(hipStreamSynchronize(h->stream));
     if (h->prof) h->flush_prof();

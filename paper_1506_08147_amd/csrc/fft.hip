@@ -25,7 +25,8 @@
 
 namespace dg {
 
-constexpr int FFT_THREADS = 512;
+constexpr int FFT_THREADS = 512;        // xy passes
+constexpr int FFT_Z_THREADS = 512;      // z pass
 constexpr int FFT_MAXPTS = 4608;        // largest LDS tile (72 KiB): z pencils of a row pair
 constexpr int FFT_XY_SMALL = 2304;      // xy planes up to 48 x 48 use a 36 KiB tile
 
@@ -133,19 +134,25 @@ template <> struct Dft<5> {
 // at buf[line*lstride + m*estride].  Ns = product of the radices done so far.
 // MAXPTS bounds the points of the tile, so the register staging is sized at
 // compile time.
-template <int R, int MAXPTS, class C>
+template <int R, int MAXPTS, int NT, class C>
 __device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, int estride,
                                       int Ns, const C* __restrict__ tw, double sgn) {
-  constexpr int MAXK = (MAXPTS / R + FFT_THREADS - 1) / FFT_THREADS;
+  constexpr int MAXK = (MAXPTS / R + NT - 1) / NT;
   const unsigned nb = n / R;
   const unsigned total = nb * nlines;
-  const unsigned m_nb = div_magic(nb), m_ns = div_magic(Ns);
+  // Consecutive threads take consecutive lines when the lines are adjacent in
+  // LDS (lstride 1), else consecutive butterflies of one line: either way
+  // neighbouring lanes touch neighbouring addresses (few bank conflicts).
+  const bool by_line = lstride == 1;
+  const unsigned dv = by_line ? (unsigned)nlines : nb;
+  const unsigned m_dv = div_magic(dv), m_ns = div_magic(Ns);
   C v[MAXK][R];
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
-    unsigned b = threadIdx.x + q * FFT_THREADS;
+    unsigned b = threadIdx.x + q * NT;
     if (b < total) {
-      unsigned line = fdiv(b, nb, m_nb), j = b - line * nb;
+      unsigned hi = fdiv(b, dv, m_dv), lo = b - hi * dv;
+      unsigned line = by_line ? lo : hi, j = by_line ? hi : lo;
       int base = line * lstride;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = buf[base + (j + r * nb) * estride];
@@ -155,9 +162,10 @@ __device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, in
   const int step = n / (Ns * R);
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
-    unsigned b = threadIdx.x + q * FFT_THREADS;
+    unsigned b = threadIdx.x + q * NT;
     if (b < total) {
-      unsigned line = fdiv(b, nb, m_nb), j = b - line * nb;
+      unsigned hi = fdiv(b, dv, m_dv), lo = b - hi * dv;
+      unsigned line = by_line ? lo : hi, j = by_line ? hi : lo;
       unsigned jq = fdiv(j, Ns, m_ns);
       int k = j - jq * Ns;
 #pragma unroll
@@ -176,7 +184,7 @@ __device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, in
   __syncthreads();
 }
 
-template <int MAXPTS, class C>
+template <int MAXPTS, int NT = FFT_THREADS, class C>
 __device__ __forceinline__ void fft_lines(C* buf, int n, int nlines, int lstride, int estride,
                                           const int* rad, int nrad, const C* __restrict__ tw,
                                           double sgn) {
@@ -184,10 +192,10 @@ __device__ __forceinline__ void fft_lines(C* buf, int n, int nlines, int lstride
   for (int s = 0; s < nrad; ++s) {
     int R = rad[s];
     switch (R) {
-      case 4: stage<4, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      case 2: stage<2, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      case 3: stage<3, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
-      default: stage<5, MAXPTS, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 4: stage<4, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 2: stage<2, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 3: stage<3, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      default: stage<5, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
     }
     Ns *= R;
   }
@@ -260,7 +268,7 @@ dg_fft_xy_fwd32_l(Elem* __restrict__ E, const int* __restrict__ active, const in
 // Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
 // (pair q, row pair m2 in [0, n2/2]).  mode 0: kinetic |G|^2/2.  mode 1:
 // Teter with band kinetic energies tkin[col].  mode 2: identity.
-template <class C>
+template <int NT, class C>
 __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const int* __restrict__ active,
                                            const int* __restrict__ prefix, int na, int col0, int ncols,
                                            int mode) {
@@ -277,18 +285,18 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
   int npts = width * n3;
   C* Z = zpair<C>(e, q);
   // LDS layout: buf[z*width + slot*n1 + x]
-  for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
+  for (int p = threadIdx.x; p < npts; p += NT) {
     int z = p / width, r = p - z * width;
     int s = r / n1, x = r - s * n1;
     int row = s ? rb : ra;
     buf[p] = Z[(long long)z * n1 * n2 + row * n1 + x];
   }
   __syncthreads();
-  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), -1.0);
+  fft_lines<FFT_MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), -1.0);
 
   const double g1 = 2.0 * M_PI / e.L[0], g2 = 2.0 * M_PI / e.L[1], g3 = 2.0 * M_PI / e.L[2];
   if (mode == 0) {
-    for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
+    for (int p = threadIdx.x; p < npts; p += NT) {
       int z = p / width, r = p - z * width;
       int s = r / n1, x = r - s * n1;
       int row = s ? rb : ra;
@@ -303,11 +311,11 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     int ca = col0 + 2 * q, cb = ca + 1;
     bool hasb = cb < col0 + nc;
     double Ta = e.tkin[ca], Tb = hasb ? e.tkin[cb] : Ta;
-    constexpr int PPT = FFT_MAXPTS / FFT_THREADS;
+    constexpr int PPT = (FFT_MAXPTS + NT - 1) / NT;
     C nv[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-      int p = threadIdx.x + u * FFT_THREADS;
+      int p = threadIdx.x + u * NT;
       if (p < npts) {
         int z = p / width, r = p - z * width;
         int s = r / n1, x = r - s * n1;
@@ -331,13 +339,13 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-      int p = threadIdx.x + u * FFT_THREADS;
+      int p = threadIdx.x + u * NT;
       if (p < npts) buf[p] = nv[u];
     }
     __syncthreads();
   }
-  fft_lines<FFT_MAXPTS>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), 1.0);
-  for (int p = threadIdx.x; p < npts; p += FFT_THREADS) {
+  fft_lines<FFT_MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), 1.0);
+  for (int p = threadIdx.x; p < npts; p += NT) {
     int z = p / width, r = p - z * width;
     int s = r / n1, x = r - s * n1;
     int row = s ? rb : ra;
@@ -345,18 +353,18 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
   }
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS)
 dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
          int na, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_MAXPTS];
-  fft_z_body(buf, E, active, prefix, na, col0, ncols, mode);
+  fft_z_body<FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS)
 dg_fft_z32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
            int na, int col0, int ncols, int mode) {
   __shared__ float2 buf[FFT_MAXPTS];
-  fft_z_body(buf, E, active, prefix, na, col0, ncols, mode);
+  fft_z_body<FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
 }
 
 // Pass 3: inverse xy transform and epilogue.  Work item (pair q, plane z).
@@ -399,8 +407,17 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
       double ya = sc * r.x + v * IA[p];
       double yb = hasb ? sc * r.y + v * IB[p] : 0.0;
       if (kp) {
+        // entries of this point four at a time, so that their loads overlap
         int g = (int)(off + p);
-        for (int t = kp[g]; t < kp[g + 1]; ++t) {
+        int t = kp[g];
+        const int t1 = kp[g + 1];
+        for (; t + 4 <= t1; t += 4) {
+          int p0 = e.kbt_p[t], p1 = e.kbt_p[t + 1], p2 = e.kbt_p[t + 2], p3 = e.kbt_p[t + 3];
+          double c0 = e.kbt_c[t], c1 = e.kbt_c[t + 1], c2 = e.kbt_c[t + 2], c3 = e.kbt_c[t + 3];
+          ya += c0 * pa[p0] + c1 * pa[p1] + c2 * pa[p2] + c3 * pa[p3];
+          if (hasb) yb += c0 * pb[p0] + c1 * pb[p1] + c2 * pb[p2] + c3 * pb[p3];
+        }
+        for (; t < t1; ++t) {
           int pr = e.kbt_p[t];
           double c = e.kbt_c[t];
           ya += c * pa[pr];

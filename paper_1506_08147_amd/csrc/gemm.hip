@@ -423,8 +423,8 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
 
 // General strided-batched product for the element-local DG blocks:
 //   C_b = alpha * op(A_b) diag(ks) op(B_b) diag(s) + beta C_b
-// for b < batch, with A_b = A + b*sa (likewise B, C; stride 0 shares an
-// operand), column-major, op = transpose when ta/tb = 1.  ks (nullable)
+// for b < batch, with A_b = A + b*sa (likewise B, C, ks, cs; stride 0 shares
+// an operand), column-major, op = transpose when ta/tb = 1.  ks (nullable)
 // weights the inner index (a diagonal quadrature weight between the two
 // factors); s_j = cs[j] (cs_pow 1) or 1/cs[j]^2 (cs_pow -2, zero where
 // cs[j] == 0), or 1 when cs is null.  With ksplit > 1 each
@@ -437,14 +437,14 @@ struct BgArgs {
   const double* ks;
   const double* cs;
   double* part;                  // ksplit * batch * M * N partial products
-  long long sa, sb, sc;
+  long long sa, sb, sc, sks, scs;
   int M, N, K, lda, ldb, ldc, batch, ta, tb, ksplit, kchunk, cs_pow;
   double alpha, beta;
 };
 
-__device__ __forceinline__ double bg_colscale(const BgArgs& a, int j) {
+__device__ __forceinline__ double bg_colscale(const BgArgs& a, int bi, int j) {
   if (!a.cs) return 1.0;
-  double c = a.cs[j];
+  double c = a.cs[a.scs * bi + j];
   if (a.cs_pow == 1) return c;
   return c != 0.0 ? 1.0 / (c * c) : 0.0;
 }
@@ -461,6 +461,7 @@ dg_bgemm(BgArgs a) {
   const int i0 = (t % ntm) * 64, j0 = (t / ntm) * 64;
   const double* A = a.A + a.sa * bi;
   const double* B = a.B + a.sb * bi;
+  const double* ksv = a.ks ? a.ks + a.sks * bi : nullptr;
   const int kbeg = kc * a.kchunk, kend = min(a.K, kbeg + a.kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = wv & 1, wj = wv >> 1;
@@ -479,7 +480,7 @@ dg_bgemm(BgArgs a) {
       double av = 0.0;
       if (i0 + ii < a.M && k0 + kk < kend) {
         av = a.ta ? A[(k0 + kk) + (long long)a.lda * (i0 + ii)] : A[(i0 + ii) + (long long)a.lda * (k0 + kk)];
-        if (a.ks) av *= a.ks[k0 + kk];
+        if (ksv) av *= ksv[k0 + kk];
       }
       As[kk * 65 + ii] = av;
       int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
@@ -518,7 +519,7 @@ dg_bgemm(BgArgs a) {
             P[i + (long long)a.M * j] = acc[x][y][r];
           } else {
             double* c = C + i + (long long)a.ldc * j;
-            double v = a.alpha * bg_colscale(a, j) * acc[x][y][r];
+            double v = a.alpha * bg_colscale(a, bi, j) * acc[x][y][r];
             *c = a.beta != 0.0 ? v + a.beta * *c : v;
           }
         }
@@ -538,7 +539,7 @@ dg_bgemm_reduce(BgArgs a) {
   double s = 0.0;
   for (int kc = 0; kc < a.ksplit; ++kc) s += a.part[((long long)kc * a.batch + bi) * mn + ij];
   double* c = a.C + a.sc * bi + i + (long long)a.ldc * j;
-  double v = a.alpha * bg_colscale(a, j) * s;
+  double v = a.alpha * bg_colscale(a, bi, j) * s;
   *c = a.beta != 0.0 ? v + a.beta * *c : v;
 }
 

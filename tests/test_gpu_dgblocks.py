@@ -39,8 +39,10 @@ def _cat(mats, dev):
 
 @pytest.fixture(scope="module")
 def small():
+    """Two elements of one geometry (batched together by the volume terms)
+    followed by a third of another."""
     els = [synth.single_element(seed=s, grid=g, n_states=J, n_atoms=4)
-           for s, g, J in [(31, (16, 16, 16), 10), (32, (18, 16, 20), 12)]]
+           for s, g, J in [(31, (16, 16, 16), 10), (34, (16, 16, 16), 10), (32, (18, 16, 20), 12)]]
     refs = [solve_element(e, tol=1e-8) for e in els]
     assert all(r["converged"] for r in refs)
     return els, refs
