@@ -589,7 +589,7 @@ namespace {
 // ---------------------------------------------------------------- helpers
 bool factor_radices(int n, int* rad, int* nrad) {
   int k = 0;
-  for (int r : {4, 2, 3, 5}) {
+  for (int r : {8, 9, 4, 2, 3, 5}) {
     while (n % r == 0) {
       if (k >= MAX_RADICES) return false;
       rad[k++] = r;

@@ -17,7 +17,7 @@
 //             operator HX = T x + V x + sum_p gamma_p beta_p (beta_p^T x)
 //             (V and the KB scatter fused), for the preconditioner the result
 //
-// 1D transforms are mixed-radix Stockham (radices 4, 2, 3, 5) in LDS with
+// 1D transforms are mixed-radix Stockham (radices 8, 9, 4, 2, 3, 5) in LDS with
 // register staging: every thread reads all its butterfly inputs of a stage,
 // the workgroup synchronises, then every thread writes its outputs, so one
 // LDS buffer suffices.  Twiddles come from a per-axis table exp(-2 pi i t/n).
@@ -130,6 +130,55 @@ template <> struct Dft<5> {
   }
 };
 
+// 8 = 4 x 2 (Cooley-Tukey): 4-point DFTs of the even and odd samples, the odd
+// ones times w8^k, then 2-point butterflies.
+template <> struct Dft<8> {
+  template <class C> static __device__ __forceinline__ void run(C* v, double sgn) {
+    const double r = 0.70710678118654752440;   // cos(pi / 4)
+    C e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<4>::run(e, sgn);
+    Dft<4>::run(o, sgn);
+    o[1] = cmul(o[1], cmake<C>(r, sgn * r));
+    o[2] = cisgn(o[2], sgn);
+    o[3] = cmul(o[3], cmake<C>(-r, sgn * r));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 4] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// 9 = 3 x 3 (Cooley-Tukey): input n = 3 n1 + n2, output k = k1 + 3 k2;
+// 3-point DFTs over n1, twiddles w9^(n2 k1), 3-point DFTs over n2.
+template <> struct Dft<9> {
+  template <class C> static __device__ __forceinline__ void run(C* v, double sgn) {
+    const double c1 = 0.76604444311897803520, s1 = 0.64278760968653932632;    // 2 pi / 9
+    const double c2 = 0.17364817766693034885, s2 = 0.98480775301220805936;    // 4 pi / 9
+    const double c4 = -0.93969262078590838405, s4 = 0.34202014332566873304;   // 8 pi / 9
+    C y[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      y[n2][0] = v[n2];
+      y[n2][1] = v[n2 + 3];
+      y[n2][2] = v[n2 + 6];
+      Dft<3>::run(y[n2], sgn);
+    }
+    y[1][1] = cmul(y[1][1], cmake<C>(c1, sgn * s1));
+    y[1][2] = cmul(y[1][2], cmake<C>(c2, sgn * s2));
+    y[2][1] = cmul(y[2][1], cmake<C>(c2, sgn * s2));
+    y[2][2] = cmul(y[2][2], cmake<C>(c4, sgn * s4));
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      C t[3] = {y[0][k1], y[1][k1], y[2][k1]};
+      Dft<3>::run(t, sgn);
+      v[k1] = t[0];
+      v[k1 + 3] = t[1];
+      v[k1 + 6] = t[2];
+    }
+  }
+};
+
 // One Stockham stage of radix R on `nlines` lines of length n stored in LDS
 // at buf[line*lstride + m*estride].  Ns = product of the radices done so far.
 // MAXPTS bounds the points of the tile, so the register staging is sized at
@@ -192,6 +241,8 @@ __device__ __forceinline__ void fft_lines(C* buf, int n, int nlines, int lstride
   for (int s = 0; s < nrad; ++s) {
     int R = rad[s];
     switch (R) {
+      case 8: stage<8, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
+      case 9: stage<9, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
       case 4: stage<4, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
       case 2: stage<2, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
       case 3: stage<3, MAXPTS, NT, C>(buf, n, nlines, lstride, estride, Ns, tw, sgn); break;
@@ -283,11 +334,18 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
   int nrows = (ra == rb) ? 1 : 2;
   int width = nrows * n1;            // lines per z-slice, contiguous in LDS
   int npts = width * n3;
+  const unsigned mw = div_magic(width);
   C* Z = zpair<C>(e, q);
-  // LDS layout: buf[z*width + slot*n1 + x]
+  // LDS layout: buf[z*width + slot*n1 + x]; point p -> (z, slot s, x)
+  auto split = [&](int p, int& z, int& s, int& x) {
+    z = (int)fdiv((unsigned)p, (unsigned)width, mw);
+    int r = p - z * width;
+    s = r >= n1;
+    x = r - s * n1;
+  };
   for (int p = threadIdx.x; p < npts; p += NT) {
-    int z = p / width, r = p - z * width;
-    int s = r / n1, x = r - s * n1;
+    int z, s, x;
+    split(p, z, s, x);
     int row = s ? rb : ra;
     buf[p] = Z[(long long)z * n1 * n2 + row * n1 + x];
   }
@@ -297,8 +355,8 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
   const double g1 = 2.0 * M_PI / e.L[0], g2 = 2.0 * M_PI / e.L[1], g3 = 2.0 * M_PI / e.L[2];
   if (mode == 0) {
     for (int p = threadIdx.x; p < npts; p += NT) {
-      int z = p / width, r = p - z * width;
-      int s = r / n1, x = r - s * n1;
+      int z, s, x;
+      split(p, z, s, x);
       int row = s ? rb : ra;
       double k1 = g1 * freq(x, n1), k2 = g2 * freq(row, n2), k3 = g3 * freq(z, n3);
       buf[p] = cscale(buf[p], 0.5 * (k1 * k1 + k2 * k2 + k3 * k3));
@@ -310,26 +368,26 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     const int nc = ncols < 0 ? e.J : ncols;
     int ca = col0 + 2 * q, cb = ca + 1;
     bool hasb = cb < col0 + nc;
-    double Ta = e.tkin[ca], Tb = hasb ? e.tkin[cb] : Ta;
+    const double ita = 1.0 / e.tkin[ca], itb = hasb ? 1.0 / e.tkin[cb] : ita;
     constexpr int PPT = (FFT_MAXPTS + NT - 1) / NT;
     C nv[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
       int p = threadIdx.x + u * NT;
       if (p < npts) {
-        int z = p / width, r = p - z * width;
-        int s = r / n1, x = r - s * n1;
+        int z, s, x;
+        split(p, z, s, x);
         int row = s ? rb : ra;
         double k1 = g1 * freq(x, n1), k2 = g2 * freq(row, n2), k3 = g3 * freq(z, n3);
         double t = 0.5 * (k1 * k1 + k2 * k2 + k3 * k3);
-        double Ka = teter_k(t / Ta), Kb = teter_k(t / Tb);
+        double Ka = teter_k(t * ita), Kb = hasb ? teter_k(t * itb) : Ka;
         if (mode == 3) {
           int sh = e.shell_of[(long long)z * n1 * n2 + row * n1 + x];
           Ka *= e.gain[(long long)ca * e.nsh + sh];
           Kb = hasb ? Kb * e.gain[(long long)cb * e.nsh + sh] : Ka;
         }
         // mirror point (-m1, -m2, -m3): the other row slot (or the same)
-        int zm = (n3 - z) % n3, xm = (n1 - x) % n1;
+        int zm = z ? n3 - z : 0, xm = x ? n1 - x : 0;
         int sm = (nrows == 2) ? 1 - s : 0;
         C zp = buf[p], zmr = buf[zm * width + sm * n1 + xm];
         double hs = 0.5 * (Ka + Kb), hd = 0.5 * (Ka - Kb);
@@ -346,8 +404,8 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
   }
   fft_lines<FFT_MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), 1.0);
   for (int p = threadIdx.x; p < npts; p += NT) {
-    int z = p / width, r = p - z * width;
-    int s = r / n1, x = r - s * n1;
+    int z, s, x;
+    split(p, z, s, x);
     int row = s ? rb : ra;
     Z[(long long)z * n1 * n2 + row * n1 + x] = buf[p];
   }
