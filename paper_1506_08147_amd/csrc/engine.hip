@@ -424,7 +424,8 @@ struct dgdft_alb {
   static constexpr int BG_KSPLIT = 128;
   void bgemm(BgArgs a, double* part) {
     if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return;
-    const long long tiles = (long long)cdiv(a.M, 64) * cdiv(a.N, 64) * a.batch;
+    const int bm = a.M <= 32 ? 32 : 64, bn = a.N <= 32 ? 32 : 64;
+    const long long tiles = (long long)cdiv(a.M, bm) * cdiv(a.N, bn) * a.batch;
     a.ksplit = 1;
     a.kchunk = a.K > 0 ? a.K : 16;
     if (part && tiles < 512 && a.K > 256) {
@@ -440,7 +441,9 @@ struct dgdft_alb {
     double by = 8.0 * ((double)a.M * a.K * (a.sa ? a.batch : 1) + (double)a.K * a.N * (a.sb ? a.batch : 1) +
                        (double)a.M * a.N * a.batch * (a.beta != 0.0 ? 2 : 1));
     pbeg(DGDFT_K_BGEMM, fl, by);
-    hipLaunchKernelGGL(dg_bgemm, dim3((unsigned)(tiles * a.ksplit)), dim3(256), 0, stream, a);
+    void (*kern)(BgArgs) = bm == 64 ? (bn == 64 ? dg_bgemm : dg_bgemm_n32)
+                                     : (bn == 64 ? dg_bgemm_m32 : dg_bgemm_s32);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * a.ksplit)), dim3(256), 0, stream, a);
     if (a.ksplit > 1) {
       long long n = (long long)a.M * a.N * a.batch;
       hipLaunchKernelGGL(dg_bgemm_reduce, dim3((unsigned)cdiv((int)n, 256)), dim3(256), 0, stream, a);

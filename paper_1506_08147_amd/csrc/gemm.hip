@@ -449,71 +449,81 @@ __device__ __forceinline__ double bg_colscale(const BgArgs& a, int bi, int j) {
   return c != 0.0 ? 1.0 / (c * c) : 0.0;
 }
 
-extern "C" __global__ void __launch_bounds__(256)
-dg_bgemm(BgArgs a) {
-  __shared__ double As[16 * 65];
-  __shared__ double Bs[16 * 65];
-  const int ntm = cdiv(a.M, 64), ntn = cdiv(a.N, 64);
+// BM x BN output tile per workgroup (64 or 32 each, so that thin operands
+// do not pay for a 64-wide tile); four waves in a 2 x 2 grid, each with
+// (BM/32) x (BN/32) MFMA blocks of 16 x 16; 16-deep K stages through LDS.
+template <int BM, int BN>
+__device__ __forceinline__ void bgemm_tile(const BgArgs& a) {
+  constexpr int MB = BM / 32, NB = BN / 32;
+  __shared__ double As[16 * (BM + 1)];
+  __shared__ double Bs[16 * (BN + 1)];
+  const int ntm = cdiv(a.M, BM), ntn = cdiv(a.N, BN);
   const long long blk = blockIdx.x;
   const int t = (int)(blk % (ntm * ntn));
   const long long rest = blk / (ntm * ntn);
   const int bi = (int)(rest % a.batch), kc = (int)(rest / a.batch);
-  const int i0 = (t % ntm) * 64, j0 = (t / ntm) * 64;
+  const int i0 = (t % ntm) * BM, j0 = (t / ntm) * BN;
   const double* A = a.A + a.sa * bi;
   const double* B = a.B + a.sb * bi;
   const double* ksv = a.ks ? a.ks + a.sks * bi : nullptr;
   const int kbeg = kc * a.kchunk, kend = min(a.K, kbeg + a.kchunk);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = wv & 1, wj = wv >> 1;
-  dbl4 acc[2][2];
+  dbl4 acc[MB][NB];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < MB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < NB; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    // op(A) tile (ii, kk): contiguous along ii when ta == 0, along kk when ta == 1
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int el = tid + 256 * q;          // 0..1023 over a 64 x 16 tile
-      int f = el & 63, s16 = el >> 6;
-      int g = el & 15, s64 = el >> 4;
-      int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
+    for (int q = 0; q < BM / 16; ++q) {
+      int el = tid + 256 * q;
+      int ii = a.ta ? el >> 4 : el % BM, kk = a.ta ? el & 15 : el / BM;
       double av = 0.0;
       if (i0 + ii < a.M && k0 + kk < kend) {
         av = a.ta ? A[(k0 + kk) + (long long)a.lda * (i0 + ii)] : A[(i0 + ii) + (long long)a.lda * (k0 + kk)];
         if (ksv) av *= ksv[k0 + kk];
       }
-      As[kk * 65 + ii] = av;
-      int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
+      As[kk * (BM + 1) + ii] = av;
+    }
+    // op(B) tile (kb, jj): contiguous along kb when tb == 0, along jj when tb == 1
+#pragma unroll
+    for (int q = 0; q < BN / 16; ++q) {
+      int el = tid + 256 * q;
+      int jj = a.tb ? el % BN : el >> 4, kb = a.tb ? el / BN : el & 15;
       double bv = 0.0;
       if (j0 + jj < a.N && k0 + kb < kend)
         bv = a.tb ? B[(j0 + jj) + (long long)a.ldb * (k0 + kb)] : B[(k0 + kb) + (long long)a.ldb * (j0 + jj)];
-      Bs[kb * 65 + jj] = bv;
+      Bs[kb * (BN + 1) + jj] = bv;
     }
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       int kk = ks * 4 + (lane >> 4);
-      double a0 = As[kk * 65 + wi * 32 + (lane & 15)];
-      double a1 = As[kk * 65 + wi * 32 + 16 + (lane & 15)];
-      double b0 = Bs[kk * 65 + wj * 32 + (lane & 15)];
-      double b1 = Bs[kk * 65 + wj * 32 + 16 + (lane & 15)];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double fa[MB], fb[NB];
+#pragma unroll
+      for (int x = 0; x < MB; ++x) fa[x] = As[kk * (BM + 1) + wi * (BM / 2) + x * 16 + (lane & 15)];
+#pragma unroll
+      for (int y = 0; y < NB; ++y) fb[y] = Bs[kk * (BN + 1) + wj * (BN / 2) + y * 16 + (lane & 15)];
+#pragma unroll
+      for (int x = 0; x < MB; ++x)
+#pragma unroll
+        for (int y = 0; y < NB; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[x], fb[y], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
   double* C = a.C + a.sc * bi;
   double* P = a.part + ((long long)kc * a.batch + bi) * a.M * a.N;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < MB; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < NB; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = i0 + wi * 32 + x * 16 + 4 * r + (lane >> 4);
-        int j = j0 + wj * 32 + y * 16 + (lane & 15);
+        int i = i0 + wi * (BM / 2) + x * 16 + 4 * r + (lane >> 4);
+        int j = j0 + wj * (BN / 2) + y * 16 + (lane & 15);
         if (i < a.M && j < a.N) {
           if (a.ksplit > 1) {
             P[i + (long long)a.M * j] = acc[x][y][r];
@@ -525,6 +535,11 @@ dg_bgemm(BgArgs a) {
         }
       }
 }
+
+extern "C" __global__ void __launch_bounds__(256) dg_bgemm(BgArgs a) { bgemm_tile<64, 64>(a); }
+extern "C" __global__ void __launch_bounds__(256) dg_bgemm_m32(BgArgs a) { bgemm_tile<32, 64>(a); }
+extern "C" __global__ void __launch_bounds__(256) dg_bgemm_n32(BgArgs a) { bgemm_tile<64, 32>(a); }
+extern "C" __global__ void __launch_bounds__(256) dg_bgemm_s32(BgArgs a) { bgemm_tile<32, 32>(a); }
 
 // C_b = alpha * cs-scaled sum over chunks of the partials + beta C_b; one
 // thread per output entry.
