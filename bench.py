@@ -312,9 +312,9 @@ def main():
     sym = max(float((v.reshape(n, n) - v.reshape(n, n).T).abs().max())
               for v, n in zip(torch.split(vol, [n * n for n in nal]), nal))
     dgb = dict(density_ms=round(1e3 * (t2 - t1), 3), nonlocal_block_ms=round(1e3 * (t3 - t2), 3),
-               electrons_check=round(float(sum(
+               electrons_check=round(sum(
                    e.dv * float(r.sum()) for e, r in zip(els, torch.split(rho, [x["ne"] for x in h.sizes])))
-                   / (2.0 * sum(nal)), 12)),
+                   / (2.0 * sum(nal)), 12),
                volume_ms=round(1e3 * (t5 - t4), 3),
                volume_bgemm=dict(launches=bg["launches"], ms=round(bg["ms"], 3),
                                  gflop=round(bg["flops"] / 1e9, 2), tflops=round(bg_tf, 2),
