@@ -434,20 +434,115 @@ __host__ __device__ void gemm_fast(T& t, int ta, int tb, int m, int n, int k, do
 // Householder tridiagonalisation reading and updating only the lower
 // triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
 // scratch of n doubles each (LDS on the device).
+// One Householder step of the device fast path of tridiagonalize_lower on the
+// trailing block A2 (m x m, lower triangle): p = tk A2 v, q = p - (tk/2)(v.p) v,
+// A2 -= v q^T + q v^T.  Each lane keeps R rows (m <= 64 R) of v, q and its
+// share of the row sums in registers; each wave takes U columns per pass so
+// that their loads are in flight together.  Every entry is read once for
+// both halves of the symmetric product; per-wave partial sums are added in
+// a fixed order.  scratch: (waves + 1) * n doubles.
+template <int R, int U, class T>
+__device__ __forceinline__ void tri_fast_step(T& t, double* A2, int lda, int n, int m,
+                                              const double* v, double* p, double* scratch,
+                                              double tk) {
+  const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  double* pc = scratch;          // column parts, one writer per entry
+  double* part = scratch + n;    // per-wave row parts
+  double vr[R], acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int i = lane + 64 * r;
+    vr[r] = i < m ? v[i] : 0.0;
+    acc[r] = 0.0;
+  }
+  for (int j0 = wv; j0 < m; j0 += U * nw) {
+    double x[U][R], vj[U], sm[U];
+    int jj[U];
+    bool has[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      jj[u] = j0 + u * nw;
+      has[u] = jj[u] < m;
+      vj[u] = has[u] ? v[jj[u]] : 0.0;
+      const double* col = A2 + (long long)lda * (has[u] ? jj[u] : j0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int i = lane + 64 * r;
+        x[u][r] = (has[u] && i >= jj[u] && i < m) ? col[i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sm[u] = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int i = lane + 64 * r;
+        if (has[u] && i >= jj[u] && i < m) {
+          sm[u] += x[u][r] * vr[r];
+          if (i > jj[u]) acc[r] += x[u][r] * vj[u];
+        }
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) sm[u] += __shfl_xor(sm[u], o, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (has[u]) pc[jj[u]] = sm[u];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int i = lane + 64 * r;
+    if (i < m) part[(long long)wv * n + i] = acc[r];
+  }
+  t.sync();
+  for (int i = t.tid(); i < m; i += t.nt()) {
+    double s = pc[i];
+    for (int w = 0; w < nw; ++w) s += part[(long long)w * n + i];
+    p[i] = s;
+  }
+  t.sync();
+  double vp = 0.0;
+  for (int i = t.tid(); i < m; i += t.nt()) { p[i] *= tk; vp += v[i] * p[i]; }
+  double K = 0.5 * tk * t.sum(vp);
+  for (int i = t.tid(); i < m; i += t.nt()) p[i] -= K * v[i];   // p := q
+  t.sync();
+  double qr[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    int i = lane + 64 * r;
+    qr[r] = i < m ? p[i] : 0.0;
+  }
+  for (int j0 = wv; j0 < m; j0 += U * nw) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = j0 + u * nw;
+      if (j >= m) break;
+      const double vj = v[j], qj = p[j];
+      double* col = A2 + (long long)lda * j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int i = lane + 64 * r;
+        if (i >= j && i < m) col[i] -= vr[r] * qj + qr[r] * vj;
+      }
+    }
+  }
+  t.sync();
+}
+
 template <class T>
 __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
                                               double* tau, double* v, double* p,
                                               double* scratch = nullptr, int scratch_size = 0) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-  // Device path for n <= 64 * TRI_R with (waves + 1) * n doubles of LDS
-  // scratch: every trailing-block entry is read once per step for both
-  // halves of the symmetric product p = A2 v (column dot for the part on and
-  // below the diagonal, register axpy per wave for the part above, summed in
-  // a fixed order), and each lane keeps its rows of v and q in registers for
-  // the rank-2 update.
-  constexpr int TRI_R = 12;
+  // Device path (tri_fast_step) for n <= 768 with (waves + 1) * n doubles of
+  // LDS scratch: 6 rows per lane and two columns per wave pass up to n = 384,
+  // else 12 rows per lane and one column per pass.
   bool fast = false;
-  if constexpr (T::is_device) fast = n <= 64 * TRI_R && scratch && (nw + 1) * n <= scratch_size;
+  if constexpr (T::is_device) fast = n <= 64 * 12 && scratch && (nw + 1) * n <= scratch_size;
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     double part = 0.0;
@@ -469,64 +564,8 @@ __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, d
     if constexpr (T::is_device) {
       if (fast) {
         double* A2 = &IDX(A, lda, k + 1, k + 1);
-        double* pc = scratch;          // column parts, one writer per entry
-        double* part = scratch + n;    // per-wave row parts
-        double vr[TRI_R], acc[TRI_R];
-#pragma unroll
-        for (int r = 0; r < TRI_R; ++r) {
-          int i = lane + 64 * r;
-          vr[r] = i < m ? v[i] : 0.0;
-          acc[r] = 0.0;
-        }
-        for (int j = wv; j < m; j += nw) {
-          const double vj = v[j];
-          const double* col = A2 + (long long)lda * j;
-          double s = 0.0;
-#pragma unroll
-          for (int r = 0; r < TRI_R; ++r) {
-            int i = lane + 64 * r;
-            if (i >= j && i < m) {
-              double a = col[i];
-              s += a * vr[r];
-              if (i > j) acc[r] += a * vj;
-            }
-          }
-          for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-          if (lane == 0) pc[j] = s;
-        }
-#pragma unroll
-        for (int r = 0; r < TRI_R; ++r) {
-          int i = lane + 64 * r;
-          if (i < m) part[(long long)wv * n + i] = acc[r];
-        }
-        t.sync();
-        for (int i = t.tid(); i < m; i += t.nt()) {
-          double s = pc[i];
-          for (int w = 0; w < nw; ++w) s += part[(long long)w * n + i];
-          p[i] = s;
-        }
-        t.sync();
-        double vp = 0.0;
-        for (int i = t.tid(); i < m; i += t.nt()) { p[i] *= tk; vp += v[i] * p[i]; }
-        double K = 0.5 * tk * t.sum(vp);
-        for (int i = t.tid(); i < m; i += t.nt()) p[i] -= K * v[i];   // p := q
-        t.sync();
-        double qr[TRI_R];
-#pragma unroll
-        for (int r = 0; r < TRI_R; ++r) {
-          int i = lane + 64 * r;
-          qr[r] = i < m ? p[i] : 0.0;
-        }
-        for (int j = wv; j < m; j += nw) {
-          const double vj = v[j], qj = p[j];
-          double* col = A2 + (long long)lda * j;
-#pragma unroll
-          for (int r = 0; r < TRI_R; ++r) {
-            int i = lane + 64 * r;
-            if (i >= j && i < m) col[i] -= vr[r] * qj + qr[r] * vj;
-          }
-        }
-        t.sync();
+        if (n <= 64 * 6) tri_fast_step<6, 2>(t, A2, lda, n, m, v, p, scratch, tk);
+        else tri_fast_step<12, 1>(t, A2, lda, n, m, v, p, scratch, tk);
         continue;
       }
     }
