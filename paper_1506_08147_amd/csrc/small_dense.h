@@ -124,8 +124,33 @@ __host__ __device__ void gemm(T& t, int ta, int tb, int m, int n, int k, double 
 // In-place Cholesky A = L L^T of the symmetric matrix A (full storage).  On
 // return the lower triangle holds L.  Returns 0 if some pivot L_kk^2 <= tol
 // (relative to the unit diagonal the callers scale to), else 1.
+// Device form: the trailing update goes one column per wave, lanes along the
+// rows (no index arithmetic per entry); same operations per entry.
+template <class T>
+__device__ int chol_lower_dev(T& t, double* A, int lda, int n, double tol) {
+  const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  int ok = 1;
+  for (int k = 0; k < n; ++k) {
+    double akk = IDX(A, lda, k, k);
+    if (!(akk > tol)) { ok = 0; break; }   // uniform across the team
+    double d = sqrt(akk);
+    t.sync();
+    for (int i = k + 1 + t.tid(); i < n; i += t.nt()) IDX(A, lda, i, k) /= d;
+    if (t.tid() == 0) IDX(A, lda, k, k) = d;
+    t.sync();
+    for (int j = k + 1 + wv; j < n; j += nw) {
+      const double ajk = IDX(A, lda, j, k);
+      for (int i = j + lane; i < n; i += 64) IDX(A, lda, i, j) -= IDX(A, lda, i, k) * ajk;
+    }
+    t.sync();
+  }
+  t.sync();
+  return ok;
+}
+
 template <class T>
 __host__ __device__ int chol_lower(T& t, double* A, int lda, int n, double tol) {
+  if constexpr (T::is_device) return chol_lower_dev(t, A, lda, n, tol);
   int ok = 1;
   for (int k = 0; k < n; ++k) {
     double akk = IDX(A, lda, k, k);
@@ -166,8 +191,61 @@ __host__ __device__ void tri_inv_lower(T& t, const double* L, int ldl, double* X
 // sum_{l<k} L[k][l] X[l][j]) / L[k][k], with thread j owning column j of
 // L^-1 stored as row j of Y.  All threads read the same L[k][l] at the same
 // time and neighbouring threads neighbouring entries of Y.
+// Device form: rows of L^-1 in blocks of B (B n <= 4096 doubles of L staged
+// in LDS); thread j carries the block's entries of its column in registers
+// and reads its earlier entries once per block.  Terms are summed in the same
+// order as below (ascending l, the structural zeros l < j skipped).
+template <class T>
+__device__ void tri_inv_lower_t_dev(T& t, const double* L, int ldl, double* Y, int ldy, int n) {
+  constexpr int LS = 4096, BMAX = 16;
+  __shared__ double Ls[LS];
+  int B = LS / n;
+  B = B > BMAX ? BMAX : B;
+  for (int k0 = 0; k0 < n; k0 += B) {
+    const int kb = n - k0 < B ? n - k0 : B, w = k0 + kb;
+    for (int p = t.tid(); p < kb * w; p += t.nt()) {
+      int kk = p / w, l = p - kk * w;
+      Ls[p] = IDX(L, ldl, k0 + kk, l);
+    }
+    t.sync();
+    for (int j = t.tid(); j < n; j += t.nt()) {
+      double s[BMAX];
+#pragma unroll
+      for (int kk = 0; kk < BMAX; ++kk) s[kk] = (k0 + kk == j) ? 1.0 : 0.0;
+      if (j < w) {
+        for (int l = j; l < k0; ++l) {
+          const double x = IDX(Y, ldy, j, l);
+#pragma unroll
+          for (int kk = 0; kk < BMAX; ++kk)
+            if (kk < kb) s[kk] -= Ls[kk * w + l] * x;
+        }
+#pragma unroll
+        for (int kk = 0; kk < BMAX; ++kk) {
+          if (kk < kb) {
+            if (k0 + kk >= j) {
+#pragma unroll
+              for (int kq = 0; kq < BMAX; ++kq)
+                if (kq < kk && k0 + kq >= j) s[kk] -= Ls[kk * w + k0 + kq] * s[kq];
+              s[kk] /= Ls[kk * w + k0 + kk];
+            } else {
+              s[kk] = 0.0;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < BMAX; ++kk)
+        if (kk < kb) IDX(Y, ldy, j, k0 + kk) = j < w ? s[kk] : 0.0;
+    }
+    t.sync();
+  }
+}
+
 template <class T>
 __host__ __device__ void tri_inv_lower_t(T& t, const double* L, int ldl, double* Y, int ldy, int n) {
+  if constexpr (T::is_device) {
+    if (n <= 4096) { tri_inv_lower_t_dev(t, L, ldl, Y, ldy, n); return; }
+  }
   for (int j = t.tid(); j < n; j += t.nt()) {
     for (int k = 0; k < n; ++k) {
       double s = (k == j) ? 1.0 : 0.0;
@@ -961,58 +1039,89 @@ __host__ __device__ void tridiag_lowest(T& t, const double* d, const double* e, 
 // Z <- H_0 H_1 ... H_{n-3} Z for the reflectors left by the tridiagonalisation
 // (Z is n x k).  Reflectors go through LDS in blocks; on the device each wave
 // holds one column of Z in registers while it applies a block (n <= 768).
+// Device back-transformation Z := H_0 ... H_{n-3} Z for n <= 64 R: reflectors
+// staged in LDS sixteen at a time (applied last to first), each wave carries
+// U columns of Z in registers (R entries per lane) through a batch, so that
+// U independent dot-product chains share every reflector load.
+template <int R, int U, class T>
+__device__ __forceinline__ void bt_fast(T& t, const double* A, int lda, const double* tau, int n,
+                                        double* Z, int ldz, int k, double* lds, int lds_size) {
+  const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  int NB = lds_size / n;
+  NB = NB > 16 ? 16 : NB;
+  for (int kb = n - 3; kb >= 0; kb -= NB) {
+    int kl = kb - NB + 1 > 0 ? kb - NB + 1 : 0;   // reflectors kb, kb-1, ..., kl
+    // stage reflectors: lds[(kk - kl) * n + i] = v_kk[i] (zero above k+1)
+    for (int q = t.tid(); q < (kb - kl + 1) * n; q += t.nt()) {
+      int kk = kl + q / n, i = q % n;
+      lds[q] = (i >= kk + 1) ? A[(long long)i + (long long)lda * kk] : 0.0;
+    }
+    t.sync();
+    for (int j0 = wv; j0 < k; j0 += U * nw) {
+      double z[U][R];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * nw;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i = lane + 64 * r;
+          z[u][r] = (j < k && i < n) ? Z[(long long)i + (long long)ldz * j] : 0.0;
+        }
+      }
+      for (int kk = kb; kk >= kl; --kk) {
+        double tk = tau[kk];
+        if (tk == 0.0) continue;
+        const double* v = lds + (kk - kl) * n;
+        double vv[R], s[U];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i = lane + 64 * r;
+          vv[r] = i < n ? v[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          s[u] = 0.0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            int i = lane + 64 * r;
+            if (i < n) s[u] += vv[r] * z[u][r];
+          }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) s[u] += __shfl_xor(s[u], o, 64);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          s[u] *= tk;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            int i = lane + 64 * r;
+            if (i < n) z[u][r] -= s[u] * vv[r];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + u * nw;
+        if (j >= k) break;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i = lane + 64 * r;
+          if (i < n) Z[(long long)i + (long long)ldz * j] = z[u][r];
+        }
+      }
+    }
+    t.sync();
+  }
+}
+
 template <class T>
 __host__ __device__ void backtransform(T& t, const double* A, int lda, const double* tau, int n,
                                        double* Z, int ldz, int k, double* lds, int lds_size) {
-  constexpr int MAXR = 12;   // column entries per lane: n <= 64 * MAXR
   if constexpr (T::is_device) {
-    if (n <= 64 * MAXR) {
-      const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-      int NB = lds_size / n;
-      NB = NB > 16 ? 16 : NB;
-      for (int kb = n - 3; kb >= 0; kb -= NB) {
-        int kl = kb - NB + 1 > 0 ? kb - NB + 1 : 0;   // reflectors kb, kb-1, ..., kl
-        // stage reflectors: lds[(kk - kl) * n + i] = v_kk[i] (zero above k+1)
-        for (int q = t.tid(); q < (kb - kl + 1) * n; q += t.nt()) {
-          int kk = kl + q / n, i = q % n;
-          lds[q] = (i >= kk + 1) ? A[(long long)i + (long long)lda * kk] : 0.0;
-        }
-        t.sync();
-        for (int j = wv; j < k; j += nw) {
-          double z[MAXR];
-#pragma unroll
-          for (int r = 0; r < MAXR; ++r) {
-            int i = lane + 64 * r;
-            z[r] = i < n ? Z[(long long)i + (long long)ldz * j] : 0.0;
-          }
-          for (int kk = kb; kk >= kl; --kk) {
-            double tk = tau[kk];
-            if (tk == 0.0) continue;
-            const double* v = lds + (kk - kl) * n;
-            double s = 0.0;
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-              int i = lane + 64 * r;
-              if (i < n) s += v[i] * z[r];
-            }
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-            s *= tk;
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-              int i = lane + 64 * r;
-              if (i < n) z[r] -= s * v[i];
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < MAXR; ++r) {
-            int i = lane + 64 * r;
-            if (i < n) Z[(long long)i + (long long)ldz * j] = z[r];
-          }
-        }
-        t.sync();
-      }
-      return;
-    }
+    if (lds_size >= n && n <= 64 * 6) { bt_fast<6, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+    if (lds_size >= n && n <= 64 * 12) { bt_fast<12, 1>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
   }
   // generic path
   double* cs = lds;
