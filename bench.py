@@ -211,9 +211,9 @@ def main():
                          "eigenvectors, ALBs); reports element updates per second")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(extended elements shard across GPUs with no communication; see the design "
-              "notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the "
+              "extended elements would be split across GPUs, each solving its share with no "
+              "communication). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     if args.warm > 0 and args.warmup < 1:
