@@ -86,7 +86,8 @@ enum Flag {
   FL_STALLK,          // residual histories recorded for the Teter fallback
   FL_RR_NCHOL,        // Rayleigh-Ritz steps reduced through a Cholesky factor of M
   FL_RR_NSERIES,      // Rayleigh-Ritz steps reduced through the series for M^-1/2
-  FL_COUNT = 14
+  FL_CARRY,           // leading block of S^T S and S^T H S known from the last step (columns; 0: none)
+  FL_COUNT = 15
 };
 
 // Virtual slots resolved per element through its buffer parity:
@@ -154,11 +155,21 @@ enum SmallMat {
   SM_V,       // vectors d, e, w, ... (a few columns of length n)
   SM_W0,      // eigensolver workspace (two consecutive matrices)
   SM_W1,
+  SM_MC,      // [C D]^T M [C D]: S^T S block of [X' P'] for the next step (ld 2J)
+  SM_HC,      // [C D]^T Hh [C D]: S^T H S block of [X' P'] for the next step (ld 2J)
   SM_COUNT
 };
 
 __host__ __device__ inline double* sm(const Elem& e, int which) {
   return e.small + (long long)which * e.small_stride;
+}
+
+// Columns of the leading [X P] block of S^T S and S^T H S carried from the
+// last Rayleigh-Ritz step (0 when none, or when it does not match the
+// current basis: J without P, 2J with P).
+__device__ inline int carried_cols(const Elem& e) {
+  const int kc = e.fl[FL_CARRY];
+  return (kc > 0 && kc == (e.fl[FL_HASP] ? 2 : 1) * e.J) ? kc : 0;
 }
 
 // Find the position of blockIdx-linear work item `b` among active elements:

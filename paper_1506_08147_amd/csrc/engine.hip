@@ -113,6 +113,9 @@ struct dgdft_alb {
   int* h_fl = nullptr;
   long long sumJ = 0, sumNg = 0, sumNgJ = 0, sumAlb = 0, sumNalb = 0;
   bool potential_loaded = false;
+  // host mirror of FL_CARRY != 0: the element's last Rayleigh-Ritz step was
+  // on the full basis (used only for the work accounting of the Gram)
+  std::vector<char> carry_host;
   std::string err;
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
@@ -324,6 +327,15 @@ struct dgdft_alb {
         by += 8.0 * K * nn;
       }
     }
+    if (g.carry) {
+      // the carried [X P] block (kc columns) is not part of the product's work
+      for (int e : act) {
+        if (e >= (int)carry_host.size() || !carry_host[e]) continue;
+        double K = g.use_ne ? eh[e].ne : eh[e].ng;
+        double kc = (hasP_host(e) ? 2.0 : 1.0) * eh[e].J;
+        fl -= g.njob * K * kc * (kc + 1.0);
+      }
+    }
     pbeg(DGDFT_K_GRAM, fl, by);
     hipLaunchKernelGGL(dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, g);
     pend();
@@ -503,6 +515,22 @@ struct dgdft_alb {
     rr_one(act, dg_rr_dchol, SMALL_THREADS, single);
     // D <- D L^-T with SM_L = L^-T
     sgemm(act, single, 0, 0, SM_Z, 0, SM_L, 0, SM_C, 1, N, Jc, Jc, N, Jc, N, 1.0, 0.0, -1, 1);
+    // [C D]^T M [C D] and [C D]^T Hh [C D]: the [X' P'] blocks of the next
+    // step's S^T S and S^T H S (dg_carry_in), so its Gram skips them
+    const int J2 = 2;
+    sgemm(act, single, 0, 0, SM_M, 0, SM_C, 0, SM_U, 0, N, J2, N, N, N, N, 1.0, 0.0, -1);
+    sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_MC, 0, J2, J2, N, N, N, J2, 1.0, 0.0, -1);
+    sgemm(act, single, 0, 0, SM_H, 0, SM_C, 0, SM_U, 0, N, J2, N, N, N, N, 1.0, 0.0, -1);
+    sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_HC, 0, J2, J2, N, N, N, J2, 1.0, 0.0, -1);
+  }
+
+  void carry_in(const std::vector<int>& act) {
+    auto P = make_prefix(act, [](int) { return 1; });
+    if (P.na == 0) return;
+    pbeg(DGDFT_K_RR, 0, 0);
+    hipLaunchKernelGGL(dg_carry_in, dim3(P.na), dim3(256), 0, stream, ed, P.active, P.na);
+    pend();
+    HCHECK(hipGetLastError());
   }
 
   // Pair log: bands [i0, i0 + cnt) of every element in `act`.
@@ -774,6 +802,7 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     return DGDFT_EUNSUPPORTED;
   }
   h->n = n_elem;
+  h->carry_host.assign(n_elem, 0);
   h->eh.assign(n_elem, Elem{});
   // ---- validate shapes, fill host descriptors
   long long offng = 0, offngj = 0, offj = 0, offalb = 0, offnalb = 0, offne = 0, offnl = 0;
@@ -1184,6 +1213,7 @@ static std::vector<int> all_elems(int n) {
 // Rayleigh-Ritz on the current X alone and rotation of X, HX (initial and
 // final steps), then the residual norms.
 static void rr_on_x(dgdft_alb* h, const std::vector<int>& act) {
+  for (int e : act) h->carry_host[e] = 0;
   GramArgs g{};
   g.A = dgdft_alb::opnd({VS_X});
   g.B[0] = dgdft_alb::opnd({VS_X});
@@ -1316,8 +1346,9 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   g3.A = dgdft_alb::opnd({VS_X, VS_P, S_W2}, {0, 1, 0});
   g3.B[0] = g3.A;
   g3.B[1] = dgdft_alb::opnd({VS_HX, VS_HP, S_HW}, {0, 1, 0});
-  g3.njob = 2; g3.out_mat[0] = SM_M; g3.out_mat[1] = SM_H; g3.upper = 1;
+  g3.njob = 2; g3.out_mat[0] = SM_M; g3.out_mat[1] = SM_H; g3.upper = 1; g3.carry = 1;
   h->gram(act, g3);
+  h->carry_in(act);
   h->per_elem(act, 1, 0);
   UpdArgs u3{};
   u3.A[0] = g3.A;
@@ -1327,6 +1358,7 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
   h->update(act, u3);
   h->per_elem(act, 3, 0);
+  for (int e : act) h->carry_host[e] = 1;
 }
 
 // Graph mode: K iterations (each followed by the residual step) of the

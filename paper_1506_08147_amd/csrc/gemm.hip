@@ -30,6 +30,7 @@ struct GramArgs {
   int out_mat[2];  // small-workspace matrix receiving each product
   int upper;       // only tiles touching the upper triangle
   int use_ne;      // K = rows of the restriction box instead of N_g
+  int carry;       // skip tiles inside the leading block carried from the last step
 };
 
 struct UpdArgs {
@@ -85,6 +86,12 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   int chunk = w / ntile, tile = w - chunk * ntile;
   int ti, tj;
   gram_tile_decode(tile, m, n, g.upper, &ti, &tj);
+  if (g.carry) {
+    // the [X P] block of both products is formed from the last step's small
+    // matrices (dg_carry_in); tiles wholly inside it are not computed
+    const int kc = carried_cols(e);
+    if ((ti + 1) * TT <= kc && (tj + 1) * TT <= kc) return;
+  }
   const int kbeg = chunk * clen;
   const int kend = min(K, kbeg + clen);
   const int tid = threadIdx.x;
@@ -342,7 +349,9 @@ struct SgArgs {
   int single;
 };
 
-__host__ __device__ inline int sg_dim(int code, int n, int J) { return code == 0 ? n : J; }
+__host__ __device__ inline int sg_dim(int code, int n, int J) {
+  return code == 0 ? n : (code == 2 ? 2 * J : J);
+}
 
 extern "C" __global__ void __launch_bounds__(256)
 dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,

@@ -178,6 +178,8 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   double* w = vec + 7 * n;
   sym_from_upper(t, H, n, n);
   sym_from_upper(t, M, n, n);
+  // a step on X alone (start, final check) leaves nothing to carry
+  if (single && t.tid() == 0) e.fl[FL_CARRY] = 0;
   if (!single) {
     double ef = 0.0;
     for (int p = t.tid(); p < n * n; p += t.nt()) {
@@ -270,6 +272,28 @@ dg_rr_form(Elem* __restrict__ E, const int* __restrict__ active, int na, int sin
   for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
     int i = p % n, j = p / n;
     A[p] = H[p] - 0.5 * (U[p] + U[j + (long long)n * i]);
+  }
+}
+
+// [X P] block of S^T S and S^T H S from the last step: with X' = S C and
+// P' = S D, [X' P']^T [X' P'] = [C D]^T M [C D] and likewise for H, which the
+// last step left in SM_MC and SM_HC.  Overwrites the leading kc x kc block of
+// both products (the tiles there were not computed).  One workgroup per
+// element.
+extern "C" __global__ void __launch_bounds__(256)
+dg_carry_in(Elem* __restrict__ E, const int* __restrict__ active, int na) {
+  const Elem& e = E[active[blockIdx.x]];
+  const int kc = carried_cols(e);
+  if (kc == 0) return;
+  const int n = (e.fl[FL_HASP] ? 3 : 2) * e.J, ldc = 2 * e.J;
+  double* M = sm(e, SM_M);
+  double* H = sm(e, SM_H);
+  const double* Mc = sm(e, SM_MC);
+  const double* Hc = sm(e, SM_HC);
+  for (int p = threadIdx.x; p < kc * kc; p += 256) {
+    int i = p % kc, j = p / kc;
+    M[i + (long long)n * j] = Mc[i + (long long)ldc * j];
+    H[i + (long long)n * j] = Hc[i + (long long)ldc * j];
   }
 }
 
@@ -385,10 +409,10 @@ dg_rr_dchol(Elem* __restrict__ E, const int* __restrict__ active, int na, int si
   if (pok) {
     tri_inv_lower_t(t, A, J, Lm, J, J);                                   // Lm = L^-T
     for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] /= dm[p / n];
-    if (t.tid() == 0) e.fl[FL_HASP_NEXT] = 1;
+    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 1; e.fl[FL_CARRY] = 2 * J; }
   } else {
     for (int p = t.tid(); p < n * J; p += t.nt()) Dn[p] = 0.0;
-    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 0; e.fl[FL_P_DROP] += 1; }
+    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 0; e.fl[FL_P_DROP] += 1; e.fl[FL_CARRY] = J; }
   }
   t.sync();
 }
