@@ -1358,7 +1358,9 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
   h->update(act, u3);
   h->per_elem(act, 3, 0);
-  for (int e : act) h->carry_host[e] = 1;
+  // the device carries the blocks while the residuals (polled before this
+  // iteration) are above CARRY_RES
+  for (int e : act) h->carry_host[e] = h->max_res(e) >= CARRY_RES;
 }
 
 // Graph mode: K iterations (each followed by the residual step) of the

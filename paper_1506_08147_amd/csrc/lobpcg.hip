@@ -156,6 +156,11 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
 // (Y, theta): lowest J eigenpairs of A from dg_rr_eig.
 constexpr double NEAR_ORTHO = 1e-8;
 constexpr double SERIES_ORTHO = 1e-4;
+// The [X P] Gram blocks formed from small matrices are used only while every
+// residual of the element is above CARRY_RES; closer to convergence both
+// products are formed in full over the grid (measured: carried blocks down
+// to the tolerance cost the slowest elements extra iterations).
+constexpr double CARRY_RES = 3e-5;
 
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
@@ -406,13 +411,16 @@ dg_rr_dchol(Elem* __restrict__ E, const int* __restrict__ active, int na, int si
     t.sync();
     pok = chol_lower(t, A, J, J, CHOL_TOL);
   }
+  double rmax = 0.0;
+  for (int i = t.tid(); i < J; i += t.nt()) rmax = fmax(rmax, e.resid[i]);
+  const bool carry = t.maxv(rmax) >= CARRY_RES;
   if (pok) {
     tri_inv_lower_t(t, A, J, Lm, J, J);                                   // Lm = L^-T
     for (int p = t.tid(); p < n * J; p += t.nt()) Ez[p] /= dm[p / n];
-    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 1; e.fl[FL_CARRY] = 2 * J; }
+    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 1; e.fl[FL_CARRY] = carry ? 2 * J : 0; }
   } else {
     for (int p = t.tid(); p < n * J; p += t.nt()) Dn[p] = 0.0;
-    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 0; e.fl[FL_P_DROP] += 1; e.fl[FL_CARRY] = J; }
+    if (t.tid() == 0) { e.fl[FL_HASP_NEXT] = 0; e.fl[FL_P_DROP] += 1; e.fl[FL_CARRY] = carry ? J : 0; }
   }
   t.sync();
 }
