@@ -464,8 +464,8 @@ __device__ __forceinline__ double bg_colscale(const BgArgs& a, int bi, int j) {
 template <int BM, int BN>
 __device__ __forceinline__ void bgemm_tile(const BgArgs& a) {
   constexpr int MB = BM / 32, NB = BN / 32;
-  __shared__ double As[16 * (BM + 1)];
-  __shared__ double Bs[16 * (BN + 1)];
+  __shared__ double As[2][16 * (BM + 1)];
+  __shared__ double Bs[2][16 * (BN + 1)];
   const int ntm = cdiv(a.M, BM), ntn = cdiv(a.N, BN);
   const long long blk = blockIdx.x;
   const int t = (int)(blk % (ntm * ntn));
@@ -483,8 +483,11 @@ __device__ __forceinline__ void bgemm_tile(const BgArgs& a) {
   for (int x = 0; x < MB; ++x)
 #pragma unroll
     for (int y = 0; y < NB; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    // op(A) tile (ii, kk): contiguous along ii when ta == 0, along kk when ta == 1
+  // stage k0 -> registers; op(A) tile (ii, kk) contiguous along ii when
+  // ta == 0, along kk when ta == 1; op(B) tile (kb, jj) along kb when tb == 0,
+  // along jj when tb == 1
+  double ra[BM / 16], rb[BN / 16];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < BM / 16; ++q) {
       int el = tid + 256 * q;
@@ -494,9 +497,8 @@ __device__ __forceinline__ void bgemm_tile(const BgArgs& a) {
         av = a.ta ? A[(k0 + kk) + (long long)a.lda * (i0 + ii)] : A[(i0 + ii) + (long long)a.lda * (k0 + kk)];
         if (ksv) av *= ksv[k0 + kk];
       }
-      As[kk * (BM + 1) + ii] = av;
+      ra[q] = av;
     }
-    // op(B) tile (kb, jj): contiguous along kb when tb == 0, along jj when tb == 1
 #pragma unroll
     for (int q = 0; q < BN / 16; ++q) {
       int el = tid + 256 * q;
@@ -504,23 +506,49 @@ __device__ __forceinline__ void bgemm_tile(const BgArgs& a) {
       double bv = 0.0;
       if (j0 + jj < a.N && k0 + kb < kend)
         bv = a.tb ? B[(j0 + jj) + (long long)a.ldb * (k0 + kb)] : B[(k0 + kb) + (long long)a.ldb * (j0 + jj)];
-      Bs[kb * (BN + 1) + jj] = bv;
+      rb[q] = bv;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < BM / 16; ++q) {
+      int el = tid + 256 * q;
+      int ii = a.ta ? el >> 4 : el % BM, kk = a.ta ? el & 15 : el / BM;
+      As[buf][kk * (BM + 1) + ii] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < BN / 16; ++q) {
+      int el = tid + 256 * q;
+      int jj = a.tb ? el % BN : el >> 4, kb = a.tb ? el / BN : el & 15;
+      Bs[buf][kb * (BN + 1) + jj] = rb[q];
+    }
+  };
+  // double-buffered: stage s + 1 is read from global memory into registers
+  // while stage s is multiplied out of LDS; one barrier per stage
+  const int nst = kend > kbeg ? (kend - kbeg + 15) / 16 : 0;
+  if (nst > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load(kbeg + 16 * (st + 1));
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       int kk = ks * 4 + (lane >> 4);
       double fa[MB], fb[NB];
 #pragma unroll
-      for (int x = 0; x < MB; ++x) fa[x] = As[kk * (BM + 1) + wi * (BM / 2) + x * 16 + (lane & 15)];
+      for (int x = 0; x < MB; ++x) fa[x] = As[cur][kk * (BM + 1) + wi * (BM / 2) + x * 16 + (lane & 15)];
 #pragma unroll
-      for (int y = 0; y < NB; ++y) fb[y] = Bs[kk * (BN + 1) + wj * (BN / 2) + y * 16 + (lane & 15)];
+      for (int y = 0; y < NB; ++y) fb[y] = Bs[cur][kk * (BN + 1) + wj * (BN / 2) + y * 16 + (lane & 15)];
 #pragma unroll
       for (int x = 0; x < MB; ++x)
 #pragma unroll
         for (int y = 0; y < NB; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[x], fb[y], acc[x][y], 0, 0, 0);
     }
+    if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
   }
   double* C = a.C + a.sc * bi;
