@@ -337,7 +337,8 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
 // all three in the element's small workspace.  Dimensions and leading
 // dimensions are given as codes resolved per element: 0 -> n = kJ (k = 1
 // for the step on X alone, else 2 or 3 by the presence of P), 1 -> J.
-// 64 x 64 tiles, four waves of 32 x 32, 16-deep K stages through LDS.
+// 64 x 64 tiles, four waves of 32 x 32, 16-deep K stages double-buffered
+// through LDS with the next stage prefetched into registers.
 struct SgArgs {
   int ta, tb;
   int ma, oa, mb, ob, mc, oc;    // small-workspace matrix and column offset (in J)
@@ -356,8 +357,8 @@ __host__ __device__ inline int sg_dim(int code, int n, int J) {
 extern "C" __global__ void __launch_bounds__(256)
 dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
          int na, SgArgs a) {
-  __shared__ double As[16 * 65];
-  __shared__ double Bs[16 * 65];
+  __shared__ double As[2][16 * 65];
+  __shared__ double Bs[2][16 * 65];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
   const Elem& e = E[active[ai]];
@@ -381,38 +382,60 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  // stage k0 -> registers (op(A) tile contiguous along i when ta == 0,
+  // along kk when ta == 1; op(B) along kk when tb == 0, along j when tb == 1)
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int el = tid + 256 * q;          // 0..1023 over a 64 x 16 tile
       int f = el & 63, s16 = el >> 6;  // f: 64-long fast index, s16: 16-long
       int g = el & 15, s64 = el >> 4;  // g: 16-long fast index, s64: 64-long
-      // op(A) tile (i, kk): contiguous along i when ta == 0, along kk when ta == 1
       int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
-      double av = 0.0;
-      if (i0 + ii < M && k0 + kk < K)
-        av = a.ta ? A[(k0 + kk) + (long long)lda * (i0 + ii)] : A[(i0 + ii) + (long long)lda * (k0 + kk)];
-      As[kk * 65 + ii] = av;
-      // op(B) tile (kk, jj): contiguous along kk when tb == 0, along jj when tb == 1
+      ra[q] = (i0 + ii < M && k0 + kk < K)
+                  ? (a.ta ? A[(k0 + kk) + (long long)lda * (i0 + ii)] : A[(i0 + ii) + (long long)lda * (k0 + kk)])
+                  : 0.0;
       int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
-      double bv = 0.0;
-      if (j0 + jj < N && k0 + kb < K)
-        bv = a.tb ? B[(j0 + jj) + (long long)ldb * (k0 + kb)] : B[(k0 + kb) + (long long)ldb * (j0 + jj)];
-      Bs[kb * 65 + jj] = bv;
+      rb[q] = (j0 + jj < N && k0 + kb < K)
+                  ? (a.tb ? B[(j0 + jj) + (long long)ldb * (k0 + kb)] : B[(k0 + kb) + (long long)ldb * (j0 + jj)])
+                  : 0.0;
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int el = tid + 256 * q;
+      int f = el & 63, s16 = el >> 6;
+      int g = el & 15, s64 = el >> 4;
+      int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
+      As[buf][kk * 65 + ii] = ra[q];
+      int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
+      Bs[buf][kb * 65 + jj] = rb[q];
+    }
+  };
+  // double-buffered K stages, the next one prefetched into registers
+  const int nst = (K + 15) / 16;
+  if (nst > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load(16 * (st + 1));
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       int kk = ks * 4 + (lane >> 4);
-      double a0 = As[kk * 65 + wi * 32 + (lane & 15)];
-      double a1 = As[kk * 65 + wi * 32 + 16 + (lane & 15)];
-      double b0 = Bs[kk * 65 + wj * 32 + (lane & 15)];
-      double b1 = Bs[kk * 65 + wj * 32 + 16 + (lane & 15)];
+      double a0 = As[cur][kk * 65 + wi * 32 + (lane & 15)];
+      double a1 = As[cur][kk * 65 + wi * 32 + 16 + (lane & 15)];
+      double b0 = Bs[cur][kk * 65 + wj * 32 + (lane & 15)];
+      double b1 = Bs[cur][kk * 65 + wj * 32 + 16 + (lane & 15)];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
+    if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
@@ -460,7 +483,8 @@ __device__ __forceinline__ double bg_colscale(const BgArgs& a, int bi, int j) {
 
 // BM x BN output tile per workgroup (64 or 32 each, so that thin operands
 // do not pay for a 64-wide tile); four waves in a 2 x 2 grid, each with
-// (BM/32) x (BN/32) MFMA blocks of 16 x 16; 16-deep K stages through LDS.
+// (BM/32) x (BN/32) MFMA blocks of 16 x 16; 16-deep K stages double-buffered
+// through LDS.
 template <int BM, int BN>
 __device__ __forceinline__ void bgemm_tile(const BgArgs& a) {
   constexpr int MB = BM / 32, NB = BN / 32;
