@@ -142,3 +142,22 @@ def test_volume_block_full_size_slab_elements():
     h = _handle(els, dev)
     _volume_check(h, els, psis, albs, sigmas, dev)
     h.close()
+
+
+def test_volume_block_rejects_bad_arguments():
+    """An LGL ratio outside 1..8 is an EINVAL with a message (checked before
+    any launch)."""
+    import torch
+    from paper_1506_08147_amd.binding import DGDFTError
+    dev = torch.device("cuda:0")
+    e = synth.single_element(seed=35, grid=(12, 12, 12), n_states=4, n_atoms=1)
+    h = _handle([e], dev)
+    psi = torch.zeros(e.ng * e.n_states, dtype=torch.float64, device=dev)
+    ne = int(np.prod(np.subtract(e.elem_hi, e.elem_lo)))
+    albs = torch.zeros(ne * e.n_alb, dtype=torch.float64, device=dev)
+    sigma = torch.ones(e.n_alb, dtype=torch.float64, device=dev)
+    for ratio in (0, 9, -1):
+        with pytest.raises(DGDFTError) as err:
+            h.dg_volume(psi, albs, sigma, ratio)
+        assert err.value.code == -1 and "lgl_ratio" in str(err.value)
+    h.close()
