@@ -509,32 +509,36 @@ __host__ __device__ void gemm_fast(T& t, int ta, int tb, int m, int n, int k, do
   }
 }
 
-// Householder tridiagonalisation reading and updating only the lower
-// triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
-// scratch of n doubles each (LDS on the device).
-// One Householder step of the device fast path of tridiagonalize_lower on the
-// trailing block A2 (m x m, lower triangle): p = tk A2 v, q = p - (tk/2)(v.p) v,
-// A2 -= v q^T + q v^T.  Each lane keeps R rows (m <= 64 R) of v, q and its
-// share of the row sums in registers; each wave takes U columns per pass so
-// that their loads are in flight together.  Every entry is read once for
-// both halves of the symmetric product; per-wave partial sums are added in
-// a fixed order.  scratch: (waves + 1) * n doubles.
+// Device fast path of tridiagonalize_lower with one pass over the trailing
+// block per Householder step: the rank-2 update left by reflector k-1 and the
+// symmetric product of reflector k (p = tk A2 v) read and write every entry
+// of A2 = A[k+1:, k+1:] once.  Column k itself is updated first, separately,
+// since reflector k is built from it.  Each entry gets the same operations in
+// the same order as with a separate product pass and update pass, so the
+// outputs are those of that two-pass form.  Each lane keeps R rows
+// (m <= 64 R) of both reflectors, q and its share of the row sums in
+// registers; each wave takes U columns per pass so that their loads are in
+// flight together; per-wave partial sums are added in a fixed order.  v, p:
+// n doubles each; scratch: (waves + 2) * n doubles (column parts, per-wave
+// row parts, second v buffer).
 template <int R, int U, class T>
-__device__ __forceinline__ void tri_fast_step(T& t, double* A2, int lda, int n, int m,
-                                              const double* v, double* p, double* scratch,
-                                              double tk) {
+__device__ __forceinline__ void tri_fused_pass(T& t, double* A2, int lda, int n, int m,
+                                               const double* v, const double* vo,
+                                               const double* qo, bool upd, double* scratch) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-  double* pc = scratch;          // column parts, one writer per entry
-  double* part = scratch + n;    // per-wave row parts
-  double vr[R], acc[R];
+  double* pc = scratch;
+  double* part = scratch + n;
+  double vr[R], acc[R], vor[R], qor[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     int i = lane + 64 * r;
     vr[r] = i < m ? v[i] : 0.0;
+    vor[r] = (upd && i < m) ? vo[i] : 0.0;
+    qor[r] = (upd && i < m) ? qo[i] : 0.0;
     acc[r] = 0.0;
   }
   for (int j0 = wv; j0 < m; j0 += U * nw) {
-    double x[U][R], vj[U], sm[U];
+    double x[U][R], vj[U], sm[U], voj[U], qoj[U];
     int jj[U];
     bool has[U];
 #pragma unroll
@@ -542,11 +546,27 @@ __device__ __forceinline__ void tri_fast_step(T& t, double* A2, int lda, int n, 
       jj[u] = j0 + u * nw;
       has[u] = jj[u] < m;
       vj[u] = has[u] ? v[jj[u]] : 0.0;
+      voj[u] = (upd && has[u]) ? vo[jj[u]] : 0.0;
+      qoj[u] = (upd && has[u]) ? qo[jj[u]] : 0.0;
       const double* col = A2 + (long long)lda * (has[u] ? jj[u] : j0);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         int i = lane + 64 * r;
         x[u][r] = (has[u] && i >= jj[u] && i < m) ? col[i] : 0.0;
+      }
+    }
+    if (upd) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        double* col = A2 + (long long)lda * (has[u] ? jj[u] : j0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          int i = lane + 64 * r;
+          if (has[u] && i >= jj[u] && i < m) {
+            x[u][r] -= vor[r] * qoj[u] + qor[r] * voj[u];
+            col[i] = x[u][r];
+          }
+        }
       }
     }
 #pragma unroll
@@ -576,51 +596,116 @@ __device__ __forceinline__ void tri_fast_step(T& t, double* A2, int lda, int n, 
     int i = lane + 64 * r;
     if (i < m) part[(long long)wv * n + i] = acc[r];
   }
-  t.sync();
-  for (int i = t.tid(); i < m; i += t.nt()) {
-    double s = pc[i];
-    for (int w = 0; w < nw; ++w) s += part[(long long)w * n + i];
-    p[i] = s;
-  }
-  t.sync();
-  double vp = 0.0;
-  for (int i = t.tid(); i < m; i += t.nt()) { p[i] *= tk; vp += v[i] * p[i]; }
-  double K = 0.5 * tk * t.sum(vp);
-  for (int i = t.tid(); i < m; i += t.nt()) p[i] -= K * v[i];   // p := q
-  t.sync();
-  double qr[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    int i = lane + 64 * r;
-    qr[r] = i < m ? p[i] : 0.0;
-  }
-  for (int j0 = wv; j0 < m; j0 += U * nw) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = j0 + u * nw;
-      if (j >= m) break;
-      const double vj = v[j], qj = p[j];
-      double* col = A2 + (long long)lda * j;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int i = lane + 64 * r;
-        if (i >= j && i < m) col[i] -= vr[r] * qj + qr[r] * vj;
-      }
-    }
+}
+
+// Lower-triangle rank-2 update B -= vo qo^T + qo vo^T of the mm x mm block B
+// (wave per column); the tail of the fused tridiagonalisation.
+template <class T>
+__device__ __forceinline__ void tri_rank2_tail(T& t, double* B, int lda, int mm, const double* vo,
+                                               const double* qo) {
+  const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  for (int j = wv; j < mm; j += nw) {
+    const double vj = vo[j], qj = qo[j];
+    double* col = B + (long long)lda * j;
+    for (int i = j + lane; i < mm; i += 64) col[i] -= vo[i] * qj + qo[i] * vj;
   }
   t.sync();
 }
 
+template <int R, int U, class T>
+__device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d, double* e,
+                                     double* tau, double* v, double* p, double* scratch) {
+  const int nw = (t.nt() + 63) >> 6;
+  double* vcur = v;
+  double* vold = scratch + (long long)(nw + 1) * n;
+  bool pend = false;   // reflector k-1's update of A[k:, k:] not yet applied (vold, q in p)
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double* colk = &IDX(A, lda, k, k);
+    // column k (rows k..n-1): pending update, then rows k+2.. into vcur[1..]
+    double part = 0.0;
+    {
+      const double vo0 = pend ? vold[0] : 0.0, qo0 = pend ? p[0] : 0.0;
+      for (int r = t.tid(); r <= m; r += t.nt()) {
+        int i = r + 2 <= m ? r + 2 : r - (m - 1);     // rows 2.. first, then 0 and 1
+        double a = colk[i];
+        if (pend) {
+          a -= vold[i] * qo0 + p[i] * vo0;
+          colk[i] = a;
+        }
+        if (i >= 2) {
+          vcur[i - 1] = a;
+          part += a * a;
+        }
+      }
+    }
+    double a2 = t.sum(part);
+    double x0 = colk[1];
+    if (a2 == 0.0) {
+      if (t.tid() == 0) { e[k] = x0; tau[k] = 0.0; }
+      if (pend) tri_rank2_tail(t, &IDX(A, lda, k + 1, k + 1), lda, m, vold + 1, p + 1);
+      pend = false;
+      t.sync();
+      continue;
+    }
+    double nrm = sqrt(x0 * x0 + a2);
+    double beta = (x0 >= 0.0) ? -nrm : nrm;
+    double v0 = x0 - beta;
+    double tk = 2.0 / (v0 * v0 + a2);
+    if (t.tid() == 0) vcur[0] = v0;
+    t.sync();                                       // every lane has read x0
+    if (t.tid() == 0) { colk[1] = v0; e[k] = beta; tau[k] = tk; }
+    double* A2 = &IDX(A, lda, k + 1, k + 1);
+    tri_fused_pass<R, U>(t, A2, lda, n, m, vcur, vold + 1, p + 1, pend, scratch);
+    t.sync();
+    {
+      const double* pc = scratch;
+      const double* pw = scratch + n;
+      for (int i = t.tid(); i < m; i += t.nt()) {
+        double s = pc[i];
+        for (int w = 0; w < nw; ++w) s += pw[(long long)w * n + i];
+        p[i] = s;
+      }
+    }
+    t.sync();
+    double vp = 0.0;
+    for (int i = t.tid(); i < m; i += t.nt()) { p[i] *= tk; vp += vcur[i] * p[i]; }
+    double K = 0.5 * tk * t.sum(vp);
+    for (int i = t.tid(); i < m; i += t.nt()) p[i] -= K * vcur[i];   // p := q
+    t.sync();
+    double* sw = vold;
+    vold = vcur;
+    vcur = sw;
+    pend = true;
+  }
+  if (pend) tri_rank2_tail(t, &IDX(A, lda, n - 2, n - 2), lda, 2, vold, p);
+  for (int i = t.tid(); i < n; i += t.nt()) d[i] = IDX(A, lda, i, i);
+  if (t.tid() == 0) {
+    if (n >= 2) e[n - 2] = IDX(A, lda, n - 1, n - 2);
+    if (n >= 1) e[n - 1] = 0.0;
+    if (n >= 2) tau[n - 2] = 0.0;
+  }
+  t.sync();
+}
+
+// Householder tridiagonalisation reading and updating only the lower
+// triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
+// scratch of n doubles each (LDS on the device).
 template <class T>
 __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
                                               double* tau, double* v, double* p,
                                               double* scratch = nullptr, int scratch_size = 0) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-  // Device path (tri_fast_step) for n <= 768 with (waves + 1) * n doubles of
-  // LDS scratch: 6 rows per lane and two columns per wave pass up to n = 384,
-  // else 12 rows per lane and one column per pass.
-  bool fast = false;
-  if constexpr (T::is_device) fast = n <= 64 * 12 && scratch && (nw + 1) * n <= scratch_size;
+  // Device path (tridiagonalize_fused) for n <= 768 with (waves + 2) * n
+  // doubles of LDS scratch: 6 rows per lane and two columns per wave pass up
+  // to n = 384, else 12 rows per lane and one column per pass.
+  if constexpr (T::is_device) {
+    if (n <= 64 * 12 && scratch && (nw + 2) * n <= scratch_size) {
+      if (n <= 64 * 6) tridiagonalize_fused<6, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
+      else tridiagonalize_fused<12, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
+      return;
+    }
+  }
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
     double part = 0.0;
@@ -639,14 +724,6 @@ __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, d
     for (int i = t.tid(); i < m; i += t.nt()) v[i] = (i == 0) ? v0 : IDX(A, lda, k + 1 + i, k);
     t.sync();
     if (t.tid() == 0) { IDX(A, lda, k + 1, k) = v0; e[k] = beta; tau[k] = tk; }
-    if constexpr (T::is_device) {
-      if (fast) {
-        double* A2 = &IDX(A, lda, k + 1, k + 1);
-        if (n <= 64 * 6) tri_fast_step<6, 2>(t, A2, lda, n, m, v, p, scratch, tk);
-        else tri_fast_step<12, 1>(t, A2, lda, n, m, v, p, scratch, tk);
-        continue;
-      }
-    }
     // p = A2 v with A2 the trailing block, lower triangle stored:
     //   rows:    sum_{j <= i} A2[i][j] v[j]       (thread per row, coalesced)
     for (int i = t.tid(); i < m; i += t.nt()) {
