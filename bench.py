@@ -28,9 +28,12 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of this
 # command, calibrated on a 1 GiB copy (profiles/slab64_fp64_hbm_traffic.md):
-# (kernel, workload, elements) -> bytes.  Valid for the kernel build that was
-# measured; set to None when the kernel changes.
-MEASURED_TRAFFIC = {("dg_update", "slab_36x36x60_J128", 64): 14.613e9}
+# (kernel, workload, elements, guard columns) -> bytes.  Valid for the kernel
+# build that was measured; removed when the kernel changes.
+MEASURED_TRAFFIC = {("dg_update", "slab_36x36x60_J128", 64, 0): 14.613e9}
+# guard columns per element when --guard is not given: 16 on the slab (block
+# of 144 columns, the tile width of the 144-wide GEMM kernels), else none
+DEFAULT_GUARD = {"slab": 16}
 
 
 def log(*a):
@@ -53,11 +56,11 @@ def workload(name, n_elem):
     return els, desc
 
 
-def cpu_baseline(el, gpu_iters, iters_sample):
-    """The oracle on one element of the same workload: a run stopped after 0
-    and after `iters_sample` iterations gives the set-up + final cost and the
-    cost per iteration; one converged solve is extrapolated to the iteration
-    count the element needs (`gpu_iters`), plus the ALB step."""
+def cpu_baseline(el, tol):
+    """The oracle on one element of the same workload: its LOBPCG (block of
+    the element's n_states columns, no guard columns) run to the tolerance,
+    then the restriction + SVD truncation; one converged element per that
+    time."""
     import numpy as np
     from oracle import alb, lobpcg as lob, teter
     from oracle.hamiltonian import FFT_WORKERS, Operator
@@ -69,24 +72,38 @@ def cpu_baseline(el, gpu_iters, iters_sample):
     op = Operator(el.grid, el.box, el.V, el.kb)
     pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
 
-    def run(k):
-        t = time.perf_counter()
-        res = lob.lobpcg(op.apply, pre, el.X0, 1e-6, k)
-        return time.perf_counter() - t, res
-
-    t0, res0 = run(0)
-    tk, _ = run(iters_sample)
-    per_it = max(tk - t0, 0.0) / iters_sample
     t = time.perf_counter()
-    alb.restrict_svd(res0.X, op.grid, el.elem_lo, el.elem_hi, op.dv, el.n_alb)
-    t_alb = time.perf_counter() - t
-    est = t0 + gpu_iters * per_it + t_alb
+    res = lob.lobpcg(op.apply, pre, el.X0, tol, 500)
+    t_solve = time.perf_counter() - t
+    alb.restrict_svd(res.X, op.grid, el.elem_lo, el.elem_hi, op.dv, el.n_alb)
+    est = time.perf_counter() - t
     return dict(value=1.0 / est, unit="elements/s", cores=int(max(FFT_WORKERS, blas)),
                 kind="oracle",
-                sample=(f"element 0 of the workload: oracle LOBPCG run for 0 and {iters_sample} "
-                        f"iterations ({t0:.1f} s, {tk:.1f} s), {per_it:.2f} s/iteration, "
-                        f"extrapolated to the {gpu_iters} iterations this element needs "
-                        f"+ ALB step ({t_alb:.2f} s): {est:.1f} s per converged element"))
+                sample=(f"element 0 of the workload: oracle LOBPCG to residual {tol:g} "
+                        f"({res.iters} iterations, converged={res.converged}, {t_solve:.1f} s) "
+                        f"+ ALB step: {est:.1f} s per converged element"))
+
+
+def start_block(els, n_guard, dev):
+    """X0 of the batch on the device: each element's seeded start columns,
+    then n_guard seeded guard columns."""
+    import numpy as np
+    import torch
+    import synth
+    parts = []
+    for k, e in enumerate(els):
+        parts.append(torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1))
+        if n_guard:
+            G = synth.guard_columns(e.ng, n_guard, (k, e.n_states))
+            parts.append(torch.from_numpy(np.ascontiguousarray(G.T)).reshape(-1))
+    return torch.cat(parts).to(dev)
+
+
+def make_handle(args, els, **kw):
+    from paper_1506_08147_amd import ALB
+    return ALB([e.grid for e in els], [e.box for e in els], [e.n_states + args.guard for e in els],
+               elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+               n_alb=[e.n_alb for e in els], n_guard=args.guard, **kw)
 
 
 def warm_mode(args, h, els, desc, V, kbt, out):
@@ -100,9 +117,7 @@ def warm_mode(args, h, els, desc, V, kbt, out):
     dev = V.device
     Vs = [torch.cat([torch.from_numpy(synth.perturbed_potential(e, s + 1)) for e in els]).to(dev)
           for s in range(args.warm)]
-    h3 = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=1e-14,
-             max_iter=3, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-             n_alb=[e.n_alb for e in els])
+    h3 = make_handle(args, els, tol=1e-14, max_iter=3)
     X = out["eigvecs"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -120,7 +135,8 @@ def warm_mode(args, h, els, desc, V, kbt, out):
                 steps=args.warm, warmup=0, ms_per_step=round(1e3 * el / args.warm, 2),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
                 data="synthetic", config=dict(desc, precision="fp64", preconditioner="teter",
-                                              warm_iterations=3, dV_amplitude=0.02),
+                                              warm_iterations=3, dV_amplitude=0.02,
+                                              guard_columns=args.guard),
                 residual_after_step=dict(max=float(max(res)), median=float(np.median(res))),
                 paper_context="1,185 element updates/s: 1,600 elements in 1.35 s on 12,800 CPU "
                               "cores (P3500 phosphorene, 80 ALBs per element); different "
@@ -134,9 +150,8 @@ def time_form(args, els, V, kbt, X0, precision, precond, w):
     import numpy as np
     import torch
     from paper_1506_08147_amd import ALB
-    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=args.tol,
-            max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-            n_alb=[e.n_alb for e in els], precision=precision, precond=precond, mlp_weights=w)
+    h = make_handle(args, els, tol=args.tol, max_iter=1000, precision=precision, precond=precond,
+                    mlp_weights=w)
     out = h.solve(V, kbt, X0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -193,7 +208,10 @@ def main():
     ap.add_argument("--elements", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--guard", type=int, default=None,
+                    help="guard columns per element: the block holds n_states + G columns, "
+                         "convergence and ALBs use the first n_states (default: 16 on the "
+                         "slab, 0 otherwise)")
     ap.add_argument("--graph", type=int, default=0,
                     help="LOBPCG iterations per captured HIP graph launch (0: eager)")
     ap.add_argument("--tune", type=int, default=0, help="1: autotune the Gram split-K at create")
@@ -210,6 +228,8 @@ def main():
                          "SCF-like steps (perturbed V, 3 LOBPCG iterations from the previous "
                          "eigenvectors, ALBs); reports element updates per second")
     args = ap.parse_args()
+    if args.guard is None:
+        args.guard = DEFAULT_GUARD.get(args.workload, 0)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the "
               "extended elements would be split across GPUs, each solving its share with no "
@@ -228,11 +248,9 @@ def main():
     log(f"inputs generated: {len(els)} elements in {time.perf_counter() - t:.1f} s")
     V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
     kbt = ALB.kb_batch([e.kb for e in els], dev)
-    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
-    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=args.tol,
-            max_iter=1000, elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-            n_alb=[e.n_alb for e in els], graph_iters=args.graph, tune=bool(args.tune),
-            precision=args.precision)
+    X0 = start_block(els, args.guard, dev)
+    h = make_handle(args, els, tol=args.tol, max_iter=1000, graph_iters=args.graph,
+                    tune=bool(args.tune), precision=args.precision)
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
@@ -276,7 +294,7 @@ def main():
         ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
-    roof["traffic"] = MEASURED_TRAFFIC.get((dom, desc["workload"], desc.get("elements")))
+    roof["traffic"] = MEASURED_TRAFFIC.get((dom, desc["workload"], desc.get("elements"), args.guard))
     roof.update(kernel=dom, launches=d["launches"], avg_launch_ms=round(per_launch_ms, 4),
                 algorithmic_flops_per_launch=d["flops"] / max(d["launches"], 1),
                 algorithmic_bytes_per_launch=d["bytes"] / max(d["launches"], 1))
@@ -337,7 +355,7 @@ def main():
                 dtype="f64" if args.precision == "fp64" else "f64+f32",
                 data="synthetic", config=dict(desc, tol=args.tol, precision=args.precision,
                                               preconditioner="teter", graph_iters=args.graph,
-                                              tuned=bool(args.tune)),
+                                              tuned=bool(args.tune), guard_columns=args.guard),
                 roofline=roof, kernels=kernels,
                 iterations=dict(mean=float(np.mean(iters)), min=int(min(iters)), max=int(max(iters))),
                 converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}",
@@ -348,7 +366,7 @@ def main():
         line["forms"] = forms
     if args.cpu_baseline:
         log("timing the oracle sample on the host")
-        line["cpu_baseline"] = cpu_baseline(els[0], stats[0]["iters"], args.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(els[0], args.tol)
     print(json.dumps(line), flush=True)
 
 

@@ -80,7 +80,7 @@ typedef struct dgdft_alb_opts {
                                * default 1                                         */
     const int32_t* elem_lo;   /* [n_elem][3] restriction box, half-open; NULL =   */
     const int32_t* elem_hi;   /*   central floor(n/3) points per axis             */
-    const int32_t* n_alb;     /* [n_elem] ALBs per element; NULL = J/2            */
+    const int32_t* n_alb;     /* [n_elem] ALBs per element; NULL = (J-n_guard)/2  */
     const float* mlp_weights; /* device [DGDFT_MLP_NTOT]: network of the learned  *
                                * preconditioner (read at every solve; may also be  *
                                * set later with dgdft_alb_set_mlp)                 */
@@ -94,6 +94,18 @@ typedef struct dgdft_alb_opts {
     int32_t tune;             /* 1: at create, time the split-K chunk count of    *
                                * the N_g-long Gram products per element shape and  *
                                * keep the fastest (see dgdft_alb_get_tuning)       */
+    int32_t n_guard;          /* guard columns (default 0): the last n_guard of    *
+                               * each element's n_states columns iterate with the  *
+                               * block but are not held to tol, and the ALBs (and  *
+                               * the volume terms) use only the first              *
+                               * n_states - n_guard states.  The block then        *
+                               * converges at the rate set by the gap to state     *
+                               * n_states + 1 instead of n_states - n_guard + 1    *
+                               * (LOBPCG, Sec. II.B, computes the lowest J_K       *
+                               * states; guards are an addition of this library).  *
+                               * Must be < every n_states.  Outputs keep all       *
+                               * n_states columns; the guard ones are returned as  *
+                               * they stand                                        */
 } dgdft_alb_opts;
 
 /* Kleinman-Bylander projectors of the whole batch, CSR by projector

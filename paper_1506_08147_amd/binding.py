@@ -48,7 +48,7 @@ class Opts(C.Structure):
                 ("max_iter", C.c_int32), ("poll_every", C.c_int32),
                 ("elem_lo", C.POINTER(C.c_int32)), ("elem_hi", C.POINTER(C.c_int32)),
                 ("n_alb", C.POINTER(C.c_int32)), ("mlp_weights", C.c_void_p),
-                ("graph_iters", C.c_int32), ("tune", C.c_int32)]
+                ("graph_iters", C.c_int32), ("tune", C.c_int32), ("n_guard", C.c_int32)]
 
 
 class KB(C.Structure):
@@ -164,11 +164,13 @@ class ALB:
     """Handle over dgdft_alb_create for a batch of extended elements.
 
     grids: (n_elem, 3) ints; boxes: (n_elem, 3) bohr; n_states: (n_elem,).
+    n_guard: the last n_guard of every element's n_states columns are guard
+    columns (iterated, not held to tol, left out of the ALBs).
     """
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
                  elem_hi=None, n_alb=None, precond="teter", mlp_weights=None, graph_iters=0,
-                 tune=False, precision="fp64"):
+                 tune=False, precision="fp64", n_guard=0):
         import torch  # noqa: F401  (device memory and streams)
         self.lib = load_library()
         self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
@@ -183,6 +185,8 @@ class ALB:
         o.poll_every = 1
         o.graph_iters = int(graph_iters)
         o.tune = 1 if tune else 0
+        o.n_guard = int(n_guard)
+        self.n_guard = int(n_guard)
         if mlp_weights is not None:
             self._mlp = mlp_weights
             o.mlp_weights = mlp_weights.data_ptr()

@@ -21,6 +21,8 @@ constexpr int KB_GMAX = 8;   // projectors sharing one support, per group
 
 struct Elem {
   int n1, n2, n3, J;
+  int jc;                    // leading states held to the tolerance and used for
+                             // the ALBs (J minus the guard columns)
   int ng;                    // n1*n2*n3
   int ld;                    // leading dimension of blocks (= ng)
   int n_proj, n_grp;
@@ -206,16 +208,19 @@ __host__ __device__ inline int gram_nchunk_e(const Elem& e, int K) {
 // chunk length, a multiple of 16
 __host__ __device__ inline int gram_chunklen(int K, int nchunk) { return cdiv(cdiv(K, nchunk), 16) * 16; }
 
-__host__ __device__ inline int gram_tiles(int m, int n, int upper) {
-  int tm = cdiv(m, GT), tn = cdiv(n, GT);
+// tile grid of a Gram product with tile edge tt (GT, or 144 for blocks of
+// 144 columns)
+__host__ __device__ inline int gram_tiles(int m, int n, int upper, int tt = GT) {
+  int tm = cdiv(m, tt), tn = cdiv(n, tt);
   if (!upper) return tm * tn;
   int c = 0;
   for (int i = 0; i < tm; ++i) c += (tn - i > 0) ? tn - i : 0;
   return c;
 }
 
-__host__ __device__ inline void gram_tile_decode(int t, int m, int n, int upper, int* ti, int* tj) {
-  int tm = cdiv(m, GT), tn = cdiv(n, GT);
+__host__ __device__ inline void gram_tile_decode(int t, int m, int n, int upper, int* ti, int* tj,
+                                                int tt = GT) {
+  int tm = cdiv(m, tt), tn = cdiv(n, tt);
   if (!upper) { *ti = t / tn; *tj = t % tn; return; }
   for (int i = 0; i < tm; ++i) {
     int row = tn - i;

@@ -310,9 +310,16 @@ struct dgdft_alb {
 
   void gram(const std::vector<int>& act, const GramArgs& g) {
     auto K = [&](int e) { return g.use_ne ? eh[e].ne : eh[e].ng; };
+    // 144 x 144 tiles when every operand's column count is a multiple of 144
+    bool t144 = !act.empty();
+    for (int e : act) {
+      t144 = t144 && cols_host(g.A, e) % GTT == 0;
+      for (int j = 0; j < g.njob; ++j) t144 = t144 && cols_host(g.B[j], e) % GTT == 0;
+    }
+    const int tt = t144 ? GTT : GT;
     auto P = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
-      for (int j = 0; j < g.njob; ++j) c += gram_tiles(m, cols_host(g.B[j], e), g.upper);
+      for (int j = 0; j < g.njob; ++j) c += gram_tiles(m, cols_host(g.B[j], e), g.upper, tt);
       return c * gram_nchunk_e(eh[e], K(e));
     });
     if (P.total == 0) return;
@@ -337,7 +344,11 @@ struct dgdft_alb {
       }
     }
     pbeg(DGDFT_K_GRAM, fl, by);
-    hipLaunchKernelGGL(dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, g);
+    if (t144)
+      hipLaunchKernelGGL(dg_gram_t144, dim3(P.total), dim3(GRAM144_THREADS), 0, stream, ed, P.active,
+                         P.prefix, P.na, g);
+    else
+      hipLaunchKernelGGL(dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, g);
     pend();
     auto R = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
@@ -352,10 +363,17 @@ struct dgdft_alb {
   }
 
   void update(const std::vector<int>& act, const UpdArgs& u) {
+    auto ncols = [&](int e) {
+      return u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
+    };
+    // 144-wide column tiles when every element's column count is a multiple
+    // of 144 (no nearly empty last tile), else 128-wide
+    bool w144 = !act.empty();
+    for (int e : act) w144 = w144 && ncols(e) % UTN == 0;
+    const int tn = w144 ? UTN : GT;
     auto P = make_prefix(act, [&](int e) {
       int K = u.use_ne ? eh[e].ne : eh[e].ng;
-      int nc = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
-      return u.njob * cdiv(K, GT) * cdiv(nc, GT);
+      return u.njob * cdiv(K, GT) * cdiv(ncols(e), tn);
     });
     if (P.total == 0) return;
     double fl = 0, by = 0;
@@ -367,7 +385,11 @@ struct dgdft_alb {
       by += u.njob * 8.0 * K * (kA + nc * (u.beta != 0.0 ? 2 : 1));
     }
     pbeg(DGDFT_K_UPDATE, fl, by);
-    hipLaunchKernelGGL(dg_update, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, u);
+    if (w144)
+      hipLaunchKernelGGL(dg_update_n144, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
+                         P.na, u);
+    else
+      hipLaunchKernelGGL(dg_update, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, u);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -604,9 +626,10 @@ struct dgdft_alb {
     flush_prof();
   }
 
+  // largest residual of the states held to the tolerance (guard columns excluded)
   double max_res(int e) const {
     double m = 0.0;
-    for (int j = 0; j < eh[e].J; ++j) m = std::max(m, h_resid[eh[e].off_j + j]);
+    for (int j = 0; j < eh[e].jc; ++j) m = std::max(m, h_resid[eh[e].off_j + j]);
     return m;
   }
 
@@ -796,6 +819,11 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     return DGDFT_EINVAL;
   }
   h->mlp_w = h->opts.mlp_weights;
+  if (h->opts.n_guard < 0) {
+    g_create_error = "n_guard must be >= 0";
+    delete h;
+    return DGDFT_EINVAL;
+  }
   if (h->opts.precision != DGDFT_PREC_FP64 && h->opts.precision != DGDFT_PREC_MIXED) {
     g_create_error = "unknown precision";
     delete h;
@@ -836,6 +864,11 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       g_create_error = buf; delete h; return DGDFT_EINVAL;
     }
     if (E.J > 1024) { g_create_error = "n_states > 1024"; delete h; return DGDFT_EUNSUPPORTED; }
+    E.jc = E.J - h->opts.n_guard;
+    if (E.jc < 1) {
+      snprintf(buf, sizeof buf, "element %d: n_guard must be < n_states", e);
+      g_create_error = buf; delete h; return DGDFT_EINVAL;
+    }
     for (int d = 0; d < 3; ++d) {
       int nd = grid[3 * e + d];
       if (h->opts.elem_lo && h->opts.elem_hi) {
@@ -852,9 +885,9 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       }
     }
     E.ne = (E.hi[0] - E.lo[0]) * (E.hi[1] - E.lo[1]) * (E.hi[2] - E.lo[2]);
-    E.nalb = h->opts.n_alb ? h->opts.n_alb[e] : E.J / 2;
-    if (E.nalb < 1 || E.nalb > std::min(E.ne, E.J)) {
-      snprintf(buf, sizeof buf, "element %d: n_alb must be in [1, min(N_E, J)]", e);
+    E.nalb = h->opts.n_alb ? h->opts.n_alb[e] : E.jc / 2;
+    if (E.nalb < 1 || E.nalb > std::min(E.ne, E.jc)) {
+      snprintf(buf, sizeof buf, "element %d: n_alb must be in [1, min(N_E, n_states - n_guard)]", e);
       g_create_error = buf; delete h; return DGDFT_EINVAL;
     }
     E.dv = E.L[0] * E.L[1] * E.L[2] / (double)E.ng;
@@ -1857,10 +1890,10 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
     for (int i = 0; i < count; ++i) {
       act[i] = i;
       if (trans) {
-        pre[i + 1] = pre[i] + gram_tiles(m, n, 0) * nch;
+        pre[i + 1] = pre[i] + gram_tiles(m, n, 0, (m % GTT == 0 && n % GTT == 0) ? GTT : GT) * nch;
         pre2[i + 1] = pre2[i] + cdiv(m * n, 256);
       } else {
-        pre[i + 1] = pre[i] + cdiv((int)K, GT) * cdiv(n, GT);
+        pre[i + 1] = pre[i] + cdiv((int)K, GT) * cdiv(n, n % UTN == 0 ? UTN : GT);
       }
     }
     int* d_act = t.alloc<int>(count);
@@ -1872,13 +1905,21 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
     if (trans) {
       GramArgs g{};
       g.A = oa; g.B[0] = ob; g.njob = 1; g.out_mat[0] = 0; g.upper = 0;
-      hipLaunchKernelGGL(dg_gram, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, g);
+      if (m % GTT == 0 && n % GTT == 0)
+        hipLaunchKernelGGL(dg_gram_t144, dim3(pre[count]), dim3(GRAM144_THREADS), 0, s, ed, d_act, d_pre,
+                           count, g);
+      else
+        hipLaunchKernelGGL(dg_gram, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, g);
       hipLaunchKernelGGL(dg_gram_reduce, dim3(pre2[count]), dim3(256), 0, s, ed, d_act, d_pre2, count, g);
     } else {
       UpdArgs u{};
       u.A[0] = oa; u.Y[0] = oc; u.njob = 1; u.cmat = 0; u.ccol0 = 0; u.ncol = n;
       u.alpha = alpha; u.beta = beta;
-      hipLaunchKernelGGL(dg_update, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, u);
+      // column tiles as in the solver: 144 wide when n is a multiple of 144
+      if (n % UTN == 0)
+        hipLaunchKernelGGL(dg_update_n144, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, u);
+      else
+        hipLaunchKernelGGL(dg_update, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, u);
     }
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(s));
@@ -2299,9 +2340,11 @@ int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* a
     for (auto [e0, G] : runs) {
       const Elem& E = h->eh[e0];
       const Sz& z = sz[e0];
-      const int J = E.J, na = E.nalb, n1 = E.n1, n2 = E.n2, n3 = E.n3;
+      // J: the states the ALBs were built from (guard columns left out);
+      // eigvecs and the restricted block keep the n_states column layout
+      const int J = E.jc, na = E.nalb, n1 = E.n1, n2 = E.n2, n3 = E.n3;
       const int m1 = z.m[0], m2 = z.m[1], m3 = z.m[2], ME = (int)z.ME;
-      const long long ngJ = (long long)E.ng * J, m12 = (long long)m1 * m2;
+      const long long ngJ = (long long)E.ng * E.J, m12 = (long long)m1 * m2;
       Parts P;
       carve(e0, G, h->vol_ws, P);
       double *bufA = P.bufA, *bufB = P.bufB, *vX = P.vX, *vY = P.vY, *vL = P.vL, *wq = P.wq,
@@ -2330,7 +2373,7 @@ int32_t dgdft_alb_dg_volume(dgdft_alb* h, const double* eigvecs, const double* a
       hipLaunchKernelGGL(dg_box_cols, dim3(cdiv(E.ne, 256), J, G), dim3(256), 0, h->stream,
                          (const Elem*)h->ed, e0, psi, bufA);
       HCHECK(hipGetLastError());
-      gemm(1, 0, J, na, E.ne, bufA, E.ne, ne * J, phi, E.ne, ne * na, Tu, J, (long long)J * na, G,
+      gemm(1, 0, J, na, E.ne, bufA, E.ne, ne * E.J, phi, E.ne, ne * na, Tu, J, (long long)J * na, G,
            E.dv, 0.0, nullptr, 0, sigma + E.off_nalb, na, -2);
       // psi at the LGL points, one axis at a time: x, y, z
       gemm(0, 0, m1, n2 * n3 * J, n1, t.I[0], m1, 0, psi, n1, ngJ, bufA, m1,

@@ -126,6 +126,10 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   };
   const int lane = tid & 63, wv = tid >> 6;
   const int wi = wv & 1, wj = wv >> 1;
+  // a wave whose 64 x 64 sub-tile lies wholly outside the m x n result (in
+  // the last tile row or column of a size that is no multiple of 128) skips
+  // its products
+  const bool live = ti * TT + wi * 64 < m && tj * TT + wj * 64 < n;
   dbl4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -140,19 +144,21 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
     if (st + 1 < nst) load(kbeg + (st + 1) * KS);
+    if (live) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
-      double fa[4], fb[4];
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        double fa[4], fb[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fa[a] = As[cur][kk * LP + wi * 64 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 4; ++a) fa[a] = As[cur][kk * LP + wi * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) fb[c] = Bs[cur][kk * LP + wj * 64 + c * 16 + (lane & 15)];
+        for (int c = 0; c < 4; ++c) fb[c] = Bs[cur][kk * LP + wj * 64 + c * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+          for (int c = 0; c < 4; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+      }
     }
     if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
@@ -166,6 +172,127 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
       for (int r = 0; r < 4; ++r) {
         int i = ti * TT + wi * 64 + a * 16 + 4 * r + (lane >> 4);
         int j = tj * TT + wj * 64 + c * 16 + (lane & 15);
+        if (i < m && j < n) part[i + (long long)m * j] = acc[a][c][r];
+      }
+}
+
+// The same product with 144 x 144 tiles, for operands whose column counts
+// are multiples of 144 (blocks of 144 states): nine waves in a 3 x 3 grid,
+// each owning 48 x 48 (3 x 3 MFMA blocks).  Chunks, carried-block skip,
+// staging and partial sums follow dg_gram.
+constexpr int GTT = 144;       // tile edge of dg_gram_t144
+constexpr int GLP = GTT + 4;
+constexpr int GRAM144_THREADS = 576;
+
+extern "C" __global__ void __launch_bounds__(GRAM144_THREADS)
+dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+             int na, GramArgs g) {
+  __shared__ double As[2][KS * GLP];
+  __shared__ double Bs[2][KS * GLP];
+  __shared__ const double* colA[GTT];
+  __shared__ const double* colB[GTT];
+  int blk = blockIdx.x;
+  int ai = find_elem(prefix, na, blk);
+  const Elem& e = E[active[ai]];
+  int w = blk - prefix[ai];
+  const int K = rowsK(e, g.use_ne);
+  const int m = opnd_cols(g.A, e);
+  const int nch = gram_nchunk_e(e, K), clen = gram_chunklen(K, nch);
+  const int n0 = opnd_cols(g.B[0], e);
+  int job = 0, n = n0;
+  int ntile = gram_tiles(m, n, g.upper, GTT);
+  if (w >= ntile * nch) {
+    job = 1;
+    w -= ntile * nch;
+    n = opnd_cols(g.B[1], e);
+    ntile = gram_tiles(m, n, g.upper, GTT);
+  }
+  if (job >= g.njob || ntile == 0 || w >= ntile * nch) return;
+  const Opnd& B = g.B[job];
+  int chunk = w / ntile, tile = w - chunk * ntile;
+  int ti, tj;
+  gram_tile_decode(tile, m, n, g.upper, &ti, &tj, GTT);
+  if (g.carry) {
+    const int kc = carried_cols(e);
+    if ((ti + 1) * GTT <= kc && (tj + 1) * GTT <= kc) return;
+  }
+  const int kbeg = chunk * clen;
+  const int kend = min(K, kbeg + clen);
+  const int tid = threadIdx.x;
+  if (tid < GTT) {
+    int c = ti * GTT + tid;
+    colA[tid] = c < m ? opnd_col(g.A, e, c) : nullptr;
+  } else if (tid < 2 * GTT) {
+    int c = tj * GTT + tid - GTT;
+    colB[tid - GTT] = c < n ? opnd_col(B, e, c) : nullptr;
+  }
+  __syncthreads();
+  // stage loads: k = tid % 16, columns tid/16 + 36u (u < 4)
+  const int lk = tid & 15, lc = tid >> 4;
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+    int k = k0 + lk;
+    bool kin = k < kend;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* pa = colA[lc + 36 * u];
+      const double* pb = colB[lc + 36 * u];
+      ra[u] = (kin && pa) ? pa[k] : 0.0;
+      rb[u] = (kin && pb) ? pb[k] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      As[buf][lk * GLP + lc + 36 * u] = ra[u];
+      Bs[buf][lk * GLP + lc + 36 * u] = rb[u];
+    }
+  };
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wi = wv % 3, wj = wv / 3;
+  const bool live = ti * GTT + wi * 48 < m && tj * GTT + wj * 48 < n;
+  dbl4 acc[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const int nst = (kend - kbeg + KS - 1) / KS;
+  if (nst > 0) {
+    load(kbeg);
+    store(0);
+    __syncthreads();
+  }
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load(kbeg + (st + 1) * KS);
+    if (live) {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        double fa[3], fb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fa[a] = As[cur][kk * GLP + wi * 48 + a * 16 + (lane & 15)];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fb[c] = Bs[cur][kk * GLP + wj * 48 + c * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+      }
+    }
+    if (st + 1 < nst) store(cur ^ 1);
+    __syncthreads();
+  }
+  double* part = e.gpart + (job ? (long long)nch * m * n0 : 0LL) + (long long)chunk * m * n;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int i = ti * GTT + wi * 48 + a * 16 + 4 * r + (lane >> 4);
+        int j = tj * GTT + wj * 48 + c * 16 + (lane & 15);
         if (i < m && j < n) part[i + (long long)m * j] = acc[a][c][r];
       }
 }
@@ -283,6 +410,9 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   };
   const int lane = tid & 63, wv = tid >> 6;
   const int wj = wv & 1, wr = wv >> 1;
+  // a wave whose 64 columns lie wholly outside Y (in the last column tile of
+  // a width that is no multiple of 128) skips its products
+  const bool live = col0 + wj * 64 < ncol;
   dbl4 acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -295,19 +425,21 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
     if (st + 1 < nst) load((st + 1) * UKS);
+    if (live) {
 #pragma unroll
-    for (int ks = 0; ks < UKS / 4; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
-      double fc[4], fa[4];
+      for (int ks = 0; ks < UKS / 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        double fc[4], fa[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fc[a] = Cs[cur][kk * LP + wj * 64 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 4; ++a) fc[a] = Cs[cur][kk * LP + wj * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) fa[c] = As[cur][kk * LP + wr * 64 + c * 16 + (lane & 15)];
+        for (int c = 0; c < 4; ++c) fa[c] = As[cur][kk * LP + wr * 64 + c * 16 + (lane & 15)];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc[a], fa[c], acc[a][c], 0, 0, 0);
+          for (int c = 0; c < 4; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc[a], fa[c], acc[a][c], 0, 0, 0);
+      }
     }
     if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
@@ -322,6 +454,132 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         int row = row0 + wr * 64 + c * 16 + (lane & 15);
+        if (row < K) {
+          double v = u.alpha * acc[a][c][r];
+          if (u.beta != 0.0) v += u.beta * y[row];
+          y[row] = v;
+        }
+      }
+    }
+}
+
+// The same product with 128 x 144 workgroup tiles, for column counts that are
+// multiples of 144 (blocks of 144 states, e.g. 128 wanted states and 16
+// guard columns), which 128-wide tiles would leave a nearly empty last
+// column tile: the four waves are stacked along the rows, each owning 32
+// rows x 144 columns (2 x 9 MFMA blocks).  Staging, K stages and the
+// epilogue follow dg_update.
+constexpr int UTN = 144;       // column tile of dg_update_n144
+constexpr int LPC = UTN + 4;
+
+extern "C" __global__ void __launch_bounds__(256, 2)
+dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+               int na, UpdArgs u) {
+  __shared__ double As[2][UKS * LP];
+  __shared__ double Cs[2][UKS * LPC];
+  __shared__ double* colY[UTN];
+  __shared__ const double* abase[6];
+  int blk = blockIdx.x;
+  int ai = find_elem(prefix, na, blk);
+  const Elem& e = E[active[ai]];
+  int w = blk - prefix[ai];
+  const int K = rowsK(e, u.use_ne);
+  const int kA = opnd_cols(u.A[0], e);
+  const int ncol = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? e.nalb : opnd_cols(u.Y[0], e));
+  const int ntr = cdiv(K, TT), ntc = cdiv(ncol, UTN);
+  if (ntr * ntc == 0) return;
+  int job = w / (ntr * ntc);
+  if (job >= u.njob) return;
+  w -= job * ntr * ntc;
+  int tr = w / ntc, tc = w - tr * ntc;
+  const Opnd& A = u.A[job];
+  const Opnd& Y = u.Y[job];
+  const double* C = sm(e, u.cmat) + (long long)u.ccol0 * kA;
+  const int row0 = tr * TT, col0 = tc * UTN;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    if (A.ncols >= 0) {
+      abase[0] = bp(e, A.slot[0]);
+    } else {
+      int q = 0;
+      for (int i = 0; i < A.nblk; ++i)
+        if (!(A.optP[i] && !has_p(e))) abase[q++] = bp(e, A.slot[i]);
+    }
+  }
+  if (tid < UTN) colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
+  __syncthreads();
+  const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
+  const long long ld = e.ld;
+  // A stage: row = tid % 128, k = tid / 128 + 2q (q < UKS/2)
+  const int ar = tid & 127, ak = tid >> 7;
+  // C stage: k = tid % 16, j = tid / 16 + 16v (v < 9)
+  const int ck = tid & 15, cj = tid >> 4;
+  const bool rin = row0 + ar < K;
+  double ra[UPD_NQ], rc[9];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < UPD_NQ; ++q) {
+      int k = k0 + ak + 2 * q;
+      double v = 0.0;
+      if (k < kA && rin) {
+        int bb = k / bcols;
+        v = abase[bb][(long long)(k - bb * bcols) * ld + row0 + ar];
+      }
+      ra[q] = v;
+    }
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      int j = col0 + cj + 16 * v;
+      int kc = k0 + ck;
+      rc[v] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LP + ar] = ra[q];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) Cs[buf][ck * LPC + cj + 16 * v] = rc[v];
+  };
+  const int lane = tid & 63, wr = tid >> 6;
+  dbl4 acc[9][2];
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+  const int nst = cdiv(kA, UKS);
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) load((st + 1) * UKS);
+#pragma unroll
+    for (int ks = 0; ks < UKS / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double fc[9], fa[2];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) fc[a] = Cs[cur][kk * LPC + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LP + wr * 32 + c * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 9; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc[a], fa[c], acc[a][c], 0, 0, 0);
+    }
+    if (st + 1 < nst) store(cur ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int jl = a * 16 + 4 * r + (lane >> 4);
+      double* y = colY[jl];
+      if (!y) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        int row = row0 + wr * 32 + c * 16 + (lane & 15);
         if (row < K) {
           double v = u.alpha * acc[a][c][r];
           if (u.beta != 0.0) v += u.beta * y[row];

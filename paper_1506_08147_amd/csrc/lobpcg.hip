@@ -14,6 +14,9 @@ namespace dg {
 
 constexpr double CHOL_TOL = 1e-10;   // smallest admissible pivot of a unit-diagonal Gram
 constexpr int SMALL_THREADS = 1024;
+// LDS of the eigensolver workgroups (doubles): the one-pass tridiagonalisation
+// needs (waves + 4) n, i.e. up to n = 512 at 1024 threads
+constexpr int EIG_LDS = 10240;
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -305,7 +308,7 @@ dg_carry_in(Elem* __restrict__ E, const int* __restrict__ active, int na) {
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   __shared__ double red[32];
-  __shared__ double lds[8192];
+  __shared__ double lds[EIG_LDS];
   DevTeam t{red};
   const Elem& e = E[active[blockIdx.x]];
   if (e.fl[FL_RR_PATH] == 1) return;
@@ -317,7 +320,7 @@ dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int sing
   double* vec = sm(e, SM_V);
   double* w = vec + 7 * n;
   // workspace: SM_W0 and SM_W1 (consecutive)
-  syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, 8192);
+  syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, EIG_LDS);
 }
 
 // Path 3: T = I - E/2 + 3 E^2/8 - 5 E^3/16 from E (SM_L), E^2 (SM_U) and
@@ -412,7 +415,7 @@ dg_rr_dchol(Elem* __restrict__ E, const int* __restrict__ active, int na, int si
     pok = chol_lower(t, A, J, J, CHOL_TOL);
   }
   double rmax = 0.0;
-  for (int i = t.tid(); i < J; i += t.nt()) rmax = fmax(rmax, e.resid[i]);
+  for (int i = t.tid(); i < e.jc; i += t.nt()) rmax = fmax(rmax, e.resid[i]);
   const bool carry = t.maxv(rmax) >= CARRY_RES;
   if (pok) {
     tri_inv_lower_t(t, A, J, Lm, J, J);                                   // Lm = L^-T
@@ -448,6 +451,10 @@ dg_gather_box(Elem* __restrict__ E, const int* __restrict__ active, const int* _
   int b1 = e.hi[0] - e.lo[0], b2 = e.hi[1] - e.lo[1];
   const double* x = bp(e, src) + (long long)j * e.ld;
   double* y = bp(e, dst) + (long long)j * e.ld;
+  if (j >= e.jc) {   // guard columns take no part in the ALBs
+    for (int r = threadIdx.x; r < e.ne; r += 256) y[r] = 0.0;
+    return;
+  }
   for (int r = threadIdx.x; r < e.ne; r += 256) {
     int i = r % b1, q = r / b1;
     int jj = q % b2, kk = q / b2;
@@ -573,7 +580,7 @@ extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, double* work,
               int method) {
   __shared__ double red[32];
-  __shared__ double lds[8192];
+  __shared__ double lds[EIG_LDS];
   DevTeam t{red};
   long long b = blockIdx.x;
   double* Aw = work + b * (2LL * n * n + 8LL * n + 6LL * n * k);
@@ -584,7 +591,7 @@ dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, 
   if (method == 1) {
     syev(t, Aw, n, n, w + b * n, Z + b * n * k, n, k, U, vec);
   } else {
-    syev_lowest(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, 8192);
+    syev_lowest(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, EIG_LDS);
   }
 }
 }  // namespace dg

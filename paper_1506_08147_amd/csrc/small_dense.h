@@ -696,13 +696,14 @@ __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, d
                                               double* tau, double* v, double* p,
                                               double* scratch = nullptr, int scratch_size = 0) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-  // Device path (tridiagonalize_fused) for n <= 768 with (waves + 2) * n
+  // Device path (tridiagonalize_fused) for n <= 512 with (waves + 2) * n
   // doubles of LDS scratch: 6 rows per lane and two columns per wave pass up
-  // to n = 384, else 12 rows per lane and one column per pass.
+  // to n = 384, else 8 rows per lane (the registers of a 1024-lane
+  // workgroup hold no more without spilling).
   if constexpr (T::is_device) {
-    if (n <= 64 * 12 && scratch && (nw + 2) * n <= scratch_size) {
+    if (n <= 64 * 8 && scratch && (nw + 2) * n <= scratch_size) {
       if (n <= 64 * 6) tridiagonalize_fused<6, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
-      else tridiagonalize_fused<12, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
+      else tridiagonalize_fused<8, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
       return;
     }
   }

@@ -129,6 +129,13 @@ def initial_guess(ng, n_states, cfg, elem, seed):
     return np.asfortranarray(rng.standard_normal((n_states, ng)).T)
 
 
+def guard_columns(ng, n_guard, key):
+    """Seeded N(0,1) start columns for guard vectors (ng x n_guard, Fortran
+    order); key: tuple of ints naming the element."""
+    rng = np.random.default_rng([9, *key])
+    return np.asfortranarray(rng.standard_normal((n_guard, ng)).T)
+
+
 def _fill_x0(elems, cfg, seed, elements):
     ids = list(range(len(elems))) if elements is None else list(elements)
 

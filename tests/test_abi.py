@@ -76,3 +76,35 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(b.LibraryMissing):
         b.load_library()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Field offsets and sizes of the ctypes mirrors equal those of the C
+    structs (the header compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    import paper_1506_08147_amd.binding as b
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"dgdft_alb_opts": b.Opts, "dgdft_kb": b.KB, "dgdft_alb_stats": b.Stats,
+             "dgdft_pairs": b.Pairs, "dgdft_train_opts": b.TrainOpts}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"):
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

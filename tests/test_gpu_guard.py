@@ -1,0 +1,90 @@
+"""Guard columns (n_guard): the block carries extra columns that iterate
+with it but are not held to the tolerance; the wanted states, the ALBs and
+the volume terms must match the oracle's solve without guards (through the
+C ABI)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import dgblocks
+from oracle.solve import solve_element
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "one_element_dense.json")
+
+
+def _span_err(A, B):
+    s = np.linalg.svd(A.T @ B, compute_uv=False)
+    return float(np.sqrt(max(0.0, 1.0 - s.min() ** 2)))
+
+
+def _handle(el, dev, n_guard, tol):
+    import torch
+    from paper_1506_08147_amd import ALB
+    h = ALB([el.grid], [el.box], [el.n_states + n_guard], tol=tol, elem_lo=[el.elem_lo],
+            elem_hi=[el.elem_hi], n_alb=[el.n_alb], n_guard=n_guard)
+    V = torch.from_numpy(el.V).to(dev)
+    X0 = np.hstack([el.X0, synth.guard_columns(el.ng, n_guard, (0, el.n_states))]) if n_guard else el.X0
+    X0 = torch.from_numpy(np.ascontiguousarray(X0.T)).reshape(-1).to(dev)
+    return h, V, ALB.kb_batch([el.kb], dev), X0
+
+
+def test_guard_columns_match_dense_and_oracle():
+    """24^3, 32 wanted states + 8 guards, residual 1e-8: the 32 eigenvalues
+    against dense LAPACK (stored), eigenvectors, ALBs and singular values
+    against the oracle's solve without guards, the volume terms against the
+    oracle on its own inputs; fewer iterations than without guards."""
+    import torch
+    dev = torch.device("cuda:0")
+    gold = json.load(open(GOLDEN))
+    el = synth.single_element(seed=0)
+    J, g = el.n_states, 8
+    ref = solve_element(el, tol=1e-8)
+    iters = {}
+    for ng in (0, g):
+        h, V, kbt, X0 = _handle(el, dev, ng, 1e-8)
+        out = h.solve(V, kbt, X0)
+        st = out["stats"][0]
+        iters[ng] = st["iters"]
+        assert out["status"] == 0 and st["converged"] and st["max_res"] <= 1e-8
+        r = {k: v.cpu().numpy() for k, v in h.split(out, 0).items()}
+        assert r["eigvals"].shape == (J + ng,) and r["eigvecs"].shape == (el.ng, J + ng)
+        w = np.asarray(gold["seeds"]["0"])
+        assert np.abs(r["eigvals"][:J] - w[:J]).max() < 1e-10
+        dv = el.dv
+        X = r["eigvecs"][:, :J] * np.sqrt(dv)
+        assert _span_err(X, ref["X"]) < 1e-6
+        assert np.abs(r["sigma"] - ref["sigma"]).max() < 1e-8
+        A = r["albs"] * np.sqrt(dv)
+        assert np.abs(A.T @ A - np.eye(el.n_alb)).max() < 1e-11
+        assert _span_err(A, ref["albs"] * np.sqrt(dv)) < 1e-6
+        # volume terms: oracle eigenvectors, ALBs and singular values (with
+        # seeded stand-ins in the guard columns of the n_states layout), which
+        # the guard columns must not enter
+        psi = ref["eigvecs"]
+        if ng:
+            psi = np.hstack([psi, synth.guard_columns(el.ng, ng, (1, J))])
+        cat = lambda M: torch.from_numpy(np.asfortranarray(M).ravel(order="F")).to(dev)  # noqa: E731
+        vol = h.dg_volume(cat(psi), cat(ref["albs"]), torch.from_numpy(ref["sigma"]).to(dev),
+                          2).cpu().numpy()
+        Ag = vol.reshape(el.n_alb, el.n_alb, order="F")
+        Ar = dgblocks.volume_block(ref["eigvecs"], ref["albs"], ref["sigma"], el.V, el.grid,
+                                   el.box, el.elem_lo, el.elem_hi, 2)
+        assert np.abs(Ag - Ar).max() < 1e-10 * np.abs(Ar).max()
+        h.close()
+    print("iterations without / with guards:", iters)
+    assert iters[g] < iters[0]
+
+
+def test_guard_count_validated():
+    """n_guard must be >= 0 and below every n_states (EINVAL at create)."""
+    from paper_1506_08147_amd import ALB
+    from paper_1506_08147_amd.binding import DGDFTError
+    el = synth.single_element(seed=1, grid=(12, 12, 12), n_states=6, n_atoms=1)
+    for ng in (-1, 6, 7):
+        with pytest.raises(DGDFTError) as err:
+            ALB([el.grid], [el.box], [el.n_states], n_guard=ng, n_alb=[2])
+        assert err.value.code == -1 and "n_guard" in str(err.value)

@@ -21,8 +21,11 @@ def _t(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-@pytest.mark.parametrize("K,m,n", [(1000, 70, 37), (4096, 64, 64), (77, 5, 130), (13824, 96, 96)])
+@pytest.mark.parametrize("K,m,n", [(1000, 70, 37), (4096, 64, 64), (77, 5, 130), (13824, 96, 96),
+                                   (13824, 144, 288), (1000, 432, 144)])
 def test_gram_product_matches_numpy(dev, K, m, n):
+    """C = A^T B split over K chunks; m and n multiples of 144 take the
+    144 x 144 tiles."""
     from paper_1506_08147_amd import gemm_batched
     rng = np.random.default_rng(K + m)
     A = rng.standard_normal((3, m, K))   # column-major K x m per problem
@@ -34,8 +37,11 @@ def test_gram_product_matches_numpy(dev, K, m, n):
         assert np.abs(got - ref).max() <= 1e-13 * np.sqrt(K) * 10
 
 
-@pytest.mark.parametrize("K,m,n", [(1000, 70, 37), (77, 5, 130), (13824, 96, 64)])
+@pytest.mark.parametrize("K,m,n", [(1000, 70, 37), (77, 5, 130), (13824, 96, 64), (1000, 70, 144),
+                                   (13824, 432, 288)])
 def test_update_product_matches_numpy(dev, K, m, n):
+    """Y = alpha A C + beta Y; n a multiple of 144 takes the 144-wide column
+    tiles."""
     from paper_1506_08147_amd import gemm_batched
     rng = np.random.default_rng(K * 3 + n)
     A = rng.standard_normal((2, m, K))
