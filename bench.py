@@ -28,9 +28,10 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of this
 # command, calibrated on a 1 GiB copy (profiles/slab64_fp64_hbm_traffic.md):
-# (kernel, workload, elements, guard columns) -> bytes.  Valid for the kernel
+# (kernel class, workload, elements, guard columns, streams) -> bytes.  Valid for the kernel
 # build that was measured; removed when the kernel changes.
-MEASURED_TRAFFIC = {("dg_update", "slab_36x36x60_J128", 64, 0): 14.613e9}
+MEASURED_TRAFFIC = {("dg_gram", "slab_36x36x60_J128", 64, 16, 2): 13.460e9,
+                    ("dg_update", "slab_36x36x60_J128", 64, 16, 2): 18.934e9}
 # guard columns per element when --guard is not given: 16 on the slab (block
 # of 144 columns, the tile width of the 144-wide GEMM kernels), else none
 DEFAULT_GUARD = {"slab": 16}
@@ -101,6 +102,7 @@ def start_block(els, n_guard, dev):
 
 def make_handle(args, els, **kw):
     from paper_1506_08147_amd import ALB
+    kw.setdefault("n_streams", args.streams)
     return ALB([e.grid for e in els], [e.box for e in els], [e.n_states + args.guard for e in els],
                elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
                n_alb=[e.n_alb for e in els], n_guard=args.guard, **kw)
@@ -144,16 +146,43 @@ def warm_mode(args, h, els, desc, V, kbt, out):
     print(json.dumps(line), flush=True)
 
 
-def time_form(args, els, V, kbt, X0, precision, precond, w):
+def roofline(ks):
+    """Dominant kernel class by time in the timed region (the small-dense
+    Rayleigh-Ritz kernels are latency-bound, not roofline kernels: only classes
+    with algorithmic flops or bytes compete): algorithmic work per launch over
+    its average HIP-event launch time."""
+    dom = max((k for k in ks if ks[k]["flops"] > 0 or ks[k]["bytes"] > 0), key=lambda k: ks[k]["ms"])
+    d = ks[dom]
+    per_launch_ms = d["ms"] / max(d["launches"], 1)
+    if d["flops"] > 0:
+        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / PEAK_FP64_TFLOPS, 4), traffic=None)
+    else:
+        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
+    roof.update(kernel=dom, launches=d["launches"], avg_launch_ms=round(per_launch_ms, 4),
+                algorithmic_flops_per_launch=d["flops"] / max(d["launches"], 1),
+                algorithmic_bytes_per_launch=d["bytes"] / max(d["launches"], 1))
+    return roof
+
+
+def time_form(args, els, V, kbt, X0, precision, precond, w, streams=None):
     """Converged elements/s of one form on the same resident inputs (1 warm-up
-    solve, args.steps timed)."""
+    solve, args.steps timed).  streams=1: one element group on one stream,
+    with the roofline of its dominant kernel (launches not sharing the GPU
+    with a second group's)."""
     import numpy as np
     import torch
     from paper_1506_08147_amd import ALB
+    kw = dict(n_streams=streams) if streams else {}
     h = make_handle(args, els, tol=args.tol, max_iter=1000, precision=precision, precond=precond,
-                    mlp_weights=w)
+                    mlp_weights=w, **kw)
     out = h.solve(V, kbt, X0)
     torch.cuda.synchronize()
+    if streams:
+        h.profile(True)
     t0 = time.perf_counter()
     n_conv = 0
     for s in range(args.steps):
@@ -162,13 +191,17 @@ def time_form(args, els, V, kbt, X0, precision, precond, w):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     st = out["stats"]
+    roof = roofline(h.kernel_stats()) if streams else None
     h.close()
     log(f"form {precision}/{precond}: {n_conv / el:.3f} elements/s")
-    return dict(value=round(n_conv / el, 4), ms_per_step=round(1e3 * el / args.steps, 2),
-                precision=precision, preconditioner=precond,
-                iterations_mean=float(np.mean([s["iters"] for s in st])),
-                converged=f"{sum(1 for s in st if s['converged'])}/{len(st)}",
-                teter_fallback_bands=int(sum(s["n_teter_fallback"] for s in st)))
+    r = dict(value=round(n_conv / el, 4), ms_per_step=round(1e3 * el / args.steps, 2),
+             precision=precision, preconditioner=precond,
+             iterations_mean=float(np.mean([s["iters"] for s in st])),
+             converged=f"{sum(1 for s in st if s['converged'])}/{len(st)}",
+             teter_fallback_bands=int(sum(s["n_teter_fallback"] for s in st)))
+    if streams:
+        r.update(streams=streams, roofline=roof)
+    return r
 
 
 def train_network(dev):
@@ -208,6 +241,8 @@ def main():
     ap.add_argument("--elements", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
+                    help="element groups on their own HIP streams")
     ap.add_argument("--guard", type=int, default=None,
                     help="guard columns per element: the block holds n_states + G columns, "
                          "convergence and ALBs use the first n_states (default: 16 on the "
@@ -280,24 +315,9 @@ def main():
     iters = [st["iters"] for st in stats]
     ms_step = 1e3 * elapsed / args.steps
 
-    # roofline of the dominant kernel class (largest time in the timed region)
-    # (the small-dense Rayleigh-Ritz kernels are latency-bound, not roofline
-    # kernels: only classes with algorithmic flops or bytes compete)
-    dom = max((k for k in ks if ks[k]["flops"] > 0 or ks[k]["bytes"] > 0), key=lambda k: ks[k]["ms"])
-    d = ks[dom]
-    per_launch_ms = d["ms"] / max(d["launches"], 1)
-    if d["flops"] > 0:
-        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / PEAK_FP64_TFLOPS, 4), traffic=None)
-    else:
-        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
-    roof["traffic"] = MEASURED_TRAFFIC.get((dom, desc["workload"], desc.get("elements"), args.guard))
-    roof.update(kernel=dom, launches=d["launches"], avg_launch_ms=round(per_launch_ms, 4),
-                algorithmic_flops_per_launch=d["flops"] / max(d["launches"], 1),
-                algorithmic_bytes_per_launch=d["bytes"] / max(d["launches"], 1))
+    roof = roofline(ks)
+    roof["traffic"] = MEASURED_TRAFFIC.get((roof["kernel"], desc["workload"], desc.get("elements"),
+                                            args.guard, args.streams))
     kernels = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3), launches=v["launches"],
                        tflops=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] else 0,
                        gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else 0)
@@ -343,6 +363,9 @@ def main():
     if args.forms and args.warm == 0:
         forms = dict(fp64_plain=dict(value=round(n_conv / elapsed, 4), ms_per_step=round(ms_step, 2),
                                      iterations_mean=float(np.mean(iters))))
+        if args.streams != 1:
+            forms["fp64_one_stream"] = time_form(args, els, V, kbt, X0, args.precision, "teter", None,
+                                                 streams=1)
         forms["mixed"] = time_form(args, els, V, kbt, X0, "mixed", "teter", None)
         w, training = train_network(dev)
         forms["mixed_learned"] = time_form(args, els, V, kbt, X0, "mixed", "learned", w)
@@ -355,7 +378,8 @@ def main():
                 dtype="f64" if args.precision == "fp64" else "f64+f32",
                 data="synthetic", config=dict(desc, tol=args.tol, precision=args.precision,
                                               preconditioner="teter", graph_iters=args.graph,
-                                              tuned=bool(args.tune), guard_columns=args.guard),
+                                              tuned=bool(args.tune), guard_columns=args.guard,
+                                              streams=args.streams),
                 roofline=roof, kernels=kernels,
                 iterations=dict(mean=float(np.mean(iters)), min=int(min(iters)), max=int(max(iters))),
                 converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}",

@@ -106,6 +106,10 @@ typedef struct dgdft_alb_opts {
                                * Must be < every n_states.  Outputs keep all       *
                                * n_states columns; the guard ones are returned as  *
                                * they stand                                        */
+    int32_t n_streams;        /* element groups iterating on their own HIP         *
+                               * streams, 1 or 2 (0 = 2): with two, one group's    *
+                               * small dense steps overlap the other's block       *
+                               * products                                          */
 } dgdft_alb_opts;
 
 /* Kleinman-Bylander projectors of the whole batch, CSR by projector

@@ -48,7 +48,8 @@ class Opts(C.Structure):
                 ("max_iter", C.c_int32), ("poll_every", C.c_int32),
                 ("elem_lo", C.POINTER(C.c_int32)), ("elem_hi", C.POINTER(C.c_int32)),
                 ("n_alb", C.POINTER(C.c_int32)), ("mlp_weights", C.c_void_p),
-                ("graph_iters", C.c_int32), ("tune", C.c_int32), ("n_guard", C.c_int32)]
+                ("graph_iters", C.c_int32), ("tune", C.c_int32), ("n_guard", C.c_int32),
+                ("n_streams", C.c_int32)]
 
 
 class KB(C.Structure):
@@ -170,7 +171,7 @@ class ALB:
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
                  elem_hi=None, n_alb=None, precond="teter", mlp_weights=None, graph_iters=0,
-                 tune=False, precision="fp64", n_guard=0):
+                 tune=False, precision="fp64", n_guard=0, n_streams=0):
         import torch  # noqa: F401  (device memory and streams)
         self.lib = load_library()
         self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
@@ -186,6 +187,7 @@ class ALB:
         o.graph_iters = int(graph_iters)
         o.tune = 1 if tune else 0
         o.n_guard = int(n_guard)
+        o.n_streams = int(n_streams)
         self.n_guard = int(n_guard)
         if mlp_weights is not None:
             self._mlp = mlp_weights

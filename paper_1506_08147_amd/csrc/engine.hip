@@ -819,6 +819,12 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     return DGDFT_EINVAL;
   }
   h->mlp_w = h->opts.mlp_weights;
+  if (h->opts.n_streams == 0) h->opts.n_streams = dgdft_alb::NGROUP;
+  if (h->opts.n_streams < 1 || h->opts.n_streams > dgdft_alb::NGROUP) {
+    g_create_error = "n_streams must be 1 or 2";
+    delete h;
+    return DGDFT_EINVAL;
+  }
   if (h->opts.n_guard < 0) {
     g_create_error = "n_guard must be >= 0";
     delete h;
@@ -1499,7 +1505,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
     HCHECK(hipEventRecord(h->g_join, h->g_stream[0]));
     for (int g = 1; g < dgdft_alb::NGROUP; ++g) HCHECK(hipStreamWaitEvent(h->g_stream[g], h->g_join, 0));
     std::vector<int> act[dgdft_alb::NGROUP];
-    for (size_t q = 0; q < pending.size(); ++q) act[q % dgdft_alb::NGROUP].push_back(pending[q]);
+    for (size_t q = 0; q < pending.size(); ++q) act[q % h->opts.n_streams].push_back(pending[q]);
     for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
       if (act[g].empty()) continue;
       h->set_group(g);
