@@ -1397,9 +1397,9 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
   h->update(act, u3);
   h->per_elem(act, 3, 0);
-  // the device carries the blocks while the residuals (polled before this
-  // iteration) are above CARRY_RES
-  for (int e : act) h->carry_host[e] = h->max_res(e) >= CARRY_RES;
+  // the device carries the blocks while the largest residual (polled before
+  // this iteration) is at least CARRY_RES, or always with guard columns
+  for (int e : act) h->carry_host[e] = h->max_res(e) >= CARRY_RES || h->eh[e].jc < h->eh[e].J;
 }
 
 // Graph mode: K iterations (each followed by the residual step) of the
