@@ -30,8 +30,8 @@ PEAK_HBM_GBS = 8000.0
 # command, calibrated on a 1 GiB copy (profiles/slab64_fp64_hbm_traffic.md):
 # (kernel class, workload, elements, guard columns, streams) -> bytes.  Valid for the kernel
 # build that was measured; removed when the kernel changes.
-MEASURED_TRAFFIC = {("dg_gram", "slab_36x36x60_J128", 64, 16, 2): 13.460e9,
-                    ("dg_update", "slab_36x36x60_J128", 64, 16, 2): 18.934e9}
+MEASURED_TRAFFIC = {("dg_gram", "slab_36x36x60_J128", 64, 16, 2): 12.344e9,
+                    ("dg_update", "slab_36x36x60_J128", 64, 16, 2): 18.935e9}
 # guard columns per element when --guard is not given: 16 on the slab (block
 # of 144 columns, the tile width of the 144-wide GEMM kernels), else none
 DEFAULT_GUARD = {"slab": 16}
