@@ -167,6 +167,8 @@ class ALB:
     grids: (n_elem, 3) ints; boxes: (n_elem, 3) bohr; n_states: (n_elem,).
     n_guard: the last n_guard of every element's n_states columns are guard
     columns (iterated, not held to tol, left out of the ALBs).
+    n_streams: element groups iterating on their own HIP streams (1 or 2;
+    0 = the library default, 2).
     """
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
