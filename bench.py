@@ -34,8 +34,8 @@ MEASURED_TRAFFIC = {("dg_gram", "slab_36x36x60_J128", 64, 16, 2): 12.344e9,
                     ("dg_update", "slab_36x36x60_J128", 64, 16, 2): 18.935e9}
 # guard columns per element when --guard is not given: 16 on the slab (block
 # of 144 columns, the tile width of the 144-wide GEMM kernels) and on the
-# uneven batch, none on the one-element workload
-DEFAULT_GUARD = {"slab": 16, "uneven": 16}
+# uneven batch, 8 on the one-element workload (32 states)
+DEFAULT_GUARD = {"slab": 16, "uneven": 16, "one": 8}
 
 
 def log(*a):
@@ -247,7 +247,7 @@ def main():
     ap.add_argument("--guard", type=int, default=None,
                     help="guard columns per element: the block holds n_states + G columns, "
                          "convergence and ALBs use the first n_states (default: 16 on the "
-                         "slab and the uneven batch, 0 on the one-element workload)")
+                         "slab and the uneven batch, 8 on the one-element workload)")
     ap.add_argument("--graph", type=int, default=0,
                     help="LOBPCG iterations per captured HIP graph launch (0: eager)")
     ap.add_argument("--tune", type=int, default=0, help="1: autotune the Gram split-K at create")
