@@ -54,8 +54,10 @@ def test_update_product_matches_numpy(dev, K, m, n):
 
 
 @pytest.mark.parametrize("method", [0, 1])
-@pytest.mark.parametrize("n,k", [(1, 1), (10, 10), (96, 32), (200, 64), (384, 128)])
+@pytest.mark.parametrize("n,k", [(1, 1), (10, 10), (96, 32), (200, 64), (384, 128), (432, 144)])
 def test_small_syev_matches_lapack(dev, n, k, method):
+    """n = 384 and 432 take the one-pass tridiagonalisation with 6 and 8 rows
+    per lane (the Rayleigh-Ritz sizes of blocks of 128 and 144 states)."""
     from paper_1506_08147_amd import small_syev
     rng = np.random.default_rng(n)
     M = rng.standard_normal((2, n, n))
