@@ -698,11 +698,12 @@ __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, d
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
   // Device path (tridiagonalize_fused) for n <= 512 with (waves + 2) * n
   // doubles of LDS scratch: 6 rows per lane and two columns per wave pass up
-  // to n = 384, else 8 rows per lane (the registers of a 1024-lane
-  // workgroup hold no more without spilling).
+  // to n = 384, else 7 or 8 rows per lane and one column per pass (the
+  // registers of a 1024-lane workgroup hold no more without spilling).
   if constexpr (T::is_device) {
     if (n <= 64 * 8 && scratch && (nw + 2) * n <= scratch_size) {
       if (n <= 64 * 6) tridiagonalize_fused<6, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
+      else if (n <= 64 * 7) tridiagonalize_fused<7, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
       else tridiagonalize_fused<8, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
       return;
     }
@@ -1199,6 +1200,7 @@ __host__ __device__ void backtransform(T& t, const double* A, int lda, const dou
                                        double* Z, int ldz, int k, double* lds, int lds_size) {
   if constexpr (T::is_device) {
     if (lds_size >= n && n <= 64 * 6) { bt_fast<6, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+    if (lds_size >= n && n <= 64 * 7) { bt_fast<7, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
     if (lds_size >= n && n <= 64 * 12) { bt_fast<12, 1>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
   }
   // generic path
