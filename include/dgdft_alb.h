@@ -422,7 +422,8 @@ int32_t dgdft_alb_nonlocal_block(dgdft_alb* h, const double* albs, double* out, 
  * the map from the restricted eigenvectors to the ALBs (zero column where
  * sigma = 0).  V: the potential loaded last, interpolated likewise.
  * eigvecs, albs, sigma: device, as dgdft_alb_solve writes them (eigvecs per
- * element N_g x J column-major with dV sum psi^2 = 1).  out: device
+ * element N_g x J column-major with dV sum psi^2 = 1; with guard columns
+ * only the first J - n_guard enter, as for the ALBs).  out: device
  * [sum n_alb^2], per element n_alb x n_alb column-major.  lgl_ratio in 1..8
  * with at most 1024 points per axis, else DGDFT_EINVAL.  The library holds a
  * workspace for the largest element between calls (released by destroy). */
