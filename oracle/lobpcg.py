@@ -26,6 +26,11 @@ Initial step: X <- X0 T (CholQR), HX = H X, Rayleigh-Ritz on X alone.
 Final step (once converged or out of iterations): HX is recomputed from
 scratch, Rayleigh-Ritz on X alone, FP64 residuals reported.
 
+Guard columns (optional, not in the paper): with n_check < J the block
+carries J - n_check extra columns that take part in every step but not in
+the stopping test of a. (nor in `converged`): the wanted n_check states then
+converge at the rate set by the gap to state J + 1.
+
 The oracle computes in this order with no blocking or fusion beyond
 NumPy/LAPACK calls on whole blocks.
 """
@@ -130,9 +135,12 @@ def next_direction(C, M, J):
     return D @ Rinv
 
 
-def lobpcg(apply_h, precond, X0, tol, max_iter) -> Result:
+def lobpcg(apply_h, precond, X0, tol, max_iter, n_check=None) -> Result:
     X0 = np.asarray(X0, dtype=np.float64)
     N, J = X0.shape
+    nc = J if n_check is None else int(n_check)
+    if not 1 <= nc <= J:
+        raise ValueError("n_check must be in 1..J")
     stats = Result(None, None, None, 0, False, [])
     T = scaled_cholqr(X0)
     if T is None:
@@ -146,8 +154,8 @@ def lobpcg(apply_h, precond, X0, tol, max_iter) -> Result:
     while True:
         R = HX - X * theta[None, :]
         r = np.linalg.norm(R, axis=0)
-        stats.history.append(float(r.max()))
-        if r.max() <= tol or it >= max_iter:
+        stats.history.append(float(r[:nc].max()))
+        if r[:nc].max() <= tol or it >= max_iter:
             break
         W = precond(R, X)
         B = X if P is None else np.hstack([X, P])
@@ -177,5 +185,5 @@ def lobpcg(apply_h, precond, X0, tol, max_iter) -> Result:
     X, HX = X @ C, HX @ C
     r = np.linalg.norm(HX - X * theta[None, :], axis=0)
     stats.theta, stats.X, stats.resid, stats.iters = theta, X, r, it
-    stats.converged = bool(r.max() <= tol)
+    stats.converged = bool(r[:nc].max() <= tol)
     return stats

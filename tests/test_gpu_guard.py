@@ -77,6 +77,16 @@ def test_guard_columns_match_dense_and_oracle():
         h.close()
     print("iterations without / with guards:", iters)
     assert iters[g] < iters[0]
+    # the oracle run the same way (guard columns, test on the 32 wanted
+    # states) takes about as many iterations
+    from oracle import lobpcg as lob, teter
+    from oracle.hamiltonian import Operator
+    op = Operator(el.grid, el.box, el.V, el.kb)
+    pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
+    X0g = np.hstack([el.X0, synth.guard_columns(el.ng, g, (0, J))])
+    refg = lob.lobpcg(op.apply, pre, X0g, 1e-8, 500, n_check=J)
+    print("oracle iterations with guards:", refg.iters)
+    assert refg.converged and abs(iters[g] - refg.iters) <= 3
 
 
 def test_guard_count_validated():

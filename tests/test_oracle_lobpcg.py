@@ -85,6 +85,30 @@ def test_one_element_workload_vs_stored_dense():
     assert np.all(res.theta >= w[:32] - 1e-12)
 
 
+def test_guard_columns_same_states_fewer_iterations():
+    """8 guard columns on the one-element workload (block of 40, the lowest
+    32 tested): the 32 eigenvalues equal the stored dense ones and bound them
+    from above, in fewer iterations than the block of 32; the guard Ritz
+    values still bound eigenvalues 33..40 from above."""
+    gold = json.load(open(GOLDEN))
+    w = np.asarray(gold["seeds"]["0"])
+    el = synth.single_element(seed=0)
+    op = Operator(el.grid, el.box, el.V, el.kb)
+    pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
+    X0 = np.hstack([el.X0, synth.guard_columns(el.ng, 8, (0, el.n_states))])
+    res = lob.lobpcg(op.apply, pre, X0, 1e-8, 400, n_check=32)
+    plain = lob.lobpcg(op.apply, pre, el.X0, 1e-8, 400)
+    assert res.converged and plain.converged
+    assert res.resid[:32].max() <= 1e-8
+    assert np.abs(res.theta[:32] - w[:32]).max() < 1e-10
+    assert np.all(res.theta[:32] >= w[:32] - 1e-12)
+    if len(w) >= 40:
+        assert np.all(res.theta[32:] >= w[32:40] - 1e-12)
+    assert res.iters < plain.iters
+    with pytest.raises(ValueError):
+        lob.lobpcg(op.apply, pre, X0, 1e-8, 1, n_check=41)
+
+
 def test_vs_arpack_on_slab_geometry():
     """An independent library (ARPACK through scipy) on a LinearOperator."""
     grid = (24, 24, 36)
