@@ -58,11 +58,12 @@ def workload(name, n_elem):
     return els, desc
 
 
-def cpu_baseline(el, tol):
-    """The oracle on one element of the same workload: its LOBPCG (block of
-    the element's n_states columns, no guard columns) run to the tolerance,
-    then the restriction + SVD truncation; one converged element per that
-    time."""
+def cpu_baseline(el, tol, n_guard):
+    """The oracle on one element of the same workload: its LOBPCG with the
+    same start block as the GPU (the element's n_states columns plus n_guard
+    guard columns, stopping test on the n_states wanted residuals) run to the
+    tolerance, then the restriction + SVD truncation; one converged element
+    per that time."""
     import numpy as np
     from oracle import alb, lobpcg as lob, teter
     from oracle.hamiltonian import FFT_WORKERS, Operator
@@ -74,15 +75,20 @@ def cpu_baseline(el, tol):
     op = Operator(el.grid, el.box, el.V, el.kb)
     pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
 
+    import synth
+    X0 = el.X0
+    if n_guard:
+        X0 = np.hstack([el.X0, synth.guard_columns(el.ng, n_guard, (0, el.n_states))])
     t = time.perf_counter()
-    res = lob.lobpcg(op.apply, pre, el.X0, tol, 500)
+    res = lob.lobpcg(op.apply, pre, X0, tol, 500, n_check=el.n_states)
     t_solve = time.perf_counter() - t
-    alb.restrict_svd(res.X, op.grid, el.elem_lo, el.elem_hi, op.dv, el.n_alb)
+    alb.restrict_svd(res.X[:, :el.n_states], op.grid, el.elem_lo, el.elem_hi, op.dv, el.n_alb)
     est = time.perf_counter() - t
     return dict(value=1.0 / est, unit="elements/s", cores=int(max(FFT_WORKERS, blas)),
                 kind="oracle",
                 sample=(f"element 0 of the workload: oracle LOBPCG to residual {tol:g} "
-                        f"({res.iters} iterations, converged={res.converged}, {t_solve:.1f} s) "
+                        f"({el.n_states} states + {n_guard} guard columns, {res.iters} "
+                        f"iterations, converged={res.converged}, {t_solve:.1f} s) "
                         f"+ ALB step: {est:.1f} s per converged element"))
 
 
@@ -391,7 +397,7 @@ def main():
         line["forms"] = forms
     if args.cpu_baseline:
         log("timing the oracle sample on the host")
-        line["cpu_baseline"] = cpu_baseline(els[0], args.tol)
+        line["cpu_baseline"] = cpu_baseline(els[0], args.tol, args.guard)
     print(json.dumps(line), flush=True)
 
 
