@@ -220,3 +220,24 @@ def test_stall_rule_flags_bands():
             assert not pre.fallback.any()
     # band 1: 0.97 > 0.9 * 1.0 at k = 3 -> fallback, kept afterwards
     assert list(pre.fallback) == [False, True]
+
+
+def test_normalisation_hand_computed_rows():
+    """Four (band, shell) rows written out by hand: band 1 has T = 2 and shells
+    t = 2, 2e, 2e^2 (x = 1, e, e^2, so log x = 0, 1, 2) with theta = 0.5; band
+    2 has T = 1 and one shell t = 1e-4 (x below the 1e-3 floor, so
+    log x = log 1e-3) with theta = 2.5; Vbar = -1 everywhere.  Population mean
+    and standard deviation per column from the standard library; the constant
+    Vbar column gets sd = 1."""
+    import math
+    import statistics
+    e = math.e
+    samples = [dict(t=np.array([2.0, 2.0 * e, 2.0 * e * e]), T=2.0, theta=0.5, vbar=-1.0),
+               dict(t=np.array([1e-4]), T=1.0, theta=2.5, vbar=-1.0)]
+    mu, sd = learned.normalisation(samples)
+    c0 = [0.0, 1.0, 2.0, math.log(1e-3)]
+    c1 = [0.5, 0.5, 0.5, 2.5]
+    assert abs(mu[0] - statistics.fmean(c0)) < 1e-14
+    assert abs(sd[0] - statistics.pstdev(c0)) < 1e-14
+    assert abs(mu[1] - 1.0) < 1e-15 and abs(sd[1] - math.sqrt(3.0) / 2.0) < 1e-15
+    assert mu[2] == -1.0 and sd[2] == 1.0

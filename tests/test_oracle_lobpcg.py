@@ -153,3 +153,149 @@ def test_solve_element_normalisation():
     assert np.abs(dv * psi.T @ psi - np.eye(8)).max() < 1e-12
     phi = out["albs"]
     assert np.abs(dv * phi.T @ phi - np.eye(el.n_alb)).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Fallback branches of the oracle's LOBPCG (Sec. II.B; Knyazev's method as
+# cited there): SVQB orthonormalisation, the rank-deficient Rayleigh-Ritz
+# reduction and the next search direction (with its P-drop case), each
+# pinned by linear algebra that does not go through the oracle.
+
+def _scaled(Y):
+    return Y / np.linalg.norm(Y, axis=0)[None, :]
+
+
+def test_svqb_orthonormalises_a_well_conditioned_block():
+    rng = np.random.default_rng(11)
+    Y = rng.standard_normal((300, 12)) * np.logspace(-3, 3, 12)[None, :]
+    T = lob.svqb(Y)
+    Q = Y @ T
+    assert np.abs(Q.T @ Q - np.eye(12)).max() < 1e-12
+    # span preserved (principal angles from an SVD-based library routine)
+    import scipy.linalg as sla
+    assert sla.subspace_angles(Y, Q).max() < 1e-10
+
+
+def test_svqb_nearly_dependent_block_clamps_only_the_small_directions():
+    """Two columns 1e-6 apart (after scaling): the scaled CholQR refuses the
+    block, SVQB returns mutually orthogonal columns whose squared norms are
+    min(1, s_i^2 / (1e-10 s_max^2)), s_i the singular values of the
+    column-scaled block (from an SVD, not the oracle's eigh)."""
+    rng = np.random.default_rng(12)
+    Y = rng.standard_normal((400, 10)) * np.linspace(0.5, 20.0, 10)[None, :]
+    Y[:, 7] = 3.0 * (Y[:, 2] + 1e-6 * np.linalg.norm(Y[:, 2]) / 20.0 * rng.standard_normal(400))
+    assert lob.scaled_cholqr(Y) is None
+    T = lob.svqb(Y)
+    G = (Y @ T).T @ (Y @ T)
+    s = np.linalg.svd(_scaled(Y), compute_uv=False)
+    lam = np.sort(s ** 2)
+    expect = np.minimum(1.0, lam / (lob.CHOL_TOL * lam.max()))
+    assert expect[0] < 0.1   # the small direction really is clamped
+    assert np.abs(np.diag(G) - expect).max() < 1e-5
+    assert np.abs(G - np.diag(np.diag(G))).max() < 1e-9
+    import scipy.linalg as sla
+    assert sla.subspace_angles(Y, Y @ T).max() < 1e-8
+
+
+def _sym_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    H = A + A.T
+    w, U = np.linalg.eigh(H)
+    return rng, H, w, U
+
+
+def test_rayleigh_ritz_full_rank_nonorthonormal_basis():
+    rng, H, w, U = _sym_problem(60, 13)
+    J = 6
+    S = U[:, :J + 3] @ rng.standard_normal((J + 3, J + 3))
+    st = lob.Result(None, None, None, 0, False, [])
+    theta, C, M = lob.rayleigh_ritz(S, H @ S, J, st)
+    X = S @ C
+    assert st.n_rr_fallback == 0
+    assert np.abs(theta - w[:J]).max() < 1e-11
+    assert np.abs(X.T @ X - np.eye(J)).max() < 1e-11
+    assert np.abs(H @ X - X * theta[None, :]).max() < 1e-10
+
+
+def test_rayleigh_ritz_rank_deficient_basis_takes_the_reduction():
+    """A basis with a duplicated column: M is singular, the oracle reduces to
+    the eigenvectors of M, and still returns the exact lowest pairs of H on
+    the span (which holds the J + 3 lowest eigenvectors)."""
+    rng, H, w, U = _sym_problem(60, 14)
+    J = 6
+    A = U[:, :J + 3] @ rng.standard_normal((J + 3, J + 3))
+    S = np.hstack([A, A[:, [1]]])
+    st = lob.Result(None, None, None, 0, False, [])
+    theta, C, M = lob.rayleigh_ritz(S, H @ S, J, st)
+    X = S @ C
+    assert st.n_rr_fallback == 1
+    assert np.abs(theta - w[:J]).max() < 1e-11
+    assert np.abs(X.T @ X - np.eye(J)).max() < 1e-10
+    assert np.abs(H @ X - X * theta[None, :]).max() < 1e-9
+    # fewer than J independent columns: breakdown
+    S2 = np.hstack([A[:, :J - 1], A[:, [0]]])
+    with pytest.raises(lob.Breakdown):
+        lob.rayleigh_ritz(S2, H @ S2, J, st)
+
+
+def test_next_direction_is_the_orthogonal_complement():
+    """D spans the part of S [0; C_P; C_W] orthogonal to S C, with
+    (S D)^T (S D) = I: checked by orthogonality, normalisation and a rank
+    count of the combined span against [C, E]."""
+    rng, H, w, U = _sym_problem(90, 15)
+    J = 5
+    S = rng.standard_normal((90, 3 * J))
+    st = lob.Result(None, None, None, 0, False, [])
+    theta, C, M = lob.rayleigh_ritz(S, H @ S, J, st)
+    D = lob.next_direction(C, M, J)
+    assert D is not None
+    X, P = S @ C, S @ D
+    assert np.abs(P.T @ P - np.eye(J)).max() < 1e-10
+    assert np.abs(X.T @ P).max() < 1e-10
+    E = C.copy()
+    E[:J] = 0.0
+    # D lies in span[C, E] and together with C spans all of it
+    B = np.hstack([C, E])
+    coef = np.linalg.lstsq(B, D, rcond=None)[0]
+    assert np.abs(B @ coef - D).max() < 1e-10
+    assert np.linalg.matrix_rank(np.hstack([C, D]), tol=1e-8) == np.linalg.matrix_rank(B, tol=1e-8)
+
+
+def test_next_direction_drops_p_when_ritz_vectors_stay_in_x():
+    """When the Ritz vectors have no P or W component (C = [I; 0; 0]) there
+    is no new direction: the oracle returns None (P is dropped)."""
+    J = 4
+    C = np.zeros((3 * J, J))
+    C[:J] = np.eye(J)
+    assert lob.next_direction(C, np.eye(3 * J), J) is None
+
+
+def test_lobpcg_without_p_still_reaches_the_dense_eigenvalues(monkeypatch):
+    """Every iteration takes the P-drop path (next_direction forced to None):
+    the method degenerates to a block preconditioned steepest descent and
+    must still converge to the dense eigenvalues."""
+    el = synth.single_element(seed=2, grid=(12, 12, 12), n_states=6, n_atoms=3)
+    monkeypatch.setattr(lob, "next_direction", lambda C, M, J: None)
+    op, res = _run(el, 1e-9, max_iter=800)
+    assert res.converged and res.n_p_drop == res.iters > 0
+    w, _ = dense.lowest(op.dense(), 8)
+    assert np.abs(res.theta - w[:6]).max() < 1e-10
+
+
+def test_lobpcg_with_svqb_for_every_w_reaches_the_dense_eigenvalues(monkeypatch):
+    """Every W orthonormalisation takes the SVQB branch (the CholQR of W
+    forced to fail; the initial block keeps its CholQR)."""
+    el = synth.single_element(seed=2, grid=(12, 12, 12), n_states=6, n_atoms=3)
+    real = lob.scaled_cholqr
+    calls = {"n": 0}
+
+    def first_only(Y):
+        calls["n"] += 1
+        return real(Y) if calls["n"] == 1 else None
+
+    monkeypatch.setattr(lob, "scaled_cholqr", first_only)
+    op, res = _run(el, 1e-9)
+    assert res.converged and res.n_chol_fallback == res.iters > 0
+    w, _ = dense.lowest(op.dense(), 8)
+    assert np.abs(res.theta - w[:6]).max() < 1e-10
