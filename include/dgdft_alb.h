@@ -218,6 +218,43 @@ int32_t dgdft_alb_apply_h(dgdft_alb* h, int32_t elem, const double* X, double* H
 int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R,
                                const double* X, double* W, int32_t ncols, void* stream);
 
+/* Block orthonormalisation step of the LOBPCG iteration (Sec. II.B: the
+ * correction block W is made orthonormal before H is applied to it), on the
+ * solver's own kernel, exported so its branches can be tested: for the
+ * J x J Gram G = Y^T Y of a block Y (J = n_states of element `elem`;
+ * device, column-major, upper triangle read) returns T (device [J*J],
+ * column-major) with Y T orthonormal:
+ *   CholQR: T = D^-1 L^-T with D^-1 G D^-1 = L L^T, D = diag(G)^1/2, when
+ *           every pivot^2 of L exceeds 1e-10;
+ *   SVQB:   otherwise T = D^-1 U Lambda^-1/2, D^-1 G D^-1 = U Lambda U^T
+ *           with Lambda clamped below at 1e-10 max(Lambda).
+ * init = 1 treats the block as the initial guess: a failed pivot test then
+ * marks breakdown (flags[3]) instead of taking SVQB (T is still written).
+ * flags: host [6] = SVQB fallbacks, Rayleigh-Ritz fallbacks, P drops,
+ * breakdown, Rayleigh-Ritz reduction path, eigensolver iteration-cap hits.
+ * Uses the element's workspace; not concurrent with a solve on h. */
+int32_t dgdft_alb_orthonormalise(dgdft_alb* h, int32_t elem, const double* G, double* T,
+                                 int32_t init, int32_t* flags, void* stream);
+
+/* Rayleigh-Ritz step of the LOBPCG iteration (operation 4 of the list in
+ * Sec. II.B) on the solver's own kernels, exported so its branches can be
+ * tested.  With J = n_states of element `elem` and n = kb J (kb = 1: the
+ * basis X alone; 2: [X W]; 3: [X P W]), Hh and M (device, n x n column-major,
+ * upper triangles read) are S^T H S and S^T S.  Outputs (device): theta [J]
+ * the lowest generalised eigenvalues of (Hh, M) ascending; C [n*J] the
+ * coefficients with C^T M C = I; for kb > 1, D [n*J] the next search
+ * direction: the part of [0; C_P; C_W] (C with its first J rows zeroed)
+ * M-orthogonal to C, normalised so that D^T M D = I, or all zero when that
+ * normalisation breaks down (P is then dropped, flags[2]).  Reductions: the
+ * binomial series for M^-1/2 when ||M - I||_F <= 1e-4 (kb > 1), a scaled
+ * Cholesky of M, or, when M is not numerically positive definite, its
+ * eigenvectors above 1e-10 of the largest eigenvalue (flags[1]; fewer than J
+ * of them sets flags[3]).  flags: host [6] as for dgdft_alb_orthonormalise.
+ * Uses the element's workspace; not concurrent with a solve on h. */
+int32_t dgdft_alb_rayleigh_ritz(dgdft_alb* h, int32_t elem, int32_t kb, const double* Hh,
+                                const double* M, double* theta, double* C, double* D,
+                                int32_t* flags, void* stream);
+
 /* Batched FP64 symmetric eigensolver used for the Rayleigh-Ritz step
  * (operation 4 of the LOBPCG list in Sec. II.B): for each of `count` n x n
  * matrices A (device, column-major, lda = n, only the upper triangle read),

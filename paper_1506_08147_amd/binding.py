@@ -22,6 +22,7 @@ EXPORTS = (
     "dgdft_alb_set_mlp", "dgdft_alb_shells", "dgdft_alb_log_capacity", "dgdft_alb_log_pairs",
     "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
     "dgdft_alb_density", "dgdft_alb_nonlocal_block", "dgdft_alb_dg_volume",
+    "dgdft_alb_orthonormalise", "dgdft_alb_rayleigh_ritz",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
@@ -143,6 +144,10 @@ def load_library():
     lib.dgdft_alb_nonlocal_block.restype = i32
     lib.dgdft_alb_dg_volume.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     lib.dgdft_alb_dg_volume.restype = i32
+    lib.dgdft_alb_orthonormalise.argtypes = [vp, i32, vp, vp, i32, P(i32), vp]
+    lib.dgdft_alb_orthonormalise.restype = i32
+    lib.dgdft_alb_rayleigh_ritz.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, P(i32), vp]
+    lib.dgdft_alb_rayleigh_ritz.restype = i32
     _lib = lib
     return lib
 
@@ -398,6 +403,35 @@ class ALB:
         self._check(self.lib.dgdft_alb_precondition(self.h, e, _ptr(R), _ptr(X), _ptr(W),
                                                     R.shape[0], _stream()))
         return W
+
+    def orthonormalise(self, e, G, init=False):
+        """T (J x J) with Y T orthonormal for the Gram G = Y^T Y (device
+        float64, J x J); returns (T, flags) with flags as in the header."""
+        import torch
+        Gc = G.t().contiguous()   # column-major
+        T = torch.empty_like(Gc)
+        fl = np.zeros(6, dtype=np.int32)
+        self._check(self.lib.dgdft_alb_orthonormalise(
+            self.h, e, _ptr(Gc), _ptr(T), int(bool(init)),
+            fl.ctypes.data_as(C.POINTER(C.c_int32)), _stream()))
+        return T.t(), fl
+
+    def rayleigh_ritz(self, e, kb, Hh, M):
+        """(theta, C, D, flags) of the Rayleigh-Ritz step on n x n matrices
+        Hh = S^T H S, M = S^T S (device float64, n = kb J); C, D are n x J
+        (D is None for kb = 1)."""
+        import torch
+        J = self.sizes[e]["J"]
+        n = kb * J
+        Hc, Mc = Hh.t().contiguous(), M.t().contiguous()
+        th = torch.empty(J, dtype=torch.float64, device=Hh.device)
+        Cm = torch.empty(J, n, dtype=torch.float64, device=Hh.device)
+        Dm = torch.empty(J, n, dtype=torch.float64, device=Hh.device) if kb > 1 else None
+        fl = np.zeros(6, dtype=np.int32)
+        self._check(self.lib.dgdft_alb_rayleigh_ritz(
+            self.h, e, int(kb), _ptr(Hc), _ptr(Mc), _ptr(th), _ptr(Cm), _ptr(Dm),
+            fl.ctypes.data_as(C.POINTER(C.c_int32)), _stream()))
+        return th, Cm.t(), (Dm.t() if Dm is not None else None), fl
 
     def profile(self, enable=True):
         """Enable per-kernel HIP-event timing and reset the counters."""

@@ -517,6 +517,11 @@ struct dgdft_alb {
       sgemm(act, single, 0, 0, SM_T, 0, SM_U, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
     }
     rr_one(act, dg_rr_eig, SMALL_THREADS, single);
+    {
+      bool wide = false;
+      for (int e : act) wide = wide || eig_wide((single ? 1 : (hasP_host(e) ? 3 : 2)) * eh[e].J);
+      if (wide) rr_one(act, dg_rr_eig_wide, EIG_WIDE_THREADS, single);
+    }
     // path 0: C = L^-T Y
     sgemm(act, single, 0, 0, SM_T, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, 1.0, 0.0, 0);
     // path 3: C = T Y
@@ -1716,6 +1721,91 @@ int32_t dgdft_alb_precondition(dgdft_alb* h, int32_t elem, const double* R, cons
   }
 }
 
+// Status words of one element to the host (after its stream has been synchronised).
+static void read_flags(dgdft_alb* h, int elem, int32_t* flags) {
+  int f[FL_COUNT];
+  HCHECK(hipMemcpyAsync(f, h->fl_arena + (size_t)elem * FL_COUNT, sizeof(f), hipMemcpyDeviceToHost,
+                        h->stream));
+  HCHECK(hipStreamSynchronize(h->stream));
+  flags[0] = f[FL_W_SVQB];
+  flags[1] = f[FL_RR_FALLBACK];
+  flags[2] = f[FL_P_DROP];
+  flags[3] = f[FL_BREAKDOWN];
+  flags[4] = f[FL_RR_PATH];
+  flags[5] = f[FL_QL_FAIL];
+}
+
+// Clear the element's status words and set P presence (start of a step test).
+static void reset_flags(dgdft_alb* h, int elem, int hasp) {
+  int f[FL_COUNT] = {};
+  f[FL_HASP] = hasp;
+  HCHECK(hipMemcpyAsync(h->fl_arena + (size_t)elem * FL_COUNT, f, sizeof(f), hipMemcpyHostToDevice,
+                        h->stream));
+  HCHECK(hipStreamSynchronize(h->stream));
+}
+
+int32_t dgdft_alb_orthonormalise(dgdft_alb* h, int32_t elem, const double* G, double* T,
+                                 int32_t init, int32_t* flags, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (elem < 0 || elem >= h->n || !G || !T || !flags) {
+    h->err = "orthonormalise: bad element or pointer";
+    return DGDFT_EINVAL;
+  }
+  bind_stream(h, stream);
+  try {
+    h->ring_reset();
+    const Elem& E = h->eh[elem];
+    const size_t nn = (size_t)E.J * E.J;
+    reset_flags(h, elem, 0);
+    HCHECK(hipMemcpyAsync(sm(E, SM_G), G, sizeof(double) * nn, hipMemcpyDeviceToDevice, h->stream));
+    std::vector<int> one{elem};
+    h->per_elem(one, 0, init ? 1 : 0);
+    HCHECK(hipMemcpyAsync(T, sm(E, SM_T), sizeof(double) * nn, hipMemcpyDeviceToDevice, h->stream));
+    read_flags(h, elem, flags);
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_alb_rayleigh_ritz(dgdft_alb* h, int32_t elem, int32_t kb, const double* Hh,
+                                const double* M, double* theta, double* Cout, double* Dout,
+                                int32_t* flags, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (elem < 0 || elem >= h->n || kb < 1 || kb > 3 || !Hh || !M || !theta || !Cout || !flags ||
+      (kb > 1 && !Dout)) {
+    h->err = "rayleigh_ritz: bad element, block count or pointer";
+    return DGDFT_EINVAL;
+  }
+  bind_stream(h, stream);
+  try {
+    h->ring_reset();
+    const Elem& E = h->eh[elem];
+    const int J = E.J, n = kb * J;
+    const size_t nn = (size_t)n * n;
+    // kb = 2 is the basis [X W] (no P), kb = 3 is [X P W]
+    reset_flags(h, elem, kb == 3);
+    h->h_fl[(size_t)elem * FL_COUNT + FL_HASP] = kb == 3;   // host mirror for the launch shapes
+    HCHECK(hipMemcpyAsync(sm(E, SM_H), Hh, sizeof(double) * nn, hipMemcpyDeviceToDevice, h->stream));
+    HCHECK(hipMemcpyAsync(sm(E, SM_M), M, sizeof(double) * nn, hipMemcpyDeviceToDevice, h->stream));
+    std::vector<int> one{elem};
+    h->rr_step(one, kb == 1);
+    HCHECK(hipMemcpyAsync(theta, E.theta, sizeof(double) * J, hipMemcpyDeviceToDevice, h->stream));
+    HCHECK(hipMemcpyAsync(Cout, sm(E, SM_C), sizeof(double) * (size_t)n * J, hipMemcpyDeviceToDevice,
+                          h->stream));
+    if (kb > 1)
+      HCHECK(hipMemcpyAsync(Dout, sm(E, SM_C) + (size_t)n * J, sizeof(double) * (size_t)n * J,
+                            hipMemcpyDeviceToDevice, h->stream));
+    read_flags(h, elem, flags);
+    h->h_fl[(size_t)elem * FL_COUNT + FL_HASP] = 0;
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
 }  // extern "C"
 
 extern "C" {
@@ -1779,8 +1869,12 @@ int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A, d
     TmpDev t;
     double* work = t.alloc<double>((size_t)count * (2 * (size_t)n * n + 8 * (size_t)n +
                                                     6 * (size_t)n * k));
-    hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
-                       method);
+    if (method == 0 && eig_wide(n))
+      hipLaunchKernelGGL(dg_syev_batch_wide, dim3(count), dim3(EIG_WIDE_THREADS), 0, s, A, w, Z, n, k,
+                         work);
+    else
+      hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
+                         method);
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(s));
     return DGDFT_OK;

@@ -308,22 +308,46 @@ dg_carry_in(Elem* __restrict__ E, const int* __restrict__ active, int na) {
   }
 }
 
-extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
-dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
-  __shared__ double red[32];
-  __shared__ double lds[EIG_LDS];
+// Matrices of order EIG_WIDE_MIN..EIG_WIDE_MAX go to dg_rr_eig_wide: 512-lane
+// workgroups whose 256 registers per lane hold 13 rows of the one-pass
+// tridiagonalisation and back-transformation per lane (the 1024-lane
+// workgroup holds 8, so above order 512 it would take the three-pass form).
+constexpr int EIG_WIDE_MIN = 513;
+constexpr int EIG_WIDE_MAX = 832;
+constexpr int EIG_WIDE_THREADS = 512;
+
+__host__ __device__ inline bool eig_wide(int n) { return n >= EIG_WIDE_MIN && n <= EIG_WIDE_MAX; }
+
+template <bool WIDE>
+__device__ __forceinline__ void rr_eig_body(Elem* __restrict__ E, const int* __restrict__ active,
+                                            int single, double* red, double* lds) {
   DevTeam t{red};
   const Elem& e = E[active[blockIdx.x]];
   if (e.fl[FL_RR_PATH] == 1) return;
   const int J = e.J;
   const int kb = single ? 1 : (has_p(e) ? 3 : 2);
   const int n = kb * J;
+  if (eig_wide(n) != WIDE) return;   // the other kernel's element
   double* A = sm(e, SM_A);
   double* Z = sm(e, SM_Z);
   double* vec = sm(e, SM_V);
   double* w = vec + 7 * n;
   // workspace: SM_W0 and SM_W1 (consecutive)
-  syev_lowest(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, EIG_LDS);
+  syev_lowest<WIDE>(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, EIG_LDS);
+}
+
+extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
+dg_rr_eig(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  __shared__ double lds[EIG_LDS];
+  rr_eig_body<false>(E, active, single, red, lds);
+}
+
+extern "C" __global__ void __launch_bounds__(EIG_WIDE_THREADS)
+dg_rr_eig_wide(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  __shared__ double lds[EIG_LDS];
+  rr_eig_body<true>(E, active, single, red, lds);
 }
 
 // Path 3: T = I - E/2 + 3 E^2/8 - 5 E^3/16 from E (SM_L), E^2 (SM_U) and
@@ -596,5 +620,21 @@ dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, 
   } else {
     syev_lowest(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, EIG_LDS);
   }
+}
+
+// method 0 for orders EIG_WIDE_MIN..EIG_WIDE_MAX on the wide-register path of
+// dg_rr_eig_wide (same layout as dg_syev_batch).
+extern "C" __global__ void __launch_bounds__(EIG_WIDE_THREADS)
+dg_syev_batch_wide(const double* __restrict__ A, double* w, double* Z, int n, int k, double* work) {
+  __shared__ double red[32];
+  __shared__ double lds[EIG_LDS];
+  DevTeam t{red};
+  long long b = blockIdx.x;
+  double* Aw = work + b * (2LL * n * n + 8LL * n + 6LL * n * k);
+  double* U = Aw + (long long)n * n;
+  double* vec = U + (long long)n * n;
+  copy_mat(t, A + b * n * n, n, Aw, n, n, n);
+  sym_from_upper(t, Aw, n, n);
+  syev_lowest<true>(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, EIG_LDS);
 }
 }  // namespace dg

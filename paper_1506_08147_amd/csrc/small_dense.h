@@ -691,11 +691,21 @@ __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d,
 // Householder tridiagonalisation reading and updating only the lower
 // triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
 // scratch of n doubles each (LDS on the device).
-template <class T>
+// WIDE: instantiate the wide-register device path (13 rows per lane, two
+// columns per wave pass, n <= 832), for workgroups of at most 512 lanes whose
+// 256 registers per lane hold it.
+template <bool WIDE = false, class T>
 __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
                                               double* tau, double* v, double* p,
                                               double* scratch = nullptr, int scratch_size = 0) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  if constexpr (T::is_device && WIDE) {
+    if (n <= 64 * 13 && scratch && (nw + 2) * n <= scratch_size) {
+      if (n <= 64 * 10) tridiagonalize_fused<10, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
+      else tridiagonalize_fused<13, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
+      return;
+    }
+  }
   // Device path (tridiagonalize_fused) for n <= 512 with (waves + 2) * n
   // doubles of LDS scratch: 6 rows per lane and two columns per wave pass up
   // to n = 384, else 7 or 8 rows per lane and one column per pass (the
@@ -1195,9 +1205,12 @@ __device__ __forceinline__ void bt_fast(T& t, const double* A, int lda, const do
   }
 }
 
-template <class T>
+template <bool WIDE = false, class T>
 __host__ __device__ void backtransform(T& t, const double* A, int lda, const double* tau, int n,
                                        double* Z, int ldz, int k, double* lds, int lds_size) {
+  if constexpr (T::is_device && WIDE) {
+    if (lds_size >= n && n <= 64 * 13) { bt_fast<13, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+  }
   if constexpr (T::is_device) {
     if (lds_size >= n && n <= 64 * 6) { bt_fast<6, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
     if (lds_size >= n && n <= 64 * 7) { bt_fast<7, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
@@ -1227,15 +1240,16 @@ __host__ __device__ void backtransform(T& t, const double* A, int lda, const dou
 // Lowest k eigenpairs of the symmetric A (lower triangle read, destroyed):
 // w[0..k) ascending, Z (n x k).  work: 9 n + 6 n k doubles; cl: k ints
 // (global); lds: >= 2n doubles (and >= k for the generic back-transform).
-template <class T>
+// WIDE: the wide-register device paths (workgroups of at most 512 lanes).
+template <bool WIDE = false, class T>
 __host__ __device__ void syev_lowest(T& t, double* A, int lda, int n, int k, double* w, double* Z,
                                      int ldz, double* work, int* cl, double* lds, int lds_size) {
   double* d = work;
   double* e = work + n;
   double* tau = work + 2 * n;
-  tridiagonalize_lower(t, A, lda, n, d, e, tau, lds, lds + n, lds + 2 * n, lds_size - 2 * n);
+  tridiagonalize_lower<WIDE>(t, A, lda, n, d, e, tau, lds, lds + n, lds + 2 * n, lds_size - 2 * n);
   tridiag_lowest(t, d, e, n, k, w, Z, ldz, work + 3 * n, cl, lds, lds_size);
-  backtransform(t, A, lda, tau, n, Z, ldz, k, lds, lds_size);
+  backtransform<WIDE>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size);
 }
 
 }  // namespace dg

@@ -53,11 +53,17 @@ def test_update_product_matches_numpy(dev, K, m, n):
         assert np.abs(C[i].T - ref).max() <= 1e-13 * np.sqrt(m) * 10
 
 
-@pytest.mark.parametrize("method", [0, 1])
-@pytest.mark.parametrize("n,k", [(1, 1), (10, 10), (96, 32), (200, 64), (384, 128), (432, 144)])
+@pytest.mark.parametrize("method,n,k", [(m, n, k) for m in (0, 1) for n, k in
+                                         [(1, 1), (10, 10), (96, 32), (200, 64), (384, 128),
+                                          (432, 144)]] +
+                         [(0, 480, 160), (0, 600, 200), (0, 768, 256), (0, 816, 272),
+                          (0, 900, 300)])
 def test_small_syev_matches_lapack(dev, n, k, method):
-    """n = 384 and 432 take the one-pass tridiagonalisation with 6 and 8 rows
-    per lane (the Rayleigh-Ritz sizes of blocks of 128 and 144 states)."""
+    """Method 0 takes the one-pass tridiagonalisation with 6 rows per lane up
+    to n = 384, 7 up to 448 and 8 up to 512 (1024-lane workgroups), 10 up to
+    640 and 13 up to 832 (512-lane workgroups; the Rayleigh-Ritz sizes of
+    blocks of up to 272 states), and the three-pass form above; the
+    back-transformation likewise (6, 7, 12 rows per lane, 13 on 512 lanes)."""
     from paper_1506_08147_amd import small_syev
     rng = np.random.default_rng(n)
     M = rng.standard_normal((2, n, n))
