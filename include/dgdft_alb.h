@@ -266,6 +266,20 @@ int32_t dgdft_alb_rayleigh_ritz(dgdft_alb* h, int32_t elem, int32_t kb, const do
 int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A,
                          double* w, double* Z, int32_t method, void* stream);
 
+/* dgdft_small_syev without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and kernels; the eigensolver's
+ * workspace is a static device array of 4 Mi doubles (32 MiB) that every GPU
+ * the library runs on holds until the process ends, so
+ *   count * (2 n^2 + 8 n + 6 n k) <= 4194304
+ * or DGDFT_EINVAL (message in dgdft_alb_last_error(NULL)).  A, w, Z stay the
+ * caller's.  All calls on one GPU share that GPU's workspace: calls that
+ * overlap in time on one GPU (two streams, two threads) race and must be
+ * serialised by the caller.  The workspace keeps the last call's contents;
+ * the kernels write every part of it they read.  Synchronises `stream`. */
+int32_t dgdft_small_syev_noalloc(int32_t count, int32_t n, int32_t k, const double* A,
+                                 double* w, double* Z, int32_t method, void* stream);
+
 /* Batched tall-skinny FP64 product on matrix cores (operations 2 and 3 of the
  * LOBPCG list in Sec. II.B), exported for tests:
  *   trans == 1: C (m x n) = A^T B with A (K x m), B (K x n)

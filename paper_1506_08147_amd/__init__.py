@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     mlp_train,
     small_gemm_batched,
     small_syev,
+    small_syev_noalloc,
     LIB_PATH,
     EXPORTS,
 )

@@ -22,7 +22,7 @@ EXPORTS = (
     "dgdft_alb_set_mlp", "dgdft_alb_shells", "dgdft_alb_log_capacity", "dgdft_alb_log_pairs",
     "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
     "dgdft_alb_density", "dgdft_alb_nonlocal_block", "dgdft_alb_dg_volume",
-    "dgdft_alb_orthonormalise", "dgdft_alb_rayleigh_ritz",
+    "dgdft_alb_orthonormalise", "dgdft_alb_rayleigh_ritz", "dgdft_small_syev_noalloc",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
@@ -107,6 +107,8 @@ def load_library():
     lib.dgdft_alb_precondition.restype = i32
     lib.dgdft_small_syev.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp]
     lib.dgdft_small_syev.restype = i32
+    lib.dgdft_small_syev_noalloc.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp]
+    lib.dgdft_small_syev_noalloc.restype = i32
     lib.dgdft_gemm_batched.argtypes = [i32, i32, i64, i32, i32, dbl, vp, vp, dbl, vp, vp]
     lib.dgdft_gemm_batched.restype = i32
     lib.dgdft_alb_last_error.argtypes = [vp]
@@ -469,6 +471,25 @@ def small_syev(A, k, method=0):
     w = torch.empty(count, n, dtype=torch.float64, device=A.device)
     Z = torch.empty(count, k, n, dtype=torch.float64, device=A.device)
     rc = lib.dgdft_small_syev(count, n, k, _ptr(A), _ptr(w), _ptr(Z), int(method), _stream())
+    if rc != 0:
+        raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
+    return w, Z
+
+
+def small_syev_noalloc(A, k, method=0, w=None, Z=None):
+    """dgdft_small_syev_noalloc: as small_syev, with the library's static
+    workspace (no device allocation inside the call).  Output tensors may be
+    passed in (w: (count, n), Z: (count, k, n)) so that nothing is allocated
+    here either; raises DGDFTError (EINVAL) when the batch exceeds the
+    workspace."""
+    import torch
+    lib = load_library()
+    count, n, _ = A.shape
+    if w is None:
+        w = torch.empty(count, n, dtype=torch.float64, device=A.device)
+    if Z is None:
+        Z = torch.empty(count, k, n, dtype=torch.float64, device=A.device)
+    rc = lib.dgdft_small_syev_noalloc(count, n, k, _ptr(A), _ptr(w), _ptr(Z), int(method), _stream())
     if rc != 0:
         raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())
     return w, Z

@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <vector>
 
 using namespace dg;
@@ -1855,27 +1856,42 @@ struct TmpDev {
 };
 }  // namespace
 
+// Workspace doubles of the batched eigensolver per matrix (its matrix copy,
+// eigenvector accumulator, vectors and inverse-iteration work).
+static size_t syev_work_doubles(int n, int k) {
+  return 2 * (size_t)n * n + 8 * (size_t)n + 6 * (size_t)n * k;
+}
+
+static bool syev_args_ok(int32_t count, int32_t n, int32_t k, const double* A, const double* w,
+                         const double* Z, int32_t method) {
+  return count >= 1 && n >= 1 && n <= 3072 && k >= 1 && k <= n && A && w && Z && method >= 0 &&
+         method <= 1;
+}
+
+static void launch_syev(int32_t count, int32_t n, int32_t k, const double* A, double* w, double* Z,
+                        int32_t method, double* work, hipStream_t s) {
+  if (method == 0 && eig_wide(n))
+    hipLaunchKernelGGL(dg_syev_batch_wide, dim3(count), dim3(EIG_WIDE_THREADS), 0, s, A, w, Z, n, k,
+                       work);
+  else
+    hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
+                       method);
+  HCHECK(hipGetLastError());
+}
+
 extern "C" {
 
 int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A, double* w, double* Z,
                          int32_t method, void* stream) {
-  if (count < 1 || n < 1 || n > 3072 || k < 1 || k > n || !A || !w || !Z || method < 0 ||
-      method > 1) {
+  if (!syev_args_ok(count, n, k, A, w, Z, method)) {
     g_create_error = "small_syev: bad arguments";
     return DGDFT_EINVAL;
   }
   hipStream_t s = (hipStream_t)stream;
   try {
     TmpDev t;
-    double* work = t.alloc<double>((size_t)count * (2 * (size_t)n * n + 8 * (size_t)n +
-                                                    6 * (size_t)n * k));
-    if (method == 0 && eig_wide(n))
-      hipLaunchKernelGGL(dg_syev_batch_wide, dim3(count), dim3(EIG_WIDE_THREADS), 0, s, A, w, Z, n, k,
-                         work);
-    else
-      hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
-                         method);
-    HCHECK(hipGetLastError());
+    double* work = t.alloc<double>((size_t)count * syev_work_doubles(n, k));
+    launch_syev(count, n, k, A, w, Z, method, work, s);
     HCHECK(hipStreamSynchronize(s));
     return DGDFT_OK;
   } catch (HipFail& f) {
@@ -2544,6 +2560,81 @@ int32_t dgdft_alb_nonlocal_block(dgdft_alb* h, const double* albs, double* out, 
     return DGDFT_OK;
   } catch (HipFail& f) {
     h->err = f.what;
+    return DGDFT_EHIP;
+  }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of dgdft_small_syev for callers that cannot
+// allocate device memory (code under graph capture, serving loops).  The
+// eigensolver's workspace is a file-scope device array of fixed size: every
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it only stands
+// for the symbol): the device address is looked up once per device with
+// hipGetSymbolAddress and kept per device.  The kernels write every part of
+// the workspace they read, so nothing needs clearing between calls.
+namespace {
+constexpr size_t NOALLOC_DOUBLES = (size_t)4 << 20;   // 32 MiB
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device); NULL with a message in g_create_error on failure.
+static double* scratch_ptr() {
+  int dev = -1;
+  hipError_t st = hipGetDevice(&dev);
+  if (st != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    g_create_error = std::string("small_syev_noalloc: no usable current device: ") +
+                     (st != hipSuccess ? hipGetErrorString(st) : "device index out of range");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    st = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (st != hipSuccess || !ptr) {
+      g_create_error = std::string("small_syev_noalloc: hipGetSymbolAddress(scratch): ") +
+                       hipGetErrorString(st);
+      return nullptr;
+    }
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
+extern "C" {
+
+int32_t dgdft_small_syev_noalloc(int32_t count, int32_t n, int32_t k, const double* A, double* w,
+                                 double* Z, int32_t method, void* stream) {
+  if (!syev_args_ok(count, n, k, A, w, Z, method)) {
+    g_create_error = "small_syev_noalloc: bad arguments";
+    return DGDFT_EINVAL;
+  }
+  const size_t need = (size_t)count * syev_work_doubles(n, k);
+  if (need > NOALLOC_DOUBLES) {
+    char buf[192];
+    snprintf(buf, sizeof buf,
+             "small_syev_noalloc: %d matrices of order %d (k = %d) need %zu doubles of workspace; "
+             "the static workspace holds %zu",
+             count, n, k, need, NOALLOC_DOUBLES);
+    g_create_error = buf;
+    return DGDFT_EINVAL;
+  }
+  double* ws = scratch_ptr();
+  if (!ws) return DGDFT_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    launch_syev(count, n, k, A, w, Z, method, ws, s);
+    HCHECK(hipStreamSynchronize(s));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    g_create_error = f.what;
     return DGDFT_EHIP;
   }
 }
