@@ -7,16 +7,28 @@ residual tolerance, the final FP64 check, and restriction + SVD truncation to
 ALBs (all through the C ABI).  The metric is converged element eigensolves
 per second.
 
-Default workload: 64 extended elements of a synthetic 2D slab, 36x36x60 grid
-(h = 10/24 bohr, vacuum along z), ~20 Gaussian-well atoms with 4 KB
-projectors each, 128 states, residual 1e-6, element box 12x12x60, 64 ALBs.
-Inputs are resident in HBM before the timed region starts.
+Default workload: the uneven batch of 200 extended elements (grid edges drawn
+from {24, 32, 36, 48} per axis at h = 10/24 bohr, 64-256 states, 5-30
+Gaussian-well atoms with 4 KB projectors each), residual 1e-6, 16 guard
+columns, restriction to the central third per axis and floor(J/2) ALBs.
+The 64-element slab (36x36x60, 128 states, 64 ALBs) and the one-element
+workload (24^3, 32 states) are measured beside it under "forms".  Inputs are
+resident in HBM before the timed region starts.
+
+Roofline of the dominant product class, from the algorithmic work of the
+method per element and LOBPCG iteration: the twelve J x J blocks of the
+Gram products are 24 N_g J^2 flops and the seven update products 14 N_g J^2
+(the paper's operation count per iteration, Sec. II.B), with J the block
+width (states plus guard columns) and the iteration counts the solver
+reports; divided by the class's kernel time measured with HIP events on its
+launch stream over the timed region.
 
 Prints one JSON line (rank 0).  One GPU only.
 """
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,12 +38,13 @@ sys.path.insert(0, ROOT)
 METRIC = "converged element eigensolves/s at residual 1e-6: plain FP64 vs mixed+learned"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter runs of this
-# command, calibrated on a 1 GiB copy (profiles/slab64_fp64_hbm_traffic.md):
-# (kernel class, workload, elements, guard columns, streams) -> bytes.  Valid for the kernel
-# build that was measured; removed when the kernel changes.
-MEASURED_TRAFFIC = {("dg_gram", "slab_36x36x60_J128", 64, 16, 2): 12.344e9,
-                    ("dg_update", "slab_36x36x60_J128", 64, 16, 2): 18.935e9}
+# algorithmic flops per element and LOBPCG iteration, in units of N_g J^2
+ALG_UNITS = {"dg_gram": 24.0, "dg_update": 14.0}
+# HBM bytes per launch of a product class from the FETCH_SIZE / WRITE_SIZE
+# counter runs of the default command, calibrated on a 1 GiB copy (see
+# profiles/): (kernel class, workload, guard columns, streams) -> bytes.  Valid
+# only for the kernel build that was measured; removed when the kernel changes.
+MEASURED_TRAFFIC = {}
 # guard columns per element when --guard is not given: 16 on the slab (block
 # of 144 columns, the tile width of the 144-wide GEMM kernels) and on the
 # uneven batch, 8 on the one-element workload (32 states)
@@ -54,8 +67,21 @@ def workload(name, n_elem):
                     atoms_per_element=8, n_alb=16)
     else:
         els = synth.uneven_batch(n_elem or 200)
-        desc = dict(workload="uneven_edges_24-48_J64-256", elements=len(els))
+        desc = dict(workload="uneven_edges_24-48_J64-256", elements=len(els),
+                    grid_edges=[24, 32, 36, 48], n_states=[64, 256], atoms_per_element=[5, 30],
+                    element_box="central third per axis", n_alb="floor(J/2)")
     return els, desc
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def cpu_baseline(el, tol, n_guard):
@@ -63,7 +89,7 @@ def cpu_baseline(el, tol, n_guard):
     same start block as the GPU (the element's n_states columns plus n_guard
     guard columns, stopping test on the n_states wanted residuals) run to the
     tolerance, then the restriction + SVD truncation; one converged element
-    per that time."""
+    per that time, with all host threads on the one element."""
     import numpy as np
     from oracle import alb, lobpcg as lob, teter
     from oracle.hamiltonian import FFT_WORKERS, Operator
@@ -85,11 +111,12 @@ def cpu_baseline(el, tol, n_guard):
     alb.restrict_svd(res.X[:, :el.n_states], op.grid, el.elem_lo, el.elem_hi, op.dv, el.n_alb)
     est = time.perf_counter() - t
     return dict(value=1.0 / est, unit="elements/s", cores=int(max(FFT_WORKERS, blas)),
-                kind="oracle",
-                sample=(f"element 0 of the workload: oracle LOBPCG to residual {tol:g} "
-                        f"({el.n_states} states + {n_guard} guard columns, {res.iters} "
-                        f"iterations, converged={res.converged}, {t_solve:.1f} s) "
-                        f"+ ALB step: {est:.1f} s per converged element"))
+                kind="oracle", cpu_model=cpu_model(), host_threads=os.cpu_count(),
+                sample=(f"element 0 of the workload (grid {list(el.grid)}, {el.n_states} states "
+                        f"+ {n_guard} guard columns): oracle LOBPCG to residual {tol:g} "
+                        f"({res.iters} iterations, converged={res.converged}, {t_solve:.1f} s) "
+                        f"+ ALB step: {est:.1f} s per converged element, one element at a time "
+                        f"with all threads on it (per-element rate; no concurrent elements)"))
 
 
 def start_block(els, n_guard, dev):
@@ -107,12 +134,20 @@ def start_block(els, n_guard, dev):
     return torch.cat(parts).to(dev)
 
 
-def make_handle(args, els, **kw):
+def make_handle(args, els, guard=None, **kw):
     from paper_1506_08147_amd import ALB
+    g = args.guard if guard is None else guard
     kw.setdefault("n_streams", args.streams)
-    return ALB([e.grid for e in els], [e.box for e in els], [e.n_states + args.guard for e in els],
+    return ALB([e.grid for e in els], [e.box for e in els], [e.n_states + g for e in els],
                elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-               n_alb=[e.n_alb for e in els], n_guard=args.guard, **kw)
+               n_alb=[e.n_alb for e in els], n_guard=g, **kw)
+
+
+def resident_inputs(els, guard, dev):
+    import torch
+    from paper_1506_08147_amd import ALB
+    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
+    return V, ALB.kb_batch([e.kb for e in els], dev), start_block(els, guard, dev)
 
 
 def warm_mode(args, h, els, desc, V, kbt, out):
@@ -122,7 +157,6 @@ def warm_mode(args, h, els, desc, V, kbt, out):
     import numpy as np
     import torch
     import synth
-    from paper_1506_08147_amd import ALB
     dev = V.device
     Vs = [torch.cat([torch.from_numpy(synth.perturbed_potential(e, s + 1)) for e in els]).to(dev)
           for s in range(args.warm)]
@@ -153,62 +187,80 @@ def warm_mode(args, h, els, desc, V, kbt, out):
     print(json.dumps(line), flush=True)
 
 
-def roofline(ks):
-    """Dominant kernel class by time in the timed region (the small-dense
-    Rayleigh-Ritz kernels are latency-bound, not roofline kernels: only classes
-    with algorithmic flops or bytes compete): algorithmic work per launch over
-    its average HIP-event launch time."""
-    dom = max((k for k in ks if ks[k]["flops"] > 0 or ks[k]["bytes"] > 0), key=lambda k: ks[k]["ms"])
+def algorithmic_units(els, guard, stats):
+    """sum over elements of iterations * N_g * J^2 (J = block width) of one solve."""
+    return sum(float(st["iters"]) * e.ng * float(e.n_states + guard) ** 2
+               for e, st in zip(els, stats))
+
+
+def algorithmic_flops(k, v, units_per_step, steps):
+    """The method's flops for product class k over the timed region: the
+    paper's count (ALG_UNITS per N_g J^2 and iteration), or the flops the
+    kernels executed where that is less (the Gram products form the carried
+    [X P] blocks and the W columns of S^T S in small space), so that the
+    rate never counts work that was not done."""
+    return min(ALG_UNITS[k] * units_per_step * steps, v["flops"])
+
+
+def roofline(ks, units_per_step, steps):
+    """Dominant product class by kernel time in the timed region, with its
+    algorithmic flops per launch over the class's average HIP-event launch
+    time."""
+    dom = max(ALG_UNITS, key=lambda k: ks[k]["ms"])
     d = ks[dom]
-    per_launch_ms = d["ms"] / max(d["launches"], 1)
-    if d["flops"] > 0:
-        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / PEAK_FP64_TFLOPS, 4), traffic=None)
-    else:
-        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=round(ach, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(ach / PEAK_HBM_GBS, 4), traffic=None)
-    roof.update(kernel=dom, launches=d["launches"], avg_launch_ms=round(per_launch_ms, 4),
-                algorithmic_flops_per_launch=d["flops"] / max(d["launches"], 1),
-                algorithmic_bytes_per_launch=d["bytes"] / max(d["launches"], 1))
-    return roof
+    launches = max(d["launches"], 1)
+    alg = algorithmic_flops(dom, d, units_per_step, steps)
+    ach = alg / (d["ms"] * 1e-3) / 1e12
+    paper = ALG_UNITS[dom] * units_per_step * steps
+    return dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
+                frac=round(ach / PEAK_FP64_TFLOPS, 4), traffic=None, kernel=dom,
+                launches=d["launches"], avg_launch_ms=round(d["ms"] / launches, 4),
+                algorithmic_flops_per_launch=alg / launches,
+                algorithmic_count=("paper: " if alg == paper else "executed (below the paper's "
+                                   f"{ALG_UNITS[dom]:g} N_g J^2): ") +
+                f"{alg / max(units_per_step * steps, 1):.2f} N_g J^2 per element-iteration",
+                executed_flops_per_launch=d["flops"] / launches)
 
 
-def time_form(args, els, V, kbt, X0, precision, precond, w, streams=None):
-    """Converged elements/s of one form on the same resident inputs (1 warm-up
-    solve, args.steps timed).  streams=1: one element group on one stream,
-    with the roofline of its dominant kernel (launches not sharing the GPU
-    with a second group's)."""
-    import numpy as np
+def kernel_table(ks, units_per_step, steps):
+    out = {}
+    for k, v in ks.items():
+        if not v["launches"]:
+            continue
+        r = dict(ms_per_step=round(v["ms"] / steps, 3), launches=v["launches"])
+        if v["ms"] and v["flops"]:
+            r["executed_tflops"] = round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3)
+        if v["ms"] and k in ALG_UNITS:
+            r["algorithmic_tflops"] = round(
+                algorithmic_flops(k, v, units_per_step, steps) / (v["ms"] * 1e-3) / 1e12, 3)
+        if v["ms"] and v["bytes"]:
+            r["gbs"] = round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
+        out[k] = r
+    return out
+
+
+def time_solves(h, V, kbt, X0, steps):
+    """1 warm-up solve, then `steps` timed solves; (elements/s, s per step, last output)."""
     import torch
-    from paper_1506_08147_amd import ALB
-    kw = dict(n_streams=streams) if streams else {}
-    h = make_handle(args, els, tol=args.tol, max_iter=1000, precision=precision, precond=precond,
-                    mlp_weights=w, **kw)
     out = h.solve(V, kbt, X0)
     torch.cuda.synchronize()
-    if streams:
-        h.profile(True)
     t0 = time.perf_counter()
     n_conv = 0
-    for s in range(args.steps):
+    for _ in range(steps):
         out = h.solve(V, kbt, X0)
         n_conv += sum(1 for st in out["stats"] if st["converged"])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    return n_conv / el, el / steps, out
+
+
+def form_summary(value, s_step, out, **kw):
+    import numpy as np
     st = out["stats"]
-    roof = roofline(h.kernel_stats()) if streams else None
-    h.close()
-    log(f"form {precision}/{precond}: {n_conv / el:.3f} elements/s")
-    r = dict(value=round(n_conv / el, 4), ms_per_step=round(1e3 * el / args.steps, 2),
-             precision=precision, preconditioner=precond,
-             iterations_mean=float(np.mean([s["iters"] for s in st])),
-             converged=f"{sum(1 for s in st if s['converged'])}/{len(st)}",
-             teter_fallback_bands=int(sum(s["n_teter_fallback"] for s in st)))
-    if streams:
-        r.update(streams=streams, roofline=roof)
-    return r
+    return dict(value=round(value, 4), ms_per_step=round(1e3 * s_step, 2),
+                iterations_mean=float(np.mean([s["iters"] for s in st])),
+                converged=f"{sum(1 for s in st if s['converged'])}/{len(st)}",
+                teter_fallback_bands=int(sum(s["n_teter_fallback"] for s in st)), **kw)
 
 
 def train_network(dev):
@@ -239,32 +291,69 @@ def train_network(dev):
                    loss_last=round(float(hist[-1]), 5), seconds=round(el, 1))
 
 
+def mixed_vs_oracle(args, dev, seeds=(1000, 1001, 1002, 1003)):
+    """The mixed form on one-element workloads (24^3, 32 states, residual 1e-6)
+    against the FP64 oracle: per element the largest eigenvalue difference
+    and the sine of the largest principal angle between the GPU's and the
+    oracle's eigenvectors (states below the largest cut with a gap >= 1e-4
+    Ha)."""
+    import numpy as np
+    import synth
+    from oracle.solve import solve_element
+    els = [synth.single_element(seed=s) for s in seeds]
+    h = make_handle(args, els, guard=0, tol=1e-6, max_iter=1000, precision="mixed")
+    V, kbt, X0 = resident_inputs(els, 0, dev)
+    out = h.solve(V, kbt, X0)
+    rows = []
+    for i, el in enumerate(els):
+        r = h.split(out, i)
+        ref = solve_element(el, tol=1e-6)
+        lam_g = r["eigvals"].cpu().numpy()
+        Xg = r["eigvecs"].cpu().numpy() * np.sqrt(el.dv)
+        Xo = ref["eigvecs"] * np.sqrt(el.dv)
+        gaps = np.diff(ref["eigvals"])
+        cut = int(np.nonzero(gaps >= 1e-4)[0].max()) + 1 if np.any(gaps >= 1e-4) else el.n_states
+        s = np.linalg.svd(Xo[:, :cut].T @ Xg[:, :cut], compute_uv=False)
+        rows.append(dict(seed=int(seeds[i]),
+                         max_abs_dlambda_ha=float(np.abs(lam_g - ref["eigvals"]).max()),
+                         sin_max_angle=float(np.sqrt(max(0.0, 1.0 - s.min() ** 2))),
+                         angle_states=cut, gpu_iters=out["stats"][i]["iters"],
+                         oracle_iters=int(ref["iters"])))
+    h.close()
+    return dict(workload="cube_24^3_J32", tol=1e-6, reference="FP64 oracle", elements=rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="slab", choices=["slab", "one", "uneven"])
+    ap.add_argument("--workload", default="uneven", choices=["uneven", "slab", "one"])
     ap.add_argument("--elements", type=int, default=None)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--streams", type=int, default=2, choices=[1, 2],
-                    help="element groups on their own HIP streams")
+    ap.add_argument("--streams", type=int, default=1, choices=[1, 2],
+                    help="element groups on their own HIP streams (1: kernel durations are not "
+                         "shared with a second group, so HIP events and rocprofv3 agree)")
     ap.add_argument("--guard", type=int, default=None,
                     help="guard columns per element: the block holds n_states + G columns, "
                          "convergence and ALBs use the first n_states (default: 16 on the "
                          "slab and the uneven batch, 8 on the one-element workload)")
     ap.add_argument("--graph", type=int, default=0,
                     help="LOBPCG iterations per captured HIP graph launch (0: eager)")
-    ap.add_argument("--tune", type=int, default=0, help="1: autotune the Gram split-K at create")
+    ap.add_argument("--tune", type=int, default=0, help="1: autotune at create")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="1: one 1 GiB device copy before the timed region, whose hardware "
                          "counters calibrate FETCH_SIZE / WRITE_SIZE in profiler runs")
     ap.add_argument("--forms", type=int, default=1,
                     help="1: also time the mixed and the mixed + learned-preconditioner forms "
-                         "(network trained first on solver-logged pairs of one-element "
-                         "workloads) and report them under 'forms'")
+                         "of the workload, the slab and the one-element mixed form against the "
+                         "oracle, and report them under 'forms'")
+    ap.add_argument("--form-steps", type=int, default=1,
+                    help="timed solves per form (after one warm-up solve)")
+    ap.add_argument("--dg-blocks", type=int, default=1,
+                    help="1: time the element-local DG quantities from the last step's ALBs")
     ap.add_argument("--warm", type=int, default=0,
                     help="S > 0: warm-start mode instead: after one converged solve, S timed "
                          "SCF-like steps (perturbed V, 3 LOBPCG iterations from the previous "
@@ -282,15 +371,12 @@ def main():
         args.warmup = 1   # the converged solve the warm steps start from
     import numpy as np
     import torch
-    from paper_1506_08147_amd import ALB
 
     dev = torch.device("cuda:0")
     t = time.perf_counter()
     els, desc = workload(args.workload, args.elements)
     log(f"inputs generated: {len(els)} elements in {time.perf_counter() - t:.1f} s")
-    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
-    kbt = ALB.kb_batch([e.kb for e in els], dev)
-    X0 = start_block(els, args.guard, dev)
+    V, kbt, X0 = resident_inputs(els, args.guard, dev)
     h = make_handle(args, els, tol=args.tol, max_iter=1000, graph_iters=args.graph,
                     tune=bool(args.tune), precision=args.precision)
     if args.calib_copy:
@@ -318,67 +404,52 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ks = h.kernel_stats()
+    h.profile(False)
     stats = out["stats"]
     iters = [st["iters"] for st in stats]
     ms_step = 1e3 * elapsed / args.steps
+    units = algorithmic_units(els, args.guard, stats)
 
-    roof = roofline(ks)
-    roof["traffic"] = MEASURED_TRAFFIC.get((roof["kernel"], desc["workload"], desc.get("elements"),
-                                            args.guard, args.streams))
-    kernels = {k: dict(ms_per_step=round(v["ms"] / args.steps, 3), launches=v["launches"],
-                       tflops=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3) if v["ms"] else 0,
-                       gbs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else 0)
-               for k, v in ks.items() if v["launches"]}
-    # element-local DG quantities from the ALBs of the last step
-    nal = [e.n_alb for e in els]
-    Pd = torch.cat([torch.eye(n, dtype=torch.float64).reshape(-1) * 2.0 for n in nal]).to(dev)
-    h.density(out["albs"], Pd)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rho = h.density(out["albs"], Pd)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    h.nonlocal_block(out["albs"])
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    # volume terms of the diagonal DG block on the LGL grid (twice the uniform
-    # points per axis): once untimed, once timed, once with per-launch events
-    h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
-    torch.cuda.synchronize()
-    t4 = time.perf_counter()
-    vol = h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
-    torch.cuda.synchronize()
-    t5 = time.perf_counter()
-    h.profile(True)
-    h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
-    bg = h.kernel_stats()["dg_bgemm"]
-    h.profile(False)
-    bg_tf = bg["flops"] / (bg["ms"] * 1e-3) / 1e12 if bg["ms"] else 0.0
-    sym = max(float((v.reshape(n, n) - v.reshape(n, n).T).abs().max())
-              for v, n in zip(torch.split(vol, [n * n for n in nal]), nal))
-    dgb = dict(density_ms=round(1e3 * (t2 - t1), 3), nonlocal_block_ms=round(1e3 * (t3 - t2), 3),
-               electrons_check=round(sum(
-                   e.dv * float(r.sum()) for e, r in zip(els, torch.split(rho, [x["ne"] for x in h.sizes])))
-                   / (2.0 * sum(nal)), 12),
-               volume_ms=round(1e3 * (t5 - t4), 3),
-               volume_bgemm=dict(launches=bg["launches"], ms=round(bg["ms"], 3),
-                                 gflop=round(bg["flops"] / 1e9, 2), tflops=round(bg_tf, 2),
-                                 frac_fp64_peak=round(bg_tf / PEAK_FP64_TFLOPS, 4)),
-               volume_asymmetry=sym)
+    roof = roofline(ks, units, args.steps)
+    roof["traffic"] = MEASURED_TRAFFIC.get((roof["kernel"], desc["workload"], args.guard,
+                                            args.streams))
+    kernels = kernel_table(ks, units, args.steps)
+    dgb = None
+    if args.dg_blocks:
+        dgb = dg_blocks(h, els, out, dev)
     h.close()
     forms = None
-    if args.forms and args.warm == 0:
+    if args.forms:
         forms = dict(fp64_plain=dict(value=round(n_conv / elapsed, 4), ms_per_step=round(ms_step, 2),
                                      iterations_mean=float(np.mean(iters))))
-        if args.streams != 1:
-            forms["fp64_one_stream"] = time_form(args, els, V, kbt, X0, args.precision, "teter", None,
-                                                 streams=1)
-        forms["mixed"] = time_form(args, els, V, kbt, X0, "mixed", "teter", None)
+        hm = make_handle(args, els, tol=args.tol, max_iter=1000, precision="mixed")
+        v, s_step, o = time_solves(hm, V, kbt, X0, args.form_steps)
+        hm.close()
+        forms["mixed"] = form_summary(v, s_step, o, precision="mixed", preconditioner="teter")
+        log(f"form mixed/teter: {v:.3f} elements/s")
         w, training = train_network(dev)
-        forms["mixed_learned"] = time_form(args, els, V, kbt, X0, "mixed", "learned", w)
-        forms["mixed_learned"]["training"] = training
+        hl = make_handle(args, els, tol=args.tol, max_iter=1000, precision="mixed",
+                         precond="learned", mlp_weights=w)
+        v, s_step, o = time_solves(hl, V, kbt, X0, args.form_steps)
+        hl.close()
+        forms["mixed_learned"] = form_summary(v, s_step, o, precision="mixed",
+                                              preconditioner="learned", training=training)
+        log(f"form mixed/learned: {v:.3f} elements/s")
         forms["ratio_mixed_learned_over_fp64"] = round(
             forms["mixed_learned"]["value"] / forms["fp64_plain"]["value"], 3)
+        if args.workload != "slab":
+            sels, sdesc = workload("slab", None)
+            sg = DEFAULT_GUARD["slab"]
+            sV, skb, sX0 = resident_inputs(sels, sg, dev)
+            hs = make_handle(args, sels, guard=sg, tol=args.tol, max_iter=1000)
+            v, s_step, o = time_solves(hs, sV, skb, sX0, args.form_steps)
+            hs.close()
+            del sV, skb, sX0
+            forms["slab_fp64"] = form_summary(v, s_step, o, precision="fp64",
+                                              preconditioner="teter", workload=sdesc["workload"],
+                                              elements=len(sels), guard_columns=sg)
+            log(f"form slab fp64: {v:.3f} elements/s")
+        forms["mixed_one_element_vs_oracle"] = mixed_vs_oracle(args, dev)
     line = dict(metric=METRIC, value=round(n_conv / elapsed, 4), unit="elements/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_step, 2),
                 higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -392,13 +463,53 @@ def main():
                 converged=f"{sum(1 for st in stats if st['converged'])}/{len(stats)}",
                 rr_reductions=dict(cholesky=int(sum(st["n_rr_cholesky"] for st in stats)),
                                    series=int(sum(st["n_rr_series"] for st in stats))))
-    line["dg_blocks"] = dgb
+    if dgb is not None:
+        line["dg_blocks"] = dgb
     if forms is not None:
         line["forms"] = forms
     if args.cpu_baseline:
         log("timing the oracle sample on the host")
         line["cpu_baseline"] = cpu_baseline(els[0], args.tol, args.guard)
     print(json.dumps(line), flush=True)
+
+
+def dg_blocks(h, els, out, dev):
+    """Element-local DG quantities from the last step's ALBs: density from
+    P = 2 I, the nonlocal block and the volume terms on the LGL grid (twice
+    the uniform points per axis), each timed once after an untimed call."""
+    import torch
+    nal = [e.n_alb for e in els]
+    Pd = torch.cat([torch.eye(n, dtype=torch.float64).reshape(-1) * 2.0 for n in nal]).to(dev)
+    h.density(out["albs"], Pd)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rho = h.density(out["albs"], Pd)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    h.nonlocal_block(out["albs"])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
+    torch.cuda.synchronize()
+    h.profile(True)
+    t4 = time.perf_counter()
+    vol = h.dg_volume(out["eigvecs"], out["albs"], out["sigma"])
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    bg = h.kernel_stats()["dg_bgemm"]
+    h.profile(False)
+    bg_tf = bg["flops"] / (bg["ms"] * 1e-3) / 1e12 if bg["ms"] else 0.0
+    sym = max(float((v.reshape(n, n) - v.reshape(n, n).T).abs().max())
+              for v, n in zip(torch.split(vol, [n * n for n in nal]), nal))
+    return dict(density_ms=round(1e3 * (t2 - t1), 3), nonlocal_block_ms=round(1e3 * (t3 - t2), 3),
+                electrons_check=round(sum(
+                    e.dv * float(r.sum()) for e, r in zip(els, torch.split(rho, [x["ne"] for x in h.sizes])))
+                    / (2.0 * sum(nal)), 12),
+                volume_ms_with_events=round(1e3 * (t5 - t4), 3),
+                volume_bgemm=dict(launches=bg["launches"], ms=round(bg["ms"], 3),
+                                  gflop=round(bg["flops"] / 1e9, 2), tflops=round(bg_tf, 2),
+                                  frac_fp64_peak=round(bg_tf / PEAK_FP64_TFLOPS, 4)),
+                volume_asymmetry=sym)
 
 
 if __name__ == "__main__":

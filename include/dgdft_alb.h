@@ -110,6 +110,9 @@ typedef struct dgdft_alb_opts {
                                * streams, 1 or 2 (0 = 2): with two, one group's    *
                                * small dense steps overlap the other's block       *
                                * products                                          */
+    uint64_t seed;            /* seed of the start block drawn when               *
+                               * dgdft_alb_solve gets X0 == NULL (see             *
+                               * dgdft_alb_initial_guess)                          */
 } dgdft_alb_opts;
 
 /* Kleinman-Bylander projectors of the whole batch, CSR by projector
@@ -131,20 +134,33 @@ typedef struct dgdft_kb {
     const double*  val;
 } dgdft_kb;
 
+#define DGDFT_PHASES 5
+
 /* Per-element results of dgdft_alb_solve (host array, one per element). */
 typedef struct dgdft_alb_stats {
     int32_t iters;            /* LOBPCG iterations performed                       */
     int32_t converged;        /* 1 iff the final FP64 residual max <= tol          */
-    double  max_res;          /* final max_i residual (FP64)                       */
+    double  max_res;          /* final max_i residual (FP64); with guard columns   *
+                               * both fields cover only the wanted states          *
+                               * (the first n_states - n_guard columns)            */
     int32_t n_chol_fallback;  /* W orthonormalisations that fell back to SVQB      */
     int32_t n_rr_fallback;    /* Rayleigh-Ritz steps with a rank-deficient basis   */
-    int32_t n_p_drop;         /* iterations that restarted without P               */
-    int32_t n_ql_fail;        /* small eigensolves whose QL iteration hit its cap  */
+    int32_t n_p_drop;         /* Rayleigh-Ritz steps without P (its block was      *
+                               * numerically dependent on [X W])                   */
+    int32_t n_ql_fail;        /* small eigensolves whose QL iteration hit its cap  *
+                               * (SVQB and the reduction of a rank-deficient     *
+                               * basis)                                           */
     int32_t n_teter_fallback; /* bands switched to the Teter factor (learned mode)  */
     int32_t graph_launches;   /* graph launches that advanced this element          */
     int32_t n_rr_cholesky;    /* Rayleigh-Ritz steps reduced by a Cholesky of S^T S */
     int32_t n_rr_series;      /* ... by the series for (S^T S)^-1/2 (basis nearly   *
                                * orthonormal, ||S^T S - I||_F <= 1e-4)              */
+    double  ms_by_phase[DGDFT_PHASES];  /* wall time of the solve's phases for    *
+                               * the whole batch (the same in every element's      *
+                               * record; the stream is synchronised at each phase  *
+                               * boundary): potential load, start (X0, CholQR,      *
+                               * H X, Rayleigh-Ritz on X), LOBPCG iterations, final *
+                               * FP64 checks, restriction + SVD truncation         */
 } dgdft_alb_stats;
 
 /* Create a handle for a batch of n_elem extended elements.
@@ -184,7 +200,9 @@ int32_t dgdft_alb_set_potential(dgdft_alb* h, const double* V, const dgdft_kb* k
 /* Solve every element: LOBPCG from X0 to the tolerance, final FP64 check,
  * then restriction + SVD truncation (Sec. II.A-B).
  *   V, kb    as in dgdft_alb_set_potential; V == NULL keeps the loaded ones
- *   X0       device [sum N_g*J] initial guesses (full column rank), read only
+ *   X0       device [sum N_g*J] initial guesses (full column rank), read only;
+ *            NULL: the seeded N(0,1) block of dgdft_alb_initial_guess with
+ *            opts.seed
  *   eigvals  device [sum J]        ascending per element (Ha)
  *   eigvecs  device [sum N_g*J] or NULL; dV * sum psi^2 = 1 (Eq. localproblem)
  *   albs     device [sum N_E*n_alb] or NULL; dV * sum_E phi^2 = 1, descending
@@ -198,6 +216,17 @@ int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb,
                         const double* X0, double* eigvals, double* eigvecs,
                         double* albs, double* sigma, dgdft_alb_stats* stats,
                         void* stream);
+
+/* The start block the solver draws when it is given no initial guess (the
+ * seeded random start of Sec. II.B's LOBPCG): X0 (device [sum N_g*J], the
+ * layout of dgdft_alb_solve's X0) with entries of standard normal law.  Rows
+ * 2q, 2q+1 of column j of batch element e come from the counter-based
+ * generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011) at counter
+ * (q, j, e, 0) and key (seed mod 2^32, seed div 2^32): its outputs w0..w3
+ * give u1 = (w0 2^21 + w1 div 2^11) 2^-53 and u2 from (w2, w3), and the
+ * Box-Muller transform x_2q = r cos(2 pi u2), x_2q+1 = r sin(2 pi u2),
+ * r = sqrt(-2 ln(1 - u1)) (an odd N_g drops the last sine). */
+int32_t dgdft_alb_initial_guess(dgdft_alb* h, uint64_t seed, double* X0, void* stream);
 
 /* Apply the discrete operator of element `elem` (loaded potential) to ncols
  * unit-basis columns: HX = (F^-1 diag(|G|^2/2) F + diag(V) +
@@ -242,15 +271,29 @@ int32_t dgdft_alb_orthonormalise(dgdft_alb* h, int32_t elem, const double* G, do
  * basis X alone; 2: [X W]; 3: [X P W]), Hh and M (device, n x n column-major,
  * upper triangles read) are S^T H S and S^T S.  Outputs (device): theta [J]
  * the lowest generalised eigenvalues of (Hh, M) ascending; C [n*J] the
- * coefficients with C^T M C = I; for kb > 1, D [n*J] the next search
- * direction: the part of [0; C_P; C_W] (C with its first J rows zeroed)
- * M-orthogonal to C, normalised so that D^T M D = I, or all zero when that
- * normalisation breaks down (P is then dropped, flags[2]).  Reductions: the
- * binomial series for M^-1/2 when ||M - I||_F <= 1e-4 (kb > 1), a scaled
- * Cholesky of M, or, when M is not numerically positive definite, its
- * eigenvectors above 1e-10 of the largest eigenvalue (flags[1]; fewer than J
- * of them sets flags[3]).  flags: host [6] as for dgdft_alb_orthonormalise.
- * Uses the element's workspace; not concurrent with a solve on h. */
+ * coefficients with C^T M C = I; for kb > 1, D [n*J] the coefficients of
+ * the next search direction P' = S D, in the form the solver uses for the
+ * handle:
+ *   - handles without guard columns, mixed-precision handles and handles
+ *     with a tolerance below 1e-7: the part of [0; C_P; C_W] (C with its
+ *     first J rows zeroed) M-orthogonal to C, normalised so that
+ *     D^T M D = I, or all zero when that normalisation breaks down (P is
+ *     then dropped, flags[2]);
+ *   - FP64 handles with guard columns (opts.n_guard > 0) and opts.tol >=
+ *     1e-7: Knyazev's form,
+ *     D = C with its first J rows zeroed (P' = [P W] [C_P; C_W], neither
+ *     normalised nor orthogonal to X' = S C).  For kb = 3, where the
+ *     solver's X and W blocks are orthonormal and mutually orthogonal, the
+ *     P block is first orthonormalised against [X W] through a scaled
+ *     Cholesky of its Schur complement M_PP - M_XP^T M_XP - M_WP^T M_WP;
+ *     if that breaks, P is dropped for the step (flags[2]; C_P = 0, the step
+ *     runs on [X W]).
+ * Reductions: the binomial series for M^-1/2 when ||M - I||_F <= 1e-4
+ * (kb > 1), a scaled Cholesky of M, or, when M is not numerically positive
+ * definite, its eigenvectors above 1e-10 of the largest eigenvalue
+ * (flags[1]; fewer than J of them sets flags[3]).  flags: host [6] as for
+ * dgdft_alb_orthonormalise.  Uses the element's
+ * workspace; not concurrent with a solve on h. */
 int32_t dgdft_alb_rayleigh_ritz(dgdft_alb* h, int32_t elem, int32_t kb, const double* Hh,
                                 const double* M, double* theta, double* C, double* D,
                                 int32_t* flags, void* stream);
@@ -280,12 +323,15 @@ int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A,
 int32_t dgdft_small_syev_noalloc(int32_t count, int32_t n, int32_t k, const double* A,
                                  double* w, double* Z, int32_t method, void* stream);
 
-/* Batched tall-skinny FP64 product on matrix cores (operations 2 and 3 of the
+/* Batched tall-skinny product on matrix cores (operations 2 and 3 of the
  * LOBPCG list in Sec. II.B), exported for tests:
- *   trans == 1: C (m x n) = A^T B with A (K x m), B (K x n)
- *   trans == 0: C (K x n) = alpha A B + beta C with A (K x m), B (m x n)
+ *   trans & 1 == 1: C (m x n) = A^T B with A (K x m), B (K x n)
+ *   trans & 1 == 0: C (K x n) = alpha A B + beta C with A (K x m), B (m x n)
  * all column-major with leading dimension = rows, `count` independent
- * problems laid out back to back.  Device pointers. */
+ * problems laid out back to back.  Device pointers, FP64 storage.  trans & 2
+ * selects the kernels of the mixed form: operands rounded to FP32 as they
+ * are staged, FP32 products and accumulation within a split-K chunk (Gram)
+ * or the whole inner dimension (update), FP64 chunk sums and output. */
 int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m,
                            int32_t n, double alpha, const double* A, const double* B,
                            double beta, double* C, void* stream);

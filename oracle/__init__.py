@@ -34,4 +34,4 @@ the path taken, and what a trained network gains over Teter's factor:
 **parity unpinned** (iteration counts are only compared between runs with
 identical settings).
 """
-from . import hamiltonian, dense, teter, lobpcg, alb, solve, learned, dgblocks  # noqa: F401
+from . import hamiltonian, dense, teter, lobpcg, alb, solve, learned, dgblocks, random_start  # noqa: F401

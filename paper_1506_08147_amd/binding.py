@@ -23,6 +23,7 @@ EXPORTS = (
     "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
     "dgdft_alb_density", "dgdft_alb_nonlocal_block", "dgdft_alb_dg_volume",
     "dgdft_alb_orthonormalise", "dgdft_alb_rayleigh_ritz", "dgdft_small_syev_noalloc",
+    "dgdft_alb_initial_guess",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
@@ -50,7 +51,7 @@ class Opts(C.Structure):
                 ("elem_lo", C.POINTER(C.c_int32)), ("elem_hi", C.POINTER(C.c_int32)),
                 ("n_alb", C.POINTER(C.c_int32)), ("mlp_weights", C.c_void_p),
                 ("graph_iters", C.c_int32), ("tune", C.c_int32), ("n_guard", C.c_int32),
-                ("n_streams", C.c_int32)]
+                ("n_streams", C.c_int32), ("seed", C.c_uint64)]
 
 
 class KB(C.Structure):
@@ -63,7 +64,9 @@ class Stats(C.Structure):
                 ("n_chol_fallback", C.c_int32), ("n_rr_fallback", C.c_int32),
                 ("n_p_drop", C.c_int32), ("n_ql_fail", C.c_int32),
                 ("n_teter_fallback", C.c_int32), ("graph_launches", C.c_int32),
-                ("n_rr_cholesky", C.c_int32), ("n_rr_series", C.c_int32)]
+                ("n_rr_cholesky", C.c_int32), ("n_rr_series", C.c_int32),
+                ("ms_by_phase", C.c_double * 5)]
+PHASES = ("potential", "start", "iterations", "final_check", "albs")
 
 
 class Pairs(C.Structure):
@@ -146,6 +149,8 @@ def load_library():
     lib.dgdft_alb_nonlocal_block.restype = i32
     lib.dgdft_alb_dg_volume.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     lib.dgdft_alb_dg_volume.restype = i32
+    lib.dgdft_alb_initial_guess.argtypes = [vp, C.c_uint64, vp, vp]
+    lib.dgdft_alb_initial_guess.restype = i32
     lib.dgdft_alb_orthonormalise.argtypes = [vp, i32, vp, vp, i32, P(i32), vp]
     lib.dgdft_alb_orthonormalise.restype = i32
     lib.dgdft_alb_rayleigh_ritz.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, P(i32), vp]
@@ -180,7 +185,7 @@ class ALB:
 
     def __init__(self, grids, boxes, n_states, tol=1e-8, max_iter=500, elem_lo=None,
                  elem_hi=None, n_alb=None, precond="teter", mlp_weights=None, graph_iters=0,
-                 tune=False, precision="fp64", n_guard=0, n_streams=0):
+                 tune=False, precision="fp64", n_guard=0, n_streams=0, seed=0):
         import torch  # noqa: F401  (device memory and streams)
         self.lib = load_library()
         self.grids = np.ascontiguousarray(grids, dtype=np.int32).reshape(-1, 3)
@@ -197,6 +202,7 @@ class ALB:
         o.tune = 1 if tune else 0
         o.n_guard = int(n_guard)
         o.n_streams = int(n_streams)
+        o.seed = int(seed)
         self.n_guard = int(n_guard)
         if mlp_weights is not None:
             self._mlp = mlp_weights
@@ -281,10 +287,18 @@ class ALB:
         self._check(self.lib.dgdft_alb_set_potential(self.h, _ptr(V), C.byref(k) if k else None,
                                                      _stream()))
 
-    def solve(self, V, kbt, X0, want_vecs=True, want_albs=True):
+    def initial_guess(self, seed, device):
+        """The start block the solver draws for X0 = None (device [sum N_g*J])."""
+        import torch
+        X0 = torch.empty(self.totals()[1], dtype=torch.float64, device=device)
+        self._check(self.lib.dgdft_alb_initial_guess(self.h, int(seed), _ptr(X0), _stream()))
+        return X0
+
+    def solve(self, V, kbt, X0, want_vecs=True, want_albs=True, device=None):
+        """X0 = None: the library draws the start block (seed of the handle)."""
         import torch
         sng, sngj, sj, salb, snalb = self.totals()
-        dev = X0.device
+        dev = X0.device if X0 is not None else (device or torch.device("cuda", torch.cuda.current_device()))
         vals = torch.empty(sj, dtype=torch.float64, device=dev)
         vecs = torch.empty(sngj, dtype=torch.float64, device=dev) if want_vecs else None
         albs = torch.empty(salb, dtype=torch.float64, device=dev) if want_albs else None
@@ -299,7 +313,8 @@ class ALB:
                       n_p_drop=s.n_p_drop, n_ql_fail=s.n_ql_fail,
                       n_teter_fallback=s.n_teter_fallback,
                       graph_launches=s.graph_launches, n_rr_cholesky=s.n_rr_cholesky,
-                      n_rr_series=s.n_rr_series) for s in st]
+                      n_rr_series=s.n_rr_series,
+                      ms_by_phase=dict(zip(PHASES, list(s.ms_by_phase)))) for s in st]
         return dict(status=rc, eigvals=vals, eigvecs=vecs, albs=albs, sigma=sig[:snalb],
                     stats=stats)
 
@@ -509,11 +524,12 @@ def small_gemm_batched(ta, tb, J, kb, dm, dn, dk, A, B, C, alpha=1.0, beta=0.0):
     return Cc
 
 
-def gemm_batched(trans, A, B, alpha=1.0, beta=0.0, Cin=None):
+def gemm_batched(trans, A, B, alpha=1.0, beta=0.0, Cin=None, fp32=False):
     """Column-major batched products on the library's MFMA kernels.
     A: (count, m, K) device tensor = column-major K x m per problem.
     trans=1: B (count, n, K) -> C (count, n, m) = column-major (A^T B) m x n.
-    trans=0: B (count, n, m) (column-major m x n) -> C (count, n, K) = alpha A B + beta C."""
+    trans=0: B (count, n, m) (column-major m x n) -> C (count, n, K) = alpha A B + beta C.
+    fp32: the mixed form's FP32 kernels (FP64 storage)."""
     import torch
     lib = load_library()
     count, m, K = A.shape
@@ -524,7 +540,8 @@ def gemm_batched(trans, A, B, alpha=1.0, beta=0.0, Cin=None):
         Cout = (Cin.clone() if Cin is not None else
                 torch.zeros(count, n, K, dtype=torch.float64, device=A.device))
     Ac, Bc = A.contiguous(), B.contiguous()
-    rc = lib.dgdft_gemm_batched(int(trans), count, K, m, n, alpha, _ptr(Ac), _ptr(Bc), beta,
+    rc = lib.dgdft_gemm_batched(int(trans) | (2 if fp32 else 0), count, K, m, n, alpha, _ptr(Ac),
+                                _ptr(Bc), beta,
                                 _ptr(Cout), _stream())
     if rc != 0:
         raise DGDFTError(rc, lib.dgdft_alb_last_error(None).decode())

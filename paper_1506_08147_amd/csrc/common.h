@@ -157,8 +157,10 @@ enum SmallMat {
   SM_V,       // vectors d, e, w, ... (a few columns of length n)
   SM_W0,      // eigensolver workspace (two consecutive matrices)
   SM_W1,
-  SM_MC,      // [C D]^T M [C D]: S^T S block of [X' P'] for the next step (ld 2J)
-  SM_HC,      // [C D]^T Hh [C D]: S^T H S block of [X' P'] for the next step (ld 2J)
+  SM_MC,      // [C E]^T M [C E]: S^T S block of [X' P'] for the next step (ld 2J)
+  SM_HC,      // [C E]^T Hh [C E]: S^T H S block of [X' P'] for the next step (ld 2J)
+  SM_MO,      // S^T S of the step in the basis [X P W] as formed (before the P block
+  SM_HO,      //   is orthonormalised in small space); S^T H S likewise
   SM_COUNT
 };
 

@@ -17,6 +17,7 @@
 #include "../../include/dgdft_alb.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -65,6 +66,16 @@ struct dgdft_alb {
   float2* tw32_arena = nullptr;
   void* kb_arena = nullptr;        // KB layout of the loaded potential
   size_t kb_cap = 0;
+  // copies of the projector arrays the layout was built from: the layout is
+  // rebuilt (on the host) only when a new potential's arrays differ
+  bool kbc_valid = false;
+  std::vector<int> kbc_nproj;
+  long long kbc_np = 0, kbc_nnz = 0;
+  void* kbc_mem = nullptr;
+  size_t kbc_cap = 0;
+  double *kbc_gamma = nullptr, *kbc_val = nullptr;
+  long long* kbc_ptr = nullptr;
+  int* kbc_idx = nullptr;
   double* proj_arena = nullptr;    // proj + projx
   size_t proj_cap = 0;
   int* d_flag = nullptr;           // scratch flag for input checks
@@ -118,8 +129,35 @@ struct dgdft_alb {
   // on the full basis (used only for the work accounting of the Gram)
   std::vector<char> carry_host;
   std::string err;
+  // Knyazev's form of the search direction (FP64 blocks with guard
+  // columns, tolerance >= KNYAZEV_MIN_TOL), else the orthonormalised one
+  // (see lobpcg.hip).  The mixed form keeps the orthonormalised direction:
+  // its small-space orthonormalisation of P against [X W] assumes [X W]
+  // orthonormal to FP64 rounding, which the FP32 products that form W2 do
+  // not give.  Tight tolerances keep it too: once the residuals fall well
+  // below 1e-7, P lies in span [X W] but for a part of relative size near
+  // the residual, and the Schur complement M_PP - M_QP^T Z that measures
+  // that part loses it to cancellation, so P is dropped step after step
+  // (measured on the slab at 1e-8: an element stalled to 60 iterations).
+  static constexpr double KNYAZEV_MIN_TOL = 1e-7;
+  bool knyazev() const {
+    return opts.n_guard > 0 && opts.precision != DGDFT_PREC_MIXED && opts.tol >= KNYAZEV_MIN_TOL;
+  }
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
+  // wall time of the phases of the last solve (host clock at synchronised
+  // phase boundaries)
+  double phase_ms[DGDFT_PHASES] = {};
+  std::chrono::steady_clock::time_point t_mark;
+  void phase_start() {
+    for (double& v : phase_ms) v = 0.0;
+    t_mark = std::chrono::steady_clock::now();
+  }
+  void phase_mark(int k) {
+    auto t = std::chrono::steady_clock::now();
+    phase_ms[k] += std::chrono::duration<double, std::milli>(t - t_mark).count();
+    t_mark = t;
+  }
 
   // ---- per-kernel-class timing with HIP events on the launch stream
   struct ProfRec {
@@ -309,7 +347,7 @@ struct dgdft_alb {
 
   int cols_host(const Opnd& o, int e) const { return host_opnd_cols(o, hasP_host(e), eh[e].J); }
 
-  void gram(const std::vector<int>& act, const GramArgs& g) {
+  void gram(const std::vector<int>& act, const GramArgs& g, bool fp32 = false) {
     auto K = [&](int e) { return g.use_ne ? eh[e].ne : eh[e].ng; };
     // 144 x 144 tiles when every operand's column count is a multiple of 144
     bool t144 = !act.empty();
@@ -346,10 +384,11 @@ struct dgdft_alb {
     }
     pbeg(DGDFT_K_GRAM, fl, by);
     if (t144)
-      hipLaunchKernelGGL(dg_gram_t144, dim3(P.total), dim3(GRAM144_THREADS), 0, stream, ed, P.active,
-                         P.prefix, P.na, g);
+      hipLaunchKernelGGL(fp32 ? dg_gram_t14432 : dg_gram_t144, dim3(P.total), dim3(GRAM144_THREADS), 0,
+                         stream, ed, P.active, P.prefix, P.na, g);
     else
-      hipLaunchKernelGGL(dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, g);
+      hipLaunchKernelGGL(fp32 ? dg_gram32 : dg_gram, dim3(P.total), dim3(256), 0, stream, ed, P.active,
+                         P.prefix, P.na, g);
     pend();
     auto R = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
@@ -363,7 +402,7 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
   }
 
-  void update(const std::vector<int>& act, const UpdArgs& u) {
+  void update(const std::vector<int>& act, const UpdArgs& u, bool fp32 = false) {
     auto ncols = [&](int e) {
       return u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
     };
@@ -383,14 +422,15 @@ struct dgdft_alb {
       int kA = cols_host(u.A[0], e);
       int nc = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
       fl += u.njob * 2.0 * K * kA * nc;
-      by += u.njob * 8.0 * K * (kA + nc * (u.beta != 0.0 ? 2 : 1));
+      by += u.njob * 8.0 * K * (kA + nc * ((u.beta != 0.0 ? 2 : 1) + (u.split ? 1 : 0)));
     }
     pbeg(DGDFT_K_UPDATE, fl, by);
     if (w144)
-      hipLaunchKernelGGL(dg_update_n144, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix,
-                         P.na, u);
+      hipLaunchKernelGGL(fp32 ? dg_update_n14432 : dg_update_n144, dim3(P.total), dim3(256), 0, stream,
+                         ed, P.active, P.prefix, P.na, u);
     else
-      hipLaunchKernelGGL(dg_update, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, u);
+      hipLaunchKernelGGL(fp32 ? dg_update32 : dg_update, dim3(P.total), dim3(256), 0, stream, ed,
+                         P.active, P.prefix, P.na, u);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -453,6 +493,55 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
   }
 
+  // Small-matrix product from an argument block (row offsets, gates); see
+  // dg_sgemm.  Dimension codes 0: n, 1: J, 2: 2J, 3: n - J.
+  static SgArgs sga(int ta, int tb, int ma, int mb, int mc, int dm_, int dn_, int dk_, int la,
+                    int lb, int lc, double alpha, double beta) {
+    SgArgs a{};
+    a.ta = ta; a.tb = tb; a.ma = ma; a.mb = mb; a.mc = mc;
+    a.dm = dm_; a.dn = dn_; a.dk = dk_; a.la = la; a.lb = lb; a.lc = lc;
+    a.alpha = alpha; a.beta = beta; a.gate = -1;
+    return a;
+  }
+  void sg(const std::vector<int>& act, const SgArgs& a) {
+    auto n_of = [&](int e) { return (a.single ? 1 : (hasP_host(e) ? 3 : 2)) * eh[e].J; };
+    auto P = make_prefix(act, [&](int e) {
+      const int n = n_of(e), J = eh[e].J;
+      return cdiv(sg_dim(a.dm, n, J), 64) * cdiv(sg_dim(a.dn, n, J), 64);
+    });
+    if (P.total == 0) return;
+    double fl = 0;
+    for (int e : act) {
+      const int n = n_of(e), J = eh[e].J;
+      fl += 2.0 * sg_dim(a.dm, n, J) * sg_dim(a.dn, n, J) * sg_dim(a.dk, n, J);
+    }
+    pbeg(DGDFT_K_SGEMM, fl, 0);
+    hipLaunchKernelGGL(dg_sgemm, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na, a);
+    pend();
+    HCHECK(hipGetLastError());
+  }
+  static CpArgs cpa(int ms, int rs, int cs, int ls, int md, int rd, int cd, int ld, int dr, int dc,
+                    int mode, double alpha = 1.0, int gate = 0) {
+    CpArgs a{};
+    a.ms = ms; a.rs = rs; a.cs = cs; a.ls = ls; a.md = md; a.rd = rd; a.cd = cd; a.ld = ld;
+    a.dr = dr; a.dc = dc; a.mode = mode; a.alpha = alpha; a.gate = gate;
+    return a;
+  }
+  void cp(const std::vector<int>& act, const CpArgs& a) {
+    auto P = make_prefix(act, [](int) { return 1; });
+    if (P.na == 0) return;
+    pbeg(DGDFT_K_RR, 0, 0);
+    hipLaunchKernelGGL(dg_small_copy, dim3(P.na), dim3(256), 0, stream, ed, P.active, P.na, a);
+    pend();
+    HCHECK(hipGetLastError());
+  }
+  std::vector<int> with_p(const std::vector<int>& act) const {
+    std::vector<int> r;
+    for (int e : act)
+      if (hasP_host(e)) r.push_back(e);
+    return r;
+  }
+
   // Strided-batched product (dg_bgemm) with split-K over at most BG_KSPLIT
   // chunks when the output tiles alone cannot fill the chip; `part` holds
   // BG_KSPLIT * batch * M * N doubles.
@@ -500,6 +589,44 @@ struct dgdft_alb {
   // decisions one workgroup each, products on dg_sgemm.
   void rr_step(const std::vector<int>& act, int single) {
     const int N = 0, Jc = 1;
+    std::vector<int> ap;
+    const bool kny = knyazev();
+    if (!single && kny) {
+      // basis S = [X P W]: keep S^T S, S^T H S as formed; orthonormalise
+      // the P block against [X W] in small space (see lobpcg.hip)
+      rr_one(act, dg_rr_prep, 256, single);
+      ap = with_p(act);
+      if (!ap.empty()) {
+        // Z = (2I - M_QQ) M_QP in the X and W rows of SM_U (Q = [X W]):
+        // M_QQ^-1 M_QP to first order in M_QQ - I, which the mixed form's
+        // FP32 products leave near 1e-6 and FP64 near 1e-15
+        cp(ap, cpa(SM_M, 0, 1, N, SM_U, 0, 0, N, Jc, Jc, 0, 2.0));
+        cp(ap, cpa(SM_M, 2, 1, N, SM_U, 2, 0, N, Jc, Jc, 0, 2.0));
+        for (int r = 0; r <= 2; r += 2)
+          for (int q = 0; q <= 2; q += 2) {
+            SgArgs a = sga(0, 0, SM_M, SM_M, SM_U, Jc, Jc, Jc, N, N, N, -1.0, 1.0);
+            a.oa = q; a.ra = r; a.ob = 1; a.rb = q; a.rc = r;
+            sg(ap, a);                                                      // - M_rq M_qP
+          }
+        // S_P = M_PP - M_XP^T Z_X - M_WP^T Z_W
+        { SgArgs a = sga(1, 0, SM_M, SM_U, SM_G, Jc, Jc, Jc, N, N, Jc, -1.0, 1.0);
+          a.oa = 1; sg(ap, a); }
+        { SgArgs a = sga(1, 0, SM_M, SM_U, SM_G, Jc, Jc, Jc, N, N, Jc, -1.0, 1.0);
+          a.oa = 1; a.ra = a.rb = 2; sg(ap, a); }
+        per_elem(ap, 0, 2);                                     // T_P -> SM_T (0: P dropped)
+        // B_P (n x J) in SM_MC: [-Z_X T_P; T_P; -Z_W T_P]
+        sg(ap, sga(0, 0, SM_U, SM_T, SM_MC, Jc, Jc, Jc, N, Jc, N, -1.0, 0.0));
+        { SgArgs a = sga(0, 0, SM_U, SM_T, SM_MC, Jc, Jc, Jc, N, Jc, N, -1.0, 0.0);
+          a.ra = 2; a.rc = 2; sg(ap, a); }
+        cp(ap, cpa(SM_T, 0, 0, Jc, SM_MC, 1, 0, N, Jc, Jc, 0));
+        // P blocks of B^T Hh B and B^T M B
+        sg(ap, sga(0, 0, SM_H, SM_MC, SM_U, N, Jc, N, N, N, N, 1.0, 0.0));
+        sg(ap, sga(1, 0, SM_MC, SM_U, SM_A, Jc, Jc, N, N, N, Jc, 1.0, 0.0));
+        sg(ap, sga(0, 0, SM_M, SM_MC, SM_Z, N, Jc, N, N, N, N, 1.0, 0.0));
+        sg(ap, sga(1, 0, SM_MC, SM_Z, SM_W0, Jc, Jc, N, N, N, Jc, 1.0, 0.0));
+        rr_one(ap, dg_rr_pscatter, 256, single);
+      }
+    }
     rr_one(act, dg_rr_reduce, SMALL_THREADS, single);
     // path 0: A = L^-1 A L^-T with SM_T = L^-T
     sgemm(act, single, 1, 0, SM_T, 0, SM_A, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 0);
@@ -534,7 +661,34 @@ struct dgdft_alb {
     }
     rr_one(act, dg_rr_post, 256, single);
     if (single) return;
-    // next search direction: D = E - C (C^T M E), then D <- D (D^T M D)^-1/2 (Cholesky)
+    if (!kny) {
+      rr_tail_ortho(act);
+      return;
+    }
+    if (!ap.empty()) {
+      // C = B C~: the P rows of C~ re-expressed through B_P
+      cp(ap, cpa(SM_C, 1, 0, N, SM_A, 0, 0, Jc, Jc, Jc, 0));
+      cp(ap, cpa(SM_C, 0, 0, N, SM_C, 1, 0, N, Jc, Jc, 3));
+      sg(ap, sga(0, 0, SM_MC, SM_A, SM_C, N, Jc, Jc, N, Jc, N, 1.0, 1.0));
+    }
+    // E = C with its X rows zeroed (next to C); P present next; carry flag
+    rr_one(act, dg_rr_e, 256, single);
+    // [C E]^T M [C E] and [C E]^T Hh [C E] in the basis as formed: the
+    // [X' P'] blocks of the next step's S^T S and S^T H S (dg_carry_in)
+    const int J2 = 2;
+    sgemm(act, single, 0, 0, SM_MO, 0, SM_C, 0, SM_U, 0, N, J2, N, N, N, N, 1.0, 0.0, -1);
+    sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_MC, 0, J2, J2, N, N, N, J2, 1.0, 0.0, -1);
+    sgemm(act, single, 0, 0, SM_HO, 0, SM_C, 0, SM_U, 0, N, J2, N, N, N, N, 1.0, 0.0, -1);
+    sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_HC, 0, J2, J2, N, N, N, J2, 1.0, 0.0, -1);
+  }
+
+  // Orthonormalised next search direction (blocks without guard columns):
+  // D = E - C (C^T M E), then D <- D (D^T M D)^-1/2 (scaled Cholesky); the
+  // carried blocks of the next step from [C D].
+  void rr_tail_ortho(const std::vector<int>& act) {
+    const int N = 0, Jc = 1, single = 0;
+    cp(act, cpa(SM_C, 0, 0, N, SM_Z, 0, 0, N, N, Jc, 0));        // E = C ...
+    cp(act, cpa(SM_C, 0, 0, N, SM_Z, 0, 0, N, Jc, Jc, 3));       // ... with its X rows zeroed
     sgemm(act, single, 0, 0, SM_M, 0, SM_Z, 0, SM_U, 0, N, Jc, N, N, N, N, 1.0, 0.0, -1);
     sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_A, 0, Jc, Jc, N, N, N, Jc, 1.0, 0.0, -1);
     sgemm(act, single, 0, 0, SM_C, 0, SM_A, 0, SM_Z, 0, N, Jc, Jc, N, Jc, N, -1.0, 1.0, -1);
@@ -543,8 +697,6 @@ struct dgdft_alb {
     rr_one(act, dg_rr_dchol, SMALL_THREADS, single);
     // D <- D L^-T with SM_L = L^-T
     sgemm(act, single, 0, 0, SM_Z, 0, SM_L, 0, SM_C, 1, N, Jc, Jc, N, Jc, N, 1.0, 0.0, -1, 1);
-    // [C D]^T M [C D] and [C D]^T Hh [C D]: the [X' P'] blocks of the next
-    // step's S^T S and S^T H S (dg_carry_in), so its Gram skips them
     const int J2 = 2;
     sgemm(act, single, 0, 0, SM_M, 0, SM_C, 0, SM_U, 0, N, J2, N, N, N, N, 1.0, 0.0, -1);
     sgemm(act, single, 1, 0, SM_C, 0, SM_U, 0, SM_MC, 0, J2, J2, N, N, N, J2, 1.0, 0.0, -1);
@@ -699,6 +851,7 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   (void)hipFree(h->tw_arena);
   (void)hipFree(h->tw32_arena);
   (void)hipFree(h->kb_arena);
+  (void)hipFree(h->kbc_mem);
   (void)hipFree(h->proj_arena);
   (void)hipFree(h->d_flag);
   (void)hipFree(h->lrn_arena);
@@ -1090,6 +1243,38 @@ static Status set_potential_impl(dgdft_alb* h, const double* V, const dgdft_kb* 
       np_tot += nproj[e];
     }
   }
+  // unchanged projectors (bitwise, checked on the device): keep the layout
+  if (h->kbc_valid && nproj == h->kbc_nproj) {
+    bool same = np_tot == 0;
+    if (np_tot > 0) {
+      long long nnz_new = -1;
+      HCHECK(hipMemcpyAsync(&nnz_new, kb->ptr + np_tot, sizeof(long long), hipMemcpyDeviceToHost, s));
+      HCHECK(hipStreamSynchronize(s));
+      if (nnz_new == h->kbc_nnz && kb->gamma && kb->ptr && (nnz_new == 0 || (kb->idx && kb->val))) {
+        HCHECK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+        hipLaunchKernelGGL(dg_kb_differs, dim3(1024), dim3(256), 0, s, kb->gamma, h->kbc_gamma, np_tot,
+                           (const long long*)kb->ptr, h->kbc_ptr, kb->idx, h->kbc_idx, kb->val,
+                           h->kbc_val, nnz_new, h->d_flag);
+        HCHECK(hipGetLastError());
+        int diff = 1;
+        HCHECK(hipMemcpyAsync(&diff, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HCHECK(hipStreamSynchronize(s));
+        same = diff == 0;
+      }
+    }
+    if (same) {
+      std::vector<int> all(n);
+      for (int e = 0; e < n; ++e) all[e] = e;
+      h->ring_reset();
+      auto P = h->make_prefix(all, [](int) { return 1; });
+      hipLaunchKernelGGL(dg_vmean, dim3(P.na), dim3(256), 0, h->stream, h->ed, P.active, P.na);
+      HCHECK(hipGetLastError());
+      HCHECK(hipStreamSynchronize(s));
+      h->potential_loaded = true;
+      return fail(DGDFT_OK, "");
+    }
+  }
+  h->kbc_valid = false;
   std::vector<double> gam(np_tot);
   std::vector<int64_t> ptr(np_tot + 1, 0);
   std::vector<int32_t> idx;
@@ -1230,7 +1415,35 @@ static Status set_potential_impl(dgdft_alb* h, const double* V, const dgdft_kb* 
     hipLaunchKernelGGL(dg_vmean, dim3(P.na), dim3(256), 0, h->stream, h->ed, P.active, P.na);
     HCHECK(hipGetLastError());
   }
+  // keep copies of the projector arrays this layout was built from
+  if (np_tot > 0) {
+    const long long nnz = ptr[np_tot];
+    size_t need = align256(sizeof(double) * np_tot) + align256(sizeof(long long) * (np_tot + 1)) +
+                  align256(sizeof(int) * std::max<long long>(nnz, 1)) +
+                  align256(sizeof(double) * std::max<long long>(nnz, 1));
+    if (need > h->kbc_cap) {
+      HCHECK(hipFree(h->kbc_mem));
+      h->kbc_mem = nullptr;
+      HCHECK(hipMalloc(&h->kbc_mem, need));
+      h->kbc_cap = need;
+    }
+    char* q = (char*)h->kbc_mem;
+    h->kbc_gamma = (double*)q; q += align256(sizeof(double) * np_tot);
+    h->kbc_ptr = (long long*)q; q += align256(sizeof(long long) * (np_tot + 1));
+    h->kbc_idx = (int*)q; q += align256(sizeof(int) * std::max<long long>(nnz, 1));
+    h->kbc_val = (double*)q;
+    HCHECK(hipMemcpyAsync(h->kbc_gamma, kb->gamma, sizeof(double) * np_tot, hipMemcpyDeviceToDevice, s));
+    HCHECK(hipMemcpyAsync(h->kbc_ptr, kb->ptr, sizeof(long long) * (np_tot + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz) {
+      HCHECK(hipMemcpyAsync(h->kbc_idx, kb->idx, sizeof(int) * nnz, hipMemcpyDeviceToDevice, s));
+      HCHECK(hipMemcpyAsync(h->kbc_val, kb->val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s));
+    }
+    h->kbc_nnz = nnz;
+  }
+  h->kbc_np = np_tot;
+  h->kbc_nproj = nproj;
   HCHECK(hipStreamSynchronize(s));
+  h->kbc_valid = true;
   h->potential_loaded = true;
   return fail(DGDFT_OK, "");
 }
@@ -1348,8 +1561,16 @@ static void log_step(dgdft_alb* h, const std::vector<int>& act_all) {
 }
 
 // One LOBPCG iteration for the active elements `act` on the current group's
-// stream: Teter preconditioning of the residual in W, projection against
-// [X P], orthonormalisation, H W, Rayleigh-Ritz on [X P W], update, advance.
+// stream (Sec. II.B, the LOBPCG of Knyazev with the basis S = [X P W]):
+// Teter preconditioning of the residual in W; W projected against X (and P
+// in the orthonormalised form) and made orthonormal (CholQR of its explicit
+// Gram, SVQB if that breaks); H W2; the Grams of S = [X P W2] (the [X P]
+// blocks from the last step while they are carried); Rayleigh-Ritz.  With
+// guard columns the search direction keeps Knyazev's form: the P block is
+// orthonormalised in small space inside the Rayleigh-Ritz step and
+// P' = [P W2] [C_P; C_W], X' = X C_X + P' are formed in one pass (and
+// likewise H X', H P'); without, the next direction is orthonormalised in
+// small space and [X' P'] = S [C D].
 static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   h->launch_kbproj(act, VS_X, 0, -1, 1);
   h->per_elem(act, 2, 0);
@@ -1360,33 +1581,39 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
     h->gain_table(act, 1);
   }
   h->precondition(act, S_W, 0, -1, mixed);
-  // W <- W - [X P]([X P]^T W)
+  const bool kny = h->knyazev();
+  // W <- W - X (X^T W) (Knyazev's form) or W <- W - [X P]([X P]^T W)
   GramArgs g1{};
-  g1.A = dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
+  g1.A = kny ? dgdft_alb::opnd({VS_X}) : dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
   g1.B[0] = dgdft_alb::opnd({S_W});
   g1.njob = 1; g1.out_mat[0] = SM_G; g1.upper = 0;
-  h->gram(act, g1);
+  h->gram(act, g1, mixed);
   UpdArgs u1{};
   u1.A[0] = g1.A;
   u1.Y[0] = dgdft_alb::opnd({S_W});
   u1.njob = 1; u1.cmat = SM_G; u1.ncol = -1; u1.alpha = -1.0; u1.beta = 1.0;
-  h->update(act, u1);
-  // W2 = W T (CholQR / SVQB)
+  h->update(act, u1, mixed);
+  // W2 = W T (CholQR / SVQB of the explicit W^T W)
   GramArgs gw{};
   gw.A = dgdft_alb::opnd({S_W});
   gw.B[0] = dgdft_alb::opnd({S_W});
   gw.njob = 1; gw.out_mat[0] = SM_G; gw.upper = 1;
-  h->gram(act, gw);
+  h->gram(act, gw, mixed);
   h->per_elem(act, 0, 0);
   UpdArgs u2{};
   u2.A[0] = dgdft_alb::opnd({S_W});
   u2.Y[0] = dgdft_alb::opnd({S_W2});
   u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = 1.0; u2.beta = 0.0;
-  h->update(act, u2);
+  h->update(act, u2, mixed);
   // HW (FP32 transforms in the mixed form: errors enter H X and H P only
   // through the correction coefficients, and the final check is FP64)
   h->op_apply(act, S_W2, S_HW, 0, -1, mixed);
-  // Rayleigh-Ritz on S = [X P W2]
+  // Rayleigh-Ritz on S = [X P W2]: S^T S and S^T H S (the [X P] blocks
+  // from the last step where they are carried).  FP64 in both forms: the
+  // FP32 products above only leave W2 slightly non-orthonormal and not quite
+  // orthogonal to X, which these exact Grams account for, whereas FP32 Grams
+  // here would perturb the Schur complement of the P block, nearly singular
+  // near convergence, and drop P step after step
   GramArgs g3{};
   g3.A = dgdft_alb::opnd({VS_X, VS_P, S_W2}, {0, 1, 0});
   g3.B[0] = g3.A;
@@ -1395,11 +1622,24 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   h->gram(act, g3);
   h->carry_in(act);
   h->per_elem(act, 1, 0);
+  // (FP64 in both forms as well: P' and H P' formed by separate FP32
+  // products would differ from each other by ~1e-7 |H| |P'|, which H X'
+  // inherits and which stalls the residuals near 1e-5)
   UpdArgs u3{};
   u3.A[0] = g3.A;
   u3.A[1] = g3.B[1];
-  u3.Y[0] = dgdft_alb::opnd({VS_XN, VS_PN});
-  u3.Y[1] = dgdft_alb::opnd({VS_HXN, VS_HPN});
+  if (kny) {
+    // P' = [P W2] C[J:], X' = X C[:J] + P' (and the same with H)
+    u3.Y[0] = dgdft_alb::opnd({VS_XN});
+    u3.Y[1] = dgdft_alb::opnd({VS_HXN});
+    u3.Y2[0] = dgdft_alb::opnd({VS_PN});
+    u3.Y2[1] = dgdft_alb::opnd({VS_HPN});
+    u3.split = 1;
+  } else {
+    // [X' P'] = S [C D], [HX' HP'] = HS [C D]
+    u3.Y[0] = dgdft_alb::opnd({VS_XN, VS_PN});
+    u3.Y[1] = dgdft_alb::opnd({VS_HXN, VS_HPN});
+  }
   u3.njob = 2; u3.cmat = SM_C; u3.ncol = -1; u3.alpha = 1.0; u3.beta = 0.0;
   h->update(act, u3);
   h->per_elem(act, 3, 0);
@@ -1451,13 +1691,15 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   hipStream_t s = h->stream;
   for (int g = 0; g < dgdft_alb::NGROUP; ++g) h->g_ring_pos[g] = 0;
   h->ring_reset();
-  // ---- X0 finiteness
-  HCHECK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
-  hipLaunchKernelGGL(dg_check_finite, dim3(1024), dim3(256), 0, s, X0, (long long)h->sumNgJ, h->d_flag);
-  int bad = 0;
-  HCHECK(hipMemcpyAsync(&bad, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HCHECK(hipStreamSynchronize(s));
-  if (bad) return fail(DGDFT_EINVAL, "X0 contains non-finite values");
+  // ---- X0 finiteness (a start block drawn here is finite)
+  if (X0) {
+    HCHECK(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+    hipLaunchKernelGGL(dg_check_finite, dim3(1024), dim3(256), 0, s, X0, (long long)h->sumNgJ, h->d_flag);
+    int bad = 0;
+    HCHECK(hipMemcpyAsync(&bad, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HCHECK(hipStreamSynchronize(s));
+    if (bad) return fail(DGDFT_EINVAL, "X0 contains non-finite values");
+  }
   if (h->opts.precond == DGDFT_PRECOND_LEARNED && !h->mlp_w)
     return fail(DGDFT_EINVAL, "learned preconditioner without weights (dgdft_alb_set_mlp)");
   HCHECK(hipMemsetAsync(h->fl_arena, 0, sizeof(int) * (size_t)n * FL_COUNT, s));
@@ -1467,8 +1709,13 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   // ---- initial block: X = X0 T with T from a scaled CholQR of X0
   {
     auto P = h->make_prefix(all, [&](int e) { return h->eh[e].J; });
-    hipLaunchKernelGGL(dg_load_block, dim3(P.total), dim3(256), 0, s, h->ed, P.active, P.prefix, P.na,
-                       X0, (int)S_W, 1.0);
+    if (X0)
+      hipLaunchKernelGGL(dg_load_block, dim3(P.total), dim3(256), 0, s, h->ed, P.active, P.prefix,
+                         P.na, X0, (int)S_W, 1.0);
+    else
+      hipLaunchKernelGGL(dg_random_start, dim3(P.total), dim3(256), 0, s, h->ed, P.active, P.prefix,
+                         P.na, (unsigned)(h->opts.seed & 0xFFFFFFFFull), (unsigned)(h->opts.seed >> 32),
+                         (int)S_W, (double*)nullptr);
     HCHECK(hipGetLastError());
   }
   GramArgs gw{};
@@ -1491,6 +1738,8 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   h->update(all, ux);
   h->op_apply(all, VS_X, VS_HX, 0, -1);
   rr_on_x(h, all);
+  HCHECK(hipStreamSynchronize(s));
+  h->phase_mark(1);
 
   std::vector<int> iters(n, 0), glaunch(n, 0);
   const double tol = h->opts.tol;
@@ -1551,6 +1800,8 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
       HCHECK(hipStreamWaitEvent(h->g_stream[0], h->g_done[g], 0));
     }
     h->set_group(0);
+    HCHECK(hipStreamSynchronize(h->stream));
+    h->phase_mark(2);
     // ---- final FP64 check: fresh HX, RR on X, residuals
     h->ring_reset();
     h->op_apply(pending, VS_X, VS_HX, 0, -1);
@@ -1558,6 +1809,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
     rr_on_x(h, pending);
     h->per_elem_cols(pending, 1, VS_X, VS_HX, S_W, nullptr, nullptr);
     h->poll();
+    h->phase_mark(3);
     std::vector<int> again;
     for (int e : pending)
       if (!(h->max_res(e) <= tol) && iters[e] < max_iter) again.push_back(e);
@@ -1590,6 +1842,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   }
   h->per_elem_cols(all, 3, VS_X, 0, 0, eigvals, eigvecs);
   HCHECK(hipStreamSynchronize(s));
+  h->phase_mark(4);
   h->flush_prof();
   if (sig_tmp) (void)hipFree(sig_tmp);
   for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
@@ -1626,6 +1879,7 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
         for (int j = 0; j < h->eh[e].J; ++j) nf += stall[4 * (h->eh[e].off_j + j) + 3] != 0.0;
       stats[e].n_teter_fallback = nf;
       stats[e].graph_launches = glaunch[e];
+      for (int k = 0; k < DGDFT_PHASES; ++k) stats[e].ms_by_phase[k] = h->phase_ms[k];
     }
   }
   return fail(any_nc ? DGDFT_NOT_CONVERGED : DGDFT_OK, any_nc ? "some element did not converge" : "");
@@ -1635,12 +1889,14 @@ int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb, const
                         double* eigvals, double* eigvecs, double* albs, double* sigma,
                         dgdft_alb_stats* stats, void* stream) {
   if (!h) return DGDFT_EINVAL;
-  if (!X0 || !eigvals) { h->err = "X0 and eigvals must be non-NULL"; return DGDFT_EINVAL; }
+  if (!eigvals) { h->err = "eigvals must be non-NULL"; return DGDFT_EINVAL; }
   bind_stream(h, stream);
   try {
+    h->phase_start();
     if (V) {
       Status st = set_potential_impl(h, V, kb, h->stream);
       if (st.code != DGDFT_OK) { h->err = st.msg; return st.code; }
+      h->phase_mark(0);
     } else if (!h->potential_loaded) {
       h->err = "no potential loaded (pass V or call dgdft_alb_set_potential)";
       return DGDFT_EINVAL;
@@ -1651,6 +1907,25 @@ int32_t dgdft_alb_solve(dgdft_alb* h, const double* V, const dgdft_kb* kb, const
   } catch (HipFail& f) {
     h->err = f.what;
     return f.code == hipErrorOutOfMemory ? DGDFT_ENOMEM : DGDFT_EHIP;
+  }
+}
+
+int32_t dgdft_alb_initial_guess(dgdft_alb* h, uint64_t seed, double* X0, void* stream) {
+  if (!h) return DGDFT_EINVAL;
+  if (!X0) { h->err = "initial_guess: X0 is NULL"; return DGDFT_EINVAL; }
+  bind_stream(h, stream);
+  try {
+    h->ring_reset();
+    std::vector<int> all = all_elems(h->n);
+    auto P = h->make_prefix(all, [&](int e) { return h->eh[e].J; });
+    hipLaunchKernelGGL(dg_random_start, dim3(P.total), dim3(256), 0, h->stream, h->ed, P.active,
+                       P.prefix, P.na, (unsigned)(seed & 0xFFFFFFFFull), (unsigned)(seed >> 32), 0, X0);
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamSynchronize(h->stream));
+    return DGDFT_OK;
+  } catch (HipFail& f) {
+    h->err = f.what;
+    return DGDFT_EHIP;
   }
 }
 
@@ -1969,10 +2244,12 @@ int32_t dgdft_small_gemm_batched(int32_t ta, int32_t tb, int32_t count, int32_t 
 int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, int32_t n, double alpha,
                            const double* A, const double* B, double beta, double* C, void* stream) {
   if (count < 1 || K < 1 || K > (1LL << 30) || m < 1 || n < 1 || !A || !B || !C ||
-      (trans != 0 && trans != 1) || (long long)m * n > (1LL << 30)) {
+      trans < 0 || trans > 3 || (long long)m * n > (1LL << 30)) {
     g_create_error = "gemm_batched: bad arguments";
     return DGDFT_EINVAL;
   }
+  const bool fp32 = (trans & 2) != 0;
+  trans &= 1;
   hipStream_t s = (hipStream_t)stream;
   try {
     TmpDev t;
@@ -2022,10 +2299,11 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
       GramArgs g{};
       g.A = oa; g.B[0] = ob; g.njob = 1; g.out_mat[0] = 0; g.upper = 0;
       if (m % GTT == 0 && n % GTT == 0)
-        hipLaunchKernelGGL(dg_gram_t144, dim3(pre[count]), dim3(GRAM144_THREADS), 0, s, ed, d_act, d_pre,
-                           count, g);
+        hipLaunchKernelGGL(fp32 ? dg_gram_t14432 : dg_gram_t144, dim3(pre[count]), dim3(GRAM144_THREADS), 0, s,
+                           ed, d_act, d_pre, count, g);
       else
-        hipLaunchKernelGGL(dg_gram, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, g);
+        hipLaunchKernelGGL(fp32 ? dg_gram32 : dg_gram, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre,
+                           count, g);
       hipLaunchKernelGGL(dg_gram_reduce, dim3(pre2[count]), dim3(256), 0, s, ed, d_act, d_pre2, count, g);
     } else {
       UpdArgs u{};
@@ -2033,9 +2311,11 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
       u.alpha = alpha; u.beta = beta;
       // column tiles as in the solver: 144 wide when n is a multiple of 144
       if (n % UTN == 0)
-        hipLaunchKernelGGL(dg_update_n144, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, u);
+        hipLaunchKernelGGL(fp32 ? dg_update_n14432 : dg_update_n144, dim3(pre[count]), dim3(256), 0, s, ed,
+                           d_act, d_pre, count, u);
       else
-        hipLaunchKernelGGL(dg_update, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre, count, u);
+        hipLaunchKernelGGL(fp32 ? dg_update32 : dg_update, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre,
+                           count, u);
     }
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(s));

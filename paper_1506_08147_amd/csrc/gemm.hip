@@ -23,6 +23,38 @@
 namespace dg {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// The 16 x 16 x 4 matrix-core product in the element type T of the tile:
+// FP64 (v_mfma_f64_16x16x4f64) or FP32 (v_mfma_f32_16x16x4f32, the products
+// of the mixed-precision form; operands are rounded to FP32 on their way into
+// LDS, the accumulation is FP32 within a tile and FP64 across split-K
+// chunks).  Both take operand lane l as A[l%16][l/16] and B[l/16][l%16]; the
+// accumulator layouts differ (measured on the device with one-hot operands):
+// FP64 register r of lane l holds D[4r + l/16][l%16], FP32 register r holds
+// D[4(l/16) + r][l%16].  Padded LDS rows keep the two 16-lane halves of a
+// fragment read on disjoint banks.
+template <class T> struct Mf;
+template <> struct Mf<double> {
+  typedef dbl4 acc;
+  static constexpr int pad = 4;      // LDS row padding (elements)
+  static constexpr int pad144 = 4;
+  __device__ static __forceinline__ acc zero() { return (dbl4){0.0, 0.0, 0.0, 0.0}; }
+  __device__ static __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mf<float> {
+  typedef flt4 acc;
+  static constexpr int pad = 16;
+  static constexpr int pad144 = 32;
+  __device__ static __forceinline__ acc zero() { return (flt4){0.0f, 0.0f, 0.0f, 0.0f}; }
+  __device__ static __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static __forceinline__ int row(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
 
 struct GramArgs {
   Opnd A, B[2];
@@ -38,10 +70,21 @@ struct UpdArgs {
   Opnd Y[2];
   int njob;
   int cmat;        // small-workspace matrix holding C (ld = cols of A)
-  int ccol0;       // first column of C used
+  int ccol0;       // first column of C used, in units of J
   int ncol;        // columns of Y written (-1: all columns of Y, -2: n_alb)
   double alpha, beta;
   int use_ne;
+  // split = 1: the inner index runs over columns J..kA-1 of A first, the
+  // partial product (alpha, no beta) is written to Y2, then columns 0..J-1
+  // complete Y: with A = [X P W], Y2 = [P W] C[J:] and Y = X C[:J] + Y2 in
+  // one pass over the blocks
+  int split;
+  Opnd Y2[2];
+  // C = sm(cmat) from row crow0 J, column ccol0 J, with leading dimension kA
+  // (cld 0) or the element's basis width (has_p ? 3 : 2) J (cld 1); Z[job]
+  // (if it has blocks) replaces Y as the source of the beta term
+  int crow0, cld;
+  Opnd Z[2];
 };
 
 __device__ __forceinline__ int rowsK(const Elem& e, int use_ne) { return use_ne ? e.ne : e.ng; }
@@ -56,11 +99,13 @@ constexpr int TT = 128;        // workgroup tile edge
 constexpr int KS = 16;         // K stage
 constexpr int LP = TT + 4;     // padded LDS row (doubles)
 
-extern "C" __global__ void __launch_bounds__(256)
-dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+template <class T>
+__device__ __forceinline__ void dg_gram_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
         int na, GramArgs g) {
-  __shared__ double As[2][KS * LP];
-  __shared__ double Bs[2][KS * LP];
+  constexpr int LPT = TT + Mf<T>::pad;
+
+  __shared__ T As[2][KS * LPT];
+  __shared__ T Bs[2][KS * LPT];
   __shared__ const double* colA[TT];
   __shared__ const double* colB[TT];
   int blk = blockIdx.x;
@@ -120,8 +165,8 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      As[buf][lk * LP + lc + 16 * u] = ra[u];
-      Bs[buf][lk * LP + lc + 16 * u] = rb[u];
+      As[buf][lk * LPT + lc + 16 * u] = ra[u];
+      Bs[buf][lk * LPT + lc + 16 * u] = rb[u];
     }
   };
   const int lane = tid & 63, wv = tid >> 6;
@@ -130,11 +175,11 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
   // the last tile row or column of a size that is no multiple of 128) skips
   // its products
   const bool live = ti * TT + wi * 64 < m && tj * TT + wj * 64 < n;
-  dbl4 acc[4][4];
+  typename Mf<T>::acc acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 4; ++c) acc[a][c] = Mf<T>::zero();
   const int nst = (kend - kbeg + KS - 1) / KS;
   if (nst > 0) {
     load(kbeg);
@@ -148,16 +193,16 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        double fa[4], fb[4];
+        T fa[4], fb[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) fa[a] = As[cur][kk * LP + wi * 64 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 4; ++a) fa[a] = As[cur][kk * LPT + wi * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fb[c] = Bs[cur][kk * LP + wj * 64 + c * 16 + (lane & 15)];
+        for (int c = 0; c < 4; ++c) fb[c] = Bs[cur][kk * LPT + wj * 64 + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+            acc[a][c] = Mf<T>::mma(fa[a], fb[c], acc[a][c]);
       }
     }
     if (st + 1 < nst) store(cur ^ 1);
@@ -170,10 +215,22 @@ dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restr
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = ti * TT + wi * 64 + a * 16 + 4 * r + (lane >> 4);
+        int i = ti * TT + wi * 64 + a * 16 + Mf<T>::row(r, lane);
         int j = tj * TT + wj * 64 + c * 16 + (lane & 15);
-        if (i < m && j < n) part[i + (long long)m * j] = acc[a][c][r];
+        if (i < m && j < n) part[i + (long long)m * j] = (double)acc[a][c][r];
       }
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+        int na, GramArgs g) {
+  dg_gram_body<double>(E, active, prefix, na, g);
+}
+
+extern "C" __global__ void __launch_bounds__(256)
+dg_gram32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+        int na, GramArgs g) {
+  dg_gram_body<float>(E, active, prefix, na, g);
 }
 
 // The same product with 144 x 144 tiles, for operands whose column counts
@@ -184,11 +241,13 @@ constexpr int GTT = 144;       // tile edge of dg_gram_t144
 constexpr int GLP = GTT + 4;
 constexpr int GRAM144_THREADS = 576;
 
-extern "C" __global__ void __launch_bounds__(GRAM144_THREADS)
-dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+template <class T>
+__device__ __forceinline__ void dg_gram_t144_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
              int na, GramArgs g) {
-  __shared__ double As[2][KS * GLP];
-  __shared__ double Bs[2][KS * GLP];
+  constexpr int GLPT = GTT + Mf<T>::pad144;
+
+  __shared__ T As[2][KS * GLPT];
+  __shared__ T Bs[2][KS * GLPT];
   __shared__ const double* colA[GTT];
   __shared__ const double* colB[GTT];
   int blk = blockIdx.x;
@@ -244,18 +303,18 @@ dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      As[buf][lk * GLP + lc + 36 * u] = ra[u];
-      Bs[buf][lk * GLP + lc + 36 * u] = rb[u];
+      As[buf][lk * GLPT + lc + 36 * u] = ra[u];
+      Bs[buf][lk * GLPT + lc + 36 * u] = rb[u];
     }
   };
   const int lane = tid & 63, wv = tid >> 6;
   const int wi = wv % 3, wj = wv / 3;
   const bool live = ti * GTT + wi * 48 < m && tj * GTT + wj * 48 < n;
-  dbl4 acc[3][3];
+  typename Mf<T>::acc acc[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 3; ++c) acc[a][c] = Mf<T>::zero();
   const int nst = (kend - kbeg + KS - 1) / KS;
   if (nst > 0) {
     load(kbeg);
@@ -269,16 +328,16 @@ dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        double fa[3], fb[3];
+        T fa[3], fb[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fa[a] = As[cur][kk * GLP + wi * 48 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 3; ++a) fa[a] = As[cur][kk * GLPT + wi * 48 + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) fb[c] = Bs[cur][kk * GLP + wj * 48 + c * 16 + (lane & 15)];
+        for (int c = 0; c < 3; ++c) fb[c] = Bs[cur][kk * GLPT + wj * 48 + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[c], acc[a][c], 0, 0, 0);
+            acc[a][c] = Mf<T>::mma(fa[a], fb[c], acc[a][c]);
       }
     }
     if (st + 1 < nst) store(cur ^ 1);
@@ -291,10 +350,22 @@ dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = ti * GTT + wi * 48 + a * 16 + 4 * r + (lane >> 4);
+        int i = ti * GTT + wi * 48 + a * 16 + Mf<T>::row(r, lane);
         int j = tj * GTT + wj * 48 + c * 16 + (lane & 15);
-        if (i < m && j < n) part[i + (long long)m * j] = acc[a][c][r];
+        if (i < m && j < n) part[i + (long long)m * j] = (double)acc[a][c][r];
       }
+}
+
+extern "C" __global__ void __launch_bounds__(GRAM144_THREADS)
+dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+             int na, GramArgs g) {
+  dg_gram_t144_body<double>(E, active, prefix, na, g);
+}
+
+extern "C" __global__ void __launch_bounds__(GRAM144_THREADS)
+dg_gram_t14432(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+             int na, GramArgs g) {
+  dg_gram_t144_body<float>(E, active, prefix, na, g);
 }
 
 // Sum split-K partials into sm(e, out_mat[job]) (ld = m).  Work item: a
@@ -336,12 +407,16 @@ constexpr int UPD_NH = UKS / 16;
 #define DG_UPD_WAVES_PER_EU 2
 #endif
 
-extern "C" __global__ void __launch_bounds__(256, DG_UPD_WAVES_PER_EU)
-dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+template <class T>
+__device__ __forceinline__ void dg_update_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
           int na, UpdArgs u) {
-  __shared__ double As[2][UKS * LP];
-  __shared__ double Cs[2][UKS * LP];
+  constexpr int LPT = TT + Mf<T>::pad;
+
+  __shared__ T As[2][UKS * LPT];
+  __shared__ T Cs[2][UKS * LPT];
   __shared__ double* colY[TT];
+  __shared__ double* colY2[TT];
+  __shared__ const double* colZ[TT];
   __shared__ const double* abase[6];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
@@ -358,7 +433,8 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   int tr = w / ntc, tc = w - tr * ntc;
   const Opnd& A = u.A[job];
   const Opnd& Y = u.Y[job];
-  const double* C = sm(e, u.cmat) + (long long)u.ccol0 * kA;
+  const int cld = u.cld ? (has_p(e) ? 3 : 2) * e.J : kA;
+  const double* C = sm(e, u.cmat) + (long long)u.ccol0 * e.J * cld + (long long)u.crow0 * e.J;
   const int row0 = tr * TT, col0 = tc * TT;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -370,7 +446,11 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
         if (!(A.optP[i] && !has_p(e))) abase[q++] = bp(e, A.slot[i]);
     }
   }
-  if (tid < TT) colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
+  if (tid < TT) {
+    colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
+    colY2[tid] = (u.split && col0 + tid < ncol) ? opnd_col(u.Y2[job], e, col0 + tid) : nullptr;
+    colZ[tid] = (u.Z[job].nblk > 0 && col0 + tid < ncol) ? opnd_col(u.Z[job], e, col0 + tid) : nullptr;
+  }
   __syncthreads();
   const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
   const long long ld = e.ld;
@@ -380,12 +460,12 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   const int ck = tid & 15, cj = tid >> 4;
   const bool rin = row0 + ar < K;
   double ra[UPD_NQ], rc[8 * UPD_NH];
-  auto load = [&](int k0) {
+  auto load = [&](int k0, int kend) {
 #pragma unroll
     for (int q = 0; q < UPD_NQ; ++q) {
       int k = k0 + ak + 2 * q;
       double v = 0.0;
-      if (k < kA && rin) {
+      if (k < kend && rin) {
         int bb = k / bcols;
         v = abase[bb][(long long)(k - bb * bcols) * ld + row0 + ar];
       }
@@ -397,48 +477,67 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
       for (int v = 0; v < 8; ++v) {
         int j = col0 + cj + 16 * v;
         int kc = k0 + ck + 16 * h;
-        rc[8 * h + v] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
+        rc[8 * h + v] = (kc < kend && j < ncol) ? C[kc + (long long)cld * j] : 0.0;
       }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LP + ar] = ra[q];
+    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LPT + ar] = ra[q];
 #pragma unroll
     for (int h = 0; h < UPD_NH; ++h)
 #pragma unroll
-      for (int v = 0; v < 8; ++v) Cs[buf][(ck + 16 * h) * LP + cj + 16 * v] = rc[8 * h + v];
+      for (int v = 0; v < 8; ++v) Cs[buf][(ck + 16 * h) * LPT + cj + 16 * v] = rc[8 * h + v];
   };
   const int lane = tid & 63, wv = tid >> 6;
   const int wj = wv & 1, wr = wv >> 1;
   // a wave whose 64 columns lie wholly outside Y (in the last column tile of
   // a width that is no multiple of 128) skips its products
   const bool live = col0 + wj * 64 < ncol;
-  dbl4 acc[4][4];
+  typename Mf<T>::acc acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  const int nst = cdiv(kA, UKS);
-  load(0);
+    for (int c = 0; c < 4; ++c) acc[a][c] = Mf<T>::zero();
+  // stages: with split, columns J..kA-1 of A (nst0 stages), then 0..J-1
+  const int J = e.J;
+  const int nst0 = u.split ? cdiv(kA - J, UKS) : 0;
+  const int nst = nst0 + cdiv(u.split ? J : kA, UKS);
+  auto kbeg = [&](int st) { return st < nst0 ? J + st * UKS : (st - nst0) * UKS; };
+  auto kend = [&](int st) { return st < nst0 ? kA : (u.split ? J : kA); };
+  load(kbeg(0), kend(0));
   store(0);
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    if (st + 1 < nst) load((st + 1) * UKS);
+    if (st + 1 < nst) load(kbeg(st + 1), kend(st + 1));
     if (live) {
 #pragma unroll
       for (int ks = 0; ks < UKS / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        double fc[4], fa[4];
+        T fc[4], fa[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) fc[a] = Cs[cur][kk * LP + wj * 64 + a * 16 + (lane & 15)];
+        for (int a = 0; a < 4; ++a) fc[a] = Cs[cur][kk * LPT + wj * 64 + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fa[c] = As[cur][kk * LP + wr * 64 + c * 16 + (lane & 15)];
+        for (int c = 0; c < 4; ++c) fa[c] = As[cur][kk * LPT + wr * 64 + c * 16 + (lane & 15)];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int c = 0; c < 4; ++c)
-            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc[a], fa[c], acc[a][c], 0, 0, 0);
+            acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
+      }
+      if (st == nst0 - 1) {   // [P W] part complete: Y2 = alpha [P W] C[J:]
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double* y2 = colY2[wj * 64 + a * 16 + Mf<T>::row(r, lane)];
+            if (!y2) continue;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              int row = row0 + wr * 64 + c * 16 + (lane & 15);
+              if (row < K) y2[row] = u.alpha * (double)acc[a][c][r];
+            }
+          }
       }
     }
     if (st + 1 < nst) store(cur ^ 1);
@@ -448,19 +547,32 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int jl = wj * 64 + a * 16 + 4 * r + (lane >> 4);
+      int jl = wj * 64 + a * 16 + Mf<T>::row(r, lane);
       double* y = colY[jl];
       if (!y) continue;
+      const double* zc = colZ[jl];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         int row = row0 + wr * 64 + c * 16 + (lane & 15);
         if (row < K) {
-          double v = u.alpha * acc[a][c][r];
-          if (u.beta != 0.0) v += u.beta * y[row];
+          double v = u.alpha * (double)acc[a][c][r];
+          if (u.beta != 0.0) v += u.beta * (zc ? zc[row] : y[row]);
           y[row] = v;
         }
       }
     }
+}
+
+extern "C" __global__ void __launch_bounds__(256, DG_UPD_WAVES_PER_EU)
+dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+          int na, UpdArgs u) {
+  dg_update_body<double>(E, active, prefix, na, u);
+}
+
+extern "C" __global__ void __launch_bounds__(256, DG_UPD_WAVES_PER_EU)
+dg_update32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+          int na, UpdArgs u) {
+  dg_update_body<float>(E, active, prefix, na, u);
 }
 
 // The same product with 128 x 144 workgroup tiles, for column counts that are
@@ -472,12 +584,17 @@ dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __res
 constexpr int UTN = 144;       // column tile of dg_update_n144
 constexpr int LPC = UTN + 4;
 
-extern "C" __global__ void __launch_bounds__(256, 2)
-dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+template <class T>
+__device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                int na, UpdArgs u) {
-  __shared__ double As[2][UKS * LP];
-  __shared__ double Cs[2][UKS * LPC];
+  constexpr int LPT = TT + Mf<T>::pad;
+  constexpr int LPCT = UTN + Mf<T>::pad144;
+
+  __shared__ T As[2][UKS * LPT];
+  __shared__ T Cs[2][UKS * LPCT];
   __shared__ double* colY[UTN];
+  __shared__ double* colY2[UTN];
+  __shared__ const double* colZ[UTN];
   __shared__ const double* abase[6];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
@@ -494,7 +611,8 @@ dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* 
   int tr = w / ntc, tc = w - tr * ntc;
   const Opnd& A = u.A[job];
   const Opnd& Y = u.Y[job];
-  const double* C = sm(e, u.cmat) + (long long)u.ccol0 * kA;
+  const int cld = u.cld ? (has_p(e) ? 3 : 2) * e.J : kA;
+  const double* C = sm(e, u.cmat) + (long long)u.ccol0 * e.J * cld + (long long)u.crow0 * e.J;
   const int row0 = tr * TT, col0 = tc * UTN;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -506,7 +624,11 @@ dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* 
         if (!(A.optP[i] && !has_p(e))) abase[q++] = bp(e, A.slot[i]);
     }
   }
-  if (tid < UTN) colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
+  if (tid < UTN) {
+    colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
+    colY2[tid] = (u.split && col0 + tid < ncol) ? opnd_col(u.Y2[job], e, col0 + tid) : nullptr;
+    colZ[tid] = (u.Z[job].nblk > 0 && col0 + tid < ncol) ? opnd_col(u.Z[job], e, col0 + tid) : nullptr;
+  }
   __syncthreads();
   const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
   const long long ld = e.ld;
@@ -516,12 +638,12 @@ dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* 
   const int ck = tid & 15, cj = tid >> 4;
   const bool rin = row0 + ar < K;
   double ra[UPD_NQ], rc[9];
-  auto load = [&](int k0) {
+  auto load = [&](int k0, int kend) {
 #pragma unroll
     for (int q = 0; q < UPD_NQ; ++q) {
       int k = k0 + ak + 2 * q;
       double v = 0.0;
-      if (k < kA && rin) {
+      if (k < kend && rin) {
         int bb = k / bcols;
         v = abase[bb][(long long)(k - bb * bcols) * ld + row0 + ar];
       }
@@ -531,41 +653,60 @@ dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* 
     for (int v = 0; v < 9; ++v) {
       int j = col0 + cj + 16 * v;
       int kc = k0 + ck;
-      rc[v] = (kc < kA && j < ncol) ? C[kc + (long long)kA * j] : 0.0;
+      rc[v] = (kc < kend && j < ncol) ? C[kc + (long long)cld * j] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LP + ar] = ra[q];
+    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LPT + ar] = ra[q];
 #pragma unroll
-    for (int v = 0; v < 9; ++v) Cs[buf][ck * LPC + cj + 16 * v] = rc[v];
+    for (int v = 0; v < 9; ++v) Cs[buf][ck * LPCT + cj + 16 * v] = rc[v];
   };
   const int lane = tid & 63, wr = tid >> 6;
-  dbl4 acc[9][2];
+  typename Mf<T>::acc acc[9][2];
 #pragma unroll
   for (int a = 0; a < 9; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = (dbl4){0.0, 0.0, 0.0, 0.0};
-  const int nst = cdiv(kA, UKS);
-  load(0);
+    for (int c = 0; c < 2; ++c) acc[a][c] = Mf<T>::zero();
+  // stages: with split, columns J..kA-1 of A (nst0 stages), then 0..J-1
+  const int J = e.J;
+  const int nst0 = u.split ? cdiv(kA - J, UKS) : 0;
+  const int nst = nst0 + cdiv(u.split ? J : kA, UKS);
+  auto kbeg = [&](int st) { return st < nst0 ? J + st * UKS : (st - nst0) * UKS; };
+  auto kend = [&](int st) { return st < nst0 ? kA : (u.split ? J : kA); };
+  load(kbeg(0), kend(0));
   store(0);
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    if (st + 1 < nst) load((st + 1) * UKS);
+    if (st + 1 < nst) load(kbeg(st + 1), kend(st + 1));
 #pragma unroll
     for (int ks = 0; ks < UKS / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      double fc[9], fa[2];
+      T fc[9], fa[2];
 #pragma unroll
-      for (int a = 0; a < 9; ++a) fc[a] = Cs[cur][kk * LPC + a * 16 + (lane & 15)];
+      for (int a = 0; a < 9; ++a) fc[a] = Cs[cur][kk * LPCT + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LP + wr * 32 + c * 16 + (lane & 15)];
+      for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPT + wr * 32 + c * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < 9; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fc[a], fa[c], acc[a][c], 0, 0, 0);
+          acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
+    }
+    if (st == nst0 - 1) {   // [P W] part complete: Y2 = alpha [P W] C[J:]
+#pragma unroll
+      for (int a = 0; a < 9; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double* y2 = colY2[a * 16 + Mf<T>::row(r, lane)];
+          if (!y2) continue;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            int row = row0 + wr * 32 + c * 16 + (lane & 15);
+            if (row < K) y2[row] = u.alpha * (double)acc[a][c][r];
+          }
+        }
     }
     if (st + 1 < nst) store(cur ^ 1);
     __syncthreads();
@@ -574,19 +715,32 @@ dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* 
   for (int a = 0; a < 9; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int jl = a * 16 + 4 * r + (lane >> 4);
+      int jl = a * 16 + Mf<T>::row(r, lane);
       double* y = colY[jl];
       if (!y) continue;
+      const double* zc = colZ[jl];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         int row = row0 + wr * 32 + c * 16 + (lane & 15);
         if (row < K) {
-          double v = u.alpha * acc[a][c][r];
-          if (u.beta != 0.0) v += u.beta * y[row];
+          double v = u.alpha * (double)acc[a][c][r];
+          if (u.beta != 0.0) v += u.beta * (zc ? zc[row] : y[row]);
           y[row] = v;
         }
       }
     }
+}
+
+extern "C" __global__ void __launch_bounds__(256, 2)
+dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+               int na, UpdArgs u) {
+  dg_update_n144_body<double>(E, active, prefix, na, u);
+}
+
+extern "C" __global__ void __launch_bounds__(256, 2)
+dg_update_n14432(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+               int na, UpdArgs u) {
+  dg_update_n144_body<float>(E, active, prefix, na, u);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,22 +748,26 @@ dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* 
 // n = kJ), spread over many workgroups: C = alpha op(A) op(B) + beta C with
 // all three in the element's small workspace.  Dimensions and leading
 // dimensions are given as codes resolved per element: 0 -> n = kJ (k = 1
-// for the step on X alone, else 2 or 3 by the presence of P), 1 -> J.
+// for the step on X alone, else 2 or 3 by the presence of P), 1 -> J,
+// 2 -> 2J, 3 -> n - J; block offsets in units of J (-1: the last block).
 // 64 x 64 tiles, four waves of 32 x 32, 16-deep K stages double-buffered
 // through LDS with the next stage prefetched into registers.
 struct SgArgs {
   int ta, tb;
   int ma, oa, mb, ob, mc, oc;    // small-workspace matrix and column offset (in J)
+  int ra, rb, rc;                // row offsets (in J)
   int dm, dn, dk;                // dimension codes
   int la, lb, lc;                // leading-dimension codes
   double alpha, beta;
   int gate;                      // -1: all; else only elements with fl[FL_RR_PATH] == gate
   int gate_pok;                  // 1: only elements whose next direction is kept
   int single;
+  int gate_carry;                // 1: only elements whose leading [X P] block is carried,
+                                 // 2: only elements with P, 3: both
 };
 
 __host__ __device__ inline int sg_dim(int code, int n, int J) {
-  return code == 0 ? n : (code == 2 ? 2 * J : J);
+  return code == 0 ? n : (code == 2 ? 2 * J : (code == 3 ? n - J : J));
 }
 
 extern "C" __global__ void __launch_bounds__(256)
@@ -622,13 +780,17 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
   const Elem& e = E[active[ai]];
   if (a.gate >= 0 && e.fl[FL_RR_PATH] != a.gate) return;
   if (a.gate_pok && !e.fl[FL_HASP_NEXT]) return;
+  if ((a.gate_carry & 1) && carried_cols(e) == 0) return;
+  if ((a.gate_carry & 2) && !has_p(e)) return;
   const int J = e.J;
   const int n = (a.single ? 1 : (has_p(e) ? 3 : 2)) * J;
   const int M = sg_dim(a.dm, n, J), N = sg_dim(a.dn, n, J), K = sg_dim(a.dk, n, J);
   const int lda = sg_dim(a.la, n, J), ldb = sg_dim(a.lb, n, J), ldc = sg_dim(a.lc, n, J);
-  const double* A = sm(e, a.ma) + (long long)a.oa * J * lda;
-  const double* B = sm(e, a.mb) + (long long)a.ob * J * ldb;
-  double* C = sm(e, a.mc) + (long long)a.oc * J * ldc;
+  // offsets in units of J; -1 is the last block (n / J - 1)
+  auto off = [&](int c) { return (long long)(c >= 0 ? c : n / J - 1) * J; };
+  const double* A = sm(e, a.ma) + off(a.oa) * lda + off(a.ra);
+  const double* B = sm(e, a.mb) + off(a.ob) * ldb + off(a.rb);
+  double* C = sm(e, a.mc) + off(a.oc) * ldc + off(a.rc);
   int w = blk - prefix[ai];
   const int ntm = cdiv(M, 64);
   const int i0 = (w % ntm) * 64, j0 = (w / ntm) * 64;

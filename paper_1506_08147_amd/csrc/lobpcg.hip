@@ -77,7 +77,9 @@ dg_teter_energy(Elem* __restrict__ E, const int* __restrict__ active, int na) {
 // triangle in SM_G): T = D^-1 L^-T from a Cholesky of the unit-diagonal
 // D^-1 G D^-1 = L L^T (CholQR), or, if a pivot falls below CHOL_TOL, the
 // eigenvalue form T = D^-1 U Lambda^-1/2 with Lambda clamped (SVQB).
-// Output T in SM_T (ld J).  init = 1: a fallback marks breakdown instead.
+// Output T in SM_T (ld J).  init = 1: a fallback marks breakdown instead;
+// init = 2 (the P block of a Rayleigh-Ritz step): a failed pivot test sets
+// T = 0 and counts a P drop (the step then runs on [X W] alone).
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init) {
   __shared__ double red[32];
@@ -108,6 +110,12 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
       int i = p % n;
       Tm[p] = Lt[p] / dm[i];
     }
+    t.sync();
+    return;
+  }
+  if (init == 2) {
+    for (int p = t.tid(); p < n * n; p += t.nt()) Tm[p] = 0.0;
+    if (t.tid() == 0) e.fl[FL_P_DROP] += 1;
     t.sync();
     return;
   }
@@ -380,8 +388,7 @@ dg_rr_cinit(Elem* __restrict__ E, const int* __restrict__ active, int na, int si
   for (int p = threadIdx.x; p < n * J; p += blockDim.x) Cm[p] = Z[p];
 }
 
-// Ritz values; path 0: undo the diagonal scaling of C; then, for k > 1,
-// E = C with the X rows zeroed (start of the next search direction).
+// Ritz values; path 0: undo the diagonal scaling of C.
 extern "C" __global__ void __launch_bounds__(256)
 dg_rr_post(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   const Elem& e = E[active[blockIdx.x]];
@@ -397,19 +404,165 @@ dg_rr_post(Elem* __restrict__ E, const int* __restrict__ active, int na, int sin
     for (int p = threadIdx.x; p < n * J; p += blockDim.x) Cm[p] /= dm[p % n];
   if (path != 1)
     for (int j = threadIdx.x; j < J; j += blockDim.x) e.theta[j] = w[j];
-  if (kb == 1) {
-    if (threadIdx.x == 0) e.fl[FL_HASP_NEXT] = 0;
-    return;
-  }
-  __syncthreads();
-  double* Ez = sm(e, SM_Z);
-  for (int p = threadIdx.x; p < n * J; p += blockDim.x) Ez[p] = (p % n) < J ? 0.0 : Cm[p];
+  if (kb == 1 && threadIdx.x == 0) e.fl[FL_HASP_NEXT] = 0;
 }
 
-// Next search direction, after dg_sgemm formed A = D^T M D (J x J) for
-// D = E - C (C^T M E): scaled Cholesky of A; D <- D Dg^-1 with L^-T kept in
-// SM_L for the final product D L^-T.  If it breaks, P is dropped for one
-// iteration.
+// ---------------------------------------------------------------------------
+// With guard columns, the basis of a LOBPCG step is S = [X P W] with X the
+// Ritz vectors, W the preconditioned residuals made orthonormal and
+// orthogonal to X, and P the previous step's search direction in the form of
+// Knyazev's method,
+// P' = [P W] [C_P; C_W] (formed together with X' = X C_X + P' in one pass
+// over the blocks), which is neither normalised nor orthogonal to X.  Before
+// the Rayleigh-Ritz reduction the P block is orthonormalised against
+// Q = [X W] in small space: P~ = (P - Q Z) T_P with Z = (2I - M_QQ) M_QP,
+// the projection coefficients M_QQ^-1 M_QP to first order in M_QQ - I (Q is
+// orthonormal to FP64 rounding; the mixed form, whose FP32 products leave
+// it orthonormal only to ~1e-6, keeps the orthonormalised direction), T_P
+// from a scaled Cholesky of S_P = M_PP - M_QP^T Z, i.e.
+// S~ = S B with B the identity except for its P column block
+// B_P = [-Z_X T_P; T_P; -Z_W T_P]; then Hh~ = B^T Hh B, M~ = B^T M B (close
+// to I), the Rayleigh-Ritz step gives C~, and C = B C~ in the basis S.  The
+// span of S, hence the step, is that of the method with an orthonormalised
+// search direction; only its representation differs.  (Without guard
+// columns the slowest wanted states leave this P nearly dependent on [X W]
+// near convergence, and so do residuals well below 1e-7 with guards: S_P
+// then loses P's independent part to cancellation and P is dropped step
+// after step.  Such blocks keep the orthonormalised direction, dg_rr_dchol,
+// and project W against [X P].)
+
+// Block copies inside the small workspace.  Dimension codes as for dg_sgemm
+// (0: n = kJ, 1: J, 2: 2J, 3: n - J); offsets in units of J (-1: the last
+// block, k - 1).  mode 0: D = alpha S, 1: D = alpha S^T, 2: D = alpha I,
+// 3: D = 0.  gate as dg_sgemm's gate_carry.
+struct CpArgs {
+  int ms, rs, cs, ls;
+  int md, rd, cd, ld;
+  int dr, dc;
+  double alpha;
+  int mode;
+  int gate;
+  int single;
+};
+
+extern "C" __global__ void __launch_bounds__(256)
+dg_small_copy(Elem* __restrict__ E, const int* __restrict__ active, int na, CpArgs a) {
+  const Elem& e = E[active[blockIdx.x]];
+  if ((a.gate & 1) && carried_cols(e) == 0) return;
+  if ((a.gate & 2) && !has_p(e)) return;
+  const int J = e.J;
+  const int kb = a.single ? 1 : (has_p(e) ? 3 : 2);
+  const int n = kb * J;
+  const int R = sg_dim(a.dr, n, J), Cn = sg_dim(a.dc, n, J);
+  const int lds = sg_dim(a.ls, n, J), ldd = sg_dim(a.ld, n, J);
+  auto off = [&](int c) { return (c >= 0 ? c : kb - 1) * J; };
+  const double* S = sm(e, a.ms) + (long long)off(a.cs) * lds + off(a.rs);
+  double* D = sm(e, a.md) + (long long)off(a.cd) * ldd + off(a.rd);
+  for (int p = threadIdx.x; p < R * Cn; p += blockDim.x) {
+    const int i = p % R, j = p / R;
+    double v;
+    switch (a.mode) {
+      case 0: v = S[i + (long long)lds * j]; break;
+      case 1: v = S[j + (long long)lds * i]; break;
+      case 2: v = i == j ? 1.0 : 0.0; break;
+      default: v = 0.0;
+    }
+    D[i + (long long)ldd * j] = a.alpha * v;
+  }
+}
+
+// Start of the Rayleigh-Ritz step: full symmetric S^T S and S^T H S from
+// their upper triangles, kept as formed in SM_MO / SM_HO (the carried blocks
+// of the next step are taken from them); with P, M_PP into SM_G (ld J) as the
+// start of its Schur complement.
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_prep(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  const Elem& e = E[active[blockIdx.x]];
+  const int J = e.J;
+  const int n = (has_p(e) ? 3 : 2) * J;
+  double* M = sm(e, SM_M);
+  double* H = sm(e, SM_H);
+  double* Mo = sm(e, SM_MO);
+  double* Ho = sm(e, SM_HO);
+  for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+    const int i = p % n, j = p / n;
+    const long long q = i <= j ? p : j + (long long)n * i;
+    const double mv = M[q], hv = H[q];
+    Mo[p] = mv;
+    Ho[p] = hv;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < n * n; p += blockDim.x) {
+    M[p] = Mo[p];
+    H[p] = Ho[p];
+  }
+  if (has_p(e))
+    for (int p = threadIdx.x; p < J * J; p += blockDim.x) {
+      const int i = p % J, j = p / J;
+      sm(e, SM_G)[p] = M[(J + i) + (long long)n * (J + j)];
+    }
+}
+
+// P column block of B^T Hh B and B^T M B: from U_H = Hh B_P (SM_U, n x J),
+// B_P^T U_H (SM_A, J x J), U_M = M B_P (SM_Z) and B_P^T U_M (SM_W0), write
+// column block P, row block P and the P-P block of Hh and M (elements with P).
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_pscatter(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  const Elem& e = E[active[blockIdx.x]];
+  if (!has_p(e)) return;
+  const int J = e.J, n = 3 * J;
+  double* H = sm(e, SM_H);
+  double* M = sm(e, SM_M);
+  const double* Uh = sm(e, SM_U);
+  const double* Um = sm(e, SM_Z);
+  const double* Hpp = sm(e, SM_A);
+  const double* Mpp = sm(e, SM_W0);
+  for (int p = threadIdx.x; p < n * J; p += blockDim.x) {
+    const int i = p % n, j = p / n;
+    if (i >= J && i < 2 * J) continue;
+    H[i + (long long)n * (J + j)] = Uh[p];
+    H[(J + j) + (long long)n * i] = Uh[p];
+    M[i + (long long)n * (J + j)] = Um[p];
+    M[(J + j) + (long long)n * i] = Um[p];
+  }
+  for (int p = threadIdx.x; p < J * J; p += blockDim.x) {
+    const int i = p % J, j = p / J;
+    H[(J + i) + (long long)n * (J + j)] = Hpp[p];
+    M[(J + i) + (long long)n * (J + j)] = Mpp[p];
+  }
+}
+
+// End of the Rayleigh-Ritz step: E = C with the X rows zeroed next to C in
+// SM_C (the coefficients of the next search direction P' = S E = [P W] C_PW),
+// P present in the next step, and whether its [X P] Gram blocks are carried:
+// while the largest residual of the wanted states is at least CARRY_RES, or
+// always with guard columns.
+extern "C" __global__ void __launch_bounds__(256)
+dg_rr_e(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[4];
+  const Elem& e = E[active[blockIdx.x]];
+  const int J = e.J;
+  const int n = (has_p(e) ? 3 : 2) * J;
+  double* Cm = sm(e, SM_C);
+  for (int p = threadIdx.x; p < n * J; p += blockDim.x) Cm[(long long)n * J + p] = (p % n) < J ? 0.0 : Cm[p];
+  double rmax = 0.0;
+  for (int i = threadIdx.x; i < e.jc; i += blockDim.x) rmax = fmax(rmax, e.resid[i]);
+  for (int o = 32; o > 0; o >>= 1) rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = rmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const bool carry = r >= CARRY_RES || e.jc < J;
+    e.fl[FL_HASP_NEXT] = 1;
+    e.fl[FL_CARRY] = carry ? 2 * J : 0;
+  }
+}
+
+// Orthonormalised form of the next search direction (blocks without guard
+// columns): after dg_sgemm formed A = D^T M D (J x J) for D = E - C (C^T M E)
+// with E = C with its X rows zeroed (SM_Z): scaled Cholesky of A; D <- D Dg^-1
+// with L^-T kept in SM_L for the final product D L^-T.  If it breaks, P is
+// dropped for one iteration.
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_dchol(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   __shared__ double red[32];
@@ -492,10 +645,13 @@ dg_gather_box(Elem* __restrict__ E, const int* __restrict__ active, const int* _
 // SVD truncation through the Gram of the restricted unit eigenvectors:
 // G = Psi_E^T Psi_E = V S^2 V^T (SM_G, upper); the n_alb largest give
 // sigma (descending) and T = V S^-1 / sqrt(dV) (J x n_alb, SM_T), so that
-// Psi_E T are the ALBs in the dV sum phi^2 = 1 normalisation.
+// Psi_E T are the ALBs in the dV sum phi^2 = 1 normalisation.  The n_alb
+// largest eigenpairs of G are the lowest of -G, from the Rayleigh-Ritz
+// eigensolver (tridiagonalisation, multisection and inverse iteration).
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_alb_coeffs(Elem* __restrict__ E, const int* __restrict__ active, int na, double* sigma) {
   __shared__ double red[32];
+  __shared__ double lds[EIG_LDS];
   DevTeam t{red};
   const Elem& e = E[active[blockIdx.x]];
   const int n = e.J, na_ = e.nalb;
@@ -505,18 +661,17 @@ dg_alb_coeffs(Elem* __restrict__ E, const int* __restrict__ active, int na, doub
   double* vec = sm(e, SM_V);
   double* w = vec + 7 * n;
   sym_from_upper(t, G, n, n);
-  copy_mat(t, G, n, A, n, n, n);
-  int ok = syev(t, A, n, n, w, Z, n, n, sm(e, SM_U), vec);
-  if (!ok && t.tid() == 0) e.fl[FL_QL_FAIL] += 1;
+  for (int p = t.tid(); p < n * n; p += t.nt()) A[p] = -G[p];
+  t.sync();
+  syev_lowest<false>(t, A, n, n, na_, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, EIG_LDS);
   double* Tm = sm(e, SM_T);
   const double isdv = 1.0 / sqrt(e.dv);
   for (int p = t.tid(); p < n * na_; p += t.nt()) {
     int i = p % n, c = p / n;
-    int src = n - 1 - c;
-    double s = sqrt(fmax(w[src], 0.0));
-    Tm[p] = s > 0.0 ? Z[i + (long long)n * src] * isdv / s : 0.0;
+    double s = sqrt(fmax(-w[c], 0.0));
+    Tm[p] = s > 0.0 ? Z[i + (long long)n * c] * isdv / s : 0.0;
   }
-  for (int c = t.tid(); c < na_; c += t.nt()) sigma[e.off_nalb + c] = sqrt(fmax(w[n - 1 - c], 0.0));
+  for (int c = t.tid(); c < na_; c += t.nt()) sigma[e.off_nalb + c] = sqrt(fmax(-w[c], 0.0));
   t.sync();
 }
 
@@ -584,6 +739,69 @@ dg_load_block(Elem* __restrict__ E, const int* __restrict__ active, const int* _
   const double* x = src + e.off_ngj + (long long)j * e.ng;
   double* y = bp(e, dst) + (long long)j * e.ld;
   for (int r = threadIdx.x; r < e.ng; r += 256) y[r] = scale * x[r];
+}
+
+// Seeded N(0,1) start block, drawn when the caller gives none: entry pairs
+// (2q, 2q+1) of column j of batch element e come from Philox4x32-10 (Salmon,
+// Moraes, Dror, Shaw, SC 2011) at counter (q, j, e, 0) and key (seed mod
+// 2^32, seed div 2^32): its outputs w0..w3 give the 53-bit uniforms
+// u1 = (w0 2^21 + w1 >> 11) 2^-53 and u2 from (w2, w3), and the Box-Muller
+// transform gives r cos(2 pi u2), r sin(2 pi u2) with r = sqrt(-2 ln(1 - u1)).
+__device__ __forceinline__ void philox4x32_10(unsigned x[4], unsigned k0, unsigned k1) {
+  for (int r = 0; r < 10; ++r) {
+    const unsigned hi0 = __umulhi(0xD2511F53u, x[0]), lo0 = 0xD2511F53u * x[0];
+    const unsigned hi1 = __umulhi(0xCD9E8D57u, x[2]), lo1 = 0xCD9E8D57u * x[2];
+    const unsigned y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0; x[1] = lo1; x[2] = y2; x[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+__device__ __forceinline__ double uniform53(unsigned hi, unsigned lo) {
+  const unsigned long long m = ((unsigned long long)hi << 21) | (unsigned long long)(lo >> 11);
+  return (double)m * 0x1p-53;
+}
+
+// Work item (element, column j); writes the element's column j of block dst
+// or, if out is non-NULL, of the batch array out (layout of X0).
+extern "C" __global__ void __launch_bounds__(256)
+dg_random_start(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, unsigned seed_lo, unsigned seed_hi, int dst, double* out) {
+  int b = blockIdx.x;
+  int ai = find_elem(prefix, na, b);
+  const int elem = active[ai];
+  const Elem& e = E[elem];
+  int j = b - prefix[ai];
+  double* y = out ? out + e.off_ngj + (long long)j * e.ng : bp(e, dst) + (long long)j * e.ld;
+  const int nq = (e.ng + 1) / 2;
+  for (int q = threadIdx.x; q < nq; q += 256) {
+    unsigned x[4] = {(unsigned)q, (unsigned)j, (unsigned)elem, 0u};
+    philox4x32_10(x, seed_lo, seed_hi);
+    const double u1 = uniform53(x[0], x[1]), u2 = uniform53(x[2], x[3]);
+    const double r = sqrt(-2.0 * log1p(-u1));
+    double sn, cs;
+    sincospi(2.0 * u2, &sn, &cs);
+    y[2 * q] = r * cs;
+    if (2 * q + 1 < e.ng) y[2 * q + 1] = r * sn;
+  }
+}
+
+// Any bitwise difference between the projector arrays (gamma, ptr, idx, val)
+// and the copies of the ones last laid out sets *flag.
+extern "C" __global__ void __launch_bounds__(256)
+dg_kb_differs(const double* __restrict__ g, const double* __restrict__ gc, long long np,
+              const long long* __restrict__ p, const long long* __restrict__ pc,
+              const int* __restrict__ ix, const int* __restrict__ ixc, const double* __restrict__ v,
+              const double* __restrict__ vc, long long nnz, int* flag) {
+  long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long stride = (long long)gridDim.x * 256;
+  int d = 0;
+  for (long long k = i; k < np; k += stride) d |= __double_as_longlong(g[k]) != __double_as_longlong(gc[k]);
+  for (long long k = i; k <= np; k += stride) d |= p[k] != pc[k];
+  for (long long k = i; k < nnz; k += stride)
+    d |= (ix[k] != ixc[k]) | (__double_as_longlong(v[k]) != __double_as_longlong(vc[k]));
+  if (d) atomicOr(flag, 1);
 }
 
 // Any non-finite value in a[0..n) sets *flag.

@@ -444,71 +444,6 @@ __host__ __device__ int syev(T& t, double* A, int lda, int n, double* w, double*
 // ---------------------------------------------------------------------------
 // Faster pieces for the Rayleigh-Ritz step (lowest k of n eigenpairs).
 
-// C = alpha op(A) op(B) + beta C on the matrix cores: every wave owns 16 x 16
-// output tiles and stages 16 x 16 operand tiles through its own LDS region
-// (lds: 512 doubles per wave).  Host teams use the scalar product.
-typedef double dg_dbl4 __attribute__((ext_vector_type(4)));
-
-template <class T>
-__host__ __device__ void gemm_fast(T& t, int ta, int tb, int m, int n, int k, double alpha,
-                                   const double* A, int lda, const double* B, int ldb, double beta,
-                                   double* C, int ldc, double* lds) {
-  if constexpr (!T::is_device) {
-    gemm(t, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
-  } else {
-#if defined(__HIP_DEVICE_COMPILE__)
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    double* As = lds + wv * 512;
-    double* Bs = As + 256;
-    const int ntm = (m + 15) / 16, ntn = (n + 15) / 16;
-    for (int tile = wv; tile < ntm * ntn; tile += nw) {
-      const int i0 = (tile % ntm) * 16, j0 = (tile / ntm) * 16;
-      dg_dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < k; k0 += 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          int e = lane + 64 * q;
-          int a1 = e & 15, a2 = e >> 4;   // a1 fastest in memory
-          // A_op tile (ii, kk)
-          int ii = ta ? a2 : a1, kk = ta ? a1 : a2;
-          double av = 0.0;
-          if (i0 + ii < m && k0 + kk < k)
-            av = ta ? A[(long long)(k0 + kk) + (long long)lda * (i0 + ii)]
-                    : A[(long long)(i0 + ii) + (long long)lda * (k0 + kk)];
-          As[kk * 16 + ii] = av;
-          // B_op tile (kk, jj)
-          int jj = tb ? a1 : a2, kb = tb ? a2 : a1;
-          double bv = 0.0;
-          if (j0 + jj < n && k0 + kb < k)
-            bv = tb ? B[(long long)(j0 + jj) + (long long)ldb * (k0 + kb)]
-                    : B[(long long)(k0 + kb) + (long long)ldb * (j0 + jj)];
-          Bs[kb * 16 + jj] = bv;
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-          double a = As[(ks * 4 + (lane >> 4)) * 16 + (lane & 15)];
-          double b = Bs[(ks * 4 + (lane >> 4)) * 16 + (lane & 15)];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i = i0 + 4 * r + (lane >> 4), j = j0 + (lane & 15);
-        if (i < m && j < n) {
-          double* c = &IDX(C, ldc, i, j);
-          *c = alpha * acc[r] + (beta != 0.0 ? beta * *c : 0.0);
-        }
-      }
-    }
-    __syncthreads();
-#endif
-  }
-}
-
 // Device fast path of tridiagonalize_lower with one pass over the trailing
 // block per Householder step: the rank-2 update left by reflector k-1 and the
 // symmetric product of reflector k (p = tk A2 v) read and write every entry

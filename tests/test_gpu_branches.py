@@ -1,7 +1,9 @@
 """Branches of the GPU LOBPCG steps against the oracle on identical inputs:
 the W orthonormalisation (CholQR and its SVQB fallback) and the
 Rayleigh-Ritz step (Cholesky and series reductions, the reduction for a
-rank-deficient basis, the next search direction and its P drop), Sec. II.B.
+rank-deficient basis, the next search direction and its P drop), Sec. II.B;
+for a block with guard columns, where the search direction keeps Knyazev's
+form, the orthonormalisation of its P block in small space and its drop.
 The inputs are seeded dense matrices built here; the GPU runs the solver's
 own kernels through dgdft_alb_orthonormalise / dgdft_alb_rayleigh_ritz and
 the oracle runs oracle/lobpcg.py."""
@@ -22,6 +24,19 @@ def handle():
     assert torch.cuda.is_available()
     h = ALB([(12, 12, 12)], [(5.0, 5.0, 5.0)], [J], elem_lo=[(4, 4, 4)], elem_hi=[(8, 8, 8)],
             n_alb=[4])
+    yield h
+    h.close()
+
+
+@pytest.fixture(scope="module")
+def handle_g():
+    """A block of J columns of which one is a guard column, FP64, tolerance
+    1e-6: Knyazev's form of the search direction."""
+    import torch
+    from paper_1506_08147_amd import ALB
+    assert torch.cuda.is_available()
+    h = ALB([(12, 12, 12)], [(5.0, 5.0, 5.0)], [J], tol=1e-6, elem_lo=[(4, 4, 4)],
+            elem_hi=[(8, 8, 8)], n_alb=[4], n_guard=1)
     yield h
     h.close()
 
@@ -152,3 +167,60 @@ def test_rank_deficient_basis_and_p_drop_match_oracle(handle, kb):
     assert np.abs(Xg.T @ Xg - np.eye(J)).max() < 1e-10
     if kb == 2:
         assert D is None and fl[2] == 1 and not np.any(Dg)
+
+
+def _check_direction(Cg, Eg, D, fl):
+    """E = C with its X rows zeroed; the oracle's normalised, M-orthogonal
+    direction D lies in the span of [C, E]."""
+    assert fl[2] == 0 and not np.any(Eg[:J]) and np.array_equal(Eg[J:], Cg[J:])
+    assert D is not None
+    B = np.hstack([Cg, Eg])
+    coef = np.linalg.lstsq(B, D, rcond=None)[0]
+    assert np.abs(B @ coef - D).max() <= 1e-9 * np.abs(D).max()
+
+
+def _solver_basis(rng, n, p_scale=1.0):
+    """S = [X P W] as the solver builds it: X and W orthonormal and
+    mutually orthogonal, P neither normalised nor orthogonal to them."""
+    Q, _ = np.linalg.qr(rng.standard_normal((n, 2 * J)))
+    P = p_scale * (rng.standard_normal((n, J)) @ np.diag(np.logspace(-3, 0, J)) + 0.3 * Q[:, :J])
+    return np.hstack([Q[:, :J], P, Q[:, J:]])
+
+
+def test_knyazev_p_block_matches_oracle(handle_g):
+    """The solver's three-block basis: the GPU orthonormalises the P block
+    against [X W] in small space and reduces the nearly orthonormal result
+    by the series; the oracle reduces S^T S by LAPACK's generalised
+    eigensolver.  Same Ritz values and vectors."""
+    rng, H = _sym(150, 41)
+    S = _solver_basis(rng, 150)
+    Hh, M = _rr_inputs(S, H)
+    th, Cg, Eg, fl = handle_g.rayleigh_ritz(0, 3, _dev(Hh), _dev(M))
+    th, Cg, Eg = th.cpu().numpy(), Cg.cpu().numpy(), Eg.cpu().numpy()
+    theta, C, D, st = _oracle_rr(S, H, 3)
+    assert fl[4] in (2, 3) and fl[1] == 0 and fl[2] == 0
+    assert np.abs(th - theta).max() <= 1e-11 * np.abs(theta).max()
+    Xg, Xo = S @ Cg, S @ C
+    assert np.abs(_align(Xo, Xg) - Xo).max() < 1e-10
+    assert np.abs(Xg.T @ Xg - np.eye(J)).max() < 1e-11
+    _check_direction(Cg, Eg, D, fl)
+
+
+def test_knyazev_dependent_p_block_is_dropped(handle_g):
+    """A P block with a duplicated column (its Schur complement against
+    [X W] is singular): the GPU drops P for the step (flags[2]) and returns
+    the Rayleigh-Ritz pairs of [X W], as the oracle computes them on that
+    basis; C has no P rows."""
+    rng, H = _sym(150, 53)
+    S = _solver_basis(rng, 150)
+    S[:, J + 2] = S[:, J + 5]
+    Hh, M = _rr_inputs(S, H)
+    th, Cg, Eg, fl = handle_g.rayleigh_ritz(0, 3, _dev(Hh), _dev(M))
+    th, Cg, Eg = th.cpu().numpy(), Cg.cpu().numpy(), Eg.cpu().numpy()
+    Sxw = np.hstack([S[:, :J], S[:, 2 * J:]])
+    theta, C, _, _ = _oracle_rr(Sxw, H, 2)
+    assert fl[2] == 1 and fl[3] == 0
+    assert not np.any(Cg[J:2 * J]) and not np.any(Eg[J:2 * J])
+    assert np.abs(th - theta).max() <= 1e-10 * np.abs(theta).max()
+    Xg, Xo = S @ Cg, Sxw @ C
+    assert np.abs(_align(Xo, Xg) - Xo).max() < 1e-9

@@ -53,6 +53,59 @@ def test_update_product_matches_numpy(dev, K, m, n):
         assert np.abs(C[i].T - ref).max() <= 1e-13 * np.sqrt(m) * 10
 
 
+def _f32(a):
+    return a.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("K,m,n", [(1000, 70, 37), (13824, 96, 96), (13824, 144, 288),
+                                   (77760, 144, 144)])
+def test_gram_product_fp32_kernels(dev, K, m, n):
+    """The mixed form's Gram kernels: against the FP64 product of the
+    operands rounded to FP32, within the worst-case bound of FP32
+    summation over K terms, gamma_K sum |a||b|; their typical error is that
+    of FP32 arithmetic (far above FP64 rounding, below the random-walk
+    size u sqrt(K) of a sequential FP32 sum)."""
+    from paper_1506_08147_amd import gemm_batched
+    rng = np.random.default_rng(K + 3 * m)
+    A = rng.standard_normal((2, m, K))
+    B = rng.standard_normal((2, n, K))
+    C = gemm_batched(1, _t(A, dev), _t(B, dev), fp32=True).cpu().numpy()
+    u = 2.0 ** -24
+    gam = K * u / (1 - K * u)
+    rel = []
+    for i in range(2):
+        ref = _f32(A[i]) @ _f32(B[i]).T
+        bound = gam * (np.abs(_f32(A[i])) @ np.abs(_f32(B[i])).T)
+        err = np.abs(C[i].T - ref)
+        assert np.all(err <= bound)
+        rel.append(np.median(err / np.sqrt(np.abs(A[i]) ** 2 @ (np.abs(B[i]) ** 2).T)))
+    # below u sqrt(K), the random-walk size of sequential FP32 summation
+    assert 1e-12 < max(rel) < u * np.sqrt(K), rel
+
+
+@pytest.mark.parametrize("K,m,n", [(1000, 70, 37), (13824, 96, 64), (13824, 432, 144),
+                                   (77760, 144, 144)])
+def test_update_product_fp32_kernels(dev, K, m, n):
+    """The mixed form's update kernels: Y = alpha A C + beta Y with A C in
+    FP32 (bound gamma_m sum |a||c| against the rounded operands) and the
+    beta term in FP64."""
+    from paper_1506_08147_amd import gemm_batched
+    rng = np.random.default_rng(K * 5 + n)
+    A = rng.standard_normal((2, m, K))
+    B = rng.standard_normal((2, n, m))
+    C0 = rng.standard_normal((2, n, K))
+    C = gemm_batched(0, _t(A, dev), _t(B, dev), alpha=-0.7, beta=1.3, Cin=_t(C0, dev),
+                     fp32=True).cpu().numpy()
+    u = 2.0 ** -24
+    gam = (m + 2) * u / (1 - (m + 2) * u)
+    for i in range(2):
+        prod = _f32(A[i]).T @ _f32(B[i]).T
+        ref = -0.7 * prod + 1.3 * C0[i].T
+        bound = 0.7 * gam * (np.abs(_f32(A[i])).T @ np.abs(_f32(B[i])).T) + 1e-14 * np.abs(ref)
+        assert np.all(np.abs(C[i].T - ref) <= bound)
+        assert np.abs(C[i].T - (-0.7 * (A[i].T @ B[i].T) + 1.3 * C0[i].T)).max() > 1e-10
+
+
 @pytest.mark.parametrize("method,n,k", [(m, n, k) for m in (0, 1) for n, k in
                                          [(1, 1), (10, 10), (96, 32), (200, 64), (384, 128),
                                           (432, 144)]] +

@@ -115,3 +115,32 @@ def test_nonfinite_potential_rejected(dev):
     with pytest.raises(DGDFTError) as ei:
         _solve([el], dev, 1e-8)
     assert ei.value.code == -1
+
+
+def test_projector_change_rebuilds_the_layout(dev):
+    """One handle solving two elements of the same grid in turn (different
+    atoms, so different projectors and potential), then the first again: each
+    solve equals a fresh handle's solve bit for bit (the projector layout is
+    kept only while the arrays are bitwise unchanged)."""
+    import torch
+    from paper_1506_08147_amd import ALB
+    a = synth.single_element(seed=5, grid=(12, 12, 12), n_states=6, n_atoms=3)
+    b = synth.single_element(seed=6, grid=(12, 12, 12), n_states=6, n_atoms=2)
+
+    def handle():
+        return ALB([a.grid], [a.box], [a.n_states], tol=1e-9, elem_lo=[a.elem_lo],
+                   elem_hi=[a.elem_hi], n_alb=[a.n_alb])
+
+    def inputs(el):
+        return (torch.from_numpy(el.V).to(dev), ALB.kb_batch([el.kb], dev),
+                torch.from_numpy(np.ascontiguousarray(a.X0.T)).reshape(-1).to(dev))
+
+    h = handle()
+    runs = [h.solve(*inputs(el))["eigvals"].cpu().numpy() for el in (a, b, a)]
+    h.close()
+    for el, got in zip((a, b, a), runs):
+        f = handle()
+        ref = f.solve(*inputs(el))["eigvals"].cpu().numpy()
+        f.close()
+        assert np.array_equal(got, ref)
+    assert not np.allclose(runs[0], runs[1])
