@@ -287,7 +287,8 @@ int32_t dgdft_alb_orthonormalise(dgdft_alb* h, int32_t elem, const double* G, do
  *     P block is first orthonormalised against [X W] through a scaled
  *     Cholesky of its Schur complement M_PP - M_XP^T M_XP - M_WP^T M_WP;
  *     if that breaks, P is dropped for the step (flags[2]; C_P = 0, the step
- *     runs on [X W]).
+ *     runs on [X W]: the P block of the reduced problem is decoupled with
+ *     M_PP = I and a diagonal above every kept Ritz value).
  * Reductions: the binomial series for M^-1/2 when ||M - I||_F <= 1e-4
  * (kb > 1), a scaled Cholesky of M, or, when M is not numerically positive
  * definite, its eigenvectors above 1e-10 of the largest eigenvalue

@@ -89,7 +89,8 @@ enum Flag {
   FL_RR_NCHOL,        // Rayleigh-Ritz steps reduced through a Cholesky factor of M
   FL_RR_NSERIES,      // Rayleigh-Ritz steps reduced through the series for M^-1/2
   FL_CARRY,           // leading block of S^T S and S^T H S known from the last step (columns; 0: none)
-  FL_COUNT = 15
+  FL_PDROP_NOW,       // the current Rayleigh-Ritz step dropped its P block (Knyazev's form)
+  FL_COUNT = 16
 };
 
 // Virtual slots resolved per element through its buffer parity:
@@ -188,7 +189,7 @@ __device__ inline int find_elem(const int* __restrict__ prefix, int na, int b) {
 }
 
 // ---- work decomposition shared by host (counts) and device (decode) ----
-constexpr int GT = 128;           // GEMM workgroup tile edge (rows and columns)
+constexpr int GT = 128;           // Gram tile edge; row tile of the update products
 constexpr int GRAM_MAXCHUNK = 8;
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -209,6 +210,17 @@ __host__ __device__ inline int gram_nchunk_e(const Elem& e, int K) {
 }
 // chunk length, a multiple of 16
 __host__ __device__ inline int gram_chunklen(int K, int nchunk) { return cdiv(cdiv(K, nchunk), 16) * 16; }
+
+// Column tile of the update products for d columns: the d columns split
+// evenly over the fewest tiles of at most TMAX columns, rounded up to the
+// 16-column MFMA block (so a tile has at most 15 idle columns; 144 for
+// blocks of 144 states).
+constexpr int TMAX = 144;
+__host__ __device__ inline int tile_edge(int d) {
+  if (d <= 0) return 16;
+  int t = cdiv(d, TMAX);
+  return cdiv(cdiv(d, t), 16) * 16;
+}
 
 // tile grid of a Gram product with tile edge tt (GT, or 144 for blocks of
 // 144 columns)

@@ -349,7 +349,9 @@ struct dgdft_alb {
 
   void gram(const std::vector<int>& act, const GramArgs& g, bool fp32 = false) {
     auto K = [&](int e) { return g.use_ne ? eh[e].ne : eh[e].ng; };
-    // 144 x 144 tiles when every operand's column count is a multiple of 144
+    // 144 x 144 tiles when every operand's column count is a multiple of
+    // 144, else 128 x 128 (measured on the uneven batch: 144-class tiles cut
+    // to each element's width ran 16% slower than 128 x 128 tiles there)
     bool t144 = !act.empty();
     for (int e : act) {
       t144 = t144 && cols_host(g.A, e) % GTT == 0;
@@ -406,14 +408,10 @@ struct dgdft_alb {
     auto ncols = [&](int e) {
       return u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? eh[e].nalb : cols_host(u.Y[0], e));
     };
-    // 144-wide column tiles when every element's column count is a multiple
-    // of 144 (no nearly empty last tile), else 128-wide
-    bool w144 = !act.empty();
-    for (int e : act) w144 = w144 && ncols(e) % UTN == 0;
-    const int tn = w144 ? UTN : GT;
+    // 128-row tiles, column tiles of tile_edge(ncol) (as dg_update_w decodes them)
     auto P = make_prefix(act, [&](int e) {
       int K = u.use_ne ? eh[e].ne : eh[e].ng;
-      return u.njob * cdiv(K, GT) * cdiv(ncols(e), tn);
+      return u.njob * cdiv(K, GT) * cdiv(ncols(e), tile_edge(ncols(e)));
     });
     if (P.total == 0) return;
     double fl = 0, by = 0;
@@ -425,12 +423,8 @@ struct dgdft_alb {
       by += u.njob * 8.0 * K * (kA + nc * ((u.beta != 0.0 ? 2 : 1) + (u.split ? 1 : 0)));
     }
     pbeg(DGDFT_K_UPDATE, fl, by);
-    if (w144)
-      hipLaunchKernelGGL(fp32 ? dg_update_n14432 : dg_update_n144, dim3(P.total), dim3(256), 0, stream,
-                         ed, P.active, P.prefix, P.na, u);
-    else
-      hipLaunchKernelGGL(fp32 ? dg_update32 : dg_update, dim3(P.total), dim3(256), 0, stream, ed,
-                         P.active, P.prefix, P.na, u);
+    hipLaunchKernelGGL(fp32 ? dg_update_w32 : dg_update_w, dim3(P.total), dim3(256), 0, stream, ed,
+                       P.active, P.prefix, P.na, u);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -2286,7 +2280,7 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
         pre[i + 1] = pre[i] + gram_tiles(m, n, 0, (m % GTT == 0 && n % GTT == 0) ? GTT : GT) * nch;
         pre2[i + 1] = pre2[i] + cdiv(m * n, 256);
       } else {
-        pre[i + 1] = pre[i] + cdiv((int)K, GT) * cdiv(n, n % UTN == 0 ? UTN : GT);
+        pre[i + 1] = pre[i] + cdiv((int)K, GT) * cdiv(n, tile_edge(n));
       }
     }
     int* d_act = t.alloc<int>(count);
@@ -2309,13 +2303,8 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
       UpdArgs u{};
       u.A[0] = oa; u.Y[0] = oc; u.njob = 1; u.cmat = 0; u.ccol0 = 0; u.ncol = n;
       u.alpha = alpha; u.beta = beta;
-      // column tiles as in the solver: 144 wide when n is a multiple of 144
-      if (n % UTN == 0)
-        hipLaunchKernelGGL(fp32 ? dg_update_n14432 : dg_update_n144, dim3(pre[count]), dim3(256), 0, s, ed,
-                           d_act, d_pre, count, u);
-      else
-        hipLaunchKernelGGL(fp32 ? dg_update32 : dg_update, dim3(pre[count]), dim3(256), 0, s, ed, d_act, d_pre,
-                           count, u);
+      hipLaunchKernelGGL(fp32 ? dg_update_w32 : dg_update_w, dim3(pre[count]), dim3(256), 0, s, ed, d_act,
+                         d_pre, count, u);
     }
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(s));

@@ -4,14 +4,14 @@
 // with a small C (operation 3); the paper distributes them by row blocks and
 // sums the J x J partial products with MPI_Allreduce.  On one GPU the same
 // split appears as split-K: each workgroup reduces one chunk of the N_g rows
-// into a 128 x 128 tile, and a second kernel sums the chunks in a fixed order
-// (deterministic, no atomics).
+// into a 128 x 128 (or 144 x 144) tile, and a second kernel sums the chunks
+// in a fixed order (deterministic, no atomics).
 //
 //   dg_gram       partial C = A^T B over one K chunk, A and B virtual
 //                 concatenations of element blocks ([X P W], [HX HP HW]),
 //                 upper block triangle only when the result is symmetric
 //   dg_gram_reduce  sum of the chunks into the element's small workspace
-//   dg_update     Y = alpha A C + beta Y with A a block concatenation and C a
+//   dg_update_w   Y = alpha A C + beta Y with A a block concatenation and C a
 //                 small matrix of the element ([X' P'] = [X P W] [C D], ...)
 //
 // Operand fragments follow the MFMA f64 16x16x4 register layout: A-fragment
@@ -397,195 +397,18 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
 // Y (K x ncol) = alpha A (K x kA) C (kA x ncol) + beta Y.  Computed as the
 // transposed product so that lanes 0..15 of an accumulator own consecutive
 // rows of Y (coalesced stores).  Work item (job, row tile, column tile) with
-// 128 x 128 tiles.  Column k of A is block k / J at column k % J of that
-// block (block base pointers resolved once per workgroup), so the LDS holds
-// only the two operand stages and the workgroup fits twice per compute unit.
+// tiles of 128 rows x tile_edge(ncol) columns (at most 144): the four waves
+// are stacked along the rows, each owning 32 rows x up to 144 columns (2 x 9
+// MFMA blocks; blocks beyond the tile's columns are skipped).  Column k of A
+// is block k / J at column k % J of that block (block base pointers resolved
+// once per workgroup), so the LDS holds only the two operand stages and the
+// workgroup fits twice per compute unit.
 constexpr int UKS = 16;        // K stage of the update
 constexpr int UPD_NQ = UKS / 2;
-constexpr int UPD_NH = UKS / 16;
-#ifndef DG_UPD_WAVES_PER_EU
-#define DG_UPD_WAVES_PER_EU 2
-#endif
+constexpr int UTN = 144;       // largest column tile
 
 template <class T>
-__device__ __forceinline__ void dg_update_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-          int na, UpdArgs u) {
-  constexpr int LPT = TT + Mf<T>::pad;
-
-  __shared__ T As[2][UKS * LPT];
-  __shared__ T Cs[2][UKS * LPT];
-  __shared__ double* colY[TT];
-  __shared__ double* colY2[TT];
-  __shared__ const double* colZ[TT];
-  __shared__ const double* abase[6];
-  int blk = blockIdx.x;
-  int ai = find_elem(prefix, na, blk);
-  const Elem& e = E[active[ai]];
-  int w = blk - prefix[ai];
-  const int K = rowsK(e, u.use_ne);
-  const int kA = opnd_cols(u.A[0], e);
-  const int ncol = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? e.nalb : opnd_cols(u.Y[0], e));
-  const int ntr = cdiv(K, TT), ntc = cdiv(ncol, TT);
-  if (ntr * ntc == 0) return;
-  int job = w / (ntr * ntc);
-  if (job >= u.njob) return;   // spare items of a grid planned for more columns
-  w -= job * ntr * ntc;
-  int tr = w / ntc, tc = w - tr * ntc;
-  const Opnd& A = u.A[job];
-  const Opnd& Y = u.Y[job];
-  const int cld = u.cld ? (has_p(e) ? 3 : 2) * e.J : kA;
-  const double* C = sm(e, u.cmat) + (long long)u.ccol0 * e.J * cld + (long long)u.crow0 * e.J;
-  const int row0 = tr * TT, col0 = tc * TT;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    if (A.ncols >= 0) {
-      abase[0] = bp(e, A.slot[0]);
-    } else {
-      int q = 0;
-      for (int i = 0; i < A.nblk; ++i)
-        if (!(A.optP[i] && !has_p(e))) abase[q++] = bp(e, A.slot[i]);
-    }
-  }
-  if (tid < TT) {
-    colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
-    colY2[tid] = (u.split && col0 + tid < ncol) ? opnd_col(u.Y2[job], e, col0 + tid) : nullptr;
-    colZ[tid] = (u.Z[job].nblk > 0 && col0 + tid < ncol) ? opnd_col(u.Z[job], e, col0 + tid) : nullptr;
-  }
-  __syncthreads();
-  const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
-  const long long ld = e.ld;
-  // A stage: row = tid % 128, k = tid / 128 + 2q (q < UKS/2)
-  const int ar = tid & 127, ak = tid >> 7;
-  // C stage: k = tid % 16 + 16h, j = tid / 16 + 16v (v < 8)
-  const int ck = tid & 15, cj = tid >> 4;
-  const bool rin = row0 + ar < K;
-  double ra[UPD_NQ], rc[8 * UPD_NH];
-  auto load = [&](int k0, int kend) {
-#pragma unroll
-    for (int q = 0; q < UPD_NQ; ++q) {
-      int k = k0 + ak + 2 * q;
-      double v = 0.0;
-      if (k < kend && rin) {
-        int bb = k / bcols;
-        v = abase[bb][(long long)(k - bb * bcols) * ld + row0 + ar];
-      }
-      ra[q] = v;
-    }
-#pragma unroll
-    for (int h = 0; h < UPD_NH; ++h)
-#pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        int j = col0 + cj + 16 * v;
-        int kc = k0 + ck + 16 * h;
-        rc[8 * h + v] = (kc < kend && j < ncol) ? C[kc + (long long)cld * j] : 0.0;
-      }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LPT + ar] = ra[q];
-#pragma unroll
-    for (int h = 0; h < UPD_NH; ++h)
-#pragma unroll
-      for (int v = 0; v < 8; ++v) Cs[buf][(ck + 16 * h) * LPT + cj + 16 * v] = rc[8 * h + v];
-  };
-  const int lane = tid & 63, wv = tid >> 6;
-  const int wj = wv & 1, wr = wv >> 1;
-  // a wave whose 64 columns lie wholly outside Y (in the last column tile of
-  // a width that is no multiple of 128) skips its products
-  const bool live = col0 + wj * 64 < ncol;
-  typename Mf<T>::acc acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = Mf<T>::zero();
-  // stages: with split, columns J..kA-1 of A (nst0 stages), then 0..J-1
-  const int J = e.J;
-  const int nst0 = u.split ? cdiv(kA - J, UKS) : 0;
-  const int nst = nst0 + cdiv(u.split ? J : kA, UKS);
-  auto kbeg = [&](int st) { return st < nst0 ? J + st * UKS : (st - nst0) * UKS; };
-  auto kend = [&](int st) { return st < nst0 ? kA : (u.split ? J : kA); };
-  load(kbeg(0), kend(0));
-  store(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) load(kbeg(st + 1), kend(st + 1));
-    if (live) {
-#pragma unroll
-      for (int ks = 0; ks < UKS / 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        T fc[4], fa[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) fc[a] = Cs[cur][kk * LPT + wj * 64 + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fa[c] = As[cur][kk * LPT + wr * 64 + c * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int c = 0; c < 4; ++c)
-            acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
-      }
-      if (st == nst0 - 1) {   // [P W] part complete: Y2 = alpha [P W] C[J:]
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            double* y2 = colY2[wj * 64 + a * 16 + Mf<T>::row(r, lane)];
-            if (!y2) continue;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              int row = row0 + wr * 64 + c * 16 + (lane & 15);
-              if (row < K) y2[row] = u.alpha * (double)acc[a][c][r];
-            }
-          }
-      }
-    }
-    if (st + 1 < nst) store(cur ^ 1);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int jl = wj * 64 + a * 16 + Mf<T>::row(r, lane);
-      double* y = colY[jl];
-      if (!y) continue;
-      const double* zc = colZ[jl];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        int row = row0 + wr * 64 + c * 16 + (lane & 15);
-        if (row < K) {
-          double v = u.alpha * (double)acc[a][c][r];
-          if (u.beta != 0.0) v += u.beta * (zc ? zc[row] : y[row]);
-          y[row] = v;
-        }
-      }
-    }
-}
-
-extern "C" __global__ void __launch_bounds__(256, DG_UPD_WAVES_PER_EU)
-dg_update(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-          int na, UpdArgs u) {
-  dg_update_body<double>(E, active, prefix, na, u);
-}
-
-extern "C" __global__ void __launch_bounds__(256, DG_UPD_WAVES_PER_EU)
-dg_update32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-          int na, UpdArgs u) {
-  dg_update_body<float>(E, active, prefix, na, u);
-}
-
-// The same product with 128 x 144 workgroup tiles, for column counts that are
-// multiples of 144 (blocks of 144 states, e.g. 128 wanted states and 16
-// guard columns), which 128-wide tiles would leave a nearly empty last
-// column tile: the four waves are stacked along the rows, each owning 32
-// rows x 144 columns (2 x 9 MFMA blocks).  Staging, K stages and the
-// epilogue follow dg_update.
-constexpr int UTN = 144;       // column tile of dg_update_n144
-constexpr int LPC = UTN + 4;
-
-template <class T>
-__device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+__device__ __forceinline__ void dg_update_w_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                int na, UpdArgs u) {
   constexpr int LPT = TT + Mf<T>::pad;
   constexpr int LPCT = UTN + Mf<T>::pad144;
@@ -603,7 +426,8 @@ __device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const 
   const int K = rowsK(e, u.use_ne);
   const int kA = opnd_cols(u.A[0], e);
   const int ncol = u.ncol >= 0 ? u.ncol : (u.ncol == -2 ? e.nalb : opnd_cols(u.Y[0], e));
-  const int ntr = cdiv(K, TT), ntc = cdiv(ncol, UTN);
+  const int tw = tile_edge(ncol);
+  const int ntr = cdiv(K, TT), ntc = cdiv(ncol, tw);
   if (ntr * ntc == 0) return;
   int job = w / (ntr * ntc);
   if (job >= u.njob) return;
@@ -613,7 +437,9 @@ __device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const 
   const Opnd& Y = u.Y[job];
   const int cld = u.cld ? (has_p(e) ? 3 : 2) * e.J : kA;
   const double* C = sm(e, u.cmat) + (long long)u.ccol0 * e.J * cld + (long long)u.crow0 * e.J;
-  const int row0 = tr * TT, col0 = tc * UTN;
+  const int row0 = tr * TT, col0 = tc * tw;
+  const int tcols = min(tw, ncol - col0);        // columns of this tile
+  const int nbc = min(9, cdiv(tcols, 16));       // its MFMA column blocks
   const int tid = threadIdx.x;
   if (tid == 0) {
     if (A.ncols >= 0) {
@@ -625,9 +451,10 @@ __device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const 
     }
   }
   if (tid < UTN) {
-    colY[tid] = (col0 + tid < ncol) ? opnd_col(Y, e, col0 + tid) : nullptr;
-    colY2[tid] = (u.split && col0 + tid < ncol) ? opnd_col(u.Y2[job], e, col0 + tid) : nullptr;
-    colZ[tid] = (u.Z[job].nblk > 0 && col0 + tid < ncol) ? opnd_col(u.Z[job], e, col0 + tid) : nullptr;
+    const bool cin = tid < tcols;
+    colY[tid] = cin ? opnd_col(Y, e, col0 + tid) : nullptr;
+    colY2[tid] = (u.split && cin) ? opnd_col(u.Y2[job], e, col0 + tid) : nullptr;
+    colZ[tid] = (u.Z[job].nblk > 0 && cin) ? opnd_col(u.Z[job], e, col0 + tid) : nullptr;
   }
   __syncthreads();
   const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
@@ -651,9 +478,9 @@ __device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const 
     }
 #pragma unroll
     for (int v = 0; v < 9; ++v) {
-      int j = col0 + cj + 16 * v;
+      const int jl = cj + 16 * v;
       int kc = k0 + ck;
-      rc[v] = (kc < kend && j < ncol) ? C[kc + (long long)cld * j] : 0.0;
+      rc[v] = (kc < kend && jl < tcols) ? C[kc + (long long)cld * (col0 + jl)] : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -690,9 +517,11 @@ __device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const 
       for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPT + wr * 32 + c * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < 9; ++a)
+        if (a < nbc) {
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-          acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
+          for (int c = 0; c < 2; ++c)
+            acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
+        }
     }
     if (st == nst0 - 1) {   // [P W] part complete: Y2 = alpha [P W] C[J:]
 #pragma unroll
@@ -732,15 +561,15 @@ __device__ __forceinline__ void dg_update_n144_body(Elem* __restrict__ E, const 
 }
 
 extern "C" __global__ void __launch_bounds__(256, 2)
-dg_update_n144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-               int na, UpdArgs u) {
-  dg_update_n144_body<double>(E, active, prefix, na, u);
+dg_update_w(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+            int na, UpdArgs u) {
+  dg_update_w_body<double>(E, active, prefix, na, u);
 }
 
 extern "C" __global__ void __launch_bounds__(256, 2)
-dg_update_n14432(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-               int na, UpdArgs u) {
-  dg_update_n144_body<float>(E, active, prefix, na, u);
+dg_update_w32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+              int na, UpdArgs u) {
+  dg_update_w_body<float>(E, active, prefix, na, u);
 }
 
 // ---------------------------------------------------------------------------

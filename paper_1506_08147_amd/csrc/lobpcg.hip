@@ -110,12 +110,16 @@ dg_cholqr(Elem* __restrict__ E, const int* __restrict__ active, int na, int init
       int i = p % n;
       Tm[p] = Lt[p] / dm[i];
     }
+    if (init == 2 && t.tid() == 0) e.fl[FL_PDROP_NOW] = 0;
     t.sync();
     return;
   }
   if (init == 2) {
     for (int p = t.tid(); p < n * n; p += t.nt()) Tm[p] = 0.0;
-    if (t.tid() == 0) e.fl[FL_P_DROP] += 1;
+    if (t.tid() == 0) {
+      e.fl[FL_P_DROP] += 1;
+      e.fl[FL_PDROP_NOW] = 1;
+    }
     t.sync();
     return;
   }
@@ -506,8 +510,15 @@ dg_rr_prep(Elem* __restrict__ E, const int* __restrict__ active, int na, int sin
 // P column block of B^T Hh B and B^T M B: from U_H = Hh B_P (SM_U, n x J),
 // B_P^T U_H (SM_A, J x J), U_M = M B_P (SM_Z) and B_P^T U_M (SM_W0), write
 // column block P, row block P and the P-P block of Hh and M (elements with P).
+// When the step dropped P (B_P = 0), the P-P blocks become M = I and
+// Hh = sigma I with no coupling, sigma = 2 max_i |Hh_ii| + 1 over the X and W
+// rows: every Ritz value of [X W] that the step keeps lies below sigma (the
+// J-th is at most theta_J, an X diagonal entry, by interlacing), so the
+// lowest J eigenpairs are those of [X W] with zero P rows, and M stays
+// nearly the identity instead of singular.
 extern "C" __global__ void __launch_bounds__(256)
 dg_rr_pscatter(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[4];
   const Elem& e = E[active[blockIdx.x]];
   if (!has_p(e)) return;
   const int J = e.J, n = 3 * J;
@@ -517,6 +528,17 @@ dg_rr_pscatter(Elem* __restrict__ E, const int* __restrict__ active, int na, int
   const double* Um = sm(e, SM_Z);
   const double* Hpp = sm(e, SM_A);
   const double* Mpp = sm(e, SM_W0);
+  const bool dropped = e.fl[FL_PDROP_NOW] != 0;
+  double sigma = 0.0;
+  if (dropped) {
+    double hm = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      if (i < J || i >= 2 * J) hm = fmax(hm, fabs(H[i + (long long)n * i]));
+    for (int o = 32; o > 0; o >>= 1) hm = fmax(hm, __shfl_xor(hm, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = hm;
+    __syncthreads();
+    sigma = 2.0 * fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) + 1.0;
+  }
   for (int p = threadIdx.x; p < n * J; p += blockDim.x) {
     const int i = p % n, j = p / n;
     if (i >= J && i < 2 * J) continue;
@@ -527,8 +549,8 @@ dg_rr_pscatter(Elem* __restrict__ E, const int* __restrict__ active, int na, int
   }
   for (int p = threadIdx.x; p < J * J; p += blockDim.x) {
     const int i = p % J, j = p / J;
-    H[(J + i) + (long long)n * (J + j)] = Hpp[p];
-    M[(J + i) + (long long)n * (J + j)] = Mpp[p];
+    H[(J + i) + (long long)n * (J + j)] = dropped ? (i == j ? sigma : 0.0) : Hpp[p];
+    M[(J + i) + (long long)n * (J + j)] = dropped ? (i == j ? 1.0 : 0.0) : Mpp[p];
   }
 }
 
