@@ -44,8 +44,7 @@ ALG_UNITS = {"dg_gram": 24.0, "dg_update": 14.0}
 # counter runs of the default command, calibrated on a 1 GiB copy (see
 # profiles/): (kernel class, workload, guard columns, streams) -> bytes.  Valid
 # only for the kernel build that was measured; removed when the kernel changes.
-MEASURED_TRAFFIC = {("dg_gram", "uneven_edges_24-48_J64-256", 16, 1): 112.315e9,
-                    ("dg_update", "uneven_edges_24-48_J64-256", 16, 1): 85.297e9}
+MEASURED_TRAFFIC = {("dg_update", "uneven_edges_24-48_J64-256", 16, 1): 85.297e9}
 # guard columns per element when --guard is not given: 16 on the slab (block
 # of 144 columns, the tile width of the 144-wide GEMM kernels) and on the
 # uneven batch, 8 on the one-element workload (32 states)
@@ -324,6 +323,31 @@ def mixed_vs_oracle(args, dev, seeds=(1000, 1001, 1002, 1003)):
     return dict(workload="cube_24^3_J32", tol=1e-6, reference="FP64 oracle", elements=rows)
 
 
+def learned_eval(args, dev, w, seeds=range(1000, 1016)):
+    """The learned preconditioner against Teter's on the one-element
+    workloads of the evaluation seeds (24^3, 32 states, mixed precision,
+    residual 1e-6, no guard columns): per seed the iterations of each and
+    the wall time of a solve of the 16 elements together."""
+    import numpy as np
+    import synth
+    els = [synth.single_element(seed=s) for s in seeds]
+    V, kbt, X0 = resident_inputs(els, 0, dev)
+    out = {}
+    for name, kw in (("teter", {}), ("learned", dict(precond="learned", mlp_weights=w))):
+        h = make_handle(args, els, guard=0, tol=1e-6, max_iter=1000, precision="mixed", **kw)
+        v, s_step, o = time_solves(h, V, kbt, X0, 1)
+        h.close()
+        out[name] = dict(iterations=[int(st["iters"]) for st in o["stats"]],
+                         converged=int(sum(1 for st in o["stats"] if st["converged"])),
+                         seconds=round(s_step, 3),
+                         teter_fallback_bands=int(sum(st["n_teter_fallback"] for st in o["stats"])))
+    it_t, it_l = np.array(out["teter"]["iterations"]), np.array(out["learned"]["iterations"])
+    out["seeds"] = list(seeds)
+    out["learned_fewer"] = int((it_l < it_t).sum())
+    out["learned_more"] = int((it_l > it_t).sum())
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,6 +460,9 @@ def main():
         forms["mixed_learned"] = form_summary(v, s_step, o, precision="mixed",
                                               preconditioner="learned", training=training)
         log(f"form mixed/learned: {v:.3f} elements/s")
+        forms["learned_vs_teter_one_element"] = learned_eval(args, dev, w)
+        log("learned vs Teter on the evaluation seeds: fewer iterations on "
+            f"{forms['learned_vs_teter_one_element']['learned_fewer']} of 16")
         forms["ratio_mixed_learned_over_fp64"] = round(
             forms["mixed_learned"]["value"] / forms["fp64_plain"]["value"], 3)
         if args.workload != "slab":

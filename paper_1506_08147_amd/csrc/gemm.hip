@@ -4,10 +4,10 @@
 // with a small C (operation 3); the paper distributes them by row blocks and
 // sums the J x J partial products with MPI_Allreduce.  On one GPU the same
 // split appears as split-K: each workgroup reduces one chunk of the N_g rows
-// into a 128 x 128 (or 144 x 144) tile, and a second kernel sums the chunks
-// in a fixed order (deterministic, no atomics).
+// into a tile of the result, and a second kernel sums the chunks in a fixed
+// order (deterministic, no atomics).
 //
-//   dg_gram       partial C = A^T B over one K chunk, A and B virtual
+//   dg_gram_w     partial C = A^T B over one K chunk, A and B virtual
 //                 concatenations of element blocks ([X P W], [HX HP HW]),
 //                 upper block triangle only when the result is symmetric
 //   dg_gram_reduce  sum of the chunks into the element's small workspace
@@ -63,6 +63,10 @@ struct GramArgs {
   int upper;       // only tiles touching the upper triangle
   int use_ne;      // K = rows of the restriction box instead of N_g
   int carry;       // skip tiles inside the leading block carried from the last step
+  // dg_gram_w: with a carried leading block (carried_cols(e) > 0), form only
+  // the columns of B after it and write them to the last columns of the
+  // m x m result (set by the host when it launches dg_gram_w for g.carry)
+  int tail;
 };
 
 struct UpdArgs {
@@ -89,25 +93,40 @@ struct UpdArgs {
 
 __device__ __forceinline__ int rowsK(const Elem& e, int use_ne) { return use_ne ? e.ne : e.ng; }
 
-// Both products use 128 x 128 workgroup tiles: four waves, each owning a
-// 64 x 64 sub-tile (4 x 4 MFMA blocks, 64 FP64 accumulators per lane).  The
-// K loop runs in stages of 16: operands of stage s+1 are loaded from global
-// memory into registers while stage s is multiplied out of LDS (double
-// buffered, one barrier per stage).  Column pointers of the block operands
-// are resolved once per workgroup into an LDS table.
-constexpr int TT = 128;        // workgroup tile edge
+// The K loop of both products runs in stages of 16: operands of stage s+1
+// are loaded from global memory into registers while stage s is multiplied
+// out of LDS (double buffered, one barrier per stage).  Column pointers of
+// the block operands are resolved once per workgroup into an LDS table.
+constexpr int TT = 128;        // row tile of the Gram and update products
 constexpr int KS = 16;         // K stage
-constexpr int LP = TT + 4;     // padded LDS row (doubles)
+constexpr int UTN = 144;       // largest column tile
 
+// columns of B that a dg_gram_w product forms (after a carried block when
+// g.tail is set)
+__device__ __forceinline__ int gram_w_cols(const GramArgs& g, const Elem& e, int job) {
+  const int c = opnd_cols(g.B[job], e);
+  const int kc = g.tail ? carried_cols(e) : 0;
+  return kc > 0 && kc < c ? c - kc : c;
+}
+
+// Gram products C = A^T B on tiles of 128 rows (columns of A) x
+// tile_edge(n) columns (columns of B): four waves stacked along the rows,
+// each owning 32 rows x up to 144 columns (2 x 9 MFMA blocks; blocks beyond
+// the tile are skipped), so an element of any width leaves at most 15 idle
+// columns per tile.  Symmetric products are formed in full (both triangles).
+// With g.tail the B columns after the carried block only: for S = [X P W],
+// S^T W and S^T H W, the columns of S^T S and S^T H S not known from the
+// last step.
 template <class T>
-__device__ __forceinline__ void dg_gram_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-        int na, GramArgs g) {
-  constexpr int LPT = TT + Mf<T>::pad;
+__device__ __forceinline__ void dg_gram_w_body(Elem* __restrict__ E, const int* __restrict__ active,
+                                               const int* __restrict__ prefix, int na, GramArgs g) {
+  constexpr int LPA = TT + Mf<T>::pad;
+  constexpr int LPB = UTN + Mf<T>::pad144;
 
-  __shared__ T As[2][KS * LPT];
-  __shared__ T Bs[2][KS * LPT];
+  __shared__ T As[2][KS * LPA];
+  __shared__ T Bs[2][KS * LPB];
   __shared__ const double* colA[TT];
-  __shared__ const double* colB[TT];
+  __shared__ const double* colB[UTN];
   int blk = blockIdx.x;
   int ai = find_elem(prefix, na, blk);
   const Elem& e = E[active[ai]];
@@ -115,71 +134,66 @@ __device__ __forceinline__ void dg_gram_body(Elem* __restrict__ E, const int* __
   const int K = rowsK(e, g.use_ne);
   const int m = opnd_cols(g.A, e);
   const int nch = gram_nchunk_e(e, K), clen = gram_chunklen(K, nch);
-  const int n0 = opnd_cols(g.B[0], e);
+  const int n0 = gram_w_cols(g, e, 0);
+  const int ntr = cdiv(m, TT);
   int job = 0, n = n0;
-  int ntile = gram_tiles(m, n, g.upper);
+  int tn = tile_edge(n);
+  int ntile = ntr * cdiv(n, tn);
   if (w >= ntile * nch) {
     job = 1;
     w -= ntile * nch;
-    n = opnd_cols(g.B[1], e);
-    ntile = gram_tiles(m, n, g.upper);
+    n = gram_w_cols(g, e, 1);
+    tn = tile_edge(n);
+    ntile = ntr * cdiv(n, tn);
   }
   // a grid sized for more blocks than the element has now (P dropped since
-  // the launch was planned, e.g. inside a captured graph) leaves spare items
+  // the launch was planned, e.g. inside a captured graph, or a carried
+  // block) leaves spare items
   if (job >= g.njob || ntile == 0 || w >= ntile * nch) return;
   const Opnd& B = g.B[job];
-  int chunk = w / ntile, tile = w - chunk * ntile;
-  int ti, tj;
-  gram_tile_decode(tile, m, n, g.upper, &ti, &tj);
-  if (g.carry) {
-    // the [X P] block of both products is formed from the last step's small
-    // matrices (dg_carry_in); tiles wholly inside it are not computed
-    const int kc = carried_cols(e);
-    if ((ti + 1) * TT <= kc && (tj + 1) * TT <= kc) return;
-  }
+  const int boff = opnd_cols(B, e) - n;          // first column of B in the product
+  const int chunk = w / ntile, tile = w - chunk * ntile;
+  const int ntc = cdiv(n, tn);
+  const int ti = tile / ntc, tj = tile - ti * ntc;
+  const int trows = min(TT, m - ti * TT), tcols = min(tn, n - tj * tn);
   const int kbeg = chunk * clen;
   const int kend = min(K, kbeg + clen);
   const int tid = threadIdx.x;
-  if (tid < TT) {
-    int c = ti * TT + tid;
-    colA[tid] = c < m ? opnd_col(g.A, e, c) : nullptr;
-  } else {
-    int c = tj * TT + tid - TT;
-    colB[tid - TT] = c < n ? opnd_col(B, e, c) : nullptr;
-  }
+  if (tid < TT) colA[tid] = tid < trows ? opnd_col(g.A, e, ti * TT + tid) : nullptr;
+  if (tid < UTN) colB[tid] = tid < tcols ? opnd_col(B, e, boff + tj * tn + tid) : nullptr;
   __syncthreads();
-  // stage loads: k = tid % 16, columns tid/16 + 16u (u < 8)
+  // stage loads: k = tid % 16; A columns tid/16 + 16u (u < 8), B columns
+  // tid/16 + 16v (v < 9)
   const int lk = tid & 15, lc = tid >> 4;
-  double ra[8], rb[8];
+  double ra[8], rb[9];
   auto load = [&](int k0) {
-    int k = k0 + lk;
-    bool kin = k < kend;
+    const int k = k0 + lk;
+    const bool kin = k < kend;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const double* pa = colA[lc + 16 * u];
-      const double* pb = colB[lc + 16 * u];
       ra[u] = (kin && pa) ? pa[k] : 0.0;
-      rb[u] = (kin && pb) ? pb[k] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 9; ++v) {
+      const double* pb = colB[lc + 16 * v];
+      rb[v] = (kin && pb) ? pb[k] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      As[buf][lk * LPT + lc + 16 * u] = ra[u];
-      Bs[buf][lk * LPT + lc + 16 * u] = rb[u];
-    }
+    for (int u = 0; u < 8; ++u) As[buf][lk * LPA + lc + 16 * u] = ra[u];
+#pragma unroll
+    for (int v = 0; v < 9; ++v) Bs[buf][lk * LPB + lc + 16 * v] = rb[v];
   };
-  const int lane = tid & 63, wv = tid >> 6;
-  const int wi = wv & 1, wj = wv >> 1;
-  // a wave whose 64 x 64 sub-tile lies wholly outside the m x n result (in
-  // the last tile row or column of a size that is no multiple of 128) skips
-  // its products
-  const bool live = ti * TT + wi * 64 < m && tj * TT + wj * 64 < n;
-  typename Mf<T>::acc acc[4][4];
+  const int lane = tid & 63, wr = tid >> 6;
+  const int nra = max(0, min(2, cdiv(trows - wr * 32, 16)));   // live row blocks of this wave
+  const int nbc = min(9, cdiv(tcols, 16));                      // live column blocks
+  typename Mf<T>::acc acc[2][9];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = Mf<T>::zero();
+    for (int a = 0; a < 9; ++a) acc[c][a] = Mf<T>::zero();
   const int nst = (kend - kbeg + KS - 1) / KS;
   if (nst > 0) {
     load(kbeg);
@@ -189,20 +203,22 @@ __device__ __forceinline__ void dg_gram_body(Elem* __restrict__ E, const int* __
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
     if (st + 1 < nst) load(kbeg + (st + 1) * KS);
-    if (live) {
+    if (nra > 0) {
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
+      for (int ks = 0; ks < KS / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        T fa[4], fb[4];
+        T fa[2], fb[9];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) fa[a] = As[cur][kk * LPT + wi * 64 + a * 16 + (lane & 15)];
+        for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPA + wr * 32 + c * 16 + (lane & 15)];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fb[c] = Bs[cur][kk * LPT + wj * 64 + c * 16 + (lane & 15)];
+        for (int a = 0; a < 9; ++a) fb[a] = Bs[cur][kk * LPB + a * 16 + (lane & 15)];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 9; ++a)
+          if (a < nbc) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            acc[a][c] = Mf<T>::mma(fa[a], fb[c], acc[a][c]);
+            for (int c = 0; c < 2; ++c)
+              if (c < nra) acc[c][a] = Mf<T>::mma(fa[c], fb[a], acc[c][a]);
+          }
       }
     }
     if (st + 1 < nst) store(cur ^ 1);
@@ -210,33 +226,35 @@ __device__ __forceinline__ void dg_gram_body(Elem* __restrict__ E, const int* __
   }
   double* part = e.gpart + (job ? (long long)nch * m * n0 : 0LL) + (long long)chunk * m * n;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int a = 0; a < 9; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = ti * TT + wi * 64 + a * 16 + Mf<T>::row(r, lane);
-        int j = tj * TT + wj * 64 + c * 16 + (lane & 15);
-        if (i < m && j < n) part[i + (long long)m * j] = (double)acc[a][c][r];
+        const int il = wr * 32 + c * 16 + Mf<T>::row(r, lane);
+        const int jl = a * 16 + (lane & 15);
+        if (il < trows && jl < tcols)
+          part[(ti * TT + il) + (long long)m * (tj * tn + jl)] = (double)acc[c][a][r];
       }
 }
 
-extern "C" __global__ void __launch_bounds__(256)
-dg_gram(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-        int na, GramArgs g) {
-  dg_gram_body<double>(E, active, prefix, na, g);
+extern "C" __global__ void __launch_bounds__(256, 2)
+dg_gram_w(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+          int na, GramArgs g) {
+  dg_gram_w_body<double>(E, active, prefix, na, g);
 }
 
-extern "C" __global__ void __launch_bounds__(256)
-dg_gram32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-        int na, GramArgs g) {
-  dg_gram_body<float>(E, active, prefix, na, g);
+extern "C" __global__ void __launch_bounds__(256, 2)
+dg_gram_w32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+            int na, GramArgs g) {
+  dg_gram_w_body<float>(E, active, prefix, na, g);
 }
 
 // The same product with 144 x 144 tiles, for operands whose column counts
 // are multiples of 144 (blocks of 144 states): nine waves in a 3 x 3 grid,
-// each owning 48 x 48 (3 x 3 MFMA blocks).  Chunks, carried-block skip,
-// staging and partial sums follow dg_gram.
+// each owning 48 x 48 (3 x 3 MFMA blocks), upper triangle only for
+// symmetric products; tiles wholly inside a carried block are skipped.
+// Chunks, staging and partial sums follow dg_gram_w.
 constexpr int GTT = 144;       // tile edge of dg_gram_t144
 constexpr int GLP = GTT + 4;
 constexpr int GRAM144_THREADS = 576;
@@ -380,10 +398,10 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
   const int K = rowsK(e, g.use_ne);
   const int m = opnd_cols(g.A, e);
   const int nch = gram_nchunk_e(e, K);
-  const int n0 = opnd_cols(g.B[0], e);
+  const int n0 = gram_w_cols(g, e, 0);
   int job = 0, n = n0;
   int nb = cdiv(m * n, 256);
-  if (w >= nb) { job = 1; w -= nb; n = opnd_cols(g.B[1], e); }
+  if (w >= nb) { job = 1; w -= nb; n = gram_w_cols(g, e, 1); }
   if (job >= g.njob) return;
   int idx = w * 256 + threadIdx.x;
   if (idx >= m * n) return;
@@ -391,7 +409,9 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
   // only entries of computed tiles are meaningful; others are never read
   double s = 0.0;
   for (int c = 0; c < nch; ++c) s += part[(long long)c * m * n + idx];
-  sm(e, g.out_mat[job])[idx] = s;
+  // a tail product fills the last n columns of the m x (columns of B) result
+  const long long off = (long long)m * (opnd_cols(g.B[job], e) - n);
+  sm(e, g.out_mat[job])[off + idx] = s;
 }
 
 // Y (K x ncol) = alpha A (K x kA) C (kA x ncol) + beta Y.  Computed as the
@@ -405,7 +425,6 @@ dg_gram_reduce(Elem* __restrict__ E, const int* __restrict__ active, const int* 
 // workgroup fits twice per compute unit.
 constexpr int UKS = 16;        // K stage of the update
 constexpr int UPD_NQ = UKS / 2;
-constexpr int UTN = 144;       // largest column tile
 
 template <class T>
 __device__ __forceinline__ void dg_update_w_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
