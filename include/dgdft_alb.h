@@ -190,6 +190,15 @@ int32_t dgdft_alb_sizes(const dgdft_alb* h, int32_t elem, int64_t* ng, int64_t* 
  * chunk count of its N_g-long Gram products (0 = the default rule). */
 int32_t dgdft_alb_get_tuning(const dgdft_alb* h, int32_t elem, int32_t* gram_split);
 
+/* Cached tuning: set element `elem`'s split-K chunk count (0 = the default
+ * rule, else 1..8), e.g. a value dgdft_alb_get_tuning returned for a
+ * handle of the same element shapes created with opts.tune = 1, so that a
+ * new handle skips the timing runs.  The three tuning modes are thus: off
+ * (opts.tune = 0), full (opts.tune = 1), cached (opts.tune = 0, then this
+ * call per element).  Synchronous; EINVAL for an index or count out of
+ * range.  Not concurrent with a solve on h. */
+int32_t dgdft_alb_set_tuning(dgdft_alb* h, int32_t elem, int32_t gram_split);
+
 /* Load the restricted potentials of all elements (V_eff^Q and V_nl^Q of
  * Sec. II.A).  V: device [sum N_g] (Ha); kb as above (n_proj may be NULL for
  * no projectors).  Validates finiteness; the data are copied, so the caller

@@ -23,7 +23,7 @@ EXPORTS = (
     "dgdft_mlp_train", "dgdft_mlp_grad", "dgdft_mlp_eval", "dgdft_alb_get_tuning",
     "dgdft_alb_density", "dgdft_alb_nonlocal_block", "dgdft_alb_dg_volume",
     "dgdft_alb_orthonormalise", "dgdft_alb_rayleigh_ritz", "dgdft_small_syev_noalloc",
-    "dgdft_alb_initial_guess",
+    "dgdft_alb_initial_guess", "dgdft_alb_set_tuning",
 )
 MLP_NW = 4481
 MLP_NTOT = 4487
@@ -143,6 +143,8 @@ def load_library():
     lib.dgdft_mlp_eval.restype = i32
     lib.dgdft_alb_get_tuning.argtypes = [vp, i32, P(C.c_int32)]
     lib.dgdft_alb_get_tuning.restype = i32
+    lib.dgdft_alb_set_tuning.argtypes = [vp, i32, i32]
+    lib.dgdft_alb_set_tuning.restype = i32
     lib.dgdft_alb_density.argtypes = [vp, vp, vp, vp, vp]
     lib.dgdft_alb_density.restype = i32
     lib.dgdft_alb_nonlocal_block.argtypes = [vp, vp, vp, vp]
@@ -349,6 +351,10 @@ class ALB:
         v = C.c_int32()
         self._check(self.lib.dgdft_alb_get_tuning(self.h, e, C.byref(v)))
         return v.value
+
+    def set_tuning(self, e, gram_split):
+        """Cached tuning: element e's split-K chunk count (0: default rule)."""
+        self._check(self.lib.dgdft_alb_set_tuning(self.h, e, int(gram_split)))
 
     def set_mlp(self, weights):
         """Network of the learned preconditioner (device FP32 tensor [MLP_NTOT])."""

@@ -106,6 +106,11 @@ struct dgdft_alb {
   hipStream_t g_stream[NGROUP] = {};
   hipEvent_t g_join = nullptr;
   hipEvent_t g_done[NGROUP] = {};
+  // per group: a second stream on which the eigensolver of the smaller
+  // Rayleigh-Ritz orders runs beside the one of the larger (fork / join)
+  hipStream_t g_aux[NGROUP] = {};
+  hipEvent_t g_fork[NGROUP] = {};
+  hipEvent_t g_auxdone[NGROUP] = {};
   // HIP-graph mode: K iterations of a group captured once per active set.
   // While capturing, prefix arrays go to a per-group table that is copied to
   // the device once, before the graph's first launch.
@@ -585,6 +590,39 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
   }
 
+  // The eigensolver of the Rayleigh-Ritz step: dg_rr_eig (orders up to 512,
+  // 1024-lane workgroups) and, when some element's order is 513..832,
+  // dg_rr_eig_wide (512 lanes); each skips the other's elements.  Outside
+  // graph capture the first runs on the group's second stream beside the
+  // second (one workgroup per element each, so together they take one
+  // compute unit per element instead of running one after the other).
+  void rr_eig_pair(const std::vector<int>& act, int single) {
+    bool wide = false;
+    for (int e : act) wide = wide || eig_wide((single ? 1 : (hasP_host(e) ? 3 : 2)) * eh[e].J);
+    if (!wide || capturing) {
+      rr_one(act, dg_rr_eig, SMALL_THREADS, single);
+      if (wide) rr_one(act, dg_rr_eig_wide, EIG_WIDE_THREADS, single);
+      return;
+    }
+    auto P = make_prefix(act, [&](int) { return 1; });   // copied on the group's stream
+    HCHECK(hipEventRecord(g_fork[cur_g], stream));
+    HCHECK(hipStreamWaitEvent(g_aux[cur_g], g_fork[cur_g], 0));
+    hipStream_t main = stream;
+    stream = g_aux[cur_g];
+    pbeg(DGDFT_K_RR, 0, 0);
+    hipLaunchKernelGGL(dg_rr_eig, dim3(P.na), dim3(SMALL_THREADS), 0, stream, ed, P.active, P.na, single);
+    pend();
+    HCHECK(hipGetLastError());
+    HCHECK(hipEventRecord(g_auxdone[cur_g], stream));
+    stream = main;
+    pbeg(DGDFT_K_RR, 0, 0);
+    hipLaunchKernelGGL(dg_rr_eig_wide, dim3(P.na), dim3(EIG_WIDE_THREADS), 0, stream, ed, P.active, P.na,
+                       single);
+    pend();
+    HCHECK(hipGetLastError());
+    HCHECK(hipStreamWaitEvent(stream, g_auxdone[cur_g], 0));
+  }
+
   // Rayleigh-Ritz step (see lobpcg.hip): per-element factorisations and
   // decisions one workgroup each, products on dg_sgemm.
   void rr_step(const std::vector<int>& act, int single) {
@@ -644,12 +682,7 @@ struct dgdft_alb {
       sgemm(act, single, 0, 0, SM_H, 0, SM_T, 0, SM_U, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
       sgemm(act, single, 0, 0, SM_T, 0, SM_U, 0, SM_A, 0, N, N, N, N, N, N, 1.0, 0.0, 3);
     }
-    rr_one(act, dg_rr_eig, SMALL_THREADS, single);
-    {
-      bool wide = false;
-      for (int e : act) wide = wide || eig_wide((single ? 1 : (hasP_host(e) ? 3 : 2)) * eh[e].J);
-      if (wide) rr_one(act, dg_rr_eig_wide, EIG_WIDE_THREADS, single);
-    }
+    rr_eig_pair(act, single);
     // path 0: C = L^-T Y
     sgemm(act, single, 0, 0, SM_T, 0, SM_Z, 0, SM_C, 0, N, Jc, N, N, N, N, 1.0, 0.0, 0);
     // path 3: C = T Y
@@ -870,6 +903,11 @@ void dgdft_alb_destroy(dgdft_alb* h) {
   for (int g = 1; g < dgdft_alb::NGROUP; ++g) {
     if (h->g_done[g]) (void)hipEventDestroy(h->g_done[g]);
     if (h->g_stream[g]) (void)hipStreamDestroy(h->g_stream[g]);
+  }
+  for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+    if (h->g_fork[g]) (void)hipEventDestroy(h->g_fork[g]);
+    if (h->g_auxdone[g]) (void)hipEventDestroy(h->g_auxdone[g]);
+    if (h->g_aux[g]) (void)hipStreamDestroy(h->g_aux[g]);
   }
   if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
   (void)hipSetDevice(cur);
@@ -1167,6 +1205,11 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
       HCHECK(hipStreamCreateWithFlags(&h->g_stream[g], hipStreamNonBlocking));
       HCHECK(hipEventCreateWithFlags(&h->g_done[g], hipEventDisableTiming));
     }
+    for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
+      HCHECK(hipStreamCreateWithFlags(&h->g_aux[g], hipStreamNonBlocking));
+      HCHECK(hipEventCreateWithFlags(&h->g_fork[g], hipEventDisableTiming));
+      HCHECK(hipEventCreateWithFlags(&h->g_auxdone[g], hipEventDisableTiming));
+    }
     HCHECK(hipEventCreateWithFlags(&h->g_join, hipEventDisableTiming));
     if (h->opts.graph_iters > 0) {
       h->cap_slots = (size_t)h->opts.graph_iters * 128;
@@ -1194,6 +1237,27 @@ int32_t dgdft_alb_get_tuning(const dgdft_alb* h, int32_t elem, int32_t* gram_spl
   if (!h || elem < 0 || elem >= h->n) return DGDFT_EINVAL;
   if (gram_split) *gram_split = h->eh[elem].gram_split;
   return DGDFT_OK;
+}
+
+int32_t dgdft_alb_set_tuning(dgdft_alb* h, int32_t elem, int32_t gram_split) {
+  if (!h) return DGDFT_EINVAL;
+  if (elem < 0 || elem >= h->n || gram_split < 0 || gram_split > GRAM_MAXCHUNK) {
+    h->err = "set_tuning: element index or split-K chunk count out of range";
+    return DGDFT_EINVAL;
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  int32_t rc = DGDFT_OK;
+  try {
+    HCHECK(hipSetDevice(h->dev));
+    h->eh[elem].gram_split = gram_split;
+    HCHECK(hipMemcpy(h->ed + elem, &h->eh[elem], sizeof(Elem), hipMemcpyHostToDevice));
+  } catch (HipFail& f) {
+    h->err = f.what;
+    rc = DGDFT_EHIP;
+  }
+  (void)hipSetDevice(cur);
+  return rc;
 }
 
 int32_t dgdft_alb_sizes(const dgdft_alb* h, int32_t elem, int64_t* ng, int64_t* ne, int32_t* n_states,

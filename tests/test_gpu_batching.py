@@ -77,3 +77,39 @@ def test_uneven_batch_graph_and_tuned(dev):
     assert ste[0] == 0 and stg[0] == 0
     for i in range(len(els)):
         assert np.abs(rg[0][i]["eigvals"] - re_[0][i]["eigvals"]).max() < 1e-8
+
+
+def test_cached_tuning_reproduces_the_tuned_handle(dev):
+    """The cached mode: a handle without tuning given, element by element,
+    the split-K counts a tuned handle chose solves exactly as the tuned one
+    (the same products in the same order, so bit for bit); counts out of
+    range are EINVAL."""
+    import torch
+    from paper_1506_08147_amd import ALB
+    from paper_1506_08147_amd.binding import DGDFTError
+    els = _elements()
+    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
+    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
+    kbt = ALB.kb_batch([e.kb for e in els], dev)
+
+    def handle(**kw):
+        return ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=1e-9,
+                   elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+                   n_alb=[e.n_alb for e in els], **kw)
+
+    ht = handle(tune=True)
+    tun = [ht.get_tuning(i) for i in range(len(els))]
+    ot = ht.solve(V, kbt, X0)
+    hc = handle()
+    for i, t in enumerate(tun):
+        hc.set_tuning(i, t)
+    assert [hc.get_tuning(i) for i in range(len(els))] == tun
+    oc = hc.solve(V, kbt, X0)
+    assert np.array_equal(ot["eigvals"].cpu().numpy(), oc["eigvals"].cpu().numpy())
+    assert [s["iters"] for s in ot["stats"]] == [s["iters"] for s in oc["stats"]]
+    for bad in ((len(els), 1), (0, -1), (0, 9)):
+        with pytest.raises(DGDFTError) as err:
+            hc.set_tuning(*bad)
+        assert err.value.code == -1
+    ht.close()
+    hc.close()
