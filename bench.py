@@ -263,31 +263,37 @@ def form_summary(value, s_step, out, **kw):
                 teter_fallback_bands=int(sum(s["n_teter_fallback"] for s in st)), **kw)
 
 
-def train_network(dev):
+def train_network(dev, guard=8):
     """Network of the learned preconditioner: pairs logged by the solver on
-    one-element workloads (seeds 100-115, 24^3, 32 states, residual 1e-8,
-    first 40 iterations), 30 epochs of Adam on the GPU."""
+    one-element workloads (seeds 100-115, 24^3, 32 states + `guard` guard
+    columns, the block layout the learned form runs with, residual 1e-8,
+    first 40 iterations), the wanted bands only, 30 epochs of Adam on the
+    GPU."""
     import numpy as np
     import torch
     import synth
     from paper_1506_08147_amd import ALB, mlp_train
     t = time.perf_counter()
     els = [synth.single_element(seed=s) for s in range(100, 116)]
-    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states for e in els], tol=1e-8,
+    h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states + guard for e in els], tol=1e-8,
             elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
-            n_alb=[e.n_alb for e in els])
-    V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
-    X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(e.X0.T)).reshape(-1) for e in els]).to(dev)
-    P = h.log_pairs(V, ALB.kb_batch([e.kb for e in els], dev), X0, 40)
+            n_alb=[e.n_alb for e in els], n_guard=guard)
+    V, kbt, X0 = resident_inputs(els, guard, dev)
+    max_log = 40
+    P = h.log_pairs(V, kbt, X0, max_log)
     h.close()
-    idx = []
+    # samples are laid out [element][logged iteration][band of the block]
+    idx, base = [], 0
     for e, nl in enumerate(P["n_logged"]):
-        idx += [e * 40 * 32 + k for k in range(nl * 32)]
+        jb = els[e].n_states + guard
+        for it in range(int(nl)):
+            idx += [base + it * jb + b for b in range(els[e].n_states)]
+        base += max_log * jb
     w = torch.from_numpy(synth.mlp_init(seed=0, last_layer=0.0)).to(dev)
     hist = mlp_train(P, w, index=np.asarray(idx), epochs=30, batch=256, lr=2e-3, seed=1)
     el = time.perf_counter() - t
     log(f"network trained in {el:.1f} s: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
-    return w, dict(samples=len(idx), epochs=30, loss_first=round(float(hist[0]), 5),
+    return w, dict(samples=len(idx), epochs=30, guard_columns=guard, loss_first=round(float(hist[0]), 5),
                    loss_last=round(float(hist[-1]), 5), seconds=round(el, 1))
 
 
@@ -323,18 +329,18 @@ def mixed_vs_oracle(args, dev, seeds=(1000, 1001, 1002, 1003)):
     return dict(workload="cube_24^3_J32", tol=1e-6, reference="FP64 oracle", elements=rows)
 
 
-def learned_eval(args, dev, w, seeds=range(1000, 1016)):
+def learned_eval(args, dev, w, seeds=range(1000, 1016), guard=8):
     """The learned preconditioner against Teter's on the one-element
-    workloads of the evaluation seeds (24^3, 32 states, mixed precision,
-    residual 1e-6, no guard columns): per seed the iterations of each and
+    workloads of the evaluation seeds (24^3, 32 states + 8 guard columns,
+    mixed precision, residual 1e-6): per seed the iterations of each and
     the wall time of a solve of the 16 elements together."""
     import numpy as np
     import synth
     els = [synth.single_element(seed=s) for s in seeds]
-    V, kbt, X0 = resident_inputs(els, 0, dev)
+    V, kbt, X0 = resident_inputs(els, guard, dev)
     out = {}
     for name, kw in (("teter", {}), ("learned", dict(precond="learned", mlp_weights=w))):
-        h = make_handle(args, els, guard=0, tol=1e-6, max_iter=1000, precision="mixed", **kw)
+        h = make_handle(args, els, guard=guard, tol=1e-6, max_iter=1000, precision="mixed", **kw)
         v, s_step, o = time_solves(h, V, kbt, X0, 1)
         h.close()
         out[name] = dict(iterations=[int(st["iters"]) for st in o["stats"]],
@@ -343,6 +349,7 @@ def learned_eval(args, dev, w, seeds=range(1000, 1016)):
                          teter_fallback_bands=int(sum(st["n_teter_fallback"] for st in o["stats"])))
     it_t, it_l = np.array(out["teter"]["iterations"]), np.array(out["learned"]["iterations"])
     out["seeds"] = list(seeds)
+    out["guard_columns"] = guard
     out["learned_fewer"] = int((it_l < it_t).sum())
     out["learned_more"] = int((it_l > it_t).sum())
     return out

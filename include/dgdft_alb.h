@@ -55,9 +55,13 @@ extern "C" {
 #define DGDFT_EBREAKDOWN      -5   /* initial block rank deficient (CholQR)       */
 
 #define DGDFT_PREC_FP64        0
-#define DGDFT_PREC_MIXED       1   /* FP32 transforms for H W and the             *
-                                    * preconditioner; Grams, Rayleigh-Ritz, X/HX   *
-                                    * updates, final check and ALBs stay FP64      */
+#define DGDFT_PREC_MIXED       1   /* FP32 transforms of the preconditioner; with *
+                                    * the orthonormalised direction (no guard      *
+                                    * columns, or tol < 1e-7) also FP32 transforms *
+                                    * for H W and FP32 MFMA products for the       *
+                                    * projection and normalisation of W; Grams of  *
+                                    * S, Rayleigh-Ritz, X/HX/P/HP updates, final   *
+                                    * check and ALBs stay FP64                     */
 
 #define DGDFT_PRECOND_TETER    0
 #define DGDFT_PRECOND_LEARNED  1   /* Teter factor times a learned per-shell gain *
@@ -283,13 +287,13 @@ int32_t dgdft_alb_orthonormalise(dgdft_alb* h, int32_t elem, const double* G, do
  * coefficients with C^T M C = I; for kb > 1, D [n*J] the coefficients of
  * the next search direction P' = S D, in the form the solver uses for the
  * handle:
- *   - handles without guard columns, mixed-precision handles and handles
- *     with a tolerance below 1e-7: the part of [0; C_P; C_W] (C with its
+ *   - handles without guard columns and handles with a tolerance below
+ *     1e-7: the part of [0; C_P; C_W] (C with its
  *     first J rows zeroed) M-orthogonal to C, normalised so that
  *     D^T M D = I, or all zero when that normalisation breaks down (P is
  *     then dropped, flags[2]);
- *   - FP64 handles with guard columns (opts.n_guard > 0) and opts.tol >=
- *     1e-7: Knyazev's form,
+ *   - handles with guard columns (opts.n_guard > 0) and opts.tol >= 1e-7:
+ *     Knyazev's form,
  *     D = C with its first J rows zeroed (P' = [P W] [C_P; C_W], neither
  *     normalised nor orthogonal to X' = S C).  For kb = 3, where the
  *     solver's X and W blocks are orthonormal and mutually orthogonal, the

@@ -134,20 +134,17 @@ struct dgdft_alb {
   // on the full basis (used only for the work accounting of the Gram)
   std::vector<char> carry_host;
   std::string err;
-  // Knyazev's form of the search direction (FP64 blocks with guard
-  // columns, tolerance >= KNYAZEV_MIN_TOL), else the orthonormalised one
-  // (see lobpcg.hip).  The mixed form keeps the orthonormalised direction:
-  // its small-space orthonormalisation of P against [X W] assumes [X W]
-  // orthonormal to FP64 rounding, which the FP32 products that form W2 do
-  // not give.  Tight tolerances keep it too: once the residuals fall well
-  // below 1e-7, P lies in span [X W] but for a part of relative size near
-  // the residual, and the Schur complement M_PP - M_QP^T Z that measures
-  // that part loses it to cancellation, so P is dropped step after step
-  // (measured on the slab at 1e-8: an element stalled to 60 iterations).
+  // Knyazev's form of the search direction (blocks with guard columns,
+  // tolerance >= KNYAZEV_MIN_TOL), else the orthonormalised one (see
+  // lobpcg.hip).  Tight tolerances keep the orthonormalised direction: once
+  // the residuals fall well below 1e-7, P lies in span [X W] but for a part
+  // of relative size near the residual, and the Schur complement
+  // M_PP - M_QP^T Z that measures that part loses it to cancellation, so P
+  // is dropped step after step (measured on the slab at 1e-8: an element
+  // stalled to 60 iterations).  In the mixed form Knyazev's direction needs
+  // H W2 and the W normalisation in FP64 (iterate()).
   static constexpr double KNYAZEV_MIN_TOL = 1e-7;
-  bool knyazev() const {
-    return opts.n_guard > 0 && opts.precision != DGDFT_PREC_MIXED && opts.tol >= KNYAZEV_MIN_TOL;
-  }
+  bool knyazev() const { return opts.n_guard > 0 && opts.tol >= KNYAZEV_MIN_TOL; }
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;
   // wall time of the phases of the last solve (host clock at synchronised
@@ -1646,32 +1643,44 @@ static void iterate(dgdft_alb* h, const std::vector<int>& act) {
   }
   h->precondition(act, S_W, 0, -1, mixed);
   const bool kny = h->knyazev();
+  // In the mixed form with Knyazev's direction only the preconditioner runs
+  // in FP32.  H W2 stays FP64: P' = [P W2] C_PW and H P' are carried from
+  // step to step unnormalised, so FP32 rounding in H W2 accumulates in H P
+  // (measured: the uneven batch diverged, residuals 26 after 60 iterations,
+  // with FP32 transforms here); so does the W normalisation, on which the
+  // small-space orthonormalisation of P relies.  FP32 products for the
+  // projection of W against X converge, but leave W2 orthogonal to X only
+  // to ~1e-7, which moves the Rayleigh-Ritz reduction off its first-order
+  // path (measured: 16.38 against 17.16 elements/s for FP64 on the uneven
+  // batch, Rayleigh-Ritz 4.78 against 3.98 s per step).
+  const bool mixed_w = mixed && !kny;
   // W <- W - X (X^T W) (Knyazev's form) or W <- W - [X P]([X P]^T W)
   GramArgs g1{};
   g1.A = kny ? dgdft_alb::opnd({VS_X}) : dgdft_alb::opnd({VS_X, VS_P}, {0, 1});
   g1.B[0] = dgdft_alb::opnd({S_W});
   g1.njob = 1; g1.out_mat[0] = SM_G; g1.upper = 0;
-  h->gram(act, g1, mixed);
+  h->gram(act, g1, mixed_w);
   UpdArgs u1{};
   u1.A[0] = g1.A;
   u1.Y[0] = dgdft_alb::opnd({S_W});
   u1.njob = 1; u1.cmat = SM_G; u1.ncol = -1; u1.alpha = -1.0; u1.beta = 1.0;
-  h->update(act, u1, mixed);
+  h->update(act, u1, mixed_w);
   // W2 = W T (CholQR / SVQB of the explicit W^T W)
   GramArgs gw{};
   gw.A = dgdft_alb::opnd({S_W});
   gw.B[0] = dgdft_alb::opnd({S_W});
   gw.njob = 1; gw.out_mat[0] = SM_G; gw.upper = 1;
-  h->gram(act, gw, mixed);
+  h->gram(act, gw, mixed_w);
   h->per_elem(act, 0, 0);
   UpdArgs u2{};
   u2.A[0] = dgdft_alb::opnd({S_W});
   u2.Y[0] = dgdft_alb::opnd({S_W2});
   u2.njob = 1; u2.cmat = SM_T; u2.ncol = -1; u2.alpha = 1.0; u2.beta = 0.0;
-  h->update(act, u2, mixed);
-  // HW (FP32 transforms in the mixed form: errors enter H X and H P only
-  // through the correction coefficients, and the final check is FP64)
-  h->op_apply(act, S_W2, S_HW, 0, -1, mixed);
+  h->update(act, u2, mixed_w);
+  // HW (FP32 transforms in the mixed form with the orthonormalised
+  // direction: errors enter H X and H P only through the correction
+  // coefficients, and the final check is FP64)
+  h->op_apply(act, S_W2, S_HW, 0, -1, mixed_w);
   // Rayleigh-Ritz on S = [X P W2]: S^T S and S^T H S (the [X P] blocks
   // from the last step where they are carried).  FP64 in both forms: the
   // FP32 products above only leave W2 slightly non-orthonormal and not quite

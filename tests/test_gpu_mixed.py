@@ -1,6 +1,9 @@
-"""Mixed-precision form (FP32 transforms for H W and the preconditioner,
-FP64 elsewhere and in the final check) against the FP64 oracle, through the
-C ABI: eigenvalue error and largest principal angle per element."""
+"""Mixed-precision form against the FP64 oracle, through the C ABI:
+eigenvalue error and largest principal angle per element.  Without guard
+columns (orthonormalised direction): FP32 transforms for H W and the
+preconditioner and FP32 products for the W projection and normalisation;
+with guard columns (Knyazev's direction): FP32 preconditioner only; FP64
+elsewhere and in the final check."""
 import numpy as np
 import pytest
 
@@ -91,3 +94,67 @@ def test_mixed_batch_matches_fp64_batch(dev):
     assert stm == 0
     for a, b in zip(rf, rm):
         assert np.abs(a["eigvals"] - b["eigvals"]).max() < 1e-6
+
+
+def test_mixed_guarded_knyazev_vs_fp64_oracle(dev):
+    """The mixed form with guard columns (Knyazev's search direction, FP32
+    preconditioner, FP64 operator and W products) on
+    two one-element workloads with 8 guards and on the first six elements
+    of the uneven batch with 16, residual 1e-6: every element converged,
+    the wanted states' residuals by the oracle's operator within 2 tol, and
+    the wanted eigenvalues within the quadratic Ritz-value bound of the
+    oracle's guarded solve at 1e-9 (one-element workloads), or within the
+    residual bound of the FP64 GPU form (uneven)."""
+    import torch
+    from oracle import lobpcg as lob, teter
+    from oracle.hamiltonian import Operator
+    from paper_1506_08147_amd import ALB
+
+    def run(els, g, precision):
+        h = ALB([e.grid for e in els], [e.box for e in els], [e.n_states + g for e in els], tol=1e-6,
+                elem_lo=[e.elem_lo for e in els], elem_hi=[e.elem_hi for e in els],
+                n_alb=[e.n_alb for e in els], n_guard=g, precision=precision)
+        V = torch.cat([torch.from_numpy(e.V) for e in els]).to(dev)
+        X0 = torch.cat([torch.from_numpy(np.ascontiguousarray(np.hstack(
+            [e.X0, synth.guard_columns(e.ng, g, (k, e.n_states))]).T)).reshape(-1)
+            for k, e in enumerate(els)]).to(dev)
+        out = h.solve(V, ALB.kb_batch([e.kb for e in els], dev), X0)
+        res = [{k: v.cpu().numpy() for k, v in h.split(out, i).items()} for i in range(len(els))]
+        st = out["stats"]
+        h.close()
+        return res, st, out["status"]
+
+    def residuals(el, r):
+        J = el.n_states
+        op = Operator(el.grid, el.box, el.V, el.kb)
+        X = r["eigvecs"][:, :J] * np.sqrt(el.dv)
+        th = r["eigvals"][:J]
+        return np.linalg.norm(op.apply(X) - X * th[None, :], axis=0), op
+
+    els = [synth.single_element(seed=s) for s in (1000, 1001)]
+    rm, sm, stat = run(els, 8, "mixed")
+    assert stat == 0 and all(s["converged"] for s in sm)
+    for k, (el, r) in enumerate(zip(els, rm)):
+        J = el.n_states
+        res, op = residuals(el, r)
+        assert res.max() <= 2e-6, res.max()
+        pre = lambda R, X: teter.precondition(R, X, op.grid, op.box)  # noqa: E731
+        X0 = np.hstack([el.X0, synth.guard_columns(el.ng, 8, (k, J))])
+        ref = lob.lobpcg(op.apply, pre, X0, 1e-9, 500, n_check=J)
+        d = r["eigvals"][:J] - ref.theta[:J]
+        bound = float(np.sum(res ** 2)) / (ref.theta[J] - r["eigvals"][:J])
+        print(f"element {k}: iters {sm[k]['iters']} max |dlambda| {np.abs(d).max():.2e}")
+        assert np.all(d >= -1e-10) and np.all(d <= bound + 1e-10)
+    un = synth.uneven_batch(6)
+    rm, sm, stat = run(un, 16, "mixed")
+    rf, sf, _ = run(un, 16, "fp64")
+    print("iters fp64", [s["iters"] for s in sf], "mixed", [s["iters"] for s in sm])
+    assert stat == 0 and all(s["converged"] for s in sm)
+    for el, a, b in zip(un, rm, rf):
+        res, _ = residuals(el, a)
+        resf, _ = residuals(el, b)
+        assert res.max() <= 2e-6
+        # both sets of Ritz values lie above the exact eigenvalues by at most
+        # the Frobenius norm of their residual blocks
+        d = np.abs(a["eigvals"][:el.n_states] - b["eigvals"][:el.n_states]).max()
+        assert d <= np.linalg.norm(res) + np.linalg.norm(resf), d
