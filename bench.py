@@ -453,7 +453,18 @@ def main():
     forms = None
     if args.forms:
         forms = dict(fp64_plain=dict(value=round(n_conv / elapsed, 4), ms_per_step=round(ms_step, 2),
-                                     iterations_mean=float(np.mean(iters))))
+                                     iterations_mean=float(np.mean(iters)), streams=args.streams))
+        if args.streams == 1:
+            # the same solve on two element groups (two streams): one group's
+            # small dense Rayleigh-Ritz steps overlap the other's products;
+            # per-kernel event times then share the GPU, so the roofline is
+            # taken from the one-stream run above
+            h2 = make_handle(args, els, tol=args.tol, max_iter=1000, n_streams=2)
+            v, s_step, o = time_solves(h2, V, kbt, X0, args.form_steps)
+            h2.close()
+            forms["fp64_two_streams"] = form_summary(v, s_step, o, precision="fp64",
+                                                     preconditioner="teter", streams=2)
+            log(f"form fp64 two streams: {v:.3f} elements/s")
         hm = make_handle(args, els, tol=args.tol, max_iter=1000, precision="mixed")
         v, s_step, o = time_solves(hm, V, kbt, X0, args.form_steps)
         hm.close()

@@ -189,7 +189,7 @@ __device__ inline int find_elem(const int* __restrict__ prefix, int na, int b) {
 }
 
 // ---- work decomposition shared by host (counts) and device (decode) ----
-constexpr int GT = 128;           // Gram tile edge; row tile of the update products
+constexpr int GT = 128;           // row tile of the Gram and update products
 constexpr int GRAM_MAXCHUNK = 8;
 
 __host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -220,29 +220,6 @@ __host__ __device__ inline int tile_edge(int d) {
   if (d <= 0) return 16;
   int t = cdiv(d, TMAX);
   return cdiv(cdiv(d, t), 16) * 16;
-}
-
-// tile grid of a Gram product with tile edge tt (GT, or 144 for blocks of
-// 144 columns)
-__host__ __device__ inline int gram_tiles(int m, int n, int upper, int tt = GT) {
-  int tm = cdiv(m, tt), tn = cdiv(n, tt);
-  if (!upper) return tm * tn;
-  int c = 0;
-  for (int i = 0; i < tm; ++i) c += (tn - i > 0) ? tn - i : 0;
-  return c;
-}
-
-__host__ __device__ inline void gram_tile_decode(int t, int m, int n, int upper, int* ti, int* tj,
-                                                int tt = GT) {
-  int tm = cdiv(m, tt), tn = cdiv(n, tt);
-  if (!upper) { *ti = t / tn; *tj = t % tn; return; }
-  for (int i = 0; i < tm; ++i) {
-    int row = tn - i;
-    if (row <= 0) break;
-    if (t < row) { *ti = i; *tj = i + t; return; }
-    t -= row;
-  }
-  *ti = 0; *tj = 0;
 }
 
 }  // namespace dg

@@ -351,23 +351,16 @@ struct dgdft_alb {
 
   void gram(const std::vector<int>& act, const GramArgs& g, bool fp32 = false) {
     auto K = [&](int e) { return g.use_ne ? eh[e].ne : eh[e].ng; };
-    // 144 x 144 tiles (upper triangle, carried tiles skipped) when every
-    // operand's column count is a multiple of 144; else dg_gram_w, 128 rows
-    // x tile_edge(n) columns, whose carried products form only the columns
-    // after the carried block (the grid is planned for the full product,
-    // which also covers elements that carry nothing)
-    bool t144 = !act.empty();
-    for (int e : act) {
-      t144 = t144 && cols_host(g.A, e) % GTT == 0;
-      for (int j = 0; j < g.njob; ++j) t144 = t144 && cols_host(g.B[j], e) % GTT == 0;
-    }
+    // dg_gram_w: 128 rows x tile_edge(n) columns; carried products form only
+    // the columns after the carried block (the grid is planned for the full
+    // product, which also covers elements that carry nothing)
     GramArgs ga = g;
-    ga.tail = (!t144 && g.carry) ? 1 : 0;
+    ga.tail = g.carry ? 1 : 0;
     auto P = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
       for (int j = 0; j < g.njob; ++j) {
         const int n = cols_host(g.B[j], e);
-        c += t144 ? gram_tiles(m, n, g.upper, GTT) : cdiv(m, GT) * cdiv(n, tile_edge(n));
+        c += cdiv(m, GT) * cdiv(n, tile_edge(n));
       }
       return c * gram_nchunk_e(eh[e], K(e));
     });
@@ -393,12 +386,8 @@ struct dgdft_alb {
       }
     }
     pbeg(DGDFT_K_GRAM, fl, by);
-    if (t144)
-      hipLaunchKernelGGL(fp32 ? dg_gram_t14432 : dg_gram_t144, dim3(P.total), dim3(GRAM144_THREADS), 0,
-                         stream, ed, P.active, P.prefix, P.na, ga);
-    else
-      hipLaunchKernelGGL(fp32 ? dg_gram_w32 : dg_gram_w, dim3(P.total), dim3(256), 0, stream, ed, P.active,
-                         P.prefix, P.na, ga);
+    hipLaunchKernelGGL(fp32 ? dg_gram_w32 : dg_gram_w, dim3(P.total), dim3(256), 0, stream, ed, P.active,
+                       P.prefix, P.na, ga);
     pend();
     auto R = make_prefix(act, [&](int e) {
       int m = cols_host(g.A, e), c = 0;
@@ -2356,8 +2345,7 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
     for (int i = 0; i < count; ++i) {
       act[i] = i;
       if (trans) {
-        pre[i + 1] = pre[i] + ((m % GTT == 0 && n % GTT == 0) ? gram_tiles(m, n, 0, GTT)
-                                                              : cdiv(m, GT) * cdiv(n, tile_edge(n))) * nch;
+        pre[i + 1] = pre[i] + cdiv(m, GT) * cdiv(n, tile_edge(n)) * nch;
         pre2[i + 1] = pre2[i] + cdiv(m * n, 256);
       } else {
         pre[i + 1] = pre[i] + cdiv((int)K, GT) * cdiv(n, tile_edge(n));
@@ -2372,12 +2360,8 @@ int32_t dgdft_gemm_batched(int32_t trans, int32_t count, int64_t K, int32_t m, i
     if (trans) {
       GramArgs g{};
       g.A = oa; g.B[0] = ob; g.njob = 1; g.out_mat[0] = 0; g.upper = 0;
-      if (m % GTT == 0 && n % GTT == 0)
-        hipLaunchKernelGGL(fp32 ? dg_gram_t14432 : dg_gram_t144, dim3(pre[count]), dim3(GRAM144_THREADS), 0, s,
-                           ed, d_act, d_pre, count, g);
-      else
-        hipLaunchKernelGGL(fp32 ? dg_gram_w32 : dg_gram_w, dim3(pre[count]), dim3(256), 0, s, ed, d_act,
-                           d_pre, count, g);
+      hipLaunchKernelGGL(fp32 ? dg_gram_w32 : dg_gram_w, dim3(pre[count]), dim3(256), 0, s, ed, d_act,
+                         d_pre, count, g);
       hipLaunchKernelGGL(dg_gram_reduce, dim3(pre2[count]), dim3(256), 0, s, ed, d_act, d_pre2, count, g);
     } else {
       UpdArgs u{};

@@ -37,8 +37,8 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 template <class T> struct Mf;
 template <> struct Mf<double> {
   typedef dbl4 acc;
-  static constexpr int pad = 4;      // LDS row padding (elements)
-  static constexpr int pad144 = 4;
+  static constexpr int pad = 4;      // LDS row padding (elements), 128-wide stages
+  static constexpr int pad144 = 4;   // 144-wide stages
   __device__ static __forceinline__ acc zero() { return (dbl4){0.0, 0.0, 0.0, 0.0}; }
   __device__ static __forceinline__ acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -60,12 +60,12 @@ struct GramArgs {
   Opnd A, B[2];
   int njob;        // 1 or 2 products sharing A
   int out_mat[2];  // small-workspace matrix receiving each product
-  int upper;       // only tiles touching the upper triangle
+  int upper;       // symmetric product (formed in full; the upper triangle is read)
   int use_ne;      // K = rows of the restriction box instead of N_g
-  int carry;       // skip tiles inside the leading block carried from the last step
-  // dg_gram_w: with a carried leading block (carried_cols(e) > 0), form only
-  // the columns of B after it and write them to the last columns of the
-  // m x m result (set by the host when it launches dg_gram_w for g.carry)
+  int carry;       // the leading block is carried from the last step (see tail)
+  // with a carried leading block (carried_cols(e) > 0), form only the
+  // columns of B after it and write them to the last columns of the m x m
+  // result (set by the host for products with g.carry)
   int tail;
 };
 
@@ -248,142 +248,6 @@ extern "C" __global__ void __launch_bounds__(256, 2)
 dg_gram_w32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
             int na, GramArgs g) {
   dg_gram_w_body<float>(E, active, prefix, na, g);
-}
-
-// The same product with 144 x 144 tiles, for operands whose column counts
-// are multiples of 144 (blocks of 144 states): nine waves in a 3 x 3 grid,
-// each owning 48 x 48 (3 x 3 MFMA blocks), upper triangle only for
-// symmetric products; tiles wholly inside a carried block are skipped.
-// Chunks, staging and partial sums follow dg_gram_w.
-constexpr int GTT = 144;       // tile edge of dg_gram_t144
-constexpr int GLP = GTT + 4;
-constexpr int GRAM144_THREADS = 576;
-
-template <class T>
-__device__ __forceinline__ void dg_gram_t144_body(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-             int na, GramArgs g) {
-  constexpr int GLPT = GTT + Mf<T>::pad144;
-
-  __shared__ T As[2][KS * GLPT];
-  __shared__ T Bs[2][KS * GLPT];
-  __shared__ const double* colA[GTT];
-  __shared__ const double* colB[GTT];
-  int blk = blockIdx.x;
-  int ai = find_elem(prefix, na, blk);
-  const Elem& e = E[active[ai]];
-  int w = blk - prefix[ai];
-  const int K = rowsK(e, g.use_ne);
-  const int m = opnd_cols(g.A, e);
-  const int nch = gram_nchunk_e(e, K), clen = gram_chunklen(K, nch);
-  const int n0 = opnd_cols(g.B[0], e);
-  int job = 0, n = n0;
-  int ntile = gram_tiles(m, n, g.upper, GTT);
-  if (w >= ntile * nch) {
-    job = 1;
-    w -= ntile * nch;
-    n = opnd_cols(g.B[1], e);
-    ntile = gram_tiles(m, n, g.upper, GTT);
-  }
-  if (job >= g.njob || ntile == 0 || w >= ntile * nch) return;
-  const Opnd& B = g.B[job];
-  int chunk = w / ntile, tile = w - chunk * ntile;
-  int ti, tj;
-  gram_tile_decode(tile, m, n, g.upper, &ti, &tj, GTT);
-  if (g.carry) {
-    const int kc = carried_cols(e);
-    if ((ti + 1) * GTT <= kc && (tj + 1) * GTT <= kc) return;
-  }
-  const int kbeg = chunk * clen;
-  const int kend = min(K, kbeg + clen);
-  const int tid = threadIdx.x;
-  if (tid < GTT) {
-    int c = ti * GTT + tid;
-    colA[tid] = c < m ? opnd_col(g.A, e, c) : nullptr;
-  } else if (tid < 2 * GTT) {
-    int c = tj * GTT + tid - GTT;
-    colB[tid - GTT] = c < n ? opnd_col(B, e, c) : nullptr;
-  }
-  __syncthreads();
-  // stage loads: k = tid % 16, columns tid/16 + 36u (u < 4)
-  const int lk = tid & 15, lc = tid >> 4;
-  double ra[4], rb[4];
-  auto load = [&](int k0) {
-    int k = k0 + lk;
-    bool kin = k < kend;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double* pa = colA[lc + 36 * u];
-      const double* pb = colB[lc + 36 * u];
-      ra[u] = (kin && pa) ? pa[k] : 0.0;
-      rb[u] = (kin && pb) ? pb[k] : 0.0;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      As[buf][lk * GLPT + lc + 36 * u] = ra[u];
-      Bs[buf][lk * GLPT + lc + 36 * u] = rb[u];
-    }
-  };
-  const int lane = tid & 63, wv = tid >> 6;
-  const int wi = wv % 3, wj = wv / 3;
-  const bool live = ti * GTT + wi * 48 < m && tj * GTT + wj * 48 < n;
-  typename Mf<T>::acc acc[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) acc[a][c] = Mf<T>::zero();
-  const int nst = (kend - kbeg + KS - 1) / KS;
-  if (nst > 0) {
-    load(kbeg);
-    store(0);
-    __syncthreads();
-  }
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) load(kbeg + (st + 1) * KS);
-    if (live) {
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        T fa[3], fb[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) fa[a] = As[cur][kk * GLPT + wi * 48 + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fb[c] = Bs[cur][kk * GLPT + wj * 48 + c * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            acc[a][c] = Mf<T>::mma(fa[a], fb[c], acc[a][c]);
-      }
-    }
-    if (st + 1 < nst) store(cur ^ 1);
-    __syncthreads();
-  }
-  double* part = e.gpart + (job ? (long long)nch * m * n0 : 0LL) + (long long)chunk * m * n;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int i = ti * GTT + wi * 48 + a * 16 + Mf<T>::row(r, lane);
-        int j = tj * GTT + wj * 48 + c * 16 + (lane & 15);
-        if (i < m && j < n) part[i + (long long)m * j] = (double)acc[a][c][r];
-      }
-}
-
-extern "C" __global__ void __launch_bounds__(GRAM144_THREADS)
-dg_gram_t144(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-             int na, GramArgs g) {
-  dg_gram_t144_body<double>(E, active, prefix, na, g);
-}
-
-extern "C" __global__ void __launch_bounds__(GRAM144_THREADS)
-dg_gram_t14432(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-             int na, GramArgs g) {
-  dg_gram_t144_body<float>(E, active, prefix, na, g);
 }
 
 // Sum split-K partials into sm(e, out_mat[job]) (ld = m).  Work item: a
