@@ -28,6 +28,8 @@ namespace dg {
 constexpr int FFT_THREADS = 512;        // xy passes
 constexpr int FFT_Z_THREADS = 512;      // z pass
 constexpr int FFT_MAXPTS = 4608;        // largest LDS tile (72 KiB): z pencils of a row pair
+// (kernels with the 72 KiB tile ask for four waves per SIMD, i.e. at most 128
+// registers per lane, so that two workgroups share a compute unit)
 constexpr int FFT_XY_SMALL = 2304;      // xy planes up to 48 x 48 use a 36 KiB tile
 
 // Exact division of small unsigned values (b * d < 2^32) by a multiply-high
@@ -195,6 +197,7 @@ __device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, in
   const bool by_line = lstride == 1;
   const unsigned dv = by_line ? (unsigned)nlines : nb;
   const unsigned m_dv = div_magic(dv), m_ns = div_magic(Ns);
+  const int step = n / (Ns * R);
   C v[MAXK][R];
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
@@ -208,7 +211,6 @@ __device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, in
     }
   }
   __syncthreads();
-  const int step = n / (Ns * R);
 #pragma unroll
   for (int q = 0; q < MAXK; ++q) {
     unsigned b = threadIdx.x + q * NT;
@@ -219,7 +221,7 @@ __device__ __forceinline__ void stage(C* buf, int n, int nlines, int lstride, in
       int k = j - jq * Ns;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        C w = tw[k * r * step];
+        C w = gld(tw + k * r * step);
         if (sgn > 0) w.y = -w.y;
         v[q][r] = cmul(v[q][r], w);
       }
@@ -279,13 +281,27 @@ __device__ __forceinline__ void fft_xy_fwd_body(C* buf, Elem* __restrict__ E,
   bool hasb = cb < col0 + nc;
   const double* A = bp(e, slot) + (long long)ca * e.ld + (long long)z * np;
   const double* B = bp(e, slot) + (long long)cb * e.ld + (long long)z * np;
-  for (int p = threadIdx.x; p < np; p += FFT_THREADS)
-    buf[p] = cmake<C>(A[p], hasb ? B[p] : 0.0);
+  {
+    // all of a lane's loads in flight before the first LDS write
+    constexpr int NL = (MAXPTS + FFT_THREADS - 1) / FFT_THREADS;
+    double ra[NL], rb[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int p = threadIdx.x + u * FFT_THREADS;
+      ra[u] = p < np ? gld(A + p) : 0.0;
+      rb[u] = (p < np && hasb) ? gld(B + p) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int p = threadIdx.x + u * FFT_THREADS;
+      if (p < np) buf[p] = cmake<C>(ra[u], rb[u]);
+    }
+  }
   __syncthreads();
   fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), -1.0);
   fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), -1.0);
   C* Z = zpair<C>(e, q) + (long long)z * np;
-  for (int p = threadIdx.x; p < np; p += FFT_THREADS) Z[p] = buf[p];
+  for (int p = threadIdx.x; p < np; p += FFT_THREADS) gst(Z + p, buf[p]);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS)
@@ -302,14 +318,14 @@ dg_fft_xy_fwd32(Elem* __restrict__ E, const int* __restrict__ active, const int*
   fft_xy_fwd_body<FFT_XY_SMALL>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_fwd_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int slot, int col0, int ncols) {
   __shared__ double2 buf[FFT_MAXPTS];
   fft_xy_fwd_body<FFT_MAXPTS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_fwd32_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                   int na, int slot, int col0, int ncols) {
   __shared__ float2 buf[FFT_MAXPTS];
@@ -343,11 +359,24 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     s = r >= n1;
     x = r - s * n1;
   };
-  for (int p = threadIdx.x; p < npts; p += NT) {
-    int z, s, x;
-    split(p, z, s, x);
-    int row = s ? rb : ra;
-    buf[p] = Z[(long long)z * n1 * n2 + row * n1 + x];
+  {
+    constexpr int NL = (FFT_MAXPTS + NT - 1) / NT;
+    C rz[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int p = threadIdx.x + u * NT;
+      if (p < npts) {
+        int z, s, x;
+        split(p, z, s, x);
+        int row = s ? rb : ra;
+        rz[u] = gld(Z + (long long)z * n1 * n2 + row * n1 + x);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int p = threadIdx.x + u * NT;
+      if (p < npts) buf[p] = rz[u];
+    }
   }
   __syncthreads();
   fft_lines<FFT_MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), -1.0);
@@ -368,7 +397,7 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     const int nc = ncols < 0 ? e.J : ncols;
     int ca = col0 + 2 * q, cb = ca + 1;
     bool hasb = cb < col0 + nc;
-    const double ita = 1.0 / e.tkin[ca], itb = hasb ? 1.0 / e.tkin[cb] : ita;
+    const double ita = 1.0 / gld(e.tkin + ca), itb = hasb ? 1.0 / gld(e.tkin + cb) : ita;
     constexpr int PPT = (FFT_MAXPTS + NT - 1) / NT;
     C nv[PPT];
 #pragma unroll
@@ -382,9 +411,9 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
         double t = 0.5 * (k1 * k1 + k2 * k2 + k3 * k3);
         double Ka = teter_k(t * ita), Kb = hasb ? teter_k(t * itb) : Ka;
         if (mode == 3) {
-          int sh = e.shell_of[(long long)z * n1 * n2 + row * n1 + x];
-          Ka *= e.gain[(long long)ca * e.nsh + sh];
-          Kb = hasb ? Kb * e.gain[(long long)cb * e.nsh + sh] : Ka;
+          int sh = gld(e.shell_of + (long long)z * n1 * n2 + row * n1 + x);
+          Ka *= gld(e.gain + (long long)ca * e.nsh + sh);
+          Kb = hasb ? Kb * gld(e.gain + (long long)cb * e.nsh + sh) : Ka;
         }
         // mirror point (-m1, -m2, -m3): the other row slot (or the same)
         int zm = z ? n3 - z : 0, xm = x ? n1 - x : 0;
@@ -407,18 +436,18 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     int z, s, x;
     split(p, z, s, x);
     int row = s ? rb : ra;
-    Z[(long long)z * n1 * n2 + row * n1 + x] = buf[p];
+    gst(Z + (long long)z * n1 * n2 + row * n1 + x, buf[p]);
   }
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS, 4)
 dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
          int na, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_MAXPTS];
   fft_z_body<FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS, 4)
 dg_fft_z32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
            int na, int col0, int ncols, int mode) {
   __shared__ float2 buf[FFT_MAXPTS];
@@ -441,7 +470,20 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
   int q = w / e.n3, z = w - q * e.n3;
   int n1 = e.n1, n2 = e.n2, np = n1 * n2;
   const C* Z = zpair<C>(e, q) + (long long)z * np;
-  for (int p = threadIdx.x; p < np; p += FFT_THREADS) buf[p] = Z[p];
+  {
+    constexpr int NL = (MAXPTS + FFT_THREADS - 1) / FFT_THREADS;
+    C rz[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int p = threadIdx.x + u * FFT_THREADS;
+      if (p < np) rz[u] = gld(Z + p);
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int p = threadIdx.x + u * FFT_THREADS;
+      if (p < np) buf[p] = rz[u];
+    }
+  }
   __syncthreads();
   fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), 1.0);
   fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), 1.0);
@@ -459,37 +501,39 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
     const int* kp = e.kbt_ptr;
     const double* pa = e.proj + (long long)(ca - col0) * e.n_proj;
     const double* pb = e.proj + (long long)(cb - col0) * e.n_proj;
+    const int* kbp = e.kbt_p;
+    const double* kbc = e.kbt_c;
     for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
       const C r = buf[p];
-      double v = V[p];
-      double ya = sc * r.x + v * IA[p];
-      double yb = hasb ? sc * r.y + v * IB[p] : 0.0;
+      double v = gld(V + p);
+      double ya = sc * r.x + v * gld(IA + p);
+      double yb = hasb ? sc * r.y + v * gld(IB + p) : 0.0;
       if (kp) {
         // entries of this point four at a time, so that their loads overlap
         int g = (int)(off + p);
-        int t = kp[g];
-        const int t1 = kp[g + 1];
+        int t = gld(kp + g);
+        const int t1 = gld(kp + g + 1);
         for (; t + 4 <= t1; t += 4) {
-          int p0 = e.kbt_p[t], p1 = e.kbt_p[t + 1], p2 = e.kbt_p[t + 2], p3 = e.kbt_p[t + 3];
-          double c0 = e.kbt_c[t], c1 = e.kbt_c[t + 1], c2 = e.kbt_c[t + 2], c3 = e.kbt_c[t + 3];
-          ya += c0 * pa[p0] + c1 * pa[p1] + c2 * pa[p2] + c3 * pa[p3];
-          if (hasb) yb += c0 * pb[p0] + c1 * pb[p1] + c2 * pb[p2] + c3 * pb[p3];
+          int p0 = gld(kbp + t), p1 = gld(kbp + t + 1), p2 = gld(kbp + t + 2), p3 = gld(kbp + t + 3);
+          double c0 = gld(kbc + t), c1 = gld(kbc + t + 1), c2 = gld(kbc + t + 2), c3 = gld(kbc + t + 3);
+          ya += c0 * gld(pa + p0) + c1 * gld(pa + p1) + c2 * gld(pa + p2) + c3 * gld(pa + p3);
+          if (hasb) yb += c0 * gld(pb + p0) + c1 * gld(pb + p1) + c2 * gld(pb + p2) + c3 * gld(pb + p3);
         }
         for (; t < t1; ++t) {
-          int pr = e.kbt_p[t];
-          double c = e.kbt_c[t];
-          ya += c * pa[pr];
-          if (hasb) yb += c * pb[pr];
+          int pr = gld(kbp + t);
+          double c = gld(kbc + t);
+          ya += c * gld(pa + pr);
+          if (hasb) yb += c * gld(pb + pr);
         }
       }
-      OA[p] = ya;
-      if (hasb) OB[p] = yb;
+      gst(OA + p, ya);
+      if (hasb) gst(OB + p, yb);
     }
   } else {
     for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
       const C r = buf[p];
-      OA[p] = sc * r.x;
-      if (hasb) OB[p] = sc * r.y;
+      gst(OA + p, sc * r.x);
+      if (hasb) gst(OB + p, sc * r.y);
     }
   }
 }
@@ -508,14 +552,14 @@ dg_fft_xy_inv32(Elem* __restrict__ E, const int* __restrict__ active, const int*
   fft_xy_inv_body<FFT_XY_SMALL>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_inv_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_MAXPTS];
   fft_xy_inv_body<FFT_MAXPTS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
+extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_inv32_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                   int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ float2 buf[FFT_MAXPTS];
@@ -542,10 +586,10 @@ dg_kb_project(Elem* __restrict__ E, const int* __restrict__ active, const int* _
 #pragma unroll
   for (int k = 0; k < KB_GMAX; ++k) acc[k] = 0.0;
   for (int s = s0 + threadIdx.x; s < s1; s += 256) {
-    double xv = x[e.grp_idx[s]];
+    double xv = gld(x + gld(e.grp_idx + s));
     const double* vv = e.grp_val + (long long)s * KB_GMAX;
 #pragma unroll
-    for (int k = 0; k < KB_GMAX; ++k) acc[k] += vv[k] * xv;
+    for (int k = 0; k < KB_GMAX; ++k) acc[k] += gld(vv + k) * xv;
   }
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll

@@ -18,6 +18,8 @@
 // lane l holds A[l%16][l/16], B-fragment lane l holds B[l/16][l%16], and
 // accumulator register r of lane l holds D[4*r + l/16][l%16] (checked on the
 // device with one-hot operands).
+#include <type_traits>
+
 #include "common.h"
 
 namespace dg {
@@ -32,13 +34,14 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 // chunks).  Both take operand lane l as A[l%16][l/16] and B[l/16][l%16]; the
 // accumulator layouts differ (measured on the device with one-hot operands):
 // FP64 register r of lane l holds D[4r + l/16][l%16], FP32 register r holds
-// D[4(l/16) + r][l%16].  Padded LDS rows keep the two 16-lane halves of a
-// fragment read on disjoint banks.
+// D[4(l/16) + r][l%16].  An odd FP64 row padding puts the sixteen k-rows
+// that a 16-lane group writes when a stage is staged (lane = k) on distinct
+// banks; a fragment read (lane = column) is contiguous either way.
 template <class T> struct Mf;
 template <> struct Mf<double> {
   typedef dbl4 acc;
-  static constexpr int pad = 4;      // LDS row padding (elements), 128-wide stages
-  static constexpr int pad144 = 4;   // 144-wide stages
+  static constexpr int pad = 1;      // LDS row padding (elements), 128-wide stages
+  static constexpr int pad144 = 1;   // 144-wide stages
   __device__ static __forceinline__ acc zero() { return (dbl4){0.0, 0.0, 0.0, 0.0}; }
   __device__ static __forceinline__ acc mma(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -97,6 +100,14 @@ __device__ __forceinline__ int rowsK(const Elem& e, int use_ne) { return use_ne 
 // are loaded from global memory into registers while stage s is multiplied
 // out of LDS (double buffered, one barrier per stage).  Column pointers of
 // the block operands are resolved once per workgroup into an LDS table.
+// A pointer that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ const double* uniform_ptr(const double* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (const double*)(((unsigned long long)hi << 32) | lo);
+}
+
 constexpr int TT = 128;        // row tile of the Gram and update products
 constexpr int KS = 16;         // K stage
 constexpr int UTN = 144;       // largest column tile
@@ -163,79 +174,111 @@ __device__ __forceinline__ void dg_gram_w_body(Elem* __restrict__ E, const int* 
   if (tid < UTN) colB[tid] = tid < tcols ? opnd_col(B, e, boff + tj * tn + tid) : nullptr;
   __syncthreads();
   // stage loads: k = tid % 16; A columns tid/16 + 16u (u < 8), B columns
-  // tid/16 + 16v (v < 9)
+  // tid/16 + 16v (v < NB).  The column pointers are read once.  Loads are
+  // unconditional (a missing column reads the tile's first column, k is
+  // clamped into the chunk, the last stage reloads itself); the values of
+  // missing columns and of k past the chunk become zero when the stage is
+  // written to LDS, at the end of the next stage's products, so a load has
+  // a whole stage of products to arrive.
   const int lk = tid & 15, lc = tid >> 4;
-  double ra[8], rb[9];
-  auto load = [&](int k0) {
-    const int k = k0 + lk;
-    const bool kin = k < kend;
+  const double* pa[8];
+  const double* pb[9];
+  unsigned live = 0;                          // bit u (A) / 8 + v (B): column exists
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double* pa = colA[lc + 16 * u];
-      ra[u] = (kin && pa) ? pa[k] : 0.0;
-    }
+  for (int u = 0; u < 8; ++u) {
+    const double* c = colA[lc + 16 * u];
+    live |= (c != nullptr) << u;
+    pa[u] = c ? c : colA[0];
+  }
 #pragma unroll
-    for (int v = 0; v < 9; ++v) {
-      const double* pb = colB[lc + 16 * v];
-      rb[v] = (kin && pb) ? pb[k] : 0.0;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) As[buf][lk * LPA + lc + 16 * u] = ra[u];
-#pragma unroll
-    for (int v = 0; v < 9; ++v) Bs[buf][lk * LPB + lc + 16 * v] = rb[v];
-  };
+  for (int v = 0; v < 9; ++v) {
+    const double* c = colB[lc + 16 * v];
+    live |= (c != nullptr) << (8 + v);
+    pb[v] = c ? c : colB[0];
+  }
   const int lane = tid & 63, wr = tid >> 6;
-  const int nra = max(0, min(2, cdiv(trows - wr * 32, 16)));   // live row blocks of this wave
-  const int nbc = min(9, cdiv(tcols, 16));                      // live column blocks
-  typename Mf<T>::acc acc[2][9];
-#pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int a = 0; a < 9; ++a) acc[c][a] = Mf<T>::zero();
+  // wave-uniform: rows of this wave in the tile, MFMA column blocks of the tile
+  const int nrow = __builtin_amdgcn_readfirstlane(trows - wr * 32);
+  const int nbc = __builtin_amdgcn_readfirstlane(min(9, cdiv(tcols, 16)));
   const int nst = (kend - kbeg + KS - 1) / KS;
-  if (nst > 0) {
-    load(kbeg);
-    store(0);
-    __syncthreads();
-  }
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) load(kbeg + (st + 1) * KS);
-    if (nra > 0) {
-#pragma unroll
-      for (int ks = 0; ks < KS / 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        T fa[2], fb[9];
-#pragma unroll
-        for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPA + wr * 32 + c * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) fb[a] = Bs[cur][kk * LPB + a * 16 + (lane & 15)];
-#pragma unroll
-        for (int a = 0; a < 9; ++a)
-          if (a < nbc) {
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-              if (c < nra) acc[c][a] = Mf<T>::mma(fa[c], fb[a], acc[c][a]);
-          }
-      }
-    }
-    if (st + 1 < nst) store(cur ^ 1);
-    __syncthreads();
-  }
   double* part = e.gpart + (job ? (long long)nch * m * n0 : 0LL) + (long long)chunk * m * n;
+  // NB column blocks per tile, fixed at compile time so that the products
+  // run without per-block branches (a wave with one live row block computes
+  // the second on zero rows)
+  auto run = [&](auto nbt) {
+    constexpr int NB = decltype(nbt)::value;
+    double ra[8], rb[NB];
+    auto load = [&](int k0) {
+      const int k = min(k0 + lk, kend - 1);
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
+      for (int u = 0; u < 8; ++u) ra[u] = gld(pa[u] + k);
 #pragma unroll
-    for (int a = 0; a < 9; ++a)
+      for (int v = 0; v < NB; ++v) rb[v] = gld(pb[v] + k);
+    };
+    auto store = [&](int buf, int k0) {
+      const bool kin = k0 + lk < kend;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int il = wr * 32 + c * 16 + Mf<T>::row(r, lane);
-        const int jl = a * 16 + (lane & 15);
-        if (il < trows && jl < tcols)
-          part[(ti * TT + il) + (long long)m * (tj * tn + jl)] = (double)acc[c][a][r];
+      for (int u = 0; u < 8; ++u)
+        As[buf][lk * LPA + lc + 16 * u] = (T)((kin && ((live >> u) & 1)) ? ra[u] : 0.0);
+#pragma unroll
+      for (int v = 0; v < NB; ++v)
+        Bs[buf][lk * LPB + lc + 16 * v] = (T)((kin && ((live >> (8 + v)) & 1)) ? rb[v] : 0.0);
+    };
+    typename Mf<T>::acc acc[2][NB];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int a = 0; a < NB; ++a) acc[c][a] = Mf<T>::zero();
+    if (nst > 0) {
+      load(kbeg);
+      store(0, kbeg);
+      __syncthreads();
+    }
+    for (int st = 0; st < nst; ++st) {
+      const int cur = st & 1;
+      const int knext = kbeg + min(st + 1, nst - 1) * KS;
+      load(knext);
+      if (nrow > 0) {
+#pragma unroll
+        for (int ks = 0; ks < KS / 4; ++ks) {
+          const int kk = ks * 4 + (lane >> 4);
+          T fa[2], fb[NB];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPA + wr * 32 + c * 16 + (lane & 15)];
+#pragma unroll
+          for (int a = 0; a < NB; ++a) fb[a] = Bs[cur][kk * LPB + a * 16 + (lane & 15)];
+#pragma unroll
+          for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[c][a] = Mf<T>::mma(fa[c], fb[a], acc[c][a]);
+        }
       }
+      if (st + 1 < nst) store(cur ^ 1, knext);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int il = wr * 32 + c * 16 + Mf<T>::row(r, lane);
+          const int jl = a * 16 + (lane & 15);
+          if (il < trows && jl < tcols)
+            gst(part + (ti * TT + il) + (long long)m * (tj * tn + jl), (double)acc[c][a][r]);
+        }
+  };
+  switch (nbc) {
+    case 1: run(std::integral_constant<int, 1>{}); break;
+    case 2: run(std::integral_constant<int, 2>{}); break;
+    case 3: run(std::integral_constant<int, 3>{}); break;
+    case 4: run(std::integral_constant<int, 4>{}); break;
+    case 5: run(std::integral_constant<int, 5>{}); break;
+    case 6: run(std::integral_constant<int, 6>{}); break;
+    case 7: run(std::integral_constant<int, 7>{}); break;
+    case 8: run(std::integral_constant<int, 8>{}); break;
+    default: run(std::integral_constant<int, 9>{}); break;
+  }
 }
 
 extern "C" __global__ void __launch_bounds__(256, 2)
@@ -322,7 +365,6 @@ __device__ __forceinline__ void dg_update_w_body(Elem* __restrict__ E, const int
   const double* C = sm(e, u.cmat) + (long long)u.ccol0 * e.J * cld + (long long)u.crow0 * e.J;
   const int row0 = tr * TT, col0 = tc * tw;
   const int tcols = min(tw, ncol - col0);        // columns of this tile
-  const int nbc = min(9, cdiv(tcols, 16));       // its MFMA column blocks
   const int tid = threadIdx.x;
   if (tid == 0) {
     if (A.ncols >= 0) {
@@ -342,105 +384,145 @@ __device__ __forceinline__ void dg_update_w_body(Elem* __restrict__ E, const int
   __syncthreads();
   const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
   const long long ld = e.ld;
-  // A stage: row = tid % 128, k = tid / 128 + 2q (q < UKS/2)
-  const int ar = tid & 127, ak = tid >> 7;
-  // C stage: k = tid % 16, j = tid / 16 + 16v (v < 9)
+  // block base pointers in scalar registers (the block index of a load is
+  // the same for a whole wave)
+  const double* ab0 = uniform_ptr(abase[0]);
+  const double* ab1 = uniform_ptr(abase[1]);
+  const double* ab2 = uniform_ptr(abase[2]);
+  const double* ab3 = uniform_ptr(abase[3]);
+  const double* ab4 = uniform_ptr(abase[4]);
+  const double* ab5 = uniform_ptr(abase[5]);
+  auto ablk = [&](int bb) {
+    return bb <= 2 ? (bb == 0 ? ab0 : bb == 1 ? ab1 : ab2) : (bb == 3 ? ab3 : bb == 4 ? ab4 : ab5);
+  };
+  // A stage: row = tid % 128, k = tid / 128 + 2q (q < UKS/2): k is the same
+  // for a whole wave.  C stage: k = tid % 16, j = tid / 16 + 16v (v < NB).
+  // Loads are unconditional (rows, k and columns clamped into range); values
+  // out of range become zero when the stage is written to LDS, at the end of
+  // the next stage's products, so a load has a whole stage to arrive.
+  const int ar = tid & 127;
+  const int ak = __builtin_amdgcn_readfirstlane(tid >> 7);
   const int ck = tid & 15, cj = tid >> 4;
   const bool rin = row0 + ar < K;
-  double ra[UPD_NQ], rc[9];
-  auto load = [&](int k0, int kend) {
-#pragma unroll
-    for (int q = 0; q < UPD_NQ; ++q) {
-      int k = k0 + ak + 2 * q;
-      double v = 0.0;
-      if (k < kend && rin) {
-        int bb = k / bcols;
-        v = abase[bb][(long long)(k - bb * bcols) * ld + row0 + ar];
-      }
-      ra[q] = v;
-    }
-#pragma unroll
-    for (int v = 0; v < 9; ++v) {
-      const int jl = cj + 16 * v;
-      int kc = k0 + ck;
-      rc[v] = (kc < kend && jl < tcols) ? C[kc + (long long)cld * (col0 + jl)] : 0.0;
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < UPD_NQ; ++q) As[buf][(ak + 2 * q) * LPT + ar] = ra[q];
-#pragma unroll
-    for (int v = 0; v < 9; ++v) Cs[buf][ck * LPCT + cj + 16 * v] = rc[v];
-  };
+  const int arow = row0 + (rin ? ar : 0);
   const int lane = tid & 63, wr = tid >> 6;
-  typename Mf<T>::acc acc[9][2];
-#pragma unroll
-  for (int a = 0; a < 9; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = Mf<T>::zero();
+  const int nbc = __builtin_amdgcn_readfirstlane(min(9, cdiv(tcols, 16)));
   // stages: with split, columns J..kA-1 of A (nst0 stages), then 0..J-1
   const int J = e.J;
   const int nst0 = u.split ? cdiv(kA - J, UKS) : 0;
   const int nst = nst0 + cdiv(u.split ? J : kA, UKS);
   auto kbeg = [&](int st) { return st < nst0 ? J + st * UKS : (st - nst0) * UKS; };
   auto kend = [&](int st) { return st < nst0 ? kA : (u.split ? J : kA); };
-  load(kbeg(0), kend(0));
-  store(0);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    if (st + 1 < nst) load(kbeg(st + 1), kend(st + 1));
+  // (scalars copied out of the argument block: the products below are a
+  // lambda, and a reference to the by-value argument would put it on the stack)
+  const double alpha = u.alpha, beta = u.beta;
+  auto run = [&](auto nbt) {
+    constexpr int NB = decltype(nbt)::value;
+    double ra[UPD_NQ], rc[NB];
+    auto load = [&](int k0, int ke) {
+      // clamped k of each q (non-decreasing, steps of 0..2), its block bb and
+      // column kc within the block (bcols >= 1: at most two wraps a step)
+      int kl = min(k0 + ak, ke - 1);
+      int bb = kl / bcols, kc = kl - bb * bcols;
 #pragma unroll
-    for (int ks = 0; ks < UKS / 4; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
-      T fc[9], fa[2];
+      for (int q = 0; q < UPD_NQ; ++q) {
+        ra[q] = gld(ablk(bb) + (long long)kc * ld + arow);
+        const int kn = min(k0 + ak + 2 * (q + 1), ke - 1);
+        kc += kn - kl;
+        kl = kn;
+        if (kc >= bcols) { kc -= bcols; ++bb; }
+        if (kc >= bcols) { kc -= bcols; ++bb; }
+      }
+      const int kcc = min(k0 + ck, ke - 1);
 #pragma unroll
-      for (int a = 0; a < 9; ++a) fc[a] = Cs[cur][kk * LPCT + a * 16 + (lane & 15)];
+      for (int v = 0; v < NB; ++v) {
+        const int jl = min(cj + 16 * v, tcols - 1);
+        rc[v] = gld(C + kcc + (long long)cld * (col0 + jl));
+      }
+    };
+    auto store = [&](int buf, int k0, int ke) {
 #pragma unroll
-      for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPT + wr * 32 + c * 16 + (lane & 15)];
+      for (int q = 0; q < UPD_NQ; ++q)
+        As[buf][(ak + 2 * q) * LPT + ar] = (T)((rin && k0 + ak + 2 * q < ke) ? ra[q] : 0.0);
+      const bool kin = k0 + ck < ke;
 #pragma unroll
-      for (int a = 0; a < 9; ++a)
-        if (a < nbc) {
+      for (int v = 0; v < NB; ++v)
+        Cs[buf][ck * LPCT + cj + 16 * v] = (T)((kin && cj + 16 * v < tcols) ? rc[v] : 0.0);
+    };
+    typename Mf<T>::acc acc[NB][2];
 #pragma unroll
-          for (int c = 0; c < 2; ++c)
-            acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
-        }
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[a][c] = Mf<T>::zero();
+    if (nst > 0) {
+      load(kbeg(0), kend(0));
+      store(0, kbeg(0), kend(0));
+      __syncthreads();
     }
-    if (st == nst0 - 1) {   // [P W] part complete: Y2 = alpha [P W] C[J:]
+    for (int st = 0; st < nst; ++st) {
+      const int cur = st & 1;
+      const int sn = min(st + 1, nst - 1);     // the last stage reloads itself
+      load(kbeg(sn), kend(sn));
 #pragma unroll
-      for (int a = 0; a < 9; ++a)
+      for (int ks = 0; ks < UKS / 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        T fc[NB], fa[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          double* y2 = colY2[a * 16 + Mf<T>::row(r, lane)];
-          if (!y2) continue;
+        for (int a = 0; a < NB; ++a) fc[a] = Cs[cur][kk * LPCT + a * 16 + (lane & 15)];
 #pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            int row = row0 + wr * 32 + c * 16 + (lane & 15);
-            if (row < K) y2[row] = u.alpha * (double)acc[a][c][r];
+        for (int c = 0; c < 2; ++c) fa[c] = As[cur][kk * LPT + wr * 32 + c * 16 + (lane & 15)];
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) acc[a][c] = Mf<T>::mma(fc[a], fa[c], acc[a][c]);
+      }
+      if (st == nst0 - 1) {   // [P W] part complete: Y2 = alpha [P W] C[J:]
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double* y2 = colY2[a * 16 + Mf<T>::row(r, lane)];
+            if (!y2) continue;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              int row = row0 + wr * 32 + c * 16 + (lane & 15);
+              if (row < K) gst(y2 + row, alpha * (double)acc[a][c][r]);
+            }
+          }
+      }
+      if (st + 1 < nst) store(cur ^ 1, kbeg(st + 1), kend(st + 1));
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int jl = a * 16 + Mf<T>::row(r, lane);
+        double* y = colY[jl];
+        if (!y) continue;
+        const double* zc = colZ[jl];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          int row = row0 + wr * 32 + c * 16 + (lane & 15);
+          if (row < K) {
+            double v = alpha * (double)acc[a][c][r];
+            if (beta != 0.0) v += beta * gld(zc ? zc + row : y + row);
+            gst(y + row, v);
           }
         }
-    }
-    if (st + 1 < nst) store(cur ^ 1);
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 9; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int jl = a * 16 + Mf<T>::row(r, lane);
-      double* y = colY[jl];
-      if (!y) continue;
-      const double* zc = colZ[jl];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        int row = row0 + wr * 32 + c * 16 + (lane & 15);
-        if (row < K) {
-          double v = u.alpha * (double)acc[a][c][r];
-          if (u.beta != 0.0) v += u.beta * (zc ? zc[row] : y[row]);
-          y[row] = v;
-        }
       }
-    }
+  };
+  switch (nbc) {
+    case 1: run(std::integral_constant<int, 1>{}); break;
+    case 2: run(std::integral_constant<int, 2>{}); break;
+    case 3: run(std::integral_constant<int, 3>{}); break;
+    case 4: run(std::integral_constant<int, 4>{}); break;
+    case 5: run(std::integral_constant<int, 5>{}); break;
+    case 6: run(std::integral_constant<int, 6>{}); break;
+    case 7: run(std::integral_constant<int, 7>{}); break;
+    case 8: run(std::integral_constant<int, 8>{}); break;
+    default: run(std::integral_constant<int, 9>{}); break;
+  }
 }
 
 extern "C" __global__ void __launch_bounds__(256, 2)

@@ -326,7 +326,7 @@ dg_carry_in(Elem* __restrict__ E, const int* __restrict__ active, int na) {
 // workgroup holds 8, so above order 512 it would take the three-pass form).
 constexpr int EIG_WIDE_MIN = 513;
 constexpr int EIG_WIDE_MAX = 832;
-constexpr int EIG_WIDE_THREADS = 512;
+constexpr int EIG_WIDE_THREADS = 1024;
 
 __host__ __device__ inline bool eig_wide(int n) { return n >= EIG_WIDE_MIN && n <= EIG_WIDE_MAX; }
 

@@ -19,6 +19,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include "gmem.h"
 
 namespace dg {
 
@@ -444,92 +445,140 @@ __host__ __device__ int syev(T& t, double* A, int lda, int n, double* w, double*
 // ---------------------------------------------------------------------------
 // Faster pieces for the Rayleigh-Ritz step (lowest k of n eigenpairs).
 
+// Sum over the 64 lanes of a wave, returned in every lane: DPP moves within
+// rows of 16 lanes (lane ^ 1, lane ^ 2, then the mirrors within 8 and 16
+// lanes), then two shuffles across rows.  Every lane adds the same operands
+// in the same order, so all lanes hold the same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  int lo = __double2loint(x), hi = __double2hiint(x);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Shapes of the one-pass tridiagonalisation (rows per lane in chunks of 64,
+// columns per wave pass, row groups) for workgroups of 1024 lanes: orders up
+// to 512, and 513..832; and the columns per wave of the back-transformation
+// for orders 513..832.
+#define TRI_R 2
+#define TRI_U 2
+#define TRI_H 4
+#define TRI_WIDE_R 4
+#define TRI_WIDE_U 2
+#define TRI_WIDE_H 4
+#define BT_WIDE_U 1
+
 // Device fast path of tridiagonalize_lower with one pass over the trailing
 // block per Householder step: the rank-2 update left by reflector k-1 and the
 // symmetric product of reflector k (p = tk A2 v) read and write every entry
 // of A2 = A[k+1:, k+1:] once.  Column k itself is updated first, separately,
 // since reflector k is built from it.  Each entry gets the same operations in
-// the same order as with a separate product pass and update pass, so the
-// outputs are those of that two-pass form.  Each lane keeps R rows
-// (m <= 64 R) of both reflectors, q and its share of the row sums in
-// registers; each wave takes U columns per pass so that their loads are in
-// flight together; per-wave partial sums are added in a fixed order.  v, p:
-// n doubles each; scratch: (waves + 2) * n doubles (column parts, per-wave
-// row parts, second v buffer).
-template <int R, int U, class T>
+// the same order as with a separate product pass and update pass.  The waves
+// form H row groups x (waves / H) column groups: row group h owns the
+// 64-row chunks h, h + H, h + 2H, ... (R chunks, m <= 64 H R), and each lane
+// keeps its rows of both reflectors, q and its share of the row sums in
+// registers; a wave takes U columns per pass and loads the next pass's
+// columns before working on the current ones, so that a pass's loads are in
+// flight while the previous pass computes.  Chunks wholly above a column's
+// diagonal or below the block are skipped.  Outputs, for the caller to add in
+// a fixed order: column parts (sum over a row group's rows i >= j of
+// A2[i][j] v[i]) at scratch[h n + j], row parts (sum over a column group's
+// columns j < i of A2[i][j] v[j]) at scratch[(H + c) n + i].  v, p: n doubles
+// each; scratch: (waves + 2) * n doubles (parts, second v buffer).
+template <int R, int U, int H, class T>
 __device__ __forceinline__ void tri_fused_pass(T& t, double* A2, int lda, int n, int m,
                                                const double* v, const double* vo,
                                                const double* qo, bool upd, double* scratch) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-  double* pc = scratch;
-  double* part = scratch + n;
+  const int h = wv % H, c = wv / H, nc = nw / H;
+  double* pc = scratch + (long long)h * n;
+  double* part = scratch + (long long)(H + c) * n;
   double vr[R], acc[R], vor[R], qor[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    int i = lane + 64 * r;
+    const int i = 64 * (h + H * r) + lane;
     vr[r] = i < m ? v[i] : 0.0;
     vor[r] = (upd && i < m) ? vo[i] : 0.0;
     qor[r] = (upd && i < m) ? qo[i] : 0.0;
     acc[r] = 0.0;
   }
-  for (int j0 = wv; j0 < m; j0 += U * nw) {
-    double x[U][R], vj[U], sm[U], voj[U], qoj[U];
-    int jj[U];
-    bool has[U];
+  const int step = U * nc;
+  double xn[U][R];
+  auto fetch = [&](int j0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      jj[u] = j0 + u * nw;
-      has[u] = jj[u] < m;
-      vj[u] = has[u] ? v[jj[u]] : 0.0;
-      voj[u] = (upd && has[u]) ? vo[jj[u]] : 0.0;
-      qoj[u] = (upd && has[u]) ? qo[jj[u]] : 0.0;
-      const double* col = A2 + (long long)lda * (has[u] ? jj[u] : j0);
+      const int j = j0 + u * nc;
+      const double* col = A2 + (long long)lda * (j < m ? j : 0);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        int i = lane + 64 * r;
-        x[u][r] = (has[u] && i >= jj[u] && i < m) ? col[i] : 0.0;
+        const int cb = 64 * (h + H * r), i = cb + lane;
+        double a = 0.0;
+        if (j < m && cb + 63 >= j && cb < m) {     // wave-uniform chunk test
+          if (i >= j && i < m) a = gld(col + i);
+        }
+        xn[u][r] = a;
       }
     }
-    if (upd) {
+  };
+  if (c < m) fetch(c);
+  for (int j0 = c; j0 < m; j0 += step) {
+    double x[U][R], vj[U], sm[U], voj[U], qoj[U];
+    int jj[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        double* col = A2 + (long long)lda * (has[u] ? jj[u] : j0);
+    for (int u = 0; u < U; ++u) {
+      jj[u] = j0 + u * nc;
+      const bool has = jj[u] < m;
+      vj[u] = has ? v[jj[u]] : 0.0;
+      voj[u] = (upd && has) ? vo[jj[u]] : 0.0;
+      qoj[u] = (upd && has) ? qo[jj[u]] : 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          int i = lane + 64 * r;
-          if (has[u] && i >= jj[u] && i < m) {
-            x[u][r] -= vor[r] * qoj[u] + qor[r] * voj[u];
-            col[i] = x[u][r];
+      for (int r = 0; r < R; ++r) x[u][r] = xn[u][r];
+    }
+    if (j0 + step < m) fetch(j0 + step);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sm[u] = 0.0;
+      const int j = jj[u];
+      double* col = A2 + (long long)lda * (j < m ? j : 0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int cb = 64 * (h + H * r), i = cb + lane;
+        if (j < m && cb + 63 >= j && cb < m) {
+          if (i >= j && i < m) {
+            double a = x[u][r];
+            if (upd) {
+              a -= vor[r] * qoj[u] + qor[r] * voj[u];
+              gst(col + i, a);
+            }
+            sm[u] += a * vr[r];
+            if (i > j) acc[r] += a * vj[u];
           }
         }
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      sm[u] = 0.0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        int i = lane + 64 * r;
-        if (has[u] && i >= jj[u] && i < m) {
-          sm[u] += x[u][r] * vr[r];
-          if (i > jj[u]) acc[r] += x[u][r] * vj[u];
-        }
-      }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) sm[u] += __shfl_xor(sm[u], o, 64);
-    }
+    for (int u = 0; u < U; ++u) sm[u] = wave_sum_dpp(sm[u]);
     if (lane == 0) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (has[u]) pc[jj[u]] = sm[u];
+        if (jj[u] < m) pc[jj[u]] = sm[u];
     }
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    int i = lane + 64 * r;
-    if (i < m) part[(long long)wv * n + i] = acc[r];
+    const int i = 64 * (h + H * r) + lane;
+    if (i < m) part[i] = acc[r];
   }
 }
 
@@ -547,12 +596,12 @@ __device__ __forceinline__ void tri_rank2_tail(T& t, double* B, int lda, int mm,
   t.sync();
 }
 
-template <int R, int U, class T>
+template <int R, int U, int H, class T>
 __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d, double* e,
                                      double* tau, double* v, double* p, double* scratch) {
   const int nw = (t.nt() + 63) >> 6;
   double* vcur = v;
-  double* vold = scratch + (long long)(nw + 1) * n;
+  double* vold = scratch + (long long)(H + nw / H) * n;   // after the parts
   bool pend = false;   // reflector k-1's update of A[k:, k:] not yet applied (vold, q in p)
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
@@ -563,10 +612,10 @@ __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d,
       const double vo0 = pend ? vold[0] : 0.0, qo0 = pend ? p[0] : 0.0;
       for (int r = t.tid(); r <= m; r += t.nt()) {
         int i = r + 2 <= m ? r + 2 : r - (m - 1);     // rows 2.. first, then 0 and 1
-        double a = colk[i];
+        double a = gld(colk + i);
         if (pend) {
           a -= vold[i] * qo0 + p[i] * vo0;
-          colk[i] = a;
+          gst(colk + i, a);
         }
         if (i >= 2) {
           vcur[i - 1] = a;
@@ -575,7 +624,7 @@ __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d,
       }
     }
     double a2 = t.sum(part);
-    double x0 = colk[1];
+    double x0 = gld(colk + 1);
     if (a2 == 0.0) {
       if (t.tid() == 0) { e[k] = x0; tau[k] = 0.0; }
       if (pend) tri_rank2_tail(t, &IDX(A, lda, k + 1, k + 1), lda, m, vold + 1, p + 1);
@@ -589,16 +638,15 @@ __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d,
     double tk = 2.0 / (v0 * v0 + a2);
     if (t.tid() == 0) vcur[0] = v0;
     t.sync();                                       // every lane has read x0
-    if (t.tid() == 0) { colk[1] = v0; e[k] = beta; tau[k] = tk; }
+    if (t.tid() == 0) { gst(colk + 1, v0); e[k] = beta; tau[k] = tk; }
     double* A2 = &IDX(A, lda, k + 1, k + 1);
-    tri_fused_pass<R, U>(t, A2, lda, n, m, vcur, vold + 1, p + 1, pend, scratch);
+    tri_fused_pass<R, U, H>(t, A2, lda, n, m, vcur, vold + 1, p + 1, pend, scratch);
     t.sync();
     {
-      const double* pc = scratch;
-      const double* pw = scratch + n;
+      const int nparts = H + nw / H;     // H column parts, then the row parts
       for (int i = t.tid(); i < m; i += t.nt()) {
-        double s = pc[i];
-        for (int w = 0; w < nw; ++w) s += pw[(long long)w * n + i];
+        double s = 0.0;
+        for (int w = 0; w < nparts; ++w) s += scratch[(long long)w * n + i];
         p[i] = s;
       }
     }
@@ -626,8 +674,8 @@ __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d,
 // Householder tridiagonalisation reading and updating only the lower
 // triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
 // scratch of n doubles each (LDS on the device).
-// WIDE: instantiate the wide-register device path (13 rows per lane, two
-// columns per wave pass, n <= 832), for workgroups of at most 512 lanes whose
+// WIDE: instantiate the wide-register device path (two row groups of up to
+// 7 chunks of 64 rows, n <= 832), for workgroups of at most 512 lanes whose
 // 256 registers per lane hold it.
 template <bool WIDE = false, class T>
 __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
@@ -635,21 +683,19 @@ __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, d
                                               double* scratch = nullptr, int scratch_size = 0) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
   if constexpr (T::is_device && WIDE) {
-    if (n <= 64 * 13 && scratch && (nw + 2) * n <= scratch_size) {
-      if (n <= 64 * 10) tridiagonalize_fused<10, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
-      else tridiagonalize_fused<13, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
+    if (n <= 64 * 13 && nw % TRI_WIDE_H == 0 && scratch &&
+        (TRI_WIDE_H + nw / TRI_WIDE_H + 1) * n <= scratch_size) {
+      tridiagonalize_fused<TRI_WIDE_R, TRI_WIDE_U, TRI_WIDE_H>(t, A, lda, n, d, e, tau, v, p, scratch);
       return;
     }
   }
   // Device path (tridiagonalize_fused) for n <= 512 with (waves + 2) * n
-  // doubles of LDS scratch: 6 rows per lane and two columns per wave pass up
-  // to n = 384, else 7 or 8 rows per lane and one column per pass (the
-  // registers of a 1024-lane workgroup hold no more without spilling).
+  // doubles of LDS scratch: two row groups of up to 4 chunks of 64 rows, two
+  // columns per wave pass (within the 128 registers per lane of a 1024-lane
+  // workgroup).
   if constexpr (T::is_device) {
-    if (n <= 64 * 8 && scratch && (nw + 2) * n <= scratch_size) {
-      if (n <= 64 * 6) tridiagonalize_fused<6, 2>(t, A, lda, n, d, e, tau, v, p, scratch);
-      else if (n <= 64 * 7) tridiagonalize_fused<7, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
-      else tridiagonalize_fused<8, 1>(t, A, lda, n, d, e, tau, v, p, scratch);
+    if (n <= 64 * 8 && nw % TRI_H == 0 && scratch && (TRI_H + nw / TRI_H + 1) * n <= scratch_size) {
+      tridiagonalize_fused<TRI_R, TRI_U, TRI_H>(t, A, lda, n, d, e, tau, v, p, scratch);
       return;
     }
   }
@@ -1071,15 +1117,18 @@ template <int R, int U, class T>
 __device__ __forceinline__ void bt_fast(T& t, const double* A, int lda, const double* tau, int n,
                                         double* Z, int ldz, int k, double* lds, int lds_size) {
   const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
-  int NB = lds_size / n;
+  // reflector block in lds[0, NB n), its tau values in lds[NB n, NB n + NB)
+  int NB = (lds_size - 16) / n;
   NB = NB > 16 ? 16 : NB;
+  double* tl = lds + (long long)NB * n;
   for (int kb = n - 3; kb >= 0; kb -= NB) {
     int kl = kb - NB + 1 > 0 ? kb - NB + 1 : 0;   // reflectors kb, kb-1, ..., kl
     // stage reflectors: lds[(kk - kl) * n + i] = v_kk[i] (zero above k+1)
     for (int q = t.tid(); q < (kb - kl + 1) * n; q += t.nt()) {
       int kk = kl + q / n, i = q % n;
-      lds[q] = (i >= kk + 1) ? A[(long long)i + (long long)lda * kk] : 0.0;
+      lds[q] = (i >= kk + 1) ? gld(A + (long long)i + (long long)lda * kk) : 0.0;
     }
+    for (int q = t.tid(); q < kb - kl + 1; q += t.nt()) tl[q] = gld(tau + kl + q);
     t.sync();
     for (int j0 = wv; j0 < k; j0 += U * nw) {
       double z[U][R];
@@ -1089,11 +1138,11 @@ __device__ __forceinline__ void bt_fast(T& t, const double* A, int lda, const do
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           int i = lane + 64 * r;
-          z[u][r] = (j < k && i < n) ? Z[(long long)i + (long long)ldz * j] : 0.0;
+          z[u][r] = (j < k && i < n) ? gld(Z + (long long)i + (long long)ldz * j) : 0.0;
         }
       }
       for (int kk = kb; kk >= kl; --kk) {
-        double tk = tau[kk];
+        double tk = tl[kk - kl];
         if (tk == 0.0) continue;
         const double* v = lds + (kk - kl) * n;
         double vv[R], s[U];
@@ -1111,10 +1160,8 @@ __device__ __forceinline__ void bt_fast(T& t, const double* A, int lda, const do
             if (i < n) s[u] += vv[r] * z[u][r];
           }
         }
-        for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) s[u] += __shfl_xor(s[u], o, 64);
-        }
+        for (int u = 0; u < U; ++u) s[u] = wave_sum_dpp(s[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           s[u] *= tk;
@@ -1132,7 +1179,7 @@ __device__ __forceinline__ void bt_fast(T& t, const double* A, int lda, const do
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           int i = lane + 64 * r;
-          if (i < n) Z[(long long)i + (long long)ldz * j] = z[u][r];
+          if (i < n) gst(Z + (long long)i + (long long)ldz * j, z[u][r]);
         }
       }
     }
@@ -1144,12 +1191,12 @@ template <bool WIDE = false, class T>
 __host__ __device__ void backtransform(T& t, const double* A, int lda, const double* tau, int n,
                                        double* Z, int ldz, int k, double* lds, int lds_size) {
   if constexpr (T::is_device && WIDE) {
-    if (lds_size >= n && n <= 64 * 13) { bt_fast<13, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+    if (lds_size >= n + 16 && n <= 64 * 13) { bt_fast<13, BT_WIDE_U>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
   }
   if constexpr (T::is_device) {
-    if (lds_size >= n && n <= 64 * 6) { bt_fast<6, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
-    if (lds_size >= n && n <= 64 * 7) { bt_fast<7, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
-    if (lds_size >= n && n <= 64 * 12) { bt_fast<12, 1>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+    if (lds_size >= n + 16 && n <= 64 * 6) { bt_fast<6, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+    if (lds_size >= n + 16 && n <= 64 * 7) { bt_fast<7, 2>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
+    if (lds_size >= n + 16 && n <= 64 * 12) { bt_fast<12, 1>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size); return; }
   }
   // generic path
   double* cs = lds;
