@@ -382,7 +382,7 @@ __device__ __forceinline__ void dg_update_w_body(Elem* __restrict__ E, const int
     colZ[tid] = (u.Z[job].nblk > 0 && cin) ? opnd_col(u.Z[job], e, col0 + tid) : nullptr;
   }
   __syncthreads();
-  const int bcols = A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J;
+  const int bcols = __builtin_amdgcn_readfirstlane(A.ncols >= 0 ? (A.ncols > 0 ? A.ncols : 1) : e.J);
   const long long ld = e.ld;
   // block base pointers in scalar registers (the block index of a load is
   // the same for a whole wave)
@@ -422,6 +422,9 @@ __device__ __forceinline__ void dg_update_w_body(Elem* __restrict__ E, const int
     auto load = [&](int k0, int ke) {
       // clamped k of each q (non-decreasing, steps of 0..2), its block bb and
       // column kc within the block (bcols >= 1: at most two wraps a step)
+      // (all of it wave-uniform: scalar registers and scalar branches)
+      k0 = __builtin_amdgcn_readfirstlane(k0);
+      ke = __builtin_amdgcn_readfirstlane(ke);
       int kl = min(k0 + ak, ke - 1);
       int bb = kl / bcols, kc = kl - bb * bcols;
 #pragma unroll
