@@ -600,7 +600,9 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = (dbl4){0.0, 0.0, 0.0, 0.0};
   // stage k0 -> registers (op(A) tile contiguous along i when ta == 0,
-  // along kk when ta == 1; op(B) along kk when tb == 0, along j when tb == 1)
+  // along kk when ta == 1; op(B) along kk when tb == 0, along j when tb == 1).
+  // Loads are unconditional at indices clamped into the matrices; entries
+  // outside become zero when the stage is written to LDS.
   double ra[4], rb[4];
   auto load = [&](int k0) {
 #pragma unroll
@@ -609,37 +611,36 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
       int f = el & 63, s16 = el >> 6;  // f: 64-long fast index, s16: 16-long
       int g = el & 15, s64 = el >> 4;  // g: 16-long fast index, s64: 64-long
       int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
-      ra[q] = (i0 + ii < M && k0 + kk < K)
-                  ? (a.ta ? A[(k0 + kk) + (long long)lda * (i0 + ii)] : A[(i0 + ii) + (long long)lda * (k0 + kk)])
-                  : 0.0;
+      const int i = min(i0 + ii, M - 1), k = min(k0 + kk, K - 1);
+      ra[q] = gld(a.ta ? A + k + (long long)lda * i : A + i + (long long)lda * k);
       int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
-      rb[q] = (j0 + jj < N && k0 + kb < K)
-                  ? (a.tb ? B[(j0 + jj) + (long long)ldb * (k0 + kb)] : B[(k0 + kb) + (long long)ldb * (j0 + jj)])
-                  : 0.0;
+      const int j = min(j0 + jj, N - 1), kq = min(k0 + kb, K - 1);
+      rb[q] = gld(a.tb ? B + j + (long long)ldb * kq : B + kq + (long long)ldb * j);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int el = tid + 256 * q;
       int f = el & 63, s16 = el >> 6;
       int g = el & 15, s64 = el >> 4;
       int ii = a.ta ? s64 : f, kk = a.ta ? g : s16;
-      As[buf][kk * 65 + ii] = ra[q];
+      As[buf][kk * 65 + ii] = (i0 + ii < M && k0 + kk < K) ? ra[q] : 0.0;
       int jj = a.tb ? f : s64, kb = a.tb ? s16 : g;
-      Bs[buf][kb * 65 + jj] = rb[q];
+      Bs[buf][kb * 65 + jj] = (j0 + jj < N && k0 + kb < K) ? rb[q] : 0.0;
     }
   };
-  // double-buffered K stages, the next one prefetched into registers
+  // double-buffered K stages, the next one prefetched into registers (the
+  // last stage reloads itself)
   const int nst = (K + 15) / 16;
   if (nst > 0) {
     load(0);
-    store(0);
+    store(0, 0);
   }
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    if (st + 1 < nst) load(16 * (st + 1));
+    load(16 * min(st + 1, nst - 1));
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       int kk = ks * 4 + (lane >> 4);
@@ -652,7 +653,7 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
       acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
-    if (st + 1 < nst) store(cur ^ 1);
+    if (st + 1 < nst) store(cur ^ 1, 16 * (st + 1));
     __syncthreads();
   }
 #pragma unroll
@@ -665,7 +666,7 @@ dg_sgemm(Elem* __restrict__ E, const int* __restrict__ active, const int* __rest
         int j = j0 + wj * 32 + y * 16 + (lane & 15);
         if (i < M && j < N) {
           double* c = C + i + (long long)ldc * j;
-          *c = a.alpha * acc[x][y][r] + (a.beta != 0.0 ? a.beta * *c : 0.0);
+          gst(c, a.alpha * acc[x][y][r] + (a.beta != 0.0 ? a.beta * gld(c) : 0.0));
         }
       }
 }
