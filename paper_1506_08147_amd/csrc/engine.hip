@@ -601,9 +601,21 @@ struct dgdft_alb {
     HCHECK(hipGetLastError());
     HCHECK(hipEventRecord(g_auxdone[cur_g], stream));
     stream = main;
+    // orders 513..832: the tridiagonalisation over TRI_NWG workgroups per
+    // element, one launch per Householder step up to the largest order an
+    // element can have (3 J, or J on X alone; an element past its own order
+    // returns at once), then the rest of the eigensolver
+    int nmax = 0;
+    for (int e : act) {
+      const int nb = (single ? 1 : 3) * eh[e].J;
+      if (nb >= EIG_WIDE_MIN) nmax = std::max(nmax, std::min(nb, EIG_WIDE_MAX));
+    }
     pbeg(DGDFT_K_RR, 0, 0);
-    hipLaunchKernelGGL(dg_rr_eig_wide, dim3(P.na), dim3(EIG_WIDE_THREADS), 0, stream, ed, P.active, P.na,
-                       single);
+    for (int k = 0; k + 2 <= nmax; ++k)
+      hipLaunchKernelGGL(dg_tri_step, dim3(P.na * TRI_NWG), dim3(TRI_STEP_THREADS), 0, stream, ed,
+                         P.active, P.na, single, k);
+    hipLaunchKernelGGL(dg_rr_eig_wide_rest, dim3(P.na), dim3(EIG_WIDE_THREADS), 0, stream, ed, P.active,
+                       P.na, single);
     pend();
     HCHECK(hipGetLastError());
     HCHECK(hipStreamWaitEvent(stream, g_auxdone[cur_g], 0));
@@ -1811,6 +1823,17 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
   // whose fresh residual is still above tol goes back to the iteration
   // (without P) while it has iterations left.
   std::vector<int> pending = all;
+  // Stall guard: an element whose largest running residual has not reached a
+  // new minimum for STALL_ITERS iterations leaves the iteration for the FP64
+  // check (fresh H X, Rayleigh-Ritz on X).  The running H X is carried by
+  // the update products, not recomputed, so near the tolerance, after
+  // dropped P blocks and Cholesky reductions of ill-conditioned bases, its
+  // drift can hold the running residuals above the tolerance while X itself
+  // has converged; the check measures X directly and sends the element back
+  // (without P, from a fresh H X) if it has not.
+  constexpr int STALL_ITERS = 4;
+  std::vector<double> best(n, 1e300);
+  std::vector<int> since(n, 0);
   // Mixed form: iterate first to max(tol, MIXED_REFRESH), refresh H X in FP64
   // (the check below), then iterate to tol: what the FP32 transforms left in
   // H X is then scaled by corrections of the size of the residual.
@@ -1835,8 +1858,11 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
         h->set_group(g);
         h->poll();
         std::vector<int> next;
-        for (int e : act[g])
-          if (!(h->max_res(e) <= target || iters[e] >= max_iter)) next.push_back(e);
+        for (int e : act[g]) {
+          const double r = h->max_res(e);
+          if (r < best[e]) { best[e] = r; since[e] = 0; } else { ++since[e]; }
+          if (!(r <= target || iters[e] >= max_iter || since[e] >= STALL_ITERS)) next.push_back(e);
+        }
         act[g].swap(next);
         if (act[g].empty()) continue;
         any = true;
@@ -1874,7 +1900,11 @@ static Status solve_impl(dgdft_alb* h, const double* X0, double* eigvals, double
     h->phase_mark(3);
     std::vector<int> again;
     for (int e : pending)
-      if (!(h->max_res(e) <= tol) && iters[e] < max_iter) again.push_back(e);
+      if (!(h->max_res(e) <= tol) && iters[e] < max_iter) {
+        again.push_back(e);
+        best[e] = 1e300;
+        since[e] = 0;
+      }
     pending.swap(again);
     target = tol;
   }
@@ -2207,10 +2237,13 @@ static bool syev_args_ok(int32_t count, int32_t n, int32_t k, const double* A, c
 
 static void launch_syev(int32_t count, int32_t n, int32_t k, const double* A, double* w, double* Z,
                         int32_t method, double* work, hipStream_t s) {
-  if (method == 0 && eig_wide(n))
-    hipLaunchKernelGGL(dg_syev_batch_wide, dim3(count), dim3(EIG_WIDE_THREADS), 0, s, A, w, Z, n, k,
-                       work);
-  else
+  if (method == 0 && eig_wide(n)) {
+    hipLaunchKernelGGL(dg_syev_batch_copy, dim3(count), dim3(256), 0, s, A, n, k, work);
+    for (int st = 0; st + 2 <= n; ++st)
+      hipLaunchKernelGGL(dg_tri_step_batch, dim3(count * TRI_NWG), dim3(TRI_STEP_THREADS), 0, s, n, k, work,
+                         st);
+    hipLaunchKernelGGL(dg_syev_batch_wide_rest, dim3(count), dim3(EIG_WIDE_THREADS), 0, s, w, Z, n, k, work);
+  } else
     hipLaunchKernelGGL(dg_syev_batch, dim3(count), dim3(SMALL_THREADS), 0, s, A, w, Z, n, k, work,
                        method);
   HCHECK(hipGetLastError());

@@ -330,7 +330,7 @@ constexpr int EIG_WIDE_THREADS = 1024;
 
 __host__ __device__ inline bool eig_wide(int n) { return n >= EIG_WIDE_MIN && n <= EIG_WIDE_MAX; }
 
-template <bool WIDE>
+template <bool WIDE, bool PRE = false>
 __device__ __forceinline__ void rr_eig_body(Elem* __restrict__ E, const int* __restrict__ active,
                                             int single, double* red, double* lds) {
   DevTeam t{red};
@@ -345,7 +345,7 @@ __device__ __forceinline__ void rr_eig_body(Elem* __restrict__ E, const int* __r
   double* vec = sm(e, SM_V);
   double* w = vec + 7 * n;
   // workspace: SM_W0 and SM_W1 (consecutive)
-  syev_lowest<WIDE>(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, EIG_LDS);
+  syev_lowest<WIDE, PRE>(t, A, n, n, J, w, Z, n, sm(e, SM_W0), (int*)(vec + 10 * n), lds, EIG_LDS);
 }
 
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
@@ -360,6 +360,31 @@ dg_rr_eig_wide(Elem* __restrict__ E, const int* __restrict__ active, int na, int
   __shared__ double red[32];
   __shared__ double lds[EIG_LDS];
   rr_eig_body<true>(E, active, single, red, lds);
+}
+
+// The tridiagonalisation of the dg_rr_eig_wide elements spread over TRI_NWG
+// workgroups each, one launch per Householder step k (see tri_step), and the
+// rest of their eigensolver after it.
+constexpr int TRI_STEP_LDS = 4 * EIG_WIDE_MAX + 4 * (EIG_WIDE_MAX / TRI_NWG + 1);
+
+extern "C" __global__ void __launch_bounds__(TRI_STEP_THREADS)
+dg_tri_step(Elem* __restrict__ E, const int* __restrict__ active, int na, int single, int k) {
+  __shared__ double red[32];
+  __shared__ double lds[TRI_STEP_LDS];
+  DevTeam t{red};
+  const int ai = blockIdx.x / TRI_NWG, w = blockIdx.x - ai * TRI_NWG;
+  const Elem& e = E[active[ai]];
+  if (e.fl[FL_RR_PATH] == 1) return;
+  const int n = (single ? 1 : (has_p(e) ? 3 : 2)) * e.J;
+  if (!eig_wide(n)) return;
+  tri_step(t, sm(e, SM_A), n, n, k, w, sm(e, SM_W0), lds);
+}
+
+extern "C" __global__ void __launch_bounds__(EIG_WIDE_THREADS)
+dg_rr_eig_wide_rest(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
+  __shared__ double red[32];
+  __shared__ double lds[EIG_LDS];
+  rr_eig_body<true, true>(E, active, single, red, lds);
 }
 
 // Path 3: T = I - E/2 + 3 E^2/8 - 5 E^3/16 from E (SM_L), E^2 (SM_U) and
@@ -862,10 +887,32 @@ dg_syev_batch(const double* __restrict__ A, double* w, double* Z, int n, int k, 
   }
 }
 
-// method 0 for orders EIG_WIDE_MIN..EIG_WIDE_MAX on the wide-register path of
-// dg_rr_eig_wide (same layout as dg_syev_batch).
+// Method 0 for orders EIG_WIDE_MIN..EIG_WIDE_MAX (same layout as
+// dg_syev_batch) in three parts: copy, one launch per Householder step over
+// TRI_NWG workgroups per matrix, the rest of the eigensolver.
+extern "C" __global__ void __launch_bounds__(256)
+dg_syev_batch_copy(const double* __restrict__ A, int n, int k, double* work) {
+  __shared__ double red[32];
+  DevTeam t{red};
+  long long b = blockIdx.x;
+  double* Aw = work + b * (2LL * n * n + 8LL * n + 6LL * n * k);
+  copy_mat(t, A + b * n * n, n, Aw, n, n, n);
+  sym_from_upper(t, Aw, n, n);
+}
+
+extern "C" __global__ void __launch_bounds__(TRI_STEP_THREADS)
+dg_tri_step_batch(int n, int k, double* work, int step) {
+  __shared__ double red[32];
+  __shared__ double lds[TRI_STEP_LDS];
+  DevTeam t{red};
+  const long long b = blockIdx.x / TRI_NWG;
+  const int w = (int)(blockIdx.x - b * TRI_NWG);
+  double* Aw = work + b * (2LL * n * n + 8LL * n + 6LL * n * k);
+  tri_step(t, Aw, n, n, step, w, Aw + (long long)n * n, lds);
+}
+
 extern "C" __global__ void __launch_bounds__(EIG_WIDE_THREADS)
-dg_syev_batch_wide(const double* __restrict__ A, double* w, double* Z, int n, int k, double* work) {
+dg_syev_batch_wide_rest(double* w, double* Z, int n, int k, double* work) {
   __shared__ double red[32];
   __shared__ double lds[EIG_LDS];
   DevTeam t{red};
@@ -873,8 +920,6 @@ dg_syev_batch_wide(const double* __restrict__ A, double* w, double* Z, int n, in
   double* Aw = work + b * (2LL * n * n + 8LL * n + 6LL * n * k);
   double* U = Aw + (long long)n * n;
   double* vec = U + (long long)n * n;
-  copy_mat(t, A + b * n * n, n, Aw, n, n, n);
-  sym_from_upper(t, Aw, n, n);
-  syev_lowest<true>(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, EIG_LDS);
+  syev_lowest<true, true>(t, Aw, n, n, k, w + b * n, Z + b * n * k, n, U, (int*)vec, lds, EIG_LDS);
 }
 }  // namespace dg

@@ -671,6 +671,226 @@ __device__ void tridiagonalize_fused(T& t, double* A, int lda, int n, double* d,
   t.sync();
 }
 
+// ---------------------------------------------------------------------------
+// The same one-pass tridiagonalisation spread over TRI_NWG workgroups of
+// TRI_STEP_THREADS lanes per matrix, one kernel launch per Householder step k
+// (launches k = 0 .. n - 2).  A launch never waits for another workgroup:
+// every workgroup of a matrix recomputes the small per-step vectors itself
+// from what the previous launch left in device memory (double-buffered by
+// the parity of k):
+//   phase A  reflector k-1 (vbuf) and the parts of p = A v (pcol, prow) ->
+//            q_{k-1} = t p - (t/2)(v.t p) v, the update still pending on the
+//            trailing block; workgroup 0 stores reflector k-1 into column
+//            k-1 of A, where the back-transformation reads it;
+//   phase B  column k with the pending update -> reflector k (d[k], e[k],
+//            tau[k], vbuf written by workgroup 0);
+//   phase C  the workgroup's columns j = w, w + TRI_NWG, ... of the trailing
+//            block A[k+1:, k+1:]: pending update applied and stored, column
+//            parts (rows i >= j) and row parts (columns j < i) of A v.
+// Launch n - 2 applies the last pending update to the 2 x 2 tail.  Each
+// entry gets the operations of the single-workgroup form; sums are taken in
+// another order.  work: d, e, tau (3 n) then the step buffers (20 n).
+constexpr int TRI_NWG = 8;
+constexpr int TRI_STEP_THREADS = 256;
+constexpr int TRI_STEP_R = 4;      // 64-row chunks per lane (4 row groups): n <= 1024
+constexpr int TRI_STEP_U = 2;      // columns per wave pass
+
+__host__ __device__ inline int tri_step_lds(int n) { return 4 * n + 4 * (n / TRI_NWG + 1); }
+__host__ __device__ inline long long tri_step_work(int n) { return (long long)(3 + 4 + 2 * TRI_NWG) * n; }
+
+template <int R, int U, class T>
+__device__ __forceinline__ void tri_step_pass(T& t, double* A2, int lda, int n, int m, int w,
+                                              const double* v, const double* vo, const double* qo,
+                                              bool upd, double* pcl, double* prow_out,
+                                              double* pcol_out) {
+  const int lane = t.tid() & 63, h = t.tid() >> 6;            // row group h of 4
+  const int ncw = w < m ? (m - w + TRI_NWG - 1) / TRI_NWG : 0;  // this workgroup's columns
+  const int NCW = n / TRI_NWG + 1;
+  double vr[R], acc[R], vor[R], qor[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = 64 * (h + 4 * r) + lane;
+    vr[r] = i < m ? v[i] : 0.0;
+    vor[r] = (upd && i < m) ? vo[i] : 0.0;
+    qor[r] = (upd && i < m) ? qo[i] : 0.0;
+    acc[r] = 0.0;
+  }
+  double xn[U][R];
+  auto fetch = [&](int t0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int j = w + TRI_NWG * (t0 + u);
+      const double* col = A2 + (long long)lda * (j < m ? j : 0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int cb = 64 * (h + 4 * r), i = cb + lane;
+        double a = 0.0;
+        if (j < m && cb + 63 >= j && cb < m) {     // wave-uniform chunk test
+          if (i >= j && i < m) a = gld(col + i);
+        }
+        xn[u][r] = a;
+      }
+    }
+  };
+  if (ncw > 0) fetch(0);
+  for (int t0 = 0; t0 < ncw; t0 += U) {
+    double x[U][R], vj[U], sm[U], voj[U], qoj[U];
+    int jj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      jj[u] = w + TRI_NWG * (t0 + u);
+      const bool has = jj[u] < m;
+      vj[u] = has ? v[jj[u]] : 0.0;
+      voj[u] = (upd && has) ? vo[jj[u]] : 0.0;
+      qoj[u] = (upd && has) ? qo[jj[u]] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[u][r] = xn[u][r];
+    }
+    if (t0 + U < ncw) fetch(t0 + U);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sm[u] = 0.0;
+      const int j = jj[u];
+      double* col = A2 + (long long)lda * (j < m ? j : 0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int cb = 64 * (h + 4 * r), i = cb + lane;
+        if (j < m && cb + 63 >= j && cb < m) {
+          if (i >= j && i < m) {
+            double a = x[u][r];
+            if (upd) {
+              a -= vor[r] * qoj[u] + qor[r] * voj[u];
+              gst(col + i, a);
+            }
+            sm[u] += a * vr[r];
+            if (i > j) acc[r] += a * vj[u];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) sm[u] = wave_sum_dpp(sm[u]);
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (t0 + u < ncw) pcl[h * NCW + t0 + u] = sm[u];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = 64 * (h + 4 * r) + lane;
+    if (i < m) gst(prow_out + i, acc[r]);
+  }
+  t.sync();
+  for (int q = t.tid(); q < ncw; q += t.nt())
+    gst(pcol_out + w + TRI_NWG * q,
+        ((pcl[q] + pcl[NCW + q]) + pcl[2 * NCW + q]) + pcl[3 * NCW + q]);
+}
+
+// Step k of the tridiagonalisation of the n x n symmetric A (lower triangle)
+// by workgroup w of the matrix.  lds: tri_step_lds(n) doubles.
+template <class T>
+__device__ void tri_step(T& t, double* A, int lda, int n, int k, int w, double* work, double* lds) {
+  if (n < 3 || k > n - 2) return;
+  double* d = work;
+  double* e = work + n;
+  double* tau = work + 2 * n;
+  double* pcol = work + 3 * n;                         // [2][n]
+  double* prow = work + 5 * n;                         // [2][TRI_NWG][n]
+  double* vbuf = work + (5 + 2 * TRI_NWG) * n;         // [2][n]
+  const int par = k & 1, opar = par ^ 1;
+  double* vo = lds;
+  double* qo = lds + n;
+  double* v = lds + 2 * n;
+  double* pt = lds + 3 * n;
+  double* pcl = lds + 4 * n;
+  const int mo = n - k;                                // rows of reflector k-1 (from row k)
+  // phase A: the update left pending by step k-1
+  if (k > 0) {
+    const double tko = gld(tau + k - 1);
+    const double* pc = pcol + (long long)opar * n;
+    const double* pr = prow + (long long)opar * TRI_NWG * n;
+    const double* vb = vbuf + (long long)opar * n;
+    double part = 0.0;
+    for (int i = t.tid(); i < mo; i += t.nt()) {
+      double s = gld(pc + i);
+      for (int q = 0; q < TRI_NWG; ++q) s += gld(pr + (long long)q * n + i);
+      const double vi = gld(vb + i);
+      const double pp = tko * s;
+      vo[i] = vi;
+      pt[i] = pp;
+      part += vi * pp;
+      if (w == 0) gst(A + (long long)(k + i) + (long long)lda * (k - 1), vi);
+    }
+    const double K = 0.5 * tko * t.sum(part);
+    for (int i = t.tid(); i < mo; i += t.nt()) qo[i] = pt[i] - K * vo[i];
+    t.sync();
+  }
+  if (k == n - 2) {
+    // 2 x 2 tail
+    if (w == 0 && t.tid() == 0) {
+      double a00 = gld(A + (long long)k + (long long)lda * k);
+      double a10 = gld(A + (long long)(k + 1) + (long long)lda * k);
+      double a11 = gld(A + (long long)(k + 1) + (long long)lda * (k + 1));
+      if (k > 0) {
+        a00 -= vo[0] * qo[0] + qo[0] * vo[0];
+        a10 -= vo[1] * qo[0] + qo[1] * vo[0];
+        a11 -= vo[1] * qo[1] + qo[1] * vo[1];
+      }
+      d[k] = a00;
+      d[k + 1] = a11;
+      e[k] = a10;
+      e[k + 1] = 0.0;
+      tau[k] = 0.0;
+    }
+    return;
+  }
+  // phase B: column k -> reflector k
+  const int m = n - k - 1;
+  const bool upd = k > 0;
+  const double vo0 = upd ? vo[0] : 0.0, qo0 = upd ? qo[0] : 0.0;
+  double part = 0.0;
+  for (int i = t.tid(); i <= m; i += t.nt()) {
+    double a = gld(A + (long long)(k + i) + (long long)lda * k);
+    if (upd) a -= vo[i] * qo0 + qo[i] * vo0;
+    if (i >= 2) {
+      v[i - 1] = a;
+      part += a * a;
+    } else {
+      pt[i] = a;       // phase A's use of pt is over (it ended with a barrier)
+    }
+  }
+  const double a2 = t.sum(part);
+  const double a0 = pt[0], x0 = pt[1];
+  double beta = x0, v0 = 0.0, tk = 0.0;
+  if (a2 != 0.0) {
+    const double nrm = sqrt(x0 * x0 + a2);
+    beta = (x0 >= 0.0) ? -nrm : nrm;
+    v0 = x0 - beta;
+    tk = 2.0 / (v0 * v0 + a2);
+  }
+  if (a2 == 0.0) {
+    for (int i = t.tid(); i < m; i += t.nt()) v[i] = 0.0;
+  } else if (t.tid() == 0) {
+    v[0] = v0;
+  }
+  t.sync();
+  if (w == 0) {
+    if (t.tid() == 0) {
+      d[k] = a0;
+      e[k] = beta;
+      tau[k] = tk;
+    }
+    double* vb = vbuf + (long long)par * n;
+    for (int i = t.tid(); i < m; i += t.nt()) gst(vb + i, v[i]);
+  }
+  // phase C: this workgroup's columns of the trailing block
+  tri_step_pass<TRI_STEP_R, TRI_STEP_U>(t, A + (long long)(k + 1) + (long long)lda * (k + 1), lda, n, m,
+                                        w, v, vo + 1, qo + 1, upd, pcl,
+                                        prow + (long long)par * TRI_NWG * n + (long long)w * n,
+                                        pcol + (long long)par * n);
+}
+
 // Householder tridiagonalisation reading and updating only the lower
 // triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
 // scratch of n doubles each (LDS on the device).
@@ -1223,13 +1443,15 @@ __host__ __device__ void backtransform(T& t, const double* A, int lda, const dou
 // w[0..k) ascending, Z (n x k).  work: 9 n + 6 n k doubles; cl: k ints
 // (global); lds: >= 2n doubles (and >= k for the generic back-transform).
 // WIDE: the wide-register device paths (workgroups of at most 512 lanes).
-template <bool WIDE = false, class T>
+// PRE: the tridiagonalisation is already done (by tri_step): d, e, tau in
+// work, reflectors in A.
+template <bool WIDE = false, bool PRE = false, class T>
 __host__ __device__ void syev_lowest(T& t, double* A, int lda, int n, int k, double* w, double* Z,
                                      int ldz, double* work, int* cl, double* lds, int lds_size) {
   double* d = work;
   double* e = work + n;
   double* tau = work + 2 * n;
-  tridiagonalize_lower<WIDE>(t, A, lda, n, d, e, tau, lds, lds + n, lds + 2 * n, lds_size - 2 * n);
+  if (!PRE) tridiagonalize_lower<WIDE>(t, A, lda, n, d, e, tau, lds, lds + n, lds + 2 * n, lds_size - 2 * n);
   tridiag_lowest(t, d, e, n, k, w, Z, ldz, work + 3 * n, cl, lds, lds_size);
   backtransform<WIDE>(t, A, lda, tau, n, Z, ldz, k, lds, lds_size);
 }
