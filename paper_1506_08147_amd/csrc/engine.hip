@@ -770,7 +770,7 @@ struct dgdft_alb {
   }
 
   void gain_table(const std::vector<int>& act, int use_stall) {
-    auto P = make_prefix(act, [&](int e) { return cdiv(eh[e].J * eh[e].nsh, 256); });
+    auto P = make_prefix(act, [&](int e) { return cdiv(eh[e].J * eh[e].nsh, MLP_WG_ROWS); });
     pbeg(DGDFT_K_OTHER, 0, 0);
     hipLaunchKernelGGL(dg_mlp_gain, dim3(P.total), dim3(256), 0, stream, ed, P.active, P.prefix, P.na,
                        mlp_w, use_stall);
@@ -2688,7 +2688,7 @@ int32_t dgdft_mlp_eval(const double* feat, int64_t n, const float* weights, doub
   }
   hipStream_t s = (hipStream_t)stream;
   try {
-    hipLaunchKernelGGL(dg_mlp_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, feat, (long long)n,
+    hipLaunchKernelGGL(dg_mlp_rows, dim3((unsigned)((n + MLP_ROWS - 1) / MLP_ROWS)), dim3(256), 0, s, feat, (long long)n,
                        weights, f);
     HCHECK(hipGetLastError());
     HCHECK(hipStreamSynchronize(s));

@@ -56,7 +56,8 @@ __device__ inline void mlp_inputs(const float* Ws, double x, double theta, doubl
   u[2] = (float)((vbar - (double)Ws[O_MU + 2]) / (double)Ws[O_SD + 2]);
 }
 
-// z(u) with the hidden layers in registers.
+// z(u) with the hidden layers in registers (one row per lane; the training
+// kernel's forward sweep).
 __device__ inline float mlp_net(const float* Ws, const float u[3]) {
   float h1[MH];
 #pragma unroll
@@ -81,40 +82,136 @@ __device__ inline float mlp_eval(const float* Ws, const float u[3]) {
   return M_FMAX * tanhf(mlp_net(Ws, u) / M_FMAX);
 }
 
+// f(u) = FMAX tanh(z(u) / FMAX) for the MLP_ROWS rows of a 256-lane
+// workgroup: the first layer per (row, 16 hidden units) on the vector ALU,
+// the 64 x 64 second layer on the FP32 matrix cores (v_mfma_f32_16x16x4f32,
+// FP32 products of the FP32 hidden values and the bfloat16-rounded weights,
+// FP32 accumulation; each wave takes 16 rows), the output layer per row.
+// inputs(r, u) fills u for local row r, for every row of the workgroup.
+// Result: out[q] is f of local row 16 (wave) + 4 (lane / 16) + q, in the
+// lanes with lane % 16 == 0.  Same parameters and operations as the
+// definition; sums are taken in another order.
+constexpr int MLP_ROWS = 64;        // rows per 256-lane workgroup
+constexpr int MLP_LDH = MH + 4;     // LDS row length of the first hidden layer
+constexpr int MLP_LDW = MH + 4;     // LDS row length of the transposed W2
+
+typedef float mlp_f4 __attribute__((ext_vector_type(4)));
+
+// Parameters into LDS as mlp_load, plus W2 transposed (W2T[k][unit]) so that
+// the 16 lanes of a fragment read consecutive units.
+__device__ inline void mlp_load_t(float* Ws, float* W2T, const float* __restrict__ w) {
+  for (int p = threadIdx.x; p < M_NTOT; p += blockDim.x) Ws[p] = p < M_NW ? bf16_round(w[p]) : w[p];
+  for (int p = threadIdx.x; p < MH * MH; p += blockDim.x) {
+    const int unit = p / MH, k = p - unit * MH;
+    W2T[k * MLP_LDW + unit] = bf16_round(w[O_W2 + p]);
+  }
+  __syncthreads();
+}
+
+template <class IN>
+__device__ inline void mlp_rows_mfma(const float* Ws, const float* W2T, float* H1, IN inputs,
+                                     float out[4]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  {
+    const int r = tid >> 2, j0 = (tid & 3) * 16;
+    float u[3];
+    inputs(r, u);
+#pragma unroll
+    for (int j = j0; j < j0 + 16; ++j) {
+      const float z = Ws[O_B1 + j] + Ws[O_W1 + 3 * j] * u[0] + Ws[O_W1 + 3 * j + 1] * u[1] +
+                      Ws[O_W1 + 3 * j + 2] * u[2];
+      H1[r * MLP_LDH + j] = silu_f(z);
+    }
+  }
+  __syncthreads();
+  float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int ra = 16 * wv + (lane & 15), kq = lane >> 4;
+#pragma unroll
+  for (int ob = 0; ob < MH / 16; ++ob) {
+    mlp_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < MH / 4; ++ks) {
+      const float a = H1[ra * MLP_LDH + 4 * ks + kq];                     // A[row][k]
+      const float b = W2T[(4 * ks + kq) * MLP_LDW + 16 * ob + (lane & 15)];  // B[k][unit]
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+    // register q of lane l: row 4 (l / 16) + q, unit 16 ob + l % 16
+    const int unit = 16 * ob + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[q] += Ws[O_W3 + unit] * silu_f(acc[q] + Ws[O_B2 + unit]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float v = part[q];
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+    out[q] = M_FMAX * tanhf((Ws[O_B3] + v) / M_FMAX);
+  }
+}
+
 // Gain table of the solve: e.gain[band * nsh + s] = exp(f) (1 for bands in
-// Teter fallback when use_stall).  Work item: 256 (band, shell) rows.
+// Teter fallback when use_stall).  Work item: MLP_WG_ROWS (band, shell) rows,
+// MLP_ROWS at a time (the parameters are staged in LDS once per workgroup).
+constexpr int MLP_WG_ROWS = 4 * MLP_ROWS;
 extern "C" __global__ void __launch_bounds__(256)
 dg_mlp_gain(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
             int na, const float* __restrict__ w, int use_stall) {
   __shared__ float Ws[M_NTOT];
+  __shared__ float W2T[MH * MLP_LDW];
+  __shared__ float H1[MLP_ROWS * MLP_LDH];
   int b = blockIdx.x;
   int ai = find_elem(prefix, na, b);
   const Elem& e = E[active[ai]];
-  mlp_load(Ws, w);
-  long long row = (long long)(b - prefix[ai]) * 256 + threadIdx.x;
-  if (row >= (long long)e.J * e.nsh) return;
-  int band = (int)(row / e.nsh), s = (int)(row - (long long)band * e.nsh);
-  if (use_stall && e.stall[4 * band + 3] != 0.0) {
-    e.gain[row] = 1.0;
-    return;
+  mlp_load_t(Ws, W2T, w);
+  const long long nrow = (long long)e.J * e.nsh;
+  const int nsh = e.nsh;
+  const int lane = threadIdx.x & 63;
+  for (int bt = 0; bt < MLP_WG_ROWS / MLP_ROWS; ++bt) {
+    const long long row0 = (long long)(b - prefix[ai]) * MLP_WG_ROWS + bt * MLP_ROWS;
+    if (row0 >= nrow) break;                         // the same for the whole workgroup
+    auto inputs = [&](int r, float u[3]) {
+      const long long row = min(row0 + r, nrow - 1);    // rows past the table: any valid input
+      const int band = (int)(row / nsh), s = (int)(row - (long long)band * nsh);
+      mlp_inputs(Ws, e.t_shell[s] / e.tkin[band], e.xhx[band], e.vbar[0], u);
+    };
+    float f[4];
+    mlp_rows_mfma(Ws, W2T, H1, inputs, f);
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long row = row0 + 16 * (threadIdx.x >> 6) + 4 * (lane >> 4) + q;
+        if (row >= nrow) continue;
+        const int band = (int)(row / nsh);
+        e.gain[row] = (use_stall && e.stall[4 * band + 3] != 0.0) ? 1.0 : exp((double)f[q]);
+      }
+    }
+    __syncthreads();                                 // H1 is rewritten by the next rows
   }
-  float u[3];
-  mlp_inputs(Ws, e.t_shell[s] / e.tkin[band], e.xhx[band], e.vbar[0], u);
-  e.gain[row] = exp((double)mlp_eval(Ws, u));
 }
 
 // f for raw feature rows (log-input taken here): feat [n][3] = (x, theta,
-// Vbar) with x = t / T; test entry.
+// Vbar) with x = t / T; test entry.  Work item: MLP_ROWS rows.
 extern "C" __global__ void __launch_bounds__(256)
 dg_mlp_rows(const double* __restrict__ feat, long long n, const float* __restrict__ w,
             double* __restrict__ f) {
   __shared__ float Ws[M_NTOT];
-  mlp_load(Ws, w);
-  long long r = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
-  float u[3];
-  mlp_inputs(Ws, feat[3 * r], feat[3 * r + 1], feat[3 * r + 2], u);
-  f[r] = (double)mlp_eval(Ws, u);
+  __shared__ float W2T[MH * MLP_LDW];
+  __shared__ float H1[MLP_ROWS * MLP_LDH];
+  mlp_load_t(Ws, W2T, w);
+  const long long row0 = (long long)blockIdx.x * MLP_ROWS;
+  auto inputs = [&](int r, float u[3]) {
+    const long long row = min(row0 + r, n - 1);
+    mlp_inputs(Ws, feat[3 * row], feat[3 * row + 1], feat[3 * row + 2], u);
+  };
+  float out[4];
+  mlp_rows_mfma(Ws, W2T, H1, inputs, out);
+  const int lane = threadIdx.x & 63;
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const long long row = row0 + 16 * (threadIdx.x >> 6) + 4 * (lane >> 4) + q;
+      if (row < n) f[row] = (double)out[q];
+    }
+  }
 }
 
 // Teter fallback (a band whose residual has not fallen below STALL_FACTOR
