@@ -183,6 +183,7 @@ constexpr double CARRY_RES = 3e-5;
 extern "C" __global__ void __launch_bounds__(SMALL_THREADS)
 dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int single) {
   __shared__ double red[32];
+  __shared__ double tiles[(SMALL_THREADS / 64) * SYM_TILE_LDS];
   DevTeam t{red};
   const Elem& e = E[active[blockIdx.x]];
   const int J = e.J;
@@ -199,23 +200,23 @@ dg_rr_reduce(Elem* __restrict__ E, const int* __restrict__ active, int na, int s
   double* vec = sm(e, SM_V);
   double* dm = vec + 6 * n;
   double* w = vec + 7 * n;
-  sym_from_upper(t, H, n, n);
-  sym_from_upper(t, M, n, n);
+  sym_from_upper_tiles(t, H, n, n, tiles);
+  sym_from_upper_tiles(t, M, n, n, tiles);
   // a step on X alone (start, final check) leaves nothing to carry
   if (single && t.tid() == 0) e.fl[FL_CARRY] = 0;
   if (!single) {
+    const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = t.nt() >> 6;
     double ef = 0.0;
-    for (int p = t.tid(); p < n * n; p += t.nt()) {
-      int i = p % n, j = p / n;
-      double v = M[p] - (i == j ? 1.0 : 0.0);
-      ef += v * v;
-    }
+    for (int j = wv; j < n; j += nw)
+      for (int i = lane; i < n; i += 64) {
+        const double v = gld(M + i + (long long)n * j) - (i == j ? 1.0 : 0.0);
+        ef += v * v;
+      }
     ef = sqrt(t.sum(ef));   // ||E||_F >= ||E||_2
     if (ef <= SERIES_ORTHO) {
-      for (int p = t.tid(); p < n * n; p += t.nt()) {
-        int i = p % n, j = p / n;
-        Lm[p] = M[p] - (i == j ? 1.0 : 0.0);      // E
-      }
+      for (int j = wv; j < n; j += nw)
+        for (int i = lane; i < n; i += 64)
+          gst(Lm + i + (long long)n * j, gld(M + i + (long long)n * j) - (i == j ? 1.0 : 0.0));   // E
       if (t.tid() == 0) {
         e.fl[FL_RR_PATH] = ef <= NEAR_ORTHO ? 2 : 3;
         e.fl[FL_RR_NSERIES] += 1;

@@ -75,6 +75,51 @@ __host__ __device__ void sym_from_upper(T& t, double* A, int lda, int n) {
   t.sync();
 }
 
+// Device form of sym_from_upper for a workgroup of whole waves: each wave
+// copies 16 x 16 tiles of the upper triangle to the lower one through its
+// own LDS tile (column reads and column writes, both contiguous, where the
+// plain form reads along rows).  lds: SYM_TILE_LDS doubles per wave.  A
+// wave's LDS writes and reads are carried out in its issue order; the fences
+// keep the compiler from moving them across each other.
+constexpr int SYM_TILE_LDS = 16 * 17;
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T>
+__device__ void sym_from_upper_tiles(T& t, double* A, int lda, int n, double* lds) {
+  const int lane = t.tid() & 63, wv = t.tid() >> 6, nw = (t.nt() + 63) >> 6;
+  double* tile = lds + wv * SYM_TILE_LDS;
+  const int nb = (n + 15) / 16;
+  const int ntiles = nb * (nb + 1) / 2;          // tiles (bi, bj), bj <= bi
+  const int r = lane & 15, ch = lane >> 4;       // four columns per instruction
+  for (int q = wv; q < ntiles; q += nw) {
+    int bi = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+    while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
+    while (bi * (bi + 1) / 2 > q) --bi;
+    const int bj = q - bi * (bi + 1) / 2;
+    // tile[c][r] = A[bj*16 + r][bi*16 + c] (upper triangle)
+#pragma unroll
+    for (int c0 = 0; c0 < 16; c0 += 4) {
+      const int c = c0 + ch, row = bj * 16 + r, col = bi * 16 + c;
+      tile[c * 17 + r] = (row < n && col < n) ? gld(A + row + (long long)lda * col) : 0.0;
+    }
+    wave_lds_sync();
+    // A[bi*16 + r][bj*16 + c] = tile[r][c] below the diagonal
+#pragma unroll
+    for (int c0 = 0; c0 < 16; c0 += 4) {
+      const int c = c0 + ch, row = bi * 16 + r, col = bj * 16 + c;
+      const double v = tile[r * 17 + c];
+      if (row < n && col < n && row > col) gst(A + row + (long long)lda * col, v);
+    }
+    wave_lds_sync();
+  }
+  t.sync();
+}
+
 template <class T>
 __host__ __device__ void copy_mat(T& t, const double* A, int lda, double* B, int ldb, int m, int n) {
   for (int p = t.tid(); p < m * n; p += t.nt()) {
