@@ -109,14 +109,15 @@ def test_update_product_fp32_kernels(dev, K, m, n):
 @pytest.mark.parametrize("method,n,k", [(m, n, k) for m in (0, 1) for n, k in
                                          [(1, 1), (10, 10), (96, 32), (200, 64), (384, 128),
                                           (432, 144)]] +
-                         [(0, 480, 160), (0, 600, 200), (0, 768, 256), (0, 816, 272),
-                          (0, 900, 300)])
+                         [(0, 480, 160), (0, 600, 200), (0, 768, 256), (0, 801, 267),
+                          (0, 816, 272), (0, 900, 300)])
 def test_small_syev_matches_lapack(dev, n, k, method):
-    """Method 0 takes the one-pass tridiagonalisation with 6 rows per lane up
-    to n = 384, 7 up to 448 and 8 up to 512 (1024-lane workgroups), 10 up to
-    640 and 13 up to 832 (512-lane workgroups; the Rayleigh-Ritz sizes of
-    blocks of up to 272 states), and the three-pass form above; the
-    back-transformation likewise (6, 7, 12 rows per lane, 13 on 512 lanes)."""
+    """Method 0 takes the one-pass tridiagonalisation in one 1024-lane
+    workgroup up to n = 512 (row groups x column groups), over eight
+    workgroups per matrix with one launch per Householder step for
+    513 <= n <= 832 (the Rayleigh-Ritz sizes of blocks of up to 277 states;
+    odd and even orders), and the three-pass form above; the
+    back-transformation keeps 6, 7 or 12 rows per lane, 13 above 768."""
     from paper_1506_08147_amd import small_syev
     rng = np.random.default_rng(n)
     M = rng.standard_normal((2, n, n))
@@ -139,6 +140,36 @@ def test_small_syev_matches_lapack(dev, n, k, method):
         assert np.abs(A @ Zi - Zi * w[i][:k]).max() <= 1e-12 * sc * np.sqrt(n)
         assert np.abs(Zi.T @ Zi - np.eye(k)).max() <= 1e-12 * np.sqrt(n)
 
+
+
+@pytest.mark.parametrize("J", [180, 267, 272])
+def test_small_syev_structured(dev, J):
+    """Method 0 on matrices whose Householder steps meet exact zeros below the
+    subdiagonal (a column with nothing to reflect): the Rayleigh-Ritz matrix
+    of a step whose P block is decoupled (the middle J x J block sigma I, no
+    coupling), a tridiagonal and a diagonal matrix, orders 3J."""
+    from paper_1506_08147_amd import small_syev
+    rng = np.random.default_rng(J)
+    n = 3 * J
+    A = rng.standard_normal((n, n))
+    A = A + A.T
+    sig = 2.0 * np.abs(np.linalg.eigvalsh(A)).max()
+    A[J:2 * J, :] = 0.0
+    A[:, J:2 * J] = 0.0
+    A[J:2 * J, J:2 * J] = sig * np.eye(J)
+    T = np.diag(rng.standard_normal(n)) + np.diag(rng.standard_normal(n - 1), 1)
+    T = T + np.triu(T, 1).T
+    D = np.diag(rng.standard_normal(n))
+    M = np.stack([A, T, D])
+    w, Z = small_syev(_t(M, dev), J, 0)
+    w, Z = w.cpu().numpy(), Z.cpu().numpy()
+    for i in range(3):
+        wr = np.linalg.eigvalsh(M[i])[:J]
+        sc = max(1.0, np.abs(wr).max())
+        assert np.abs(w[i][:J] - wr).max() <= 1e-13 * sc * n
+        Zi = Z[i].T
+        assert np.abs(M[i] @ Zi - Zi * w[i][:J]).max() <= 1e-12 * sc * np.sqrt(n)
+        assert np.abs(Zi.T @ Zi - np.eye(J)).max() <= 1e-12 * np.sqrt(n)
 
 def _handle(els):
     from paper_1506_08147_amd import ALB
