@@ -376,6 +376,9 @@ def main():
                     help="LOBPCG iterations per captured HIP graph launch (0: eager)")
     ap.add_argument("--tune", type=int, default=0, help="1: autotune at create")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precond", default="teter", choices=["teter", "learned"],
+                    help="preconditioner of the timed form (learned: the network trained as "
+                         "for the mixed + learned form)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="1: one 1 GiB device copy before the timed region, whose hardware "
                          "counters calibrate FETCH_SIZE / WRITE_SIZE in profiler runs")
@@ -410,8 +413,13 @@ def main():
     els, desc = workload(args.workload, args.elements)
     log(f"inputs generated: {len(els)} elements in {time.perf_counter() - t:.1f} s")
     V, kbt, X0 = resident_inputs(els, args.guard, dev)
+    extra = {}
+    if args.precond == "learned":
+        # the network the mixed + learned form uses (trained before timing)
+        w_main, _ = train_network(dev)
+        extra = dict(precond="learned", mlp_weights=w_main)
     h = make_handle(args, els, tol=args.tol, max_iter=1000, graph_iters=args.graph,
-                    tune=bool(args.tune), precision=args.precision)
+                    tune=bool(args.tune), precision=args.precision, **extra)
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
@@ -502,7 +510,7 @@ def main():
                 higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype="f64" if args.precision == "fp64" else "f64+f32",
                 data="synthetic", config=dict(desc, tol=args.tol, precision=args.precision,
-                                              preconditioner="teter", graph_iters=args.graph,
+                                              preconditioner=args.precond, graph_iters=args.graph,
                                               tuned=bool(args.tune), guard_columns=args.guard,
                                               streams=args.streams),
                 roofline=roof, kernels=kernels,
