@@ -273,20 +273,54 @@ struct dgdft_alb {
     return false;
   }
 
+  // The xy passes of a batch: elements whose planes hold at most FFT_XY_TINY
+  // points on 256-lane workgroups, the others on 512 lanes (the 72 KiB tile
+  // when some plane exceeds FFT_XY_SMALL).  Prefix arrays per set, shared by
+  // the forward and the inverse pass.
+  struct XYSets {
+    std::vector<int> tiny, rest;
+    Prefix Pt, Pr;
+    bool big = false;
+  };
+  template <class F>
+  XYSets xy_sets(const std::vector<int>& act, F pairs) {
+    XYSets x;
+    for (int e : act) (eh[e].n1 * eh[e].n2 <= FFT_XY_TINY ? x.tiny : x.rest).push_back(e);
+    if (!x.tiny.empty()) x.Pt = make_prefix(x.tiny, [&](int e) { return pairs(e) * eh[e].n3; });
+    if (!x.rest.empty()) x.Pr = make_prefix(x.rest, [&](int e) { return pairs(e) * eh[e].n3; });
+    x.big = big_planes(x.rest);
+    return x;
+  }
+  void xy_fwd(const XYSets& x, bool fp32, int slot, int col0, int ncols_fixed) {
+    if (!x.tiny.empty())
+      hipLaunchKernelGGL(fp32 ? dg_fft_xy_fwd32_s : dg_fft_xy_fwd_s, dim3(x.Pt.total), dim3(FFT_TINY_THREADS), 0,
+                         stream, ed, x.Pt.active, x.Pt.prefix, x.Pt.na, slot, col0, ncols_fixed);
+    if (!x.rest.empty())
+      hipLaunchKernelGGL(fp32 ? (x.big ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd32) : (x.big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd),
+                         dim3(x.Pr.total), dim3(FFT_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
+                         slot, col0, ncols_fixed);
+  }
+  void xy_inv(const XYSets& x, bool fp32, int in_slot, int out_slot, int col0, int ncols_fixed, int mode) {
+    if (!x.tiny.empty())
+      hipLaunchKernelGGL(fp32 ? dg_fft_xy_inv32_s : dg_fft_xy_inv_s, dim3(x.Pt.total), dim3(FFT_TINY_THREADS), 0,
+                         stream, ed, x.Pt.active, x.Pt.prefix, x.Pt.na, in_slot, out_slot, col0, ncols_fixed, mode);
+    if (!x.rest.empty())
+      hipLaunchKernelGGL(fp32 ? (x.big ? dg_fft_xy_inv32_l : dg_fft_xy_inv32) : (x.big ? dg_fft_xy_inv_l : dg_fft_xy_inv),
+                         dim3(x.Pr.total), dim3(FFT_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
+                         in_slot, out_slot, col0, ncols_fixed, mode);
+  }
+
   // fp32: the transforms run in FP32 (the V and KB terms stay FP64)
   void op_apply(const std::vector<int>& act, int in_slot, int out_slot, int col0, int ncols_fixed,
                 bool fp32 = false) {
     // ncols_fixed < 0: all J columns
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
     launch_kbproj(act, in_slot, col0, ncols_fixed, 0);
-    auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
+    const XYSets xs = xy_sets(act, [&](int e) { return cdiv(nc(e), 2); });
     double pts = 0;   // grid points x column pairs
     for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
-    const bool big = big_planes(act);
     pbeg(DGDFT_K_FFT_XY_FWD, 0, (fp32 ? 24.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd32) : (big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd),
-                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, in_slot,
-                       col0, ncols_fixed);
+    xy_fwd(xs, fp32, in_slot, col0, ncols_fixed);
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
@@ -294,9 +328,7 @@ struct dgdft_alb {
                        P2.active, P2.prefix, P2.na, col0, ncols_fixed, 0);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 48.0 : 56.0) * pts);
-    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_inv32_l : dg_fft_xy_inv32) : (big ? dg_fft_xy_inv_l : dg_fft_xy_inv),
-                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, in_slot,
-                       out_slot, col0, ncols_fixed, 0);
+    xy_inv(xs, fp32, in_slot, out_slot, col0, ncols_fixed, 0);
     pend();
     HCHECK(hipGetLastError());
   }
@@ -314,14 +346,11 @@ struct dgdft_alb {
 
   void precondition(const std::vector<int>& act, int slot, int col0, int ncols_fixed, bool fp32 = false) {
     auto nc = [&](int e) { return ncols_fixed < 0 ? eh[e].J : ncols_fixed; };
-    auto P1 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * eh[e].n3; });
+    const XYSets xs = xy_sets(act, [&](int e) { return cdiv(nc(e), 2); });
     double pts = 0;
     for (int e : act) pts += (double)cdiv(nc(e), 2) * eh[e].ng;
-    const bool big = big_planes(act);
     pbeg(DGDFT_K_FFT_XY_FWD, 0, (fp32 ? 24.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd32) : (big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd),
-                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, slot,
-                       col0, ncols_fixed);
+    xy_fwd(xs, fp32, slot, col0, ncols_fixed);
     pend();
     auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
@@ -330,9 +359,7 @@ struct dgdft_alb {
                        opts.precond == DGDFT_PRECOND_NONE ? 2 : opts.precond == DGDFT_PRECOND_LEARNED ? 3 : 1);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 24.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? (big ? dg_fft_xy_inv32_l : dg_fft_xy_inv32) : (big ? dg_fft_xy_inv_l : dg_fft_xy_inv),
-                       dim3(P1.total), dim3(FFT_THREADS), 0, stream, ed, P1.active, P1.prefix, P1.na, slot,
-                       slot, col0, ncols_fixed, 1);
+    xy_inv(xs, fp32, slot, slot, col0, ncols_fixed, 1);
     pend();
     HCHECK(hipGetLastError());
   }

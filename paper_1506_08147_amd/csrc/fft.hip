@@ -31,6 +31,11 @@ constexpr int FFT_MAXPTS = 4608;        // largest LDS tile (72 KiB): z pencils 
 // (kernels with the 72 KiB tile ask for four waves per SIMD, i.e. at most 128
 // registers per lane, so that two workgroups share a compute unit)
 constexpr int FFT_XY_SMALL = 2304;      // xy planes up to 48 x 48 use a 36 KiB tile
+// xy planes up to 1152 points (36 x 32): 256-lane workgroups with an 18 KiB
+// tile, twice as many planes in flight per compute unit (a first radix-8
+// stage of a 24 x 24 plane has 72 butterflies, one wave's worth)
+constexpr int FFT_XY_TINY = 1152;
+constexpr int FFT_TINY_THREADS = 256;
 
 // Exact division of small unsigned values (b * d < 2^32) by a multiply-high
 // with m = floor((2^32 - 1) / d) + 1; d == 1 handled apart.
@@ -265,7 +270,7 @@ __device__ __forceinline__ double teter_k(double x) {
 // Pass 1: xy-plane forward transform.  Work item (pair q, plane z).
 // Columns col0 + 2q and col0 + 2q + 1 (if < col0 + ncols) of block `slot`;
 // ncols < 0 means all J columns of the element (here and below).
-template <int MAXPTS, class C>
+template <int MAXPTS, int NT, class C>
 __device__ __forceinline__ void fft_xy_fwd_body(C* buf, Elem* __restrict__ E,
                                                 const int* __restrict__ active,
                                                 const int* __restrict__ prefix, int na, int slot,
@@ -283,53 +288,67 @@ __device__ __forceinline__ void fft_xy_fwd_body(C* buf, Elem* __restrict__ E,
   const double* B = bp(e, slot) + (long long)cb * e.ld + (long long)z * np;
   {
     // all of a lane's loads in flight before the first LDS write
-    constexpr int NL = (MAXPTS + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int NL = (MAXPTS + NT - 1) / NT;
     double ra[NL], rb[NL];
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const int p = threadIdx.x + u * FFT_THREADS;
+      const int p = threadIdx.x + u * NT;
       ra[u] = p < np ? gld(A + p) : 0.0;
       rb[u] = (p < np && hasb) ? gld(B + p) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const int p = threadIdx.x + u * FFT_THREADS;
+      const int p = threadIdx.x + u * NT;
       if (p < np) buf[p] = cmake<C>(ra[u], rb[u]);
     }
   }
   __syncthreads();
-  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), -1.0);
-  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), -1.0);
+  fft_lines<MAXPTS, NT>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), -1.0);
+  fft_lines<MAXPTS, NT>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), -1.0);
   C* Z = zpair<C>(e, q) + (long long)z * np;
-  for (int p = threadIdx.x; p < np; p += FFT_THREADS) gst(Z + p, buf[p]);
+  for (int p = threadIdx.x; p < np; p += NT) gst(Z + p, buf[p]);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS)
 dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
               int na, int slot, int col0, int ncols) {
   __shared__ double2 buf[FFT_XY_SMALL];
-  fft_xy_fwd_body<FFT_XY_SMALL>(buf, E, active, prefix, na, slot, col0, ncols);
+  fft_xy_fwd_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS)
 dg_fft_xy_fwd32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int slot, int col0, int ncols) {
   __shared__ float2 buf[FFT_XY_SMALL];
-  fft_xy_fwd_body<FFT_XY_SMALL>(buf, E, active, prefix, na, slot, col0, ncols);
+  fft_xy_fwd_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_fwd_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int slot, int col0, int ncols) {
   __shared__ double2 buf[FFT_MAXPTS];
-  fft_xy_fwd_body<FFT_MAXPTS>(buf, E, active, prefix, na, slot, col0, ncols);
+  fft_xy_fwd_body<FFT_MAXPTS, FFT_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_fwd32_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                   int na, int slot, int col0, int ncols) {
   __shared__ float2 buf[FFT_MAXPTS];
-  fft_xy_fwd_body<FFT_MAXPTS>(buf, E, active, prefix, na, slot, col0, ncols);
+  fft_xy_fwd_body<FFT_MAXPTS, FFT_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_fwd_s(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int slot, int col0, int ncols) {
+  __shared__ double2 buf[FFT_XY_TINY];
+  fft_xy_fwd_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_fwd32_s(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                  int na, int slot, int col0, int ncols) {
+  __shared__ float2 buf[FFT_XY_TINY];
+  fft_xy_fwd_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
 // Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
@@ -458,7 +477,7 @@ dg_fft_z32(Elem* __restrict__ E, const int* __restrict__ active, const int* __re
 // mode 0 (operator): out = T x + V x + KB, reading x from block `in_slot`
 //   and the projections beta^T x from e.proj (n_proj x ncols).
 // mode 1 (plain): out = result (preconditioner; out may equal in).
-template <int MAXPTS, class C>
+template <int MAXPTS, int NT, class C>
 __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
                                                 const int* __restrict__ active,
                                                 const int* __restrict__ prefix, int na, int in_slot,
@@ -471,22 +490,22 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
   int n1 = e.n1, n2 = e.n2, np = n1 * n2;
   const C* Z = zpair<C>(e, q) + (long long)z * np;
   {
-    constexpr int NL = (MAXPTS + FFT_THREADS - 1) / FFT_THREADS;
+    constexpr int NL = (MAXPTS + NT - 1) / NT;
     C rz[NL];
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const int p = threadIdx.x + u * FFT_THREADS;
+      const int p = threadIdx.x + u * NT;
       if (p < np) rz[u] = gld(Z + p);
     }
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const int p = threadIdx.x + u * FFT_THREADS;
+      const int p = threadIdx.x + u * NT;
       if (p < np) buf[p] = rz[u];
     }
   }
   __syncthreads();
-  fft_lines<MAXPTS>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), 1.0);
-  fft_lines<MAXPTS>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), 1.0);
+  fft_lines<MAXPTS, NT>(buf, n2, n1, 1, n1, e.rad[1], e.nrad[1], twiddles<C>(e, 1), 1.0);
+  fft_lines<MAXPTS, NT>(buf, n1, n2, n1, 1, e.rad[0], e.nrad[0], twiddles<C>(e, 0), 1.0);
   const double sc = 1.0 / (double)e.ng;
   const int nc = ncols < 0 ? e.J : ncols;
   int ca = col0 + 2 * q, cb = ca + 1;
@@ -503,7 +522,7 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
     const double* pb = e.proj + (long long)(cb - col0) * e.n_proj;
     const int* kbp = e.kbt_p;
     const double* kbc = e.kbt_c;
-    for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
+    for (int p = threadIdx.x; p < np; p += NT) {
       const C r = buf[p];
       double v = gld(V + p);
       double ya = sc * r.x + v * gld(IA + p);
@@ -530,7 +549,7 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
       if (hasb) gst(OB + p, yb);
     }
   } else {
-    for (int p = threadIdx.x; p < np; p += FFT_THREADS) {
+    for (int p = threadIdx.x; p < np; p += NT) {
       const C r = buf[p];
       gst(OA + p, sc * r.x);
       if (hasb) gst(OB + p, sc * r.y);
@@ -542,28 +561,44 @@ extern "C" __global__ void __launch_bounds__(FFT_THREADS)
 dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
               int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_XY_SMALL];
-  fft_xy_inv_body<FFT_XY_SMALL>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+  fft_xy_inv_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS)
 dg_fft_xy_inv32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ float2 buf[FFT_XY_SMALL];
-  fft_xy_inv_body<FFT_XY_SMALL>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+  fft_xy_inv_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_inv_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_MAXPTS];
-  fft_xy_inv_body<FFT_MAXPTS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+  fft_xy_inv_body<FFT_MAXPTS, FFT_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_inv32_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                   int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
   __shared__ float2 buf[FFT_MAXPTS];
-  fft_xy_inv_body<FFT_MAXPTS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+  fft_xy_inv_body<FFT_MAXPTS, FFT_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_inv_s(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_XY_TINY];
+  fft_xy_inv_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols,
+                                                 mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_inv32_s(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                  int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_XY_TINY];
+  fft_xy_inv_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols,
+                                                 mode);
 }
 
 // ---------------------------------------------------------------------------
