@@ -48,7 +48,7 @@ struct Status {
   std::string msg;
 };
 
-constexpr int PREFIX_RING = 160;  // prefix arrays between two host polls
+constexpr int PREFIX_RING = 256;  // prefix arrays between two host polls
 
 }  // namespace
 
@@ -310,6 +310,25 @@ struct dgdft_alb {
                          in_slot, out_slot, col0, ncols_fixed, mode);
   }
 
+  // The z pass of a batch by pencil size (2 n1 n3 points of a row pair):
+  // 18 KiB and 36 KiB tiles on 256-lane workgroups, else the 72 KiB tile.
+  template <class F>
+  void z_pass(const std::vector<int>& act, F pairs, bool fp32, int col0, int ncols_fixed, int mode) {
+    std::vector<int> cls[3];
+    for (int e : act) {
+      const int pts = 2 * eh[e].n1 * eh[e].n3;
+      cls[pts <= FFT_XY_TINY ? 0 : pts <= FFT_XY_SMALL ? 1 : 2].push_back(e);
+    }
+    for (int c = 0; c < 3; ++c) {
+      if (cls[c].empty()) continue;
+      auto P = make_prefix(cls[c], [&](int e) { return pairs(e) * (eh[e].n2 / 2 + 1); });
+      auto k = c == 0 ? (fp32 ? dg_fft_z32_s : dg_fft_z_s)
+                      : c == 1 ? (fp32 ? dg_fft_z32_m : dg_fft_z_m) : (fp32 ? dg_fft_z32 : dg_fft_z);
+      hipLaunchKernelGGL(k, dim3(P.total), dim3(c == 2 ? FFT_Z_THREADS : FFT_TINY_THREADS), 0, stream, ed,
+                         P.active, P.prefix, P.na, col0, ncols_fixed, mode);
+    }
+  }
+
   // fp32: the transforms run in FP32 (the V and KB terms stay FP64)
   void op_apply(const std::vector<int>& act, int in_slot, int out_slot, int col0, int ncols_fixed,
                 bool fp32 = false) {
@@ -322,10 +341,8 @@ struct dgdft_alb {
     pbeg(DGDFT_K_FFT_XY_FWD, 0, (fp32 ? 24.0 : 32.0) * pts);
     xy_fwd(xs, fp32, in_slot, col0, ncols_fixed);
     pend();
-    auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_Z_THREADS), 0, stream, ed,
-                       P2.active, P2.prefix, P2.na, col0, ncols_fixed, 0);
+    z_pass(act, [&](int e) { return cdiv(nc(e), 2); }, fp32, col0, ncols_fixed, 0);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 48.0 : 56.0) * pts);
     xy_inv(xs, fp32, in_slot, out_slot, col0, ncols_fixed, 0);
@@ -352,11 +369,9 @@ struct dgdft_alb {
     pbeg(DGDFT_K_FFT_XY_FWD, 0, (fp32 ? 24.0 : 32.0) * pts);
     xy_fwd(xs, fp32, slot, col0, ncols_fixed);
     pend();
-    auto P2 = make_prefix(act, [&](int e) { return cdiv(nc(e), 2) * (eh[e].n2 / 2 + 1); });
     pbeg(DGDFT_K_FFT_Z, 0, (fp32 ? 16.0 : 32.0) * pts);
-    hipLaunchKernelGGL(fp32 ? dg_fft_z32 : dg_fft_z, dim3(P2.total), dim3(FFT_Z_THREADS), 0, stream, ed,
-                       P2.active, P2.prefix, P2.na, col0, ncols_fixed,
-                       opts.precond == DGDFT_PRECOND_NONE ? 2 : opts.precond == DGDFT_PRECOND_LEARNED ? 3 : 1);
+    z_pass(act, [&](int e) { return cdiv(nc(e), 2); }, fp32, col0, ncols_fixed,
+           opts.precond == DGDFT_PRECOND_NONE ? 2 : opts.precond == DGDFT_PRECOND_LEARNED ? 3 : 1);
     pend();
     pbeg(DGDFT_K_FFT_XY_INV, 0, (fp32 ? 24.0 : 32.0) * pts);
     xy_inv(xs, fp32, slot, slot, col0, ncols_fixed, 1);
@@ -1237,7 +1252,7 @@ int32_t dgdft_alb_create(dgdft_alb** out, const int32_t* grid, const double* box
     }
     HCHECK(hipEventCreateWithFlags(&h->g_join, hipEventDisableTiming));
     if (h->opts.graph_iters > 0) {
-      h->cap_slots = (size_t)h->opts.graph_iters * 128;
+      h->cap_slots = (size_t)h->opts.graph_iters * 192;
       for (int g = 0; g < dgdft_alb::NGROUP; ++g) {
         h->cap_host[g].assign(h->cap_slots * h->ring_stride, 0);
         HCHECK(hipMalloc(&h->cap_dev[g], sizeof(int) * h->cap_slots * h->ring_stride));

@@ -354,7 +354,7 @@ dg_fft_xy_fwd32_s(Elem* __restrict__ E, const int* __restrict__ active, const in
 // Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
 // (pair q, row pair m2 in [0, n2/2]).  mode 0: kinetic |G|^2/2.  mode 1:
 // Teter with band kinetic energies tkin[col].  mode 2: identity.
-template <int NT, class C>
+template <int MAXPTS, int NT, class C>
 __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const int* __restrict__ active,
                                            const int* __restrict__ prefix, int na, int col0, int ncols,
                                            int mode) {
@@ -379,7 +379,7 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     x = r - s * n1;
   };
   {
-    constexpr int NL = (FFT_MAXPTS + NT - 1) / NT;
+    constexpr int NL = (MAXPTS + NT - 1) / NT;
     C rz[NL];
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
@@ -398,7 +398,7 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     }
   }
   __syncthreads();
-  fft_lines<FFT_MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), -1.0);
+  fft_lines<MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), -1.0);
 
   const double g1 = 2.0 * M_PI / e.L[0], g2 = 2.0 * M_PI / e.L[1], g3 = 2.0 * M_PI / e.L[2];
   if (mode == 0) {
@@ -417,7 +417,7 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     int ca = col0 + 2 * q, cb = ca + 1;
     bool hasb = cb < col0 + nc;
     const double ita = 1.0 / gld(e.tkin + ca), itb = hasb ? 1.0 / gld(e.tkin + cb) : ita;
-    constexpr int PPT = (FFT_MAXPTS + NT - 1) / NT;
+    constexpr int PPT = (MAXPTS + NT - 1) / NT;
     C nv[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
@@ -450,7 +450,7 @@ __device__ __forceinline__ void fft_z_body(C* buf, Elem* __restrict__ E, const i
     }
     __syncthreads();
   }
-  fft_lines<FFT_MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), 1.0);
+  fft_lines<MAXPTS, NT>(buf, n3, width, 1, width, e.rad[2], e.nrad[2], twiddles<C>(e, 2), 1.0);
   for (int p = threadIdx.x; p < npts; p += NT) {
     int z, s, x;
     split(p, z, s, x);
@@ -463,14 +463,45 @@ extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS, 4)
 dg_fft_z(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
          int na, int col0, int ncols, int mode) {
   __shared__ double2 buf[FFT_MAXPTS];
-  fft_z_body<FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
+  fft_z_body<FFT_MAXPTS, FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_Z_THREADS, 4)
 dg_fft_z32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
            int na, int col0, int ncols, int mode) {
   __shared__ float2 buf[FFT_MAXPTS];
-  fft_z_body<FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
+  fft_z_body<FFT_MAXPTS, FFT_Z_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
+}
+
+// z pencils of at most FFT_XY_TINY and FFT_XY_SMALL points on 256-lane
+// workgroups with 18 and 36 KiB tiles (more pencils in flight per compute
+// unit than the 72 KiB tile allows).
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_z_s(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+           int na, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_XY_TINY];
+  fft_z_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_z32_s(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+             int na, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_XY_TINY];
+  fft_z_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_z_m(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+           int na, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_XY_SMALL];
+  fft_z_body<FFT_XY_SMALL, FFT_TINY_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_z32_m(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+             int na, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_XY_SMALL];
+  fft_z_body<FFT_XY_SMALL, FFT_TINY_THREADS>(buf, E, active, prefix, na, col0, ncols, mode);
 }
 
 // Pass 3: inverse xy transform and epilogue.  Work item (pair q, plane z).
