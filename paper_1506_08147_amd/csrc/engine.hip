@@ -273,10 +273,11 @@ struct dgdft_alb {
     return false;
   }
 
-  // The xy passes of a batch: elements whose planes hold at most FFT_XY_TINY
-  // points on 256-lane workgroups, the others on 512 lanes (the 72 KiB tile
-  // when some plane exceeds FFT_XY_SMALL).  Prefix arrays per set, shared by
-  // the forward and the inverse pass.
+  // The xy passes of a batch on 256-lane workgroups: elements whose planes
+  // hold at most FFT_XY_TINY points with an 18 KiB tile, the others with a
+  // 36 KiB tile (or 512 lanes and the 72 KiB tile when some plane exceeds
+  // FFT_XY_SMALL).  Prefix arrays per set, shared by the forward and the
+  // inverse pass.
   struct XYSets {
     std::vector<int> tiny, rest;
     Prefix Pt, Pr;
@@ -295,19 +296,31 @@ struct dgdft_alb {
     if (!x.tiny.empty())
       hipLaunchKernelGGL(fp32 ? dg_fft_xy_fwd32_s : dg_fft_xy_fwd_s, dim3(x.Pt.total), dim3(FFT_TINY_THREADS), 0,
                          stream, ed, x.Pt.active, x.Pt.prefix, x.Pt.na, slot, col0, ncols_fixed);
-    if (!x.rest.empty())
-      hipLaunchKernelGGL(fp32 ? (x.big ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd32) : (x.big ? dg_fft_xy_fwd_l : dg_fft_xy_fwd),
-                         dim3(x.Pr.total), dim3(FFT_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
-                         slot, col0, ncols_fixed);
+    if (!x.rest.empty()) {
+      if (x.big)
+        hipLaunchKernelGGL(fp32 ? dg_fft_xy_fwd32_l : dg_fft_xy_fwd_l,
+                           dim3(x.Pr.total), dim3(FFT_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
+                           slot, col0, ncols_fixed);
+      else
+        hipLaunchKernelGGL(fp32 ? dg_fft_xy_fwd32_m : dg_fft_xy_fwd_m,
+                           dim3(x.Pr.total), dim3(FFT_TINY_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
+                           slot, col0, ncols_fixed);
+    }
   }
   void xy_inv(const XYSets& x, bool fp32, int in_slot, int out_slot, int col0, int ncols_fixed, int mode) {
     if (!x.tiny.empty())
       hipLaunchKernelGGL(fp32 ? dg_fft_xy_inv32_s : dg_fft_xy_inv_s, dim3(x.Pt.total), dim3(FFT_TINY_THREADS), 0,
                          stream, ed, x.Pt.active, x.Pt.prefix, x.Pt.na, in_slot, out_slot, col0, ncols_fixed, mode);
-    if (!x.rest.empty())
-      hipLaunchKernelGGL(fp32 ? (x.big ? dg_fft_xy_inv32_l : dg_fft_xy_inv32) : (x.big ? dg_fft_xy_inv_l : dg_fft_xy_inv),
-                         dim3(x.Pr.total), dim3(FFT_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
-                         in_slot, out_slot, col0, ncols_fixed, mode);
+    if (!x.rest.empty()) {
+      if (x.big)
+        hipLaunchKernelGGL(fp32 ? dg_fft_xy_inv32_l : dg_fft_xy_inv_l,
+                           dim3(x.Pr.total), dim3(FFT_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
+                           in_slot, out_slot, col0, ncols_fixed, mode);
+      else
+        hipLaunchKernelGGL(fp32 ? dg_fft_xy_inv32_m : dg_fft_xy_inv_m,
+                           dim3(x.Pr.total), dim3(FFT_TINY_THREADS), 0, stream, ed, x.Pr.active, x.Pr.prefix, x.Pr.na,
+                           in_slot, out_slot, col0, ncols_fixed, mode);
+    }
   }
 
   // The z pass of a batch by pencil size (2 n1 n3 points of a row pair):

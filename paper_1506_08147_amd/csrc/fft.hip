@@ -351,6 +351,20 @@ dg_fft_xy_fwd32_s(Elem* __restrict__ E, const int* __restrict__ active, const in
   fft_xy_fwd_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_fwd_m(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int slot, int col0, int ncols) {
+  __shared__ double2 buf[FFT_XY_SMALL];
+  fft_xy_fwd_body<FFT_XY_SMALL, FFT_TINY_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_fwd32_m(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                  int na, int slot, int col0, int ncols) {
+  __shared__ float2 buf[FFT_XY_SMALL];
+  fft_xy_fwd_body<FFT_XY_SMALL, FFT_TINY_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
+}
+
 // Pass 2: z transform + G-space diagonal + inverse z transform.  Work item
 // (pair q, row pair m2 in [0, n2/2]).  mode 0: kinetic |G|^2/2.  mode 1:
 // Teter with band kinetic energies tkin[col].  mode 2: identity.
@@ -630,6 +644,22 @@ dg_fft_xy_inv32_s(Elem* __restrict__ E, const int* __restrict__ active, const in
   __shared__ float2 buf[FFT_XY_TINY];
   fft_xy_inv_body<FFT_XY_TINY, FFT_TINY_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols,
                                                  mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_inv_m(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ double2 buf[FFT_XY_SMALL];
+  fft_xy_inv_body<FFT_XY_SMALL, FFT_TINY_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols,
+                                                  mode);
+}
+
+extern "C" __global__ void __launch_bounds__(FFT_TINY_THREADS)
+dg_fft_xy_inv32_m(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
+                  int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
+  __shared__ float2 buf[FFT_XY_SMALL];
+  fft_xy_inv_body<FFT_XY_SMALL, FFT_TINY_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols,
+                                                  mode);
 }
 
 // ---------------------------------------------------------------------------
