@@ -44,8 +44,8 @@ ALG_UNITS = {"dg_gram": 24.0, "dg_update": 14.0}
 # counter runs of the default command, calibrated on a 1 GiB copy (see
 # profiles/): (kernel class, workload, guard columns, streams) -> bytes.  Valid
 # only for the kernel build that was measured; removed when the kernel changes.
-MEASURED_TRAFFIC = {("dg_gram", "uneven_edges_24-48_J64-256", 16, 1): 105.633e9,
-                    ("dg_update", "uneven_edges_24-48_J64-256", 16, 1): 85.417e9}
+MEASURED_TRAFFIC = {("dg_gram", "uneven_edges_24-48_J64-256", 16, 1): 105.643e9,
+                    ("dg_update", "uneven_edges_24-48_J64-256", 16, 1): 85.412e9}
 # guard columns per element when --guard is not given: 16 on the slab (block
 # of 144 columns, the tile width of the 144-wide GEMM kernels) and on the
 # uneven batch, 8 on the one-element workload (32 states)
