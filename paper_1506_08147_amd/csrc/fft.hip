@@ -316,13 +316,6 @@ dg_fft_xy_fwd(Elem* __restrict__ E, const int* __restrict__ active, const int* _
   fft_xy_fwd_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
 }
 
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
-dg_fft_xy_fwd32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-                int na, int slot, int col0, int ncols) {
-  __shared__ float2 buf[FFT_XY_SMALL];
-  fft_xy_fwd_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, slot, col0, ncols);
-}
-
 extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
 dg_fft_xy_fwd_l(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
                 int na, int slot, int col0, int ncols) {
@@ -600,20 +593,6 @@ __device__ __forceinline__ void fft_xy_inv_body(C* buf, Elem* __restrict__ E,
       if (hasb) gst(OB + p, sc * r.y);
     }
   }
-}
-
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
-dg_fft_xy_inv(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-              int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
-  __shared__ double2 buf[FFT_XY_SMALL];
-  fft_xy_inv_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
-}
-
-extern "C" __global__ void __launch_bounds__(FFT_THREADS)
-dg_fft_xy_inv32(Elem* __restrict__ E, const int* __restrict__ active, const int* __restrict__ prefix,
-                int na, int in_slot, int out_slot, int col0, int ncols, int mode) {
-  __shared__ float2 buf[FFT_XY_SMALL];
-  fft_xy_inv_body<FFT_XY_SMALL, FFT_THREADS>(buf, E, active, prefix, na, in_slot, out_slot, col0, ncols, mode);
 }
 
 extern "C" __global__ void __launch_bounds__(FFT_THREADS, 4)
