@@ -632,11 +632,12 @@ struct dgdft_alb {
   }
 
   // The eigensolver of the Rayleigh-Ritz step: dg_rr_eig (orders up to 512,
-  // 1024-lane workgroups) and, when some element's order is 513..832,
-  // dg_rr_eig_wide (512 lanes); each skips the other's elements.  Outside
-  // graph capture the first runs on the group's second stream beside the
-  // second (one workgroup per element each, so together they take one
-  // compute unit per element instead of running one after the other).
+  // one 1024-lane workgroup per element) and, when some element's order is
+  // 513..832, for those elements the tridiagonalisation over TRI_NWG
+  // workgroups each (dg_tri_step, one launch per Householder step) and
+  // dg_rr_eig_wide_rest (inside graph capture the single-workgroup
+  // dg_rr_eig_wide instead); each skips the other's elements.  Outside graph
+  // capture dg_rr_eig runs on the group's second stream beside the others.
   void rr_eig_pair(const std::vector<int>& act, int single) {
     bool wide = false;
     for (int e : act) wide = wide || eig_wide((single ? 1 : (hasP_host(e) ? 3 : 2)) * eh[e].J);

@@ -321,10 +321,10 @@ dg_carry_in(Elem* __restrict__ E, const int* __restrict__ active, int na) {
   }
 }
 
-// Matrices of order EIG_WIDE_MIN..EIG_WIDE_MAX go to dg_rr_eig_wide: 512-lane
-// workgroups whose 256 registers per lane hold 13 rows of the one-pass
-// tridiagonalisation and back-transformation per lane (the 1024-lane
-// workgroup holds 8, so above order 512 it would take the three-pass form).
+// Matrices of order EIG_WIDE_MIN..EIG_WIDE_MAX go to the wide path: the
+// one-pass tridiagonalisation on four row groups (dg_rr_eig_wide) or over
+// TRI_NWG workgroups per matrix (dg_tri_step), and a back-transformation
+// with 13 rows per lane, on 1024-lane workgroups.
 constexpr int EIG_WIDE_MIN = 513;
 constexpr int EIG_WIDE_MAX = 832;
 constexpr int EIG_WIDE_THREADS = 1024;

@@ -939,9 +939,8 @@ __device__ void tri_step(T& t, double* A, int lda, int n, int k, int w, double* 
 // Householder tridiagonalisation reading and updating only the lower
 // triangle of the symmetric A.  Same outputs as tridiagonalize().  v, p:
 // scratch of n doubles each (LDS on the device).
-// WIDE: instantiate the wide-register device path (two row groups of up to
-// 7 chunks of 64 rows, n <= 832), for workgroups of at most 512 lanes whose
-// 256 registers per lane hold it.
+// WIDE: instantiate the device path for orders up to 832 (TRI_WIDE_H row
+// groups of up to TRI_WIDE_R chunks of 64 rows).
 template <bool WIDE = false, class T>
 __host__ __device__ void tridiagonalize_lower(T& t, double* A, int lda, int n, double* d, double* e,
                                               double* tau, double* v, double* p,
@@ -1487,7 +1486,7 @@ __host__ __device__ void backtransform(T& t, const double* A, int lda, const dou
 // Lowest k eigenpairs of the symmetric A (lower triangle read, destroyed):
 // w[0..k) ascending, Z (n x k).  work: 9 n + 6 n k doubles; cl: k ints
 // (global); lds: >= 2n doubles (and >= k for the generic back-transform).
-// WIDE: the wide-register device paths (workgroups of at most 512 lanes).
+// WIDE: the device paths for orders up to 832.
 // PRE: the tridiagonalisation is already done (by tri_step): d, e, tau in
 // work, reflectors in A.
 template <bool WIDE = false, bool PRE = false, class T>
