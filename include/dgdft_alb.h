@@ -319,7 +319,10 @@ int32_t dgdft_alb_rayleigh_ritz(dgdft_alb* h, int32_t elem, int32_t kb, const do
  * eigenvectors (device [count*n*k]).  n <= 3072.
  * method 0: Householder tridiagonalisation, bisection and inverse iteration
  *           for the k lowest only (w[0..k) written per matrix) -- the path of
- *           the solver; method 1: implicit QL on the whole spectrum. */
+ *           the solver; for 513 <= n <= 832 the tridiagonalisation runs over
+ *           eight workgroups per matrix, one kernel launch per Householder
+ *           step (n + 1 launches in all, e.g. in a captured graph);
+ *           method 1: implicit QL on the whole spectrum. */
 int32_t dgdft_small_syev(int32_t count, int32_t n, int32_t k, const double* A,
                          double* w, double* Z, int32_t method, void* stream);
 
