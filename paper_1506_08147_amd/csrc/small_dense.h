@@ -237,13 +237,13 @@ __host__ __device__ void tri_inv_lower(T& t, const double* L, int ldl, double* X
 // sum_{l<k} L[k][l] X[l][j]) / L[k][k], with thread j owning column j of
 // L^-1 stored as row j of Y.  All threads read the same L[k][l] at the same
 // time and neighbouring threads neighbouring entries of Y.
-// Device form: rows of L^-1 in blocks of B (B n <= 4096 doubles of L staged
+// Device form: rows of L^-1 in blocks of B (B n <= 13312 doubles of L staged
 // in LDS); thread j carries the block's entries of its column in registers
 // and reads its earlier entries once per block.  Terms are summed in the same
 // order as below (ascending l, the structural zeros l < j skipped).
 template <class T>
 __device__ void tri_inv_lower_t_dev(T& t, const double* L, int ldl, double* Y, int ldy, int n) {
-  constexpr int LS = 4096, BMAX = 16;
+  constexpr int LS = 16 * 832, BMAX = 16;   // blocks of 16 rows up to n = 832
   __shared__ double Ls[LS];
   int B = LS / n;
   B = B > BMAX ? BMAX : B;
